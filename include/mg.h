@@ -1,0 +1,185 @@
+/*
+ * mg.h -- C ABI of the MI355X (gfx950) Mixture Graph library (libmg.so).
+ *
+ * The Mixture Graph (Al-Thelaya, Agus, Schneider, IEEE VIS 2020) factors the
+ * normalized histogram mipmap of a segmentation volume into a DAG of binary
+ * linear interpolations. This library builds that graph on the CPU and runs
+ * its data-parallel hot path on the GPU:
+ *
+ *   - box-histogram queries: every box is cut into maximal aligned mipmap
+ *     cubes, each cube's voxel count is scattered onto the graph node that
+ *     holds its mixture, and that mass is pushed down the DAG in reverse
+ *     topological order to per-segment counts;
+ *   - transfer-function propagation: one colour per segment carried from the
+ *     sources to every node in topological order.
+ *
+ * Conventions for every entry point:
+ *   - Return value: MG_OK (0) or a negative MG_E* code; mg_last_error() then
+ *     holds a message for the calling thread. No entry point throws, aborts
+ *     or exits.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory on the graph's device (e.g. from torch tensors). The
+ *     caller owns every input and output buffer and keeps device buffers alive
+ *     until the work queued on `stream` has finished.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Query and propagation calls only enqueue work and never allocate; errors
+ *     of the queued kernels surface at the next synchronisation.
+ *   - Volumes are x fastest: voxel (x, y, z) is element x + nx*(y + ny*z).
+ *   - Boxes are uint32 rows (x0, y0, z0, dx, dy, dz): the half-open range
+ *     [x0, x0+dx) x [y0, y0+dy) x [z0, z0+dz), clipped to the volume; an
+ *     origin at or past the volume or a zero extent is an empty box (all-zero
+ *     histogram), never an error.
+ *   - Segments: the distinct IDs of the volume, in increasing order, are the
+ *     graph's sources 0 .. S-1; mg_segment_ids() maps them back.
+ *   - Calls that share a graph and a workspace must not overlap in time (use
+ *     one stream, or one workspace per stream).
+ */
+#ifndef MG_H
+#define MG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MG_OK 0
+#define MG_EINVAL (-1)    /* bad argument (null pointer, size, flag)              */
+#define MG_ENOMEM (-2)    /* host or device allocation failed                      */
+#define MG_EDEVICE (-3)   /* HIP runtime error (message has the HIP error string)  */
+#define MG_ESTATE (-4)    /* call out of order (e.g. query before mg_upload)       */
+#define MG_EDEPTH (-5)    /* graph deeper than mg_build_opts.max_depth             */
+#define MG_EIO (-6)       /* file error in mg_save / mg_load                        */
+#define MG_EFORMAT (-7)   /* corrupt or incompatible graph file or graph arrays    */
+#define MG_ELIMIT (-8)    /* a size beyond what this build supports (message says) */
+
+typedef struct mg_graph mg_graph; /* opaque; owned by the library, freed by mg_free */
+
+typedef struct {
+    uint32_t nx, ny, nz;   /* level-0 dimensions, each >= 1, nx*ny*nz < 2^32       */
+    uint32_t defer;        /* 1: deferred, load-balanced step schedule (Sec.
+                              "Reconstruction"); 0: one step per topological level */
+    uint32_t max_depth;    /* 0: no cap; else fail with MG_EDEPTH beyond it         */
+    uint32_t threads;      /* CPU threads for the build; 0 = all hardware threads   */
+    uint32_t reserved[4];  /* must be 0                                             */
+} mg_build_opts;
+
+#define MG_MAX_LEVELS 24
+
+typedef struct {
+    uint32_t nseg;          /* S: number of sources (distinct IDs)                   */
+    uint32_t n_nodes;       /* sources + internal nodes                              */
+    uint32_t depth;         /* topological depth = number of steps                   */
+    uint32_t n_levels;      /* mip levels (level 0 .. n_levels-1, last is 1^3)        */
+    uint32_t dims[MG_MAX_LEVELS][3]; /* per level (nx, ny, nz)                       */
+    uint64_t map_voxels;    /* total mip voxels over all levels                      */
+    uint64_t device_bytes;  /* device memory held after mg_upload (0 before)         */
+    int32_t device;         /* device ordinal after mg_upload, else -1                */
+    uint32_t max_mixture;   /* largest number of segments in one node's mixture      */
+} mg_info_t;
+
+/* Build a graph from a host uint32 ID volume (CPU; Sec. "Normalized Histogram
+ * Mipmap" Eq. (mip), Sec. "Factorization", Sec. "Compression", Sec.
+ * "Reconstruction"). Mip levels halve each axis rounding up down to 1^3; every
+ * mip voxel's mixture is the exact normalized histogram of its level-0 support.
+ * Each distinct mixture becomes one node, factored into binary lerps
+ * n = (1 - w) a + w b with exact rational w in (0, 1/2]; nodes are numbered by
+ * schedule step (sources first). On success *out owns host copies of the DAG
+ * and of one node ID per mip voxel. `ids` is read only during the call. */
+int mg_build(const uint32_t *ids, const mg_build_opts *opts, mg_graph **out);
+
+int mg_info(const mg_graph *g, mg_info_t *out);
+
+/* Host copies of the DAG, each array n_nodes long (NULL skips it): for node n,
+ * child_a/child_b are its two predecessors and w[n] = wnum[n]/wden[n] the
+ * weight of child_b, alpha[n] = w rounded to fp32; sources have a = b = n,
+ * w = 0. rank[n] is the topological level (Sec. "Reconstruction"), step[n]
+ * the step it runs in; step_ptr (depth + 2 entries) delimits the nodes of each
+ * step: step s holds IDs [step_ptr[s], step_ptr[s+1]), step 0 the sources. */
+int mg_export_dag(const mg_graph *g, uint32_t *child_a, uint32_t *child_b, float *alpha,
+                  uint64_t *wnum, uint64_t *wden, uint32_t *rank, uint32_t *step,
+                  uint32_t *step_ptr);
+
+/* Host copy of level `level`'s node IDs, x fastest, dims[level] voxels. */
+int mg_export_map(const mg_graph *g, uint32_t level, uint32_t *out);
+
+/* Original volume ID of each source, S entries (host). */
+int mg_segment_ids(const mg_graph *g, uint32_t *out);
+
+/* Copy the graph to device `device` (allocates device memory once; the
+ * current device is restored). Builds the per-level transposed node-ID copies
+ * on the device. Must precede every GPU entry point. */
+int mg_upload(mg_graph *g, int device);
+
+/* Bytes of device workspace that query calls of up to `max_boxes` boxes need. */
+int mg_workspace_bytes(const mg_graph *g, uint32_t max_boxes, uint64_t *bytes);
+
+/* Prepare a workspace once after allocating it (enqueued on `stream`). */
+int mg_workspace_init(mg_graph *g, void *d_work, uint64_t work_bytes, void *stream);
+
+/* Box histograms, the batched path (Sec. "Fast Sub-Volume Queries"; the
+ * decomposition of the appendix algorithm "Footprint assembly in 3D").
+ *   d_boxes  device uint32 [n][6]
+ *   d_out    device fp32 [n][S]: fraction of each segment's voxels in the
+ *            clipped box (counts divided by the box volume in fp64, rounded
+ *            to fp32); all zeros for an empty box. Counts from cubes whose
+ *            node is a source are exact integers; mass pushed through the DAG
+ *            is accumulated in fp32 with compensated (two-sum) updates.
+ *   d_work   workspace of mg_workspace_bytes(g, n) bytes, initialised once.
+ */
+int mg_query_boxes(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *d_out,
+                   void *d_work, uint64_t work_bytes, void *stream);
+
+/* The same results by one plain workgroup per box, in input order: the
+ * straightforward GPU kernel the batched path is measured against. */
+int mg_query_boxes_plain(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *d_out,
+                         void *d_work, uint64_t work_bytes, void *stream);
+
+/* mg_query_boxes that also reports the work of each box, for roofline
+ * accounting: d_stats device uint32 [n][2] = (cubes in the box's footprint,
+ * distinct internal graph nodes the box touched: scattered onto or reached
+ * by the push). */
+int mg_query_boxes_stats(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *d_out,
+                         uint32_t *d_stats, void *d_work, uint64_t work_bytes, void *stream);
+
+/* Competitor: the naive range query (Sec. "Results", range queries): every
+ * level-0 voxel of the box is read and counted. Same output as above. */
+int mg_naive_boxes(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *d_out,
+                   void *d_work, uint64_t work_bytes, void *stream);
+
+/* Footprint of each box as seen by the GPU decomposition: d_level_counts
+ * device uint32 [n][n_levels] cubes per level. If d_cubes is not NULL, also
+ * appends every cube as uint32 (box, level, cx, cy, cz, node) at slot
+ * atomicAdd(d_count, 1) while the slot is below `cap` (d_count device uint32,
+ * zeroed by the caller); order is unspecified. */
+int mg_footprint(mg_graph *g, const uint32_t *d_boxes, uint32_t n, uint32_t *d_level_counts,
+                 uint32_t *d_cubes, uint32_t cap, uint32_t *d_count, void *stream);
+
+/* Transfer-function propagation (Sec. "Reconstruction", colour palette of
+ * Sec. "Rendering"): d_tf device uint8 [T][S][4] RGBA8; source s of TF t gets
+ * byte/255 per channel, every internal node v_n = v_a + w_n (v_b - v_a) in
+ * fp32, step by step. d_node_rgba device fp32 [T][n_nodes][4]. */
+int mg_propagate_tf(mg_graph *g, const uint8_t *d_tf, uint32_t T, float *d_node_rgba,
+                    void *stream);
+
+/* Persist / restore the host graph (raw arrays with a header and checksums;
+ * not the paper's bit-packed stream). mg_load validates the arrays (IDs in
+ * range, children before parents, weights in (0, 1/2]) and returns
+ * MG_EFORMAT on any mismatch. */
+int mg_save(const mg_graph *g, const char *path);
+int mg_load(const char *path, mg_graph **out);
+
+/* Kernel timing: when enabled, the dominant kernel of each query /
+ * propagation call is bracketed by HIP events on the call's stream;
+ * mg_timing_read synchronises those events and returns the summed
+ * milliseconds and the number of launches since the last read. */
+int mg_timing_enable(mg_graph *g, int enable);
+int mg_timing_read(mg_graph *g, double *ms, uint32_t *launches);
+
+const char *mg_last_error(void);
+void mg_free(mg_graph *g);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MG_H */

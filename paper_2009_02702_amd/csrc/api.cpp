@@ -1,0 +1,326 @@
+// C ABI entry points (host side): argument checks, error strings, build,
+// export, save/load. GPU work is delegated to kernels.hip.
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "mg_internal.hpp"
+
+struct mg_graph {
+    mg::Graph g;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int done(int code, const std::string &msg)
+{
+    if (code != MG_OK) g_err = msg;
+    return code;
+}
+
+// ---- save / load: "MGRAPH01" + header + arrays, each followed by FNV-1a 64
+constexpr char kMagic[8] = {'M', 'G', 'R', 'A', 'P', 'H', '0', '1'};
+
+uint64_t fnv(const void *p, size_t n, uint64_t h = 0xcbf29ce484222325ULL)
+{
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 0x100000001b3ULL;
+    return h;
+}
+
+bool wr(FILE *f, const void *p, size_t n)
+{
+    return n == 0 || fwrite(p, 1, n, f) == n;
+}
+
+template <class T>
+bool wr_vec(FILE *f, const std::vector<T> &v)
+{
+    const uint64_t n = v.size();
+    const uint64_t h = fnv(v.data(), n * sizeof(T));
+    return wr(f, &n, 8) && wr(f, v.data(), n * sizeof(T)) && wr(f, &h, 8);
+}
+
+bool rd(FILE *f, void *p, size_t n)
+{
+    return n == 0 || fread(p, 1, n, f) == n;
+}
+
+template <class T>
+int rd_vec(FILE *f, std::vector<T> *v, uint64_t limit)
+{
+    uint64_t n = 0, h = 0;
+    if (!rd(f, &n, 8)) return MG_EIO;
+    if (n > limit) return MG_EFORMAT;
+    try {
+        v->resize(n);
+    } catch (...) {
+        return MG_ENOMEM;
+    }
+    if (!rd(f, v->data(), n * sizeof(T)) || !rd(f, &h, 8)) return MG_EIO;
+    if (h != fnv(v->data(), n * sizeof(T))) return MG_EFORMAT;
+    return MG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mg_last_error(void) { return g_err.c_str(); }
+
+int mg_build(const uint32_t *ids, const mg_build_opts *opts, mg_graph **out)
+{
+    if (!ids || !opts || !out) return fail(MG_EINVAL, "mg_build: null argument");
+    *out = nullptr;
+    if (opts->nx == 0 || opts->ny == 0 || opts->nz == 0) return fail(MG_EINVAL, "mg_build: zero dimension");
+    const uint64_t nvox = uint64_t(opts->nx) * opts->ny * opts->nz;
+    if (nvox >= (1ull << 32))
+        return fail(MG_ELIMIT, "mg_build: volumes of 2^32 voxels or more are not supported (32-bit counters)");
+    for (uint32_t r : opts->reserved)
+        if (r) return fail(MG_EINVAL, "mg_build: reserved fields must be 0");
+    if (opts->defer > 1) return fail(MG_EINVAL, "mg_build: defer must be 0 or 1");
+    mg_graph *h = new (std::nothrow) mg_graph;
+    if (!h) return fail(MG_ENOMEM, "mg_build: out of host memory");
+    std::string err;
+    int rc;
+    try {
+        rc = mg::build_graph(ids, opts, &h->g, &err);
+    } catch (const std::bad_alloc &) {
+        rc = MG_ENOMEM, err = "mg_build: out of host memory";
+    } catch (const std::exception &e) {
+        rc = MG_EINVAL, err = std::string("mg_build: ") + e.what();
+    }
+    if (rc != MG_OK) {
+        delete h;
+        return fail(rc, err);
+    }
+    *out = h;
+    return MG_OK;
+}
+
+int mg_info(const mg_graph *h, mg_info_t *out)
+{
+    if (!h || !out) return fail(MG_EINVAL, "mg_info: null argument");
+    const mg::Graph &g = h->g;
+    std::memset(out, 0, sizeof(*out));
+    out->nseg = g.nseg;
+    out->n_nodes = g.n_nodes;
+    out->depth = g.depth;
+    out->n_levels = g.n_levels;
+    for (uint32_t l = 0; l < g.n_levels; ++l)
+        for (int a = 0; a < 3; ++a) out->dims[l][a] = g.lev_dims[3 * l + a];
+    out->map_voxels = g.lev_off.empty() ? 0 : g.lev_off[g.n_levels];
+    out->device_bytes = g.dev.bytes;
+    out->device = g.dev.device;
+    out->max_mixture = g.max_mixture;
+    return MG_OK;
+}
+
+int mg_export_dag(const mg_graph *h, uint32_t *child_a, uint32_t *child_b, float *alpha, uint64_t *wnum,
+                  uint64_t *wden, uint32_t *rank, uint32_t *step, uint32_t *step_ptr)
+{
+    if (!h) return fail(MG_EINVAL, "mg_export_dag: null graph");
+    const mg::Graph &g = h->g;
+    const size_t n = g.n_nodes;
+    if (child_a) std::memcpy(child_a, g.child_a.data(), n * 4);
+    if (child_b) std::memcpy(child_b, g.child_b.data(), n * 4);
+    if (alpha) std::memcpy(alpha, g.alpha.data(), n * 4);
+    if (wnum) std::memcpy(wnum, g.wnum.data(), n * 8);
+    if (wden) std::memcpy(wden, g.wden.data(), n * 8);
+    if (rank) std::memcpy(rank, g.rank.data(), n * 4);
+    if (step) std::memcpy(step, g.step.data(), n * 4);
+    if (step_ptr) std::memcpy(step_ptr, g.step_ptr.data(), g.step_ptr.size() * 4);
+    return MG_OK;
+}
+
+int mg_export_map(const mg_graph *h, uint32_t level, uint32_t *out)
+{
+    if (!h || !out) return fail(MG_EINVAL, "mg_export_map: null argument");
+    const mg::Graph &g = h->g;
+    if (level >= g.n_levels) return fail(MG_EINVAL, "mg_export_map: level out of range");
+    std::memcpy(out, g.maps.data() + g.lev_off[level], (g.lev_off[level + 1] - g.lev_off[level]) * 4);
+    return MG_OK;
+}
+
+int mg_segment_ids(const mg_graph *h, uint32_t *out)
+{
+    if (!h || !out) return fail(MG_EINVAL, "mg_segment_ids: null argument");
+    std::memcpy(out, h->g.seg_ids.data(), h->g.seg_ids.size() * 4);
+    return MG_OK;
+}
+
+int mg_upload(mg_graph *h, int device)
+{
+    if (!h) return fail(MG_EINVAL, "mg_upload: null graph");
+    if (device < 0) return fail(MG_EINVAL, "mg_upload: negative device");
+    std::string err;
+    return done(mg::dev_upload(&h->g, device, &err), err);
+}
+
+int mg_workspace_bytes(const mg_graph *h, uint32_t max_boxes, uint64_t *bytes)
+{
+    if (!h || !bytes) return fail(MG_EINVAL, "mg_workspace_bytes: null argument");
+    *bytes = mg::dev_workspace_bytes(h->g, max_boxes);
+    return MG_OK;
+}
+
+int mg_workspace_init(mg_graph *h, void *d_work, uint64_t work_bytes, void *stream)
+{
+    if (!h || !d_work) return fail(MG_EINVAL, "mg_workspace_init: null argument");
+    std::string err;
+    return done(mg::dev_workspace_init(&h->g, d_work, work_bytes, stream, &err), err);
+}
+
+static int query_common(mg_graph *h, const uint32_t *boxes, uint32_t n, float *out, void *work,
+                        uint64_t bytes, void *stream, int variant, const char *name, uint32_t *stats = nullptr)
+{
+    if (!h) return fail(MG_EINVAL, std::string(name) + ": null graph");
+    if (n == 0) return MG_OK;
+    if (!boxes || !out || !work) return fail(MG_EINVAL, std::string(name) + ": null buffer");
+    std::string err;
+    return done(mg::dev_query(&h->g, boxes, n, out, work, bytes, stream, variant, stats, &err), err);
+}
+
+int mg_query_boxes(mg_graph *h, const uint32_t *d_boxes, uint32_t n, float *d_out, void *d_work,
+                   uint64_t work_bytes, void *stream)
+{
+    return query_common(h, d_boxes, n, d_out, d_work, work_bytes, stream, mg::kQueryBatched, "mg_query_boxes");
+}
+
+int mg_query_boxes_plain(mg_graph *h, const uint32_t *d_boxes, uint32_t n, float *d_out, void *d_work,
+                         uint64_t work_bytes, void *stream)
+{
+    return query_common(h, d_boxes, n, d_out, d_work, work_bytes, stream, mg::kQueryPlain,
+                        "mg_query_boxes_plain");
+}
+
+int mg_query_boxes_stats(mg_graph *h, const uint32_t *d_boxes, uint32_t n, float *d_out, uint32_t *d_stats,
+                         void *d_work, uint64_t work_bytes, void *stream)
+{
+    if (n && !d_stats) return fail(MG_EINVAL, "mg_query_boxes_stats: null stats buffer");
+    return query_common(h, d_boxes, n, d_out, d_work, work_bytes, stream, mg::kQueryBatched,
+                        "mg_query_boxes_stats", d_stats);
+}
+
+int mg_naive_boxes(mg_graph *h, const uint32_t *d_boxes, uint32_t n, float *d_out, void *d_work,
+                   uint64_t work_bytes, void *stream)
+{
+    return query_common(h, d_boxes, n, d_out, d_work, work_bytes, stream, mg::kQueryNaive, "mg_naive_boxes");
+}
+
+int mg_footprint(mg_graph *h, const uint32_t *d_boxes, uint32_t n, uint32_t *d_level_counts, uint32_t *d_cubes,
+                 uint32_t cap, uint32_t *d_count, void *stream)
+{
+    if (!h) return fail(MG_EINVAL, "mg_footprint: null graph");
+    if (n == 0) return MG_OK;
+    if (!d_boxes || !d_level_counts) return fail(MG_EINVAL, "mg_footprint: null buffer");
+    if (d_cubes && !d_count) return fail(MG_EINVAL, "mg_footprint: d_cubes needs d_count");
+    std::string err;
+    return done(mg::dev_footprint(&h->g, d_boxes, n, d_level_counts, d_cubes, cap, d_count, stream, &err), err);
+}
+
+int mg_propagate_tf(mg_graph *h, const uint8_t *d_tf, uint32_t T, float *d_node_rgba, void *stream)
+{
+    if (!h) return fail(MG_EINVAL, "mg_propagate_tf: null graph");
+    if (T == 0) return MG_OK;
+    if (!d_tf || !d_node_rgba) return fail(MG_EINVAL, "mg_propagate_tf: null buffer");
+    std::string err;
+    return done(mg::dev_propagate_tf(&h->g, d_tf, T, d_node_rgba, stream, &err), err);
+}
+
+int mg_timing_enable(mg_graph *h, int enable)
+{
+    if (!h) return fail(MG_EINVAL, "mg_timing_enable: null graph");
+    std::string err;
+    return done(mg::dev_timing_enable(&h->g, enable, &err), err);
+}
+
+int mg_timing_read(mg_graph *h, double *ms, uint32_t *launches)
+{
+    if (!h || !ms || !launches) return fail(MG_EINVAL, "mg_timing_read: null argument");
+    std::string err;
+    return done(mg::dev_timing_read(&h->g, ms, launches, &err), err);
+}
+
+int mg_save(const mg_graph *h, const char *path)
+{
+    if (!h || !path) return fail(MG_EINVAL, "mg_save: null argument");
+    const mg::Graph &g = h->g;
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(MG_EIO, std::string("mg_save: cannot open ") + path);
+    uint32_t hdr[8] = {g.dims[0], g.dims[1], g.dims[2], g.nseg, g.n_nodes, g.depth, g.n_levels, g.max_mixture};
+    bool ok = wr(f, kMagic, 8) && wr(f, hdr, sizeof(hdr)) && wr_vec(f, g.seg_ids) && wr_vec(f, g.child_a) &&
+              wr_vec(f, g.child_b) && wr_vec(f, g.alpha) && wr_vec(f, g.wnum) && wr_vec(f, g.wden) &&
+              wr_vec(f, g.rank) && wr_vec(f, g.step) && wr_vec(f, g.step_ptr) && wr_vec(f, g.lev_off) &&
+              wr_vec(f, g.maps);
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? MG_OK : fail(MG_EIO, std::string("mg_save: write failed for ") + path);
+}
+
+int mg_load(const char *path, mg_graph **out)
+{
+    if (!path || !out) return fail(MG_EINVAL, "mg_load: null argument");
+    *out = nullptr;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(MG_EIO, std::string("mg_load: cannot open ") + path);
+    mg_graph *h = new (std::nothrow) mg_graph;
+    if (!h) {
+        std::fclose(f);
+        return fail(MG_ENOMEM, "mg_load: out of host memory");
+    }
+    mg::Graph &g = h->g;
+    char magic[8];
+    uint32_t hdr[8];
+    int rc = MG_OK;
+    if (!rd(f, magic, 8) || !rd(f, hdr, sizeof(hdr))) rc = MG_EIO;
+    else if (std::memcmp(magic, kMagic, 8) != 0) rc = MG_EFORMAT;
+    if (rc == MG_OK) {
+        g.dims[0] = hdr[0], g.dims[1] = hdr[1], g.dims[2] = hdr[2];
+        g.nseg = hdr[3], g.n_nodes = hdr[4], g.depth = hdr[5], g.n_levels = hdr[6], g.max_mixture = hdr[7];
+        const uint64_t nvox = uint64_t(g.dims[0]) * g.dims[1] * g.dims[2];
+        const uint64_t N = g.n_nodes, lim_maps = 2 * nvox + 64;
+        if (g.dims[0] == 0 || g.dims[1] == 0 || g.dims[2] == 0 || nvox >= (1ull << 32) ||
+            g.n_levels > MG_MAX_LEVELS)
+            rc = MG_EFORMAT;
+        if (rc == MG_OK) rc = rd_vec(f, &g.seg_ids, N);
+        if (rc == MG_OK) rc = rd_vec(f, &g.child_a, N);
+        if (rc == MG_OK) rc = rd_vec(f, &g.child_b, N);
+        if (rc == MG_OK) rc = rd_vec(f, &g.alpha, N);
+        if (rc == MG_OK) rc = rd_vec(f, &g.wnum, N);
+        if (rc == MG_OK) rc = rd_vec(f, &g.wden, N);
+        if (rc == MG_OK) rc = rd_vec(f, &g.rank, N);
+        if (rc == MG_OK) rc = rd_vec(f, &g.step, N);
+        if (rc == MG_OK) rc = rd_vec(f, &g.step_ptr, uint64_t(g.depth) + 2);
+        if (rc == MG_OK) rc = rd_vec(f, &g.lev_off, uint64_t(MG_MAX_LEVELS) + 1);
+        if (rc == MG_OK) rc = rd_vec(f, &g.maps, lim_maps);
+        if (rc == MG_OK) mg::level_dims(g.dims, &g.lev_dims);
+    }
+    std::fclose(f);
+    std::string err;
+    if (rc == MG_OK) rc = mg::validate_graph(g, &err);
+    else err = rc == MG_EIO ? "mg_load: read failed" : "mg_load: corrupt or incompatible file";
+    if (rc != MG_OK) {
+        delete h;
+        return fail(rc, err.empty() ? "mg_load: invalid graph" : "mg_load: " + err);
+    }
+    *out = h;
+    return MG_OK;
+}
+
+void mg_free(mg_graph *h)
+{
+    if (!h) return;
+    mg::dev_free(&h->g);
+    delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,625 @@
+// CPU construction of the Mixture Graph from a uint32 segment-ID volume.
+//
+// Paper sections followed (Al-Thelaya, Agus, Schneider, "The Mixture Graph"):
+//  * Sec. "Normalized Histogram Mipmap", Eq. (mip): levels halve every axis
+//    (rounding up) down to 1^3. A mip voxel holds the normalized histogram of
+//    its level-0 support; here it is kept as integer counts reduced by their
+//    gcd, so mixtures are compared exactly (border voxels are weighted by
+//    their level-0 voxel counts).
+//  * Sec. "Factorization": a mixture with k > 1 non-zero entries becomes
+//    binary linear interpolations whose leaves are the segments (sources);
+//    Sec. "Compression": identical nodes are re-used, which needs equal
+//    mixtures, i.e. equal ratios. Every distinct mixture here is one node and
+//    nodes are deduplicated on their exact reduced count vector.
+//  * Sec. "Implementation Details": (i, j, w) and (j, i, 1 - w) are the same
+//    interpolation; the orientation with w <= 1/2 is stored (the heavier part
+//    is child a), ties broken by the lower node ID.
+//  * Sec. "Reconstruction": topological level = 1 + max of the two
+//    predecessors' levels (one linear scan, since predecessors are created
+//    first); deferred scheduling of nodes whose successors are all at least
+//    two levels up, filling each step to at least ceil(N / depth) nodes.
+//
+// How a mixture is split differs from the paper's greedy pair search (max
+// occurrence / max reduction over all mixtures): the segments of a mixture,
+// in increasing segment order, are halved recursively, so every node's
+// sub-tree has exactly k - 1 internal nodes and depth ceil(log2 k). This keeps
+// the graph shallow (fewer synchronisation steps, smaller fp32 error in the
+// push) and the closure of any node exactly its own sub-tree.
+//
+// Mip voxels are not materialised as mixtures: a voxel whose children all
+// hold the same node holds that node too (a sum of proportional count
+// vectors is proportional); only voxels with differing children merge their
+// children's reduced count vectors, scaled back to voxel counts.
+#include <algorithm>
+#include <atomic>
+#include <cstring>
+#include <functional>
+#include <numeric>
+#include <thread>
+
+#include "mg_internal.hpp"
+
+namespace mg {
+namespace {
+
+constexpr uint32_t kMixed = 0xFFFFFFFFu;
+
+unsigned resolve_threads(uint32_t t)
+{
+    unsigned hw = std::thread::hardware_concurrency();
+    if (hw == 0) hw = 1;
+    return t == 0 ? hw : std::min<unsigned>(t, 4 * hw);
+}
+
+// Run fn(begin, end, worker) over [0, n) in `nt` contiguous chunks, in order.
+void parallel_chunks(uint64_t n, unsigned nt, const std::function<void(uint64_t, uint64_t, unsigned)> &fn)
+{
+    if (n == 0) return;
+    if (nt <= 1 || n < 4096) {
+        fn(0, n, 0);
+        return;
+    }
+    std::vector<std::thread> th;
+    const uint64_t chunk = (n + nt - 1) / nt;
+    for (unsigned t = 0; t < nt; ++t) {
+        const uint64_t b = t * chunk, e = std::min<uint64_t>(n, b + chunk);
+        if (b >= e) break;
+        th.emplace_back(fn, b, e, t);
+    }
+    for (auto &x : th) x.join();
+}
+
+inline uint64_t mix64(uint64_t x)
+{
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdULL;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ULL;
+    x ^= x >> 33;
+    return x;
+}
+
+uint64_t hash_mixture(const uint32_t *seg, const uint64_t *cnt, uint32_t k)
+{
+    uint64_t h = 0x9E3779B97F4A7C15ULL ^ k;
+    for (uint32_t i = 0; i < k; ++i) {
+        h = mix64(h ^ (uint64_t(seg[i]) * 0x100000001B3ULL));
+        h = mix64(h ^ cnt[i]);
+    }
+    return h | 1;  // 0 marks an empty hash slot
+}
+
+uint64_t gcd64(uint64_t a, uint64_t b)
+{
+    while (b) {
+        const uint64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// Node store during construction: reduced mixtures, DAG edges, and a hash
+// index from mixture to node ID. Sources are nodes 0 .. S-1.
+class NodeStore {
+public:
+    explicit NodeStore(uint32_t nseg)
+    {
+        off_.reserve(nseg + 1);
+        off_.push_back(0);
+        for (uint32_t s = 0; s < nseg; ++s) {
+            seg_.push_back(s);
+            cnt_.push_back(1);
+            off_.push_back(seg_.size());
+            total_.push_back(1);
+            a_.push_back(s);
+            b_.push_back(s);
+            wn_.push_back(0);
+            wd_.push_back(1);
+        }
+        rehash(1024);
+    }
+
+    uint32_t size() const { return uint32_t(total_.size()); }
+    uint64_t total(uint32_t n) const { return total_[n]; }
+    uint32_t len(uint32_t n) const { return uint32_t(off_[n + 1] - off_[n]); }
+    const uint32_t *seg(uint32_t n) const { return seg_.data() + off_[n]; }
+    const uint64_t *cnt(uint32_t n) const { return cnt_.data() + off_[n]; }
+
+    // Node of a reduced, segment-sorted count vector, or kMixed if absent (read only).
+    uint32_t find(const uint32_t *s, const uint64_t *c, uint32_t k, uint64_t h) const
+    {
+        if (k == 1) return s[0];
+        const uint64_t mask = hkey_.size() - 1;
+        for (uint64_t i = h & mask;; i = (i + 1) & mask) {
+            if (hkey_[i] == 0) return kMixed;
+            if (hkey_[i] == h) {
+                const uint32_t n = hval_[i];
+                if (len(n) == k && std::equal(s, s + k, seg(n)) && std::equal(c, c + k, cnt(n))) return n;
+            }
+        }
+    }
+
+    // Node of a reduced, segment-sorted count vector; factor it if new.
+    uint32_t get(const uint32_t *s, const uint64_t *c, uint32_t k)
+    {
+        if (k == 1) return s[0];
+        const uint64_t h = hash_mixture(s, c, k);
+        const uint32_t f = find(s, c, k, h);
+        if (f != kMixed) return f;
+        return make(s, c, k, h);
+    }
+
+    uint64_t nbytes_mix() const { return seg_.size() * 12; }
+
+    std::vector<uint32_t> a_, b_;
+    std::vector<uint64_t> wn_, wd_;
+
+private:
+    // Split the k >= 2 entries into the first floor(k/2) and the rest.
+    uint32_t make(const uint32_t *s, const uint64_t *c, uint32_t k, uint64_t h)
+    {
+        // own copies: the recursion below may grow storage that s / c point into
+        const std::vector<uint32_t> ss(s, s + k);
+        const std::vector<uint64_t> cc(c, c + k);
+        const uint32_t hl = k / 2, hr = k - hl;
+        uint64_t tl = 0, tr = 0, gl = 0, gr = 0;
+        for (uint32_t i = 0; i < hl; ++i) tl += cc[i], gl = gcd64(gl, cc[i]);
+        for (uint32_t i = hl; i < k; ++i) tr += cc[i], gr = gcd64(gr, cc[i]);
+        std::vector<uint64_t> red(k);
+        for (uint32_t i = 0; i < hl; ++i) red[i] = cc[i] / gl;
+        for (uint32_t i = hl; i < k; ++i) red[i] = cc[i] / gr;
+        const uint32_t nl = get(ss.data(), red.data(), hl);
+        const uint32_t nr = get(ss.data() + hl, red.data() + hl, hr);
+        uint32_t a, b;
+        uint64_t wn;
+        if (tl > tr || (tl == tr && nl < nr)) {
+            a = nl, b = nr, wn = tr;
+        } else {
+            a = nr, b = nl, wn = tl;
+        }
+        const uint64_t wd = tl + tr;
+        const uint64_t g = gcd64(wn, wd);
+        const uint32_t id = size();
+        seg_.insert(seg_.end(), ss.begin(), ss.end());
+        cnt_.insert(cnt_.end(), cc.begin(), cc.end());
+        off_.push_back(seg_.size());
+        total_.push_back(wd);
+        a_.push_back(a);
+        b_.push_back(b);
+        wn_.push_back(wn / g);
+        wd_.push_back(wd / g);
+        insert(h, id);
+        return id;
+    }
+
+    void insert(uint64_t h, uint32_t id)
+    {
+        if (2 * (++used_) > hkey_.size()) rehash(hkey_.size() * 2);
+        const uint64_t mask = hkey_.size() - 1;
+        uint64_t i = h & mask;
+        while (hkey_[i] != 0) i = (i + 1) & mask;
+        hkey_[i] = h;
+        hval_[i] = id;
+    }
+
+    void rehash(uint64_t cap)
+    {
+        std::vector<uint64_t> ok;
+        std::vector<uint32_t> ov;
+        ok.swap(hkey_);
+        ov.swap(hval_);
+        hkey_.assign(cap, 0);
+        hval_.assign(cap, 0);
+        const uint64_t mask = cap - 1;
+        for (uint64_t j = 0; j < ok.size(); ++j) {
+            if (ok[j] == 0) continue;
+            uint64_t i = ok[j] & mask;
+            while (hkey_[i] != 0) i = (i + 1) & mask;
+            hkey_[i] = ok[j];
+            hval_[i] = ov[j];
+        }
+    }
+
+    std::vector<uint32_t> seg_;
+    std::vector<uint64_t> cnt_;
+    std::vector<uint64_t> off_;
+    std::vector<uint64_t> total_;
+    std::vector<uint64_t> hkey_;
+    std::vector<uint32_t> hval_;
+    uint64_t used_ = 0;
+};
+
+// Distinct IDs in increasing order and the compacted level-0 map.
+int compact_ids(const uint32_t *ids, uint64_t nvox, unsigned nt, std::vector<uint32_t> *seg_ids,
+                uint32_t *map0, std::string *err)
+{
+    uint32_t maxid = 0;
+    {
+        std::vector<uint32_t> mx(nt, 0);
+        parallel_chunks(nvox, nt, [&](uint64_t b, uint64_t e, unsigned t) {
+            uint32_t m = 0;
+            for (uint64_t i = b; i < e; ++i) m = std::max(m, ids[i]);
+            mx[t] = m;
+        });
+        for (uint32_t m : mx) maxid = std::max(maxid, m);
+    }
+    if (maxid < (1u << 26)) {
+        // direct table
+        std::vector<std::atomic<uint8_t>> seen(uint64_t(maxid) + 1);
+        for (auto &s : seen) s.store(0, std::memory_order_relaxed);
+        parallel_chunks(nvox, nt, [&](uint64_t b, uint64_t e, unsigned) {
+            uint32_t last = 0xFFFFFFFFu;
+            for (uint64_t i = b; i < e; ++i) {
+                if (ids[i] == last) continue;
+                last = ids[i];
+                seen[last].store(1, std::memory_order_relaxed);
+            }
+        });
+        std::vector<uint32_t> lut(uint64_t(maxid) + 1, 0);
+        seg_ids->clear();
+        for (uint64_t v = 0; v <= maxid; ++v)
+            if (seen[v].load(std::memory_order_relaxed)) {
+                lut[v] = uint32_t(seg_ids->size());
+                seg_ids->push_back(uint32_t(v));
+            }
+        parallel_chunks(nvox, nt, [&](uint64_t b, uint64_t e, unsigned) {
+            for (uint64_t i = b; i < e; ++i) map0[i] = lut[ids[i]];
+        });
+        return MG_OK;
+    }
+    // sparse IDs: per-chunk sorted distinct lists, merged; then binary search
+    std::vector<std::vector<uint32_t>> parts(nt);
+    parallel_chunks(nvox, nt, [&](uint64_t b, uint64_t e, unsigned t) {
+        std::vector<uint32_t> v;
+        uint32_t last = 0;
+        bool have = false;
+        for (uint64_t i = b; i < e; ++i) {
+            if (have && ids[i] == last) continue;
+            last = ids[i];
+            have = true;
+            v.push_back(last);
+            if (v.size() > (1u << 20)) {
+                std::sort(v.begin(), v.end());
+                v.erase(std::unique(v.begin(), v.end()), v.end());
+            }
+        }
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+        parts[t].swap(v);
+    });
+    seg_ids->clear();
+    for (auto &p : parts) seg_ids->insert(seg_ids->end(), p.begin(), p.end());
+    std::sort(seg_ids->begin(), seg_ids->end());
+    seg_ids->erase(std::unique(seg_ids->begin(), seg_ids->end()), seg_ids->end());
+    const std::vector<uint32_t> &sid = *seg_ids;
+    parallel_chunks(nvox, nt, [&](uint64_t b, uint64_t e, unsigned) {
+        for (uint64_t i = b; i < e; ++i)
+            map0[i] = uint32_t(std::lower_bound(sid.begin(), sid.end(), ids[i]) - sid.begin());
+    });
+    (void)err;
+    return MG_OK;
+}
+
+inline uint64_t extent(uint64_t i, unsigned lev, uint64_t dim)
+{
+    const uint64_t lo = i << lev, hi = std::min<uint64_t>((i + 1) << lev, dim);
+    return hi - lo;
+}
+
+}  // namespace
+
+void level_dims(const uint32_t dims[3], std::vector<uint32_t> *out)
+{
+    out->clear();
+    uint32_t d[3] = {dims[0], dims[1], dims[2]};
+    for (;;) {
+        out->insert(out->end(), d, d + 3);
+        if (d[0] <= 1 && d[1] <= 1 && d[2] <= 1) break;
+        for (int a = 0; a < 3; ++a) d[a] = (d[a] + 1) / 2;
+    }
+}
+
+int build_graph(const uint32_t *ids, const mg_build_opts *o, Graph *g, std::string *err)
+{
+    const uint64_t nx = o->nx, ny = o->ny, nz = o->nz;
+    const uint64_t nvox = nx * ny * nz;
+    const unsigned nt = resolve_threads(o->threads);
+    g->dims[0] = o->nx, g->dims[1] = o->ny, g->dims[2] = o->nz;
+    level_dims(g->dims, &g->lev_dims);
+    g->n_levels = uint32_t(g->lev_dims.size() / 3);
+    if (g->n_levels > MG_MAX_LEVELS) {
+        *err = "too many mip levels";
+        return MG_ELIMIT;
+    }
+    g->lev_off.assign(g->n_levels + 1, 0);
+    for (uint32_t l = 0; l < g->n_levels; ++l)
+        g->lev_off[l + 1] = g->lev_off[l] +
+                            uint64_t(g->lev_dims[3 * l]) * g->lev_dims[3 * l + 1] * g->lev_dims[3 * l + 2];
+    try {
+        g->maps.assign(g->lev_off[g->n_levels], 0);
+    } catch (...) {
+        *err = "host allocation of the node maps failed";
+        return MG_ENOMEM;
+    }
+    int rc = compact_ids(ids, nvox, nt, &g->seg_ids, g->maps.data(), err);
+    if (rc) return rc;
+    g->nseg = uint32_t(g->seg_ids.size());
+
+    NodeStore store(g->nseg);
+
+    for (uint32_t l = 1; l < g->n_levels; ++l) {
+        const uint64_t px = g->lev_dims[3 * (l - 1)], py = g->lev_dims[3 * (l - 1) + 1],
+                       pz = g->lev_dims[3 * (l - 1) + 2];
+        const uint64_t cx = g->lev_dims[3 * l], cy = g->lev_dims[3 * l + 1], cz = g->lev_dims[3 * l + 2];
+        const uint32_t *prev = g->maps.data() + g->lev_off[l - 1];
+        uint32_t *cur = g->maps.data() + g->lev_off[l];
+        const uint64_t ncur = cx * cy * cz;
+
+        // pass A: voxels whose children share one node inherit it
+        std::vector<std::vector<uint64_t>> mixed_parts(nt);
+        parallel_chunks(ncur, nt, [&](uint64_t b, uint64_t e, unsigned t) {
+            auto &mp = mixed_parts[t];
+            for (uint64_t v = b; v < e; ++v) {
+                const uint64_t x = v % cx, y = (v / cx) % cy, z = v / (cx * cy);
+                uint32_t first = kMixed;
+                bool same = true;
+                for (int dz = 0; dz < 2 && same; ++dz) {
+                    const uint64_t zz = 2 * z + dz;
+                    if (zz >= pz) break;
+                    for (int dy = 0; dy < 2 && same; ++dy) {
+                        const uint64_t yy = 2 * y + dy;
+                        if (yy >= py) break;
+                        for (int dx = 0; dx < 2; ++dx) {
+                            const uint64_t xx = 2 * x + dx;
+                            if (xx >= px) break;
+                            const uint32_t n = prev[xx + px * (yy + py * zz)];
+                            if (first == kMixed) first = n;
+                            else if (n != first) { same = false; break; }
+                        }
+                    }
+                }
+                if (same) cur[v] = first;
+                else { cur[v] = kMixed; mp.push_back(v); }
+            }
+        });
+        std::vector<uint64_t> mixed;
+        for (auto &p : mixed_parts) mixed.insert(mixed.end(), p.begin(), p.end());
+        mixed_parts.clear();
+        if (mixed.empty()) continue;
+
+        // pass B: reduced count vector of every mixed voxel (read-only on the store)
+        struct Rec { uint64_t off; uint32_t k; uint64_t h; };
+        const unsigned nparts = std::min<unsigned>(nt, unsigned((mixed.size() + 1023) / 1024));
+        std::vector<std::vector<uint32_t>> bseg(std::max(1u, nparts));
+        std::vector<std::vector<uint64_t>> bcnt(std::max(1u, nparts));
+        std::vector<Rec> recs(mixed.size());
+        std::vector<uint32_t> part_of(mixed.size());
+        parallel_chunks(mixed.size(), std::max(1u, nparts), [&](uint64_t b, uint64_t e, unsigned t) {
+            std::vector<std::pair<uint32_t, uint64_t>> acc;
+            auto &S = bseg[t];
+            auto &C = bcnt[t];
+            for (uint64_t i = b; i < e; ++i) {
+                const uint64_t v = mixed[i];
+                const uint64_t x = v % cx, y = (v / cx) % cy, z = v / (cx * cy);
+                uint32_t cn[8];
+                uint64_t cw[8];
+                int nc = 0;
+                for (int dz = 0; dz < 2; ++dz) {
+                    const uint64_t zz = 2 * z + dz;
+                    if (zz >= pz) break;
+                    for (int dy = 0; dy < 2; ++dy) {
+                        const uint64_t yy = 2 * y + dy;
+                        if (yy >= py) break;
+                        for (int dx = 0; dx < 2; ++dx) {
+                            const uint64_t xx = 2 * x + dx;
+                            if (xx >= px) break;
+                            const uint32_t n = prev[xx + px * (yy + py * zz)];
+                            const uint64_t nvx = extent(xx, l - 1, nx) * extent(yy, l - 1, ny) * extent(zz, l - 1, nz);
+                            int j = 0;
+                            while (j < nc && cn[j] != n) ++j;
+                            if (j == nc) { cn[nc] = n; cw[nc] = 0; ++nc; }
+                            cw[j] += nvx;
+                        }
+                    }
+                }
+                acc.clear();
+                for (int j = 0; j < nc; ++j) {
+                    const uint32_t n = cn[j];
+                    const uint64_t scale = cw[j] / store.total(n);  // voxels / reduced total
+                    const uint32_t k = store.len(n);
+                    const uint32_t *sg = store.seg(n);
+                    const uint64_t *ct = store.cnt(n);
+                    for (uint32_t q = 0; q < k; ++q) acc.emplace_back(sg[q], ct[q] * scale);
+                }
+                std::sort(acc.begin(), acc.end());
+                const uint64_t off = S.size();
+                uint64_t gg = 0;
+                for (size_t q = 0; q < acc.size();) {
+                    size_t r = q;
+                    uint64_t s = 0;
+                    while (r < acc.size() && acc[r].first == acc[q].first) s += acc[r++].second;
+                    S.push_back(acc[q].first);
+                    C.push_back(s);
+                    gg = gcd64(gg, s);
+                    q = r;
+                }
+                const uint32_t k = uint32_t(S.size() - off);
+                for (uint32_t q = 0; q < k; ++q) C[off + q] /= gg;
+                recs[i] = Rec{off, k, hash_mixture(S.data() + off, C.data() + off, k)};
+                part_of[i] = t;
+            }
+        });
+
+        // pass C1: parallel lookup of mixtures that already have a node
+        parallel_chunks(mixed.size(), nt, [&](uint64_t b, uint64_t e, unsigned) {
+            for (uint64_t i = b; i < e; ++i) {
+                const Rec &r = recs[i];
+                const unsigned t = part_of[i];
+                cur[mixed[i]] = store.find(bseg[t].data() + r.off, bcnt[t].data() + r.off, r.k, r.h);
+            }
+        });
+        // pass C2: create the missing ones in voxel order (deterministic IDs)
+        for (uint64_t i = 0; i < mixed.size(); ++i) {
+            if (cur[mixed[i]] != kMixed) continue;
+            const Rec &r = recs[i];
+            const unsigned t = part_of[i];
+            cur[mixed[i]] = store.get(bseg[t].data() + r.off, bcnt[t].data() + r.off, r.k);
+        }
+    }
+
+    // ---- topological levels (children are created before parents)
+    const uint32_t N = store.size();
+    std::vector<uint32_t> rank(N, 0);
+    uint32_t depth = 0;
+    for (uint32_t n = g->nseg; n < N; ++n) {
+        rank[n] = std::max(rank[store.a_[n]], rank[store.b_[n]]) + 1;
+        depth = std::max(depth, rank[n]);
+    }
+    if (o->max_depth && depth > o->max_depth) {
+        *err = "graph depth " + std::to_string(depth) + " exceeds max_depth " + std::to_string(o->max_depth);
+        return MG_EDEPTH;
+    }
+    uint32_t maxmix = 1;
+    for (uint32_t n = g->nseg; n < N; ++n) maxmix = std::max(maxmix, store.len(n));
+
+    // ---- step schedule
+    std::vector<uint32_t> step(N, 0);
+    if (o->defer && depth > 1) {
+        std::vector<uint32_t> last(N, depth);  // sinks may run as late as the last step
+        for (uint32_t n = g->nseg; n < N; ++n) {
+            last[store.a_[n]] = std::min(last[store.a_[n]], rank[n] - 1);
+            last[store.b_[n]] = std::min(last[store.b_[n]], rank[n] - 1);
+        }
+        // bucket[r][d]: not yet scheduled nodes of rank r whose window ends at d
+        std::vector<std::vector<uint32_t>> by_rank(depth + 1);
+        for (uint32_t n = g->nseg; n < N; ++n) by_rank[rank[n]].push_back(n);
+        std::vector<std::vector<uint32_t>> pool(depth + 1);  // indexed by window end
+        std::vector<size_t> head(depth + 1, 0);
+        const uint64_t target = (uint64_t(N - g->nseg) + depth - 1) / depth;
+        for (uint32_t s = 1; s <= depth; ++s) {
+            for (uint32_t n : by_rank[s]) pool[last[n]].push_back(n);
+            uint64_t taken = 0;
+            for (uint32_t d = s; d <= depth; ++d) {
+                auto &pl = pool[d];
+                while (head[d] < pl.size() && (d == s || taken < target)) {
+                    step[pl[head[d]++]] = s;
+                    ++taken;
+                }
+                if (taken >= target && d > s) break;
+            }
+        }
+    } else {
+        for (uint32_t n = g->nseg; n < N; ++n) step[n] = rank[n];
+    }
+
+    // ---- renumber by (step, creation order); sources keep 0 .. S-1
+    std::vector<uint32_t> cnt(depth + 2, 0);
+    for (uint32_t n = g->nseg; n < N; ++n) cnt[step[n]]++;
+    g->step_ptr.assign(depth + 2, 0);
+    g->step_ptr[0] = 0;
+    g->step_ptr[1] = g->nseg;
+    for (uint32_t s = 1; s <= depth; ++s) g->step_ptr[s + 1] = g->step_ptr[s] + cnt[s];
+    std::vector<uint32_t> pos(g->step_ptr.begin(), g->step_ptr.end());
+    std::vector<uint32_t> perm(N);
+    for (uint32_t n = 0; n < g->nseg; ++n) perm[n] = n;
+    for (uint32_t n = g->nseg; n < N; ++n) perm[n] = pos[step[n]]++;
+
+    g->n_nodes = N;
+    g->depth = depth;
+    g->max_mixture = maxmix;
+    g->child_a.assign(N, 0);
+    g->child_b.assign(N, 0);
+    g->alpha.assign(N, 0.f);
+    g->wnum.assign(N, 0);
+    g->wden.assign(N, 1);
+    g->rank.assign(N, 0);
+    g->step.assign(N, 0);
+    for (uint32_t n = 0; n < N; ++n) {
+        const uint32_t p = perm[n];
+        g->child_a[p] = perm[store.a_[n]];
+        g->child_b[p] = perm[store.b_[n]];
+        g->wnum[p] = store.wn_[n];
+        g->wden[p] = store.wd_[n];
+        g->alpha[p] = n < g->nseg ? 0.f : float(double(store.wn_[n]) / double(store.wd_[n]));
+        g->rank[p] = rank[n];
+        g->step[p] = step[n];
+    }
+    const uint64_t total = g->maps.size();
+    uint32_t *mp = g->maps.data();
+    const uint64_t first_internal = g->lev_off[1];
+    parallel_chunks(total - first_internal, nt, [&](uint64_t b, uint64_t e, unsigned) {
+        for (uint64_t i = b; i < e; ++i) mp[first_internal + i] = perm[mp[first_internal + i]];
+    });
+    return MG_OK;
+}
+
+int validate_graph(const Graph &g, std::string *err)
+{
+    const uint32_t N = g.n_nodes, S = g.nseg;
+    if (S == 0 || N < S || g.child_a.size() != N || g.child_b.size() != N || g.alpha.size() != N ||
+        g.wnum.size() != N || g.wden.size() != N || g.rank.size() != N || g.step.size() != N ||
+        g.step_ptr.size() != size_t(g.depth) + 2 || g.seg_ids.size() != S) {
+        *err = "graph arrays have inconsistent sizes";
+        return MG_EFORMAT;
+    }
+    if (g.step_ptr[0] != 0 || g.step_ptr[1] != S || g.step_ptr[g.depth + 1] != N) {
+        *err = "step_ptr does not delimit the nodes";
+        return MG_EFORMAT;
+    }
+    for (uint32_t s = 0; s <= g.depth; ++s)
+        if (g.step_ptr[s] > g.step_ptr[s + 1]) {
+            *err = "step_ptr is not monotone";
+            return MG_EFORMAT;
+        }
+    for (uint32_t s = 1; s < S; ++s)
+        if (g.seg_ids[s] <= g.seg_ids[s - 1]) {
+            *err = "segment IDs are not increasing";
+            return MG_EFORMAT;
+        }
+    uint32_t st = 1;
+    for (uint32_t n = S; n < N; ++n) {
+        while (n >= g.step_ptr[st + 1]) ++st;
+        const uint32_t a = g.child_a[n], b = g.child_b[n];
+        if (a >= n || b >= n || a == b) {
+            *err = "node " + std::to_string(n) + " has a predecessor that is not an earlier node";
+            return MG_EFORMAT;
+        }
+        if (g.step[n] != st || g.step[a] >= st || g.step[b] >= st) {
+            *err = "node " + std::to_string(n) + " runs before one of its predecessors";
+            return MG_EFORMAT;
+        }
+        if (g.rank[n] != std::max(g.rank[a], g.rank[b]) + 1 || g.rank[n] > st) {
+            *err = "node " + std::to_string(n) + " has an inconsistent topological level";
+            return MG_EFORMAT;
+        }
+        if (g.wnum[n] == 0 || 2 * g.wnum[n] > g.wden[n]) {
+            *err = "node " + std::to_string(n) + " has a weight outside (0, 1/2]";
+            return MG_EFORMAT;
+        }
+        if (g.alpha[n] != float(double(g.wnum[n]) / double(g.wden[n]))) {
+            *err = "node " + std::to_string(n) + " has an fp32 weight that does not match its ratio";
+            return MG_EFORMAT;
+        }
+    }
+    std::vector<uint32_t> ld;
+    level_dims(g.dims, &ld);
+    if (ld != g.lev_dims || g.n_levels != ld.size() / 3 || g.lev_off.size() != g.n_levels + 1 ||
+        g.maps.size() != g.lev_off[g.n_levels]) {
+        *err = "level dimensions do not match the volume";
+        return MG_EFORMAT;
+    }
+    for (uint64_t i = 0; i < g.lev_off[1]; ++i)
+        if (g.maps[i] >= S) {
+            *err = "a level-0 voxel does not hold a source";
+            return MG_EFORMAT;
+        }
+    for (uint64_t i = g.lev_off[1]; i < g.maps.size(); ++i)
+        if (g.maps[i] >= N) {
+            *err = "a mip voxel holds an out-of-range node";
+            return MG_EFORMAT;
+        }
+    return MG_OK;
+}
+
+}  // namespace mg

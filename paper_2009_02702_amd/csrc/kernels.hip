@@ -1,0 +1,1173 @@
+// HIP kernels for gfx950 (MI355X): box-histogram queries over the Mixture
+// Graph, the naive level-0 range scan, transfer-function propagation, and the
+// device side of upload / workspaces / timing.
+//
+// Box decomposition (Sec. "Fast Sub-Volume Queries" and the appendix
+// algorithm "Footprint assembly in 3D"). The footprint of a box is the set of
+// maximal aligned mipmap cubes inside it. Per axis and level l, the level-l
+// cells fully inside [x0, x1) are [a_l, b_l) with a_l = ceil(x0 / 2^l) and
+// b_l = floor(x1 / 2^l); the cells of that range not covered by a level-(l+1)
+// cell inside the box are the (at most two) 1D footprint steps of level l.
+// The tensor product of the 1D step lists, tessellated by cubes of the
+// smallest level, groups by level into a hollow shell: the outer block
+// [a_l, b_l)^3 minus the inner block [2 a_{l+1}, 2 b_{l+1})^3, i.e. at most
+// six slabs one cell thick. The kernels enumerate those <= 6 slabs per level
+// instead of the up to (2 log2 D)^3 rectangles; the cube set is the same.
+// Slabs that are one cell thick along x are read from a transposed copy of
+// the level's node map (y fastest) so that every slab streams contiguous rows.
+//
+// Each cube contributes its 8^l voxels to the node its mip voxel holds
+// ("denormalized" samples). Cubes whose node is a source add straight to the
+// segment's integer count; other nodes collect integer counts in a per-query
+// hash table, then their mass is pushed down the DAG step by step in reverse
+// order (node n = (1 - w_n) a_n + w_n b_n gives a the share 1 - w_n and b the
+// share w_n). Mass is fp32 with a two-sum compensation term per entry; the
+// final per-segment count is summed in fp64 and divided by the box volume.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "mg_internal.hpp"
+
+namespace mg {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr uint32_t kMaxLevelsDev = 16;          // dims up to 32768 per axis
+constexpr int kMaxSlabs = 6 * kMaxLevelsDev;
+constexpr uint32_t kHashLds = 2048;           // per-query hash slots in LDS
+constexpr uint32_t kHashGlobal = 1u << 18;    // per-worker hash slots in the fallback tables
+constexpr uint32_t kSegLdsMax = 2048;         // sources kept in LDS
+constexpr uint32_t kFallbackWorkers = 64;     // workers of the global-table kernel
+constexpr int kUnroll = 4;
+constexpr uint32_t kMaxSteps = 64;              // graph depth the step table holds
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            *err = std::string(#expr) + ": " + hipGetErrorString(e_);                  \
+            return MG_EDEVICE;                                                         \
+        }                                                                              \
+    } while (0)
+
+// ---------------------------------------------------------------- constants
+
+struct LevelTable {
+    uint32_t n_levels;
+    uint32_t vol[3];
+    uint32_t dims[MG_MAX_LEVELS][3];
+    uint64_t off[MG_MAX_LEVELS];     // element offset of each level in maps
+    uint64_t total;                  // elements of one full copy (maps_t starts here)
+};
+
+// Unsigned division by a runtime-invariant divisor (Granlund and Montgomery,
+// "Division by Invariant Integers using Multiplication", PLDI 1994): with
+// s = ceil(log2 d) and m = floor(2^32 (2^s - d) / d) + 1, n / d equals
+// (umulhi(n, m) + n) >> s for every 32-bit n.
+struct FastDiv {
+    uint32_t d, m, s;
+};
+
+__host__ __device__ inline FastDiv make_fastdiv(uint32_t d)
+{
+    FastDiv f;
+    f.d = d;
+    uint32_t s = 0;
+    while ((uint64_t(1) << s) < d) ++s;
+    f.s = s;
+    f.m = uint32_t(((uint64_t(1) << 32) * ((uint64_t(1) << s) - d)) / d + 1);
+    return f;
+}
+
+__device__ inline uint32_t fdiv(uint32_t n, const FastDiv &f)
+{
+    const uint64_t t = uint64_t(__umulhi(n, f.m)) + n;
+    return uint32_t(t >> f.s);
+}
+
+struct Slab {
+    uint32_t count;      // cubes
+    uint32_t level;
+    uint32_t transposed; // 1: read from maps_t (y fastest)
+    uint32_t bx, by, bz; // first cube, level coordinates
+    FastDiv e0, e1;      // extents of the fastest and middle iteration axes
+    uint32_t s1;         // element stride of the middle axis
+    uint32_t pad;
+    uint64_t s2;         // element stride of the slowest axis
+    uint64_t base;       // element index of the first cube in the combined map buffer
+};
+
+// Element index and level coordinates of cube r of a slab.
+__device__ inline uint64_t slab_addr(const Slab &sl, uint32_t r)
+{
+    const uint32_t q = fdiv(r, sl.e0);
+    const uint32_t i0 = r - q * sl.e0.d;
+    const uint32_t i2 = fdiv(q, sl.e1);
+    const uint32_t i1 = q - i2 * sl.e1.d;
+    return sl.base + i0 + uint64_t(i1) * sl.s1 + uint64_t(i2) * sl.s2;
+}
+
+__device__ inline void slab_coords(const Slab &sl, uint32_t r, uint32_t *x, uint32_t *y, uint32_t *z)
+{
+    const uint32_t q = fdiv(r, sl.e0);
+    const uint32_t i0 = r - q * sl.e0.d;
+    const uint32_t i2 = fdiv(q, sl.e1);
+    const uint32_t i1 = q - i2 * sl.e1.d;
+    if (sl.transposed) {
+        *x = sl.bx + i2, *y = sl.by + i0, *z = sl.bz + i1;
+    } else {
+        *x = sl.bx + i0, *y = sl.by + i1, *z = sl.bz + i2;
+    }
+}
+
+// Clipped box: half-open ranges; returns false for an empty box.
+__device__ inline bool clip_box(const uint32_t *b, const LevelTable &lt, uint32_t lo[3], uint32_t hi[3])
+{
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {
+        const uint64_t l = b[a], h = uint64_t(b[a]) + b[3 + a];
+        lo[a] = uint32_t(l < lt.vol[a] ? l : lt.vol[a]);
+        hi[a] = uint32_t(h < lt.vol[a] ? h : lt.vol[a]);
+        ok = ok && lo[a] < hi[a];
+    }
+    return ok;
+}
+
+template <bool WRITE>
+__device__ inline void put_slab(Slab *out, int *n, const LevelTable &lt, uint32_t lev, uint32_t x0, uint32_t x1,
+                                uint32_t y0, uint32_t y1, uint32_t z0, uint32_t z1)
+{
+    if (x1 <= x0 || y1 <= y0 || z1 <= z0) return;
+    if (!WRITE) {
+        ++*n;
+        return;
+    }
+    const uint32_t ex = x1 - x0, ey = y1 - y0, ez = z1 - z0;
+    const uint32_t X = lt.dims[lev][0], Y = lt.dims[lev][1], Z = lt.dims[lev][2];
+    Slab s;
+    s.count = ex * ey * ez;
+    s.level = lev;
+    s.bx = x0, s.by = y0, s.bz = z0;
+    s.pad = 0;
+    if (ex < ey) {
+        // rows along y in the transposed copy: index y + Y (z + Z x)
+        s.transposed = 1;
+        s.e0 = make_fastdiv(ey);
+        s.e1 = make_fastdiv(ez);
+        s.s1 = Y;
+        s.s2 = uint64_t(Y) * Z;
+        s.base = lt.total + lt.off[lev] + y0 + uint64_t(Y) * (z0 + uint64_t(Z) * x0);
+    } else {
+        s.transposed = 0;
+        s.e0 = make_fastdiv(ex);
+        s.e1 = make_fastdiv(ey);
+        s.s1 = X;
+        s.s2 = uint64_t(X) * Y;
+        s.base = lt.off[lev] + x0 + uint64_t(X) * (y0 + uint64_t(Y) * z0);
+    }
+    out[(*n)++] = s;
+}
+
+// Slabs of level `lev` of the box's footprint (at most 6), written to out[0..]
+// when WRITE. Returns their count.
+template <bool WRITE>
+__device__ inline int level_slabs(const LevelTable &lt, const uint32_t lo[3], const uint32_t hi[3], uint32_t lev,
+                                  Slab *out)
+{
+    uint32_t a[3], b[3], ia[3], ib[3];
+    bool outer = true, inner = true;
+    for (int d = 0; d < 3; ++d) {
+        const uint64_t one = uint64_t(1) << lev;
+        a[d] = uint32_t((uint64_t(lo[d]) + one - 1) >> lev);
+        b[d] = hi[d] >> lev;
+        outer = outer && a[d] < b[d];
+        const uint32_t pa = uint32_t((uint64_t(lo[d]) + 2 * one - 1) >> (lev + 1));
+        const uint32_t pb = hi[d] >> (lev + 1);
+        inner = inner && pa < pb;
+        ia[d] = 2 * pa;
+        ib[d] = 2 * pb;
+    }
+    int n = 0;
+    if (!outer) return 0;
+    if (!inner) {
+        put_slab<WRITE>(out, &n, lt, lev, a[0], b[0], a[1], b[1], a[2], b[2]);
+        return n;
+    }
+    put_slab<WRITE>(out, &n, lt, lev, a[0], ia[0], a[1], b[1], a[2], b[2]);       // x low face
+    put_slab<WRITE>(out, &n, lt, lev, ib[0], b[0], a[1], b[1], a[2], b[2]);       // x high face
+    put_slab<WRITE>(out, &n, lt, lev, ia[0], ib[0], a[1], ia[1], a[2], b[2]);     // y low face
+    put_slab<WRITE>(out, &n, lt, lev, ia[0], ib[0], ib[1], b[1], a[2], b[2]);     // y high face
+    put_slab<WRITE>(out, &n, lt, lev, ia[0], ib[0], ia[1], ib[1], a[2], ia[2]);   // z low face
+    put_slab<WRITE>(out, &n, lt, lev, ia[0], ib[0], ia[1], ib[1], ib[2], b[2]);   // z high face
+    return n;
+}
+
+// Wave 0 fills the slab table of one box in LDS; returns via LDS the slab
+// count. Lane l handles level l. Must be called by all threads of the block
+// (contains no barrier itself).
+__device__ inline void build_slabs(const LevelTable &lt, const uint32_t lo[3], const uint32_t hi[3], Slab *slabs,
+                                   int *n_slabs)
+{
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x < 64) {
+        const int k = lane < int(lt.n_levels) ? level_slabs<false>(lt, lo, hi, uint32_t(lane), nullptr) : 0;
+        // exclusive prefix over lanes of k
+        int incl = k;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += v;
+        }
+        if (k) level_slabs<true>(lt, lo, hi, uint32_t(lane), slabs + (incl - k));
+        if (lane == 63) *n_slabs = incl;
+    }
+}
+
+// ---------------------------------------------------------------- per-query state
+
+// Table of internal nodes touched by one query, plus per-source accumulators.
+// Pointers are into LDS or into a global per-worker region; the same code
+// serves both (the compiler resolves the address space after inlining).
+struct QueryState {
+    uint32_t *keys;     // [cap] node ID or kEmpty
+    uint32_t *cnt;      // [cap] integer voxel count scattered from cubes
+    float *hi, *lo;     // [cap] pushed mass and its compensation
+    uint32_t *used;     // [cap] slots in insertion order
+    uint32_t *n_used;   // scalar
+    uint32_t *flags;    // scalar: bit 0 = overflow
+    uint32_t cap;       // power of two
+    uint32_t limit;     // load-factor cap on n_used
+    uint32_t *seg_cnt;  // [S] exact integer counts
+    float *seg_hi, *seg_lo;  // [S] pushed mass and its compensation
+};
+
+// Loads of per-query state written by other threads of the block: relaxed
+// agent-scope atomics, so that the global-memory variant reads L2 rather than
+// a possibly stale L1 line (in LDS these are plain ds_read).
+template <class T>
+__device__ inline T ld(const T *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline uint32_t hash_node(uint32_t k)
+{
+    k ^= k >> 16;
+    k *= 0x7feb352dU;
+    k ^= k >> 15;
+    k *= 0x846ca68bU;
+    k ^= k >> 16;
+    return k;
+}
+
+// Slot of node `key`, inserting it if absent. Returns kEmpty on overflow.
+__device__ inline uint32_t table_slot(const QueryState &st, uint32_t key)
+{
+    const uint32_t mask = st.cap - 1;
+    uint32_t slot = hash_node(key) & mask;
+    for (uint32_t probe = 0; probe < st.cap; ++probe) {
+        uint32_t k = ld(&st.keys[slot]);
+        if (k == key) return slot;
+        if (k == kEmpty) {
+            const uint32_t old = atomicCAS(&st.keys[slot], kEmpty, key);
+            if (old == kEmpty) {
+                const uint32_t idx = atomicAdd(st.n_used, 1u);
+                st.used[idx] = slot;
+                if (idx >= st.limit) atomicOr(st.flags, 1u);
+                return slot;
+            }
+            if (old == key) return slot;
+        }
+        slot = (slot + 1) & mask;
+    }
+    atomicOr(st.flags, 1u);
+    return kEmpty;
+}
+
+__device__ inline void add_count(const QueryState &st, uint32_t nseg, uint32_t node, uint32_t c)
+{
+    if (node < nseg) {
+        atomicAdd(&st.seg_cnt[node], c);
+    } else {
+        const uint32_t slot = table_slot(st, node);
+        if (slot != kEmpty) atomicAdd(&st.cnt[slot], c);
+    }
+}
+
+// Compensated accumulation: the atomic returns the value it added to, so the
+// exact rounding error of that addition is recovered with two-sum and
+// accumulated, with the incoming compensation, in the second word.
+__device__ inline void add_mass_at(float *hi, float *lo, float h, float l)
+{
+    const float old = atomicAdd(hi, h);
+    const float s = old + h;
+    const float bp = s - old;
+    const float e = (old - (s - bp)) + (h - bp);
+    atomicAdd(lo, e + l);
+}
+
+__device__ inline void add_mass(const QueryState &st, uint32_t nseg, uint32_t node, float h, float l)
+{
+    if (node < nseg) {
+        add_mass_at(&st.seg_hi[node], &st.seg_lo[node], h, l);
+    } else {
+        const uint32_t slot = table_slot(st, node);
+        if (slot != kEmpty) add_mass_at(&st.hi[slot], &st.lo[slot], h, l);
+    }
+}
+
+// Scatter: every cube of every slab adds 8^level to its node. Lanes holding
+// the same node are merged first (one ballot per distinct node in the wave;
+// all cubes of a slab share the level, so the sum is popcount * 8^level).
+__device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint32_t *__restrict__ maps,
+                                     const QueryState &st, uint32_t nseg)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    for (int si = 0; si < n_slabs; ++si) {
+        const Slab sl = slabs[si];
+        const uint32_t w8 = 1u << (3 * sl.level);
+        for (uint32_t b0 = threadIdx.x & ~63u; b0 < sl.count; b0 += kUnroll * kBlock) {
+            uint32_t node[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t r = b0 + lane + u * kBlock;
+                node[u] = r < sl.count ? maps[slab_addr(sl, r)] : kEmpty;
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                uint64_t pending = __ballot(node[u] != kEmpty);
+                while (pending) {
+                    const int leader = __ffsll((unsigned long long)pending) - 1;
+                    const uint32_t key = __shfl(node[u], leader, 64);
+                    const uint64_t match = __ballot(node[u] == key) & pending;
+                    if (int(lane) == leader) add_count(st, nseg, key, uint32_t(__popcll(match)) * w8);
+                    pending &= ~match;
+                }
+            }
+        }
+    }
+}
+
+// Convert integer counts to (hi, lo) mass and push down the DAG, step by step
+// from the highest step present. All threads of the block must call.
+__device__ inline void push_mass(const QueryState &st, uint32_t nseg, const NodeTriple *__restrict__ nodes,
+                                 const uint32_t *step_ptr_lds, uint32_t depth, uint32_t *max_step_lds)
+{
+    const uint32_t nu = *st.n_used;
+    if (nu == 0) return;  // uniform
+    uint32_t my_max = 0;
+    for (uint32_t i = threadIdx.x; i < nu; i += kBlock) {
+        const uint32_t slot = ld(&st.used[i]);
+        const uint32_t c = ld(&st.cnt[slot]);
+        st.hi[slot] = float(c & 0xFFFFFF00u);  // both parts exact in fp32
+        st.lo[slot] = float(c & 0xFFu);
+        const uint32_t key = ld(&st.keys[slot]);
+        uint32_t s = 1;
+        while (s < depth && key >= step_ptr_lds[s + 1]) ++s;
+        my_max = max(my_max, s);
+    }
+    atomicMax(max_step_lds, my_max);
+    __syncthreads();
+    const uint32_t top = *max_step_lds;
+    for (uint32_t s = top; s >= 1; --s) {
+        const uint32_t lo_id = step_ptr_lds[s], hi_id = step_ptr_lds[s + 1];
+        const uint32_t n_now = ld(st.n_used);
+        __syncthreads();  // every thread has read n_now before any insert of this step
+        for (uint32_t i = threadIdx.x; i < n_now; i += kBlock) {
+            const uint32_t slot = ld(&st.used[i]);
+            const uint32_t key = ld(&st.keys[slot]);
+            if (key < lo_id || key >= hi_id) continue;
+            const float mh = ld(&st.hi[slot]), ml = ld(&st.lo[slot]);
+            const NodeTriple t = nodes[key];
+            const float wb = t.w, wa = 1.0f - t.w;
+            const float ah = wa * mh, al = fmaf(wa, mh, -ah) + wa * ml;
+            const float bh = wb * mh, bl = fmaf(wb, mh, -bh) + wb * ml;
+            add_mass(st, nseg, t.a, ah, al);
+            add_mass(st, nseg, t.b, bh, bl);
+        }
+        __syncthreads();
+        if (s == 1) break;
+    }
+}
+
+struct QueryArgs {
+    LevelTable lt;
+    const uint32_t *boxes;
+    float *out;
+    const uint32_t *maps;         // maps then maps_t
+    const NodeTriple *nodes;
+    const uint32_t *step_ptr;     // [depth + 2]
+    uint32_t nseg;
+    uint32_t depth;
+    uint32_t n;
+    const uint32_t *order;        // query order (batched) or nullptr (identity)
+    uint32_t *counters;           // [0] next query, [1] overflow count, [2] next fallback query
+    uint32_t *overflow;           // overflowed query indices
+    uint32_t *stats;              // optional [n][2]: cubes, table entries (graph nodes) touched
+    // fallback global regions (per worker)
+    uint32_t *g_keys, *g_cnt, *g_used;
+    float *g_hi, *g_lo;
+    uint32_t *g_seg_cnt;
+    float *g_seg_hi, *g_seg_lo;
+};
+
+// LDS layout of the query kernels (dynamic shared memory).
+struct LdsLayout {
+    uint32_t seg_bytes, table_bytes, total;
+    __host__ __device__ static LdsLayout make(uint32_t nseg, bool seg_global, bool table_global)
+    {
+        LdsLayout L;
+        L.seg_bytes = seg_global ? 0 : nseg * 12u;
+        L.table_bytes = table_global ? 0 : kHashLds * 20u;
+        L.total = L.seg_bytes + L.table_bytes;
+        return L;
+    }
+};
+
+struct QueryShared {
+    Slab slabs[kMaxSlabs];
+    uint32_t step_ptr[kMaxSteps + 2];
+    int n_slabs;
+    uint32_t n_used;
+    uint32_t flags;
+    uint32_t max_step;
+    uint32_t q;
+};
+
+// One query, by the whole block. `st` must be clean (keys empty, values 0).
+__device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const QueryState &st, uint32_t q,
+                                 bool report_overflow)
+{
+    uint32_t lo[3], hi[3];
+    const bool nonempty = clip_box(A.boxes + 6 * uint64_t(q), A.lt, lo, hi);
+    if (threadIdx.x == 0) {
+        sh.n_used = 0;
+        sh.flags = 0;
+        sh.max_step = 1;
+        sh.n_slabs = 0;
+    }
+    __syncthreads();
+    if (nonempty) build_slabs(A.lt, lo, hi, sh.slabs, &sh.n_slabs);
+    __syncthreads();
+    scatter_slabs(sh.slabs, sh.n_slabs, A.maps, st, A.nseg);
+    __syncthreads();
+    if (A.depth > 0) push_mass(st, A.nseg, A.nodes, sh.step_ptr, A.depth, &sh.max_step);
+    __syncthreads();
+    const bool overflow = (sh.flags & 1u) != 0;
+    if (A.stats && threadIdx.x == 0 && (!overflow || !report_overflow)) {
+        uint32_t cubes = 0;
+        for (int i = 0; i < sh.n_slabs; ++i) cubes += sh.slabs[i].count;
+        A.stats[2 * uint64_t(q)] = cubes;
+        A.stats[2 * uint64_t(q) + 1] = sh.n_used;
+    }
+    if (!overflow) {
+        const double vol = nonempty ? double(hi[0] - lo[0]) * double(hi[1] - lo[1]) * double(hi[2] - lo[2]) : 0.0;
+        float *o = A.out + uint64_t(q) * A.nseg;
+        for (uint32_t s = threadIdx.x; s < A.nseg; s += kBlock) {
+            const double c = double(ld(&st.seg_cnt[s])) + double(ld(&st.seg_hi[s])) + double(ld(&st.seg_lo[s]));
+            o[s] = nonempty ? float(c / vol) : 0.0f;
+        }
+    } else if (report_overflow) {
+        if (threadIdx.x == 0) {
+            const uint32_t k = atomicAdd(&A.counters[1], 1u);
+            A.overflow[k] = q;
+        }
+    } else {
+        // even the per-worker global table overflowed: make the failure visible
+        float *o = A.out + uint64_t(q) * A.nseg;
+        for (uint32_t s = threadIdx.x; s < A.nseg; s += kBlock) o[s] = __builtin_nanf("");
+    }
+    // restore a clean state for the next query
+    const uint32_t nu = min(sh.n_used, st.cap);
+    for (uint32_t i = threadIdx.x; i < nu; i += kBlock) {
+        const uint32_t slot = ld(&st.used[i]);
+        st.keys[slot] = kEmpty;
+        st.cnt[slot] = 0;
+        st.hi[slot] = 0.f;
+        st.lo[slot] = 0.f;
+    }
+    for (uint32_t s = threadIdx.x; s < A.nseg; s += kBlock) {
+        st.seg_cnt[s] = 0;
+        st.seg_hi[s] = 0.f;
+        st.seg_lo[s] = 0.f;
+    }
+    __syncthreads();
+}
+
+__device__ inline void load_step_ptr(const QueryArgs &A, QueryShared &sh)
+{
+    for (uint32_t i = threadIdx.x; i < A.depth + 2; i += kBlock) sh.step_ptr[i] = A.step_ptr[i];
+}
+
+__device__ inline QueryState lds_state(char *dyn, QueryShared &sh, uint32_t nseg)
+{
+    QueryState st;
+    const LdsLayout L = LdsLayout::make(nseg, false, false);
+    uint32_t *seg = reinterpret_cast<uint32_t *>(dyn);
+    st.seg_cnt = seg;
+    st.seg_hi = reinterpret_cast<float *>(seg + nseg);
+    st.seg_lo = reinterpret_cast<float *>(seg + 2 * nseg);
+    uint32_t *t = reinterpret_cast<uint32_t *>(dyn + L.seg_bytes);
+    st.keys = t;
+    st.cnt = t + kHashLds;
+    st.hi = reinterpret_cast<float *>(t + 2 * kHashLds);
+    st.lo = reinterpret_cast<float *>(t + 3 * kHashLds);
+    st.used = t + 4 * kHashLds;
+    st.cap = kHashLds;
+    st.limit = kHashLds / 2;
+    st.n_used = &sh.n_used;
+    st.flags = &sh.flags;
+    return st;
+}
+
+__device__ inline void clear_lds_state(const QueryState &st, uint32_t nseg)
+{
+    for (uint32_t i = threadIdx.x; i < st.cap; i += kBlock) {
+        st.keys[i] = kEmpty;
+        st.cnt[i] = 0;
+        st.hi[i] = 0.f;
+        st.lo[i] = 0.f;
+    }
+    for (uint32_t s = threadIdx.x; s < nseg; s += kBlock) {
+        st.seg_cnt[s] = 0;
+        st.seg_hi[s] = 0.f;
+        st.seg_lo[s] = 0.f;
+    }
+}
+
+// Plain: one block per query in input order, state in LDS.
+__global__ __launch_bounds__(kBlock) void query_plain_kernel(QueryArgs A)
+{
+    extern __shared__ __align__(16) char dyn[];
+    __shared__ QueryShared sh;
+    const QueryState st = lds_state(dyn, sh, A.nseg);
+    load_step_ptr(A, sh);
+    clear_lds_state(st, A.nseg);
+    __syncthreads();
+    run_query(A, sh, st, blockIdx.x, true);
+}
+
+// Batched: persistent blocks take queries in the given order from a counter.
+__global__ __launch_bounds__(kBlock) void query_batched_kernel(QueryArgs A)
+{
+    extern __shared__ __align__(16) char dyn[];
+    __shared__ QueryShared sh;
+    const QueryState st = lds_state(dyn, sh, A.nseg);
+    load_step_ptr(A, sh);
+    clear_lds_state(st, A.nseg);
+    for (;;) {
+        if (threadIdx.x == 0) sh.q = atomicAdd(&A.counters[0], 1u);
+        __syncthreads();
+        const uint32_t k = sh.q;
+        if (k >= A.n) break;  // uniform
+        run_query(A, sh, st, A.order ? A.order[k] : k, true);
+    }
+}
+
+// Fallback for overflowed queries: per-worker tables and source arrays in the
+// workspace (global memory), drained from the overflow list.
+__global__ __launch_bounds__(kBlock) void query_fallback_kernel(QueryArgs A)
+{
+    __shared__ QueryShared sh;
+    QueryState st;
+    const uint64_t w = blockIdx.x;
+    st.keys = A.g_keys + w * kHashGlobal;
+    st.cnt = A.g_cnt + w * kHashGlobal;
+    st.hi = A.g_hi + w * kHashGlobal;
+    st.lo = A.g_lo + w * kHashGlobal;
+    st.used = A.g_used + w * kHashGlobal;
+    st.cap = kHashGlobal;
+    st.limit = kHashGlobal;
+    st.n_used = &sh.n_used;
+    st.flags = &sh.flags;
+    st.seg_cnt = A.g_seg_cnt + w * A.nseg;
+    st.seg_hi = A.g_seg_hi + w * A.nseg;
+    st.seg_lo = A.g_seg_lo + w * A.nseg;
+    load_step_ptr(A, sh);
+    __syncthreads();
+    const uint32_t n_over = ld(&A.counters[1]);
+    for (;;) {
+        if (threadIdx.x == 0) sh.q = atomicAdd(&A.counters[2], 1u);
+        __syncthreads();
+        const uint32_t k = sh.q;
+        if (k >= n_over) break;
+        run_query(A, sh, st, A.overflow[k], false);
+    }
+}
+
+// Per-query work estimate (cubes) and log2 bucket for the largest-first order.
+__global__ void query_size_kernel(LevelTable lt, const uint32_t *boxes, uint32_t n, uint32_t *bucket_of,
+                                  uint32_t *bucket_count)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    uint32_t lo[3], hi[3];
+    uint64_t cubes = 0;
+    if (clip_box(boxes + 6 * uint64_t(q), lt, lo, hi)) {
+        for (uint32_t l = 0; l < lt.n_levels; ++l) {
+            uint64_t outer = 1, inner = 1;
+            for (int d = 0; d < 3; ++d) {
+                const uint64_t one = uint64_t(1) << l;
+                const uint64_t a = (uint64_t(lo[d]) + one - 1) >> l, b = hi[d] >> l;
+                const uint64_t pa = (uint64_t(lo[d]) + 2 * one - 1) >> (l + 1), pb = hi[d] >> (l + 1);
+                outer *= b > a ? b - a : 0;
+                inner *= pb > pa ? 2 * (pb - pa) : 0;
+            }
+            cubes += outer - inner;
+        }
+    }
+    // 32 buckets, largest work first: bucket 0 holds >= 2^31 cubes
+    const uint32_t lg = cubes ? 63 - __clzll(cubes) : 0;
+    const uint32_t bkt = 31 - min(lg, 31u);
+    bucket_of[q] = bkt;
+    atomicAdd(&bucket_count[bkt], 1u);
+}
+
+__global__ void query_order_kernel(const uint32_t *bucket_of, uint32_t n, uint32_t *bucket_count, uint32_t *order)
+{
+    // bucket_count holds, on entry, exclusive offsets prepared by the scan below
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const uint32_t pos = atomicAdd(&bucket_count[32 + bucket_of[q]], 1u);
+    order[pos] = q;
+}
+
+__global__ void bucket_scan_kernel(uint32_t *bucket_count)
+{
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int b = 0; b < 32; ++b) {
+            bucket_count[32 + b] = acc;
+            acc += bucket_count[b];
+        }
+    }
+}
+
+__global__ void reset_counters_kernel(uint32_t *c, uint32_t n)
+{
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0;
+}
+
+// ---------------------------------------------------------------- naive scan
+
+struct NaiveArgs {
+    LevelTable lt;
+    const uint32_t *boxes;
+    float *out;
+    const uint32_t *map0;
+    uint32_t nseg;
+    uint32_t n;
+};
+
+// Naive range query: every level-0 voxel of the box is read and counted.
+__global__ __launch_bounds__(kBlock) void naive_kernel(NaiveArgs A)
+{
+    extern __shared__ __align__(16) char dyn[];
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(dyn);
+    const uint32_t q = blockIdx.x;
+    for (uint32_t s = threadIdx.x; s < A.nseg; s += kBlock) cnt[s] = 0;
+    uint32_t lo[3], hi[3];
+    const bool nonempty = clip_box(A.boxes + 6 * uint64_t(q), A.lt, lo, hi);
+    __syncthreads();
+    if (nonempty) {
+        const uint32_t ex = hi[0] - lo[0], ey = hi[1] - lo[1], ez = hi[2] - lo[2];
+        const FastDiv fx = make_fastdiv(ex), fy = make_fastdiv(ey);
+        const uint64_t X = A.lt.vol[0], XY = uint64_t(A.lt.vol[0]) * A.lt.vol[1];
+        const uint64_t base = lo[0] + X * lo[1] + XY * lo[2];
+        const uint64_t total = uint64_t(ex) * ey * ez;
+        const uint32_t lane = threadIdx.x & 63;
+        // the box is one flat range of voxels (fewer than 2^32: the volume is)
+        for (uint64_t b0 = threadIdx.x & ~63u; b0 < total; b0 += kUnroll * kBlock) {
+            uint32_t v[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint64_t r = b0 + lane + u * kBlock;
+                if (r < total) {
+                    const uint32_t rr = uint32_t(r);
+                    const uint32_t qy = fdiv(rr, fx);
+                    const uint32_t ix = rr - qy * ex;
+                    const uint32_t iz = fdiv(qy, fy);
+                    const uint32_t iy = qy - iz * ey;
+                    v[u] = A.map0[base + ix + X * iy + XY * iz];
+                } else {
+                    v[u] = kEmpty;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                uint64_t pending = __ballot(v[u] != kEmpty);
+                while (pending) {
+                    const int leader = __ffsll((unsigned long long)pending) - 1;
+                    const uint32_t key = __shfl(v[u], leader, 64);
+                    const uint64_t match = __ballot(v[u] == key) & pending;
+                    if (int(lane) == leader) atomicAdd(&cnt[key], uint32_t(__popcll(match)));
+                    pending &= ~match;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const double vol = nonempty ? double(hi[0] - lo[0]) * double(hi[1] - lo[1]) * double(hi[2] - lo[2]) : 0.0;
+    float *o = A.out + uint64_t(q) * A.nseg;
+    for (uint32_t s = threadIdx.x; s < A.nseg; s += kBlock) o[s] = nonempty ? float(double(cnt[s]) / vol) : 0.0f;
+}
+
+// ---------------------------------------------------------------- footprint (test view)
+
+__global__ __launch_bounds__(kBlock) void footprint_kernel(LevelTable lt, const uint32_t *boxes, uint32_t n,
+                                                           const uint32_t *maps, uint32_t *level_counts,
+                                                           uint32_t *cubes, uint32_t cap, uint32_t *count)
+{
+    __shared__ Slab slabs[kMaxSlabs];
+    __shared__ int n_slabs;
+    __shared__ uint32_t per_level[MG_MAX_LEVELS];
+    const uint32_t q = blockIdx.x;
+    if (threadIdx.x == 0) n_slabs = 0;
+    if (threadIdx.x < MG_MAX_LEVELS) per_level[threadIdx.x] = 0;
+    uint32_t lo[3], hi[3];
+    const bool nonempty = clip_box(boxes + 6 * uint64_t(q), lt, lo, hi);
+    __syncthreads();
+    if (nonempty) build_slabs(lt, lo, hi, slabs, &n_slabs);
+    __syncthreads();
+    for (int si = 0; si < n_slabs; ++si) {
+        const Slab sl = slabs[si];
+        if (threadIdx.x == 0) atomicAdd(&per_level[sl.level], sl.count);
+        if (!cubes) continue;
+        for (uint32_t r = threadIdx.x; r < sl.count; r += kBlock) {
+            uint32_t x, y, z;
+            slab_coords(sl, r, &x, &y, &z);
+            const uint32_t node = maps[slab_addr(sl, r)];
+            const uint32_t k = atomicAdd(count, 1u);
+            if (k < cap) {
+                uint32_t *c = cubes + 6 * uint64_t(k);
+                c[0] = q, c[1] = sl.level, c[2] = x, c[3] = y, c[4] = z, c[5] = node;
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t l = threadIdx.x; l < lt.n_levels; l += kBlock) level_counts[uint64_t(q) * lt.n_levels + l] = per_level[l];
+}
+
+// ---------------------------------------------------------------- TF propagation
+
+__global__ void tf_sources_kernel(const uint8_t *tf, uint32_t T, uint32_t nseg, uint32_t n_nodes, float4 *out)
+{
+    const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= uint64_t(T) * nseg) return;
+    const uint32_t t = uint32_t(i / nseg), s = uint32_t(i % nseg);
+    const uchar4 c = reinterpret_cast<const uchar4 *>(tf)[i];
+    const float k = 1.0f / 255.0f;
+    out[uint64_t(t) * n_nodes + s] = make_float4(float(c.x) * k, float(c.y) * k, float(c.z) * k, float(c.w) * k);
+}
+
+__global__ void tf_step_kernel(const NodeTriple *__restrict__ nodes, uint32_t lo_id, uint32_t hi_id, uint32_t T,
+                               uint32_t n_nodes, float4 *out)
+{
+    const uint32_t n = lo_id + blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= hi_id) return;
+    const NodeTriple t = nodes[n];
+    for (uint32_t k = 0; k < T; ++k) {
+        float4 *o = out + uint64_t(k) * n_nodes;
+        const float4 va = o[t.a], vb = o[t.b];
+        float4 r;
+        r.x = fmaf(t.w, vb.x - va.x, va.x);
+        r.y = fmaf(t.w, vb.y - va.y, va.y);
+        r.z = fmaf(t.w, vb.z - va.z, va.z);
+        r.w = fmaf(t.w, vb.w - va.w, va.w);
+        o[n] = r;
+    }
+}
+
+// ---------------------------------------------------------------- upload helpers
+
+__global__ void transpose_level_kernel(const uint32_t *src, uint32_t *dst, uint32_t X, uint32_t Y, uint32_t Z)
+{
+    // dst[y + Y (z + Z x)] = src[x + X (y + Y z)]
+    const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint64_t total = uint64_t(X) * Y * Z;
+    if (i >= total) return;
+    const uint32_t x = uint32_t(i % X);
+    const uint64_t yz = i / X;
+    const uint32_t y = uint32_t(yz % Y), z = uint32_t(yz / Y);
+    dst[y + uint64_t(Y) * (z + uint64_t(Z) * x)] = src[i];
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint64_t n, uint32_t v)
+{
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+LevelTable level_table(const Graph &g)
+{
+    LevelTable lt;
+    std::memset(&lt, 0, sizeof(lt));
+    lt.n_levels = g.n_levels;
+    for (int a = 0; a < 3; ++a) lt.vol[a] = g.dims[a];
+    for (uint32_t l = 0; l < g.n_levels; ++l) {
+        for (int a = 0; a < 3; ++a) lt.dims[l][a] = g.lev_dims[3 * l + a];
+        lt.off[l] = g.lev_off[l];
+    }
+    lt.total = g.lev_off[g.n_levels];
+    return lt;
+}
+
+// ---------------------------------------------------------------- workspace layout
+
+struct Workspace {
+    uint32_t *counters;   // 64 u32: [0] next, [1] overflow count, [2] next fallback
+    uint32_t *buckets;    // 64 u32
+    uint32_t *bucket_of;  // [max_boxes]
+    uint32_t *order;      // [max_boxes]
+    uint32_t *overflow;   // [max_boxes]
+    uint32_t *g_keys, *g_cnt, *g_used;
+    float *g_hi, *g_lo;
+    uint32_t *g_seg_cnt;
+    float *g_seg_hi, *g_seg_lo;
+    uint64_t bytes;
+    uint32_t max_boxes;
+};
+
+inline uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
+
+// Carves the workspace; with base == nullptr only computes the size.
+Workspace carve(const Graph &g, char *base, uint32_t max_boxes)
+{
+    Workspace w;
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        char *p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    // fixed-size part first, so that its layout does not depend on max_boxes
+    w.counters = reinterpret_cast<uint32_t *>(take(64 * 4));
+    w.buckets = reinterpret_cast<uint32_t *>(take(64 * 4));
+    const uint64_t hs = uint64_t(kFallbackWorkers) * kHashGlobal;
+    w.g_keys = reinterpret_cast<uint32_t *>(take(hs * 4));
+    w.g_cnt = reinterpret_cast<uint32_t *>(take(hs * 4));
+    w.g_used = reinterpret_cast<uint32_t *>(take(hs * 4));
+    w.g_hi = reinterpret_cast<float *>(take(hs * 4));
+    w.g_lo = reinterpret_cast<float *>(take(hs * 4));
+    const uint64_t ss = uint64_t(kFallbackWorkers) * g.nseg;
+    w.g_seg_cnt = reinterpret_cast<uint32_t *>(take(ss * 4));
+    w.g_seg_hi = reinterpret_cast<float *>(take(ss * 4));
+    w.g_seg_lo = reinterpret_cast<float *>(take(ss * 4));
+    w.bucket_of = reinterpret_cast<uint32_t *>(take(uint64_t(max_boxes) * 4));
+    w.order = reinterpret_cast<uint32_t *>(take(uint64_t(max_boxes) * 4));
+    w.overflow = reinterpret_cast<uint32_t *>(take(uint64_t(max_boxes) * 4));
+    w.bytes = off;
+    w.max_boxes = max_boxes;
+    return w;
+}
+
+int check_device(Graph *g, std::string *err)
+{
+    if (g->dev.device < 0) {
+        *err = "graph is not on a device: call mg_upload first";
+        return MG_ESTATE;
+    }
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != g->dev.device) HIP_TRY(hipSetDevice(g->dev.device));
+    return MG_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    DeviceGuard() { (void)hipGetDevice(&prev); }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+int timing_begin(Graph *g, hipStream_t s, std::string *err)
+{
+    DeviceState &d = g->dev;
+    if (!d.timing) return MG_OK;
+    if (d.ev_used >= d.ev_start.size()) {
+        hipEvent_t a, b;
+        HIP_TRY(hipEventCreate(&a));
+        HIP_TRY(hipEventCreate(&b));
+        d.ev_start.push_back(a);
+        d.ev_stop.push_back(b);
+    }
+    HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(d.ev_start[d.ev_used]), s));
+    return MG_OK;
+}
+
+int timing_end(Graph *g, hipStream_t s, std::string *err)
+{
+    DeviceState &d = g->dev;
+    if (!d.timing) return MG_OK;
+    HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(d.ev_stop[d.ev_used]), s));
+    d.ev_used++;
+    return MG_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- entry points
+
+int dev_upload(Graph *g, int device, std::string *err)
+{
+    DeviceGuard guard;
+    if (g->dev.device >= 0) dev_free(g);
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device >= ndev) {
+        *err = "mg_upload: device " + std::to_string(device) + " does not exist";
+        return MG_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(device));
+    DeviceState &d = g->dev;
+    const uint64_t nmap = g->lev_off[g->n_levels];
+    const uint64_t bytes_nodes = uint64_t(g->n_nodes) * sizeof(NodeTriple);
+    const uint64_t bytes_maps = 2 * nmap * 4;
+    std::vector<NodeTriple> nodes(g->n_nodes);
+    for (uint32_t n = 0; n < g->n_nodes; ++n) nodes[n] = NodeTriple{g->child_a[n], g->child_b[n], g->alpha[n]};
+    if (hipMalloc(&d.nodes, bytes_nodes) != hipSuccess || hipMalloc(&d.step_ptr, g->step_ptr.size() * 4) != hipSuccess ||
+        hipMalloc(&d.maps, bytes_maps) != hipSuccess) {
+        (void)hipGetLastError();
+        dev_free(g);
+        *err = "mg_upload: device allocation failed";
+        return MG_ENOMEM;
+    }
+    d.maps_t = d.maps + nmap;
+    d.device = device;
+    d.bytes = bytes_nodes + g->step_ptr.size() * 4 + bytes_maps;
+    HIP_TRY(hipMemcpy(d.nodes, nodes.data(), bytes_nodes, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d.step_ptr, g->step_ptr.data(), g->step_ptr.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d.maps, g->maps.data(), nmap * 4, hipMemcpyHostToDevice));
+    for (uint32_t l = 0; l < g->n_levels; ++l) {
+        const uint32_t X = g->lev_dims[3 * l], Y = g->lev_dims[3 * l + 1], Z = g->lev_dims[3 * l + 2];
+        const uint64_t cnt = uint64_t(X) * Y * Z;
+        const uint32_t blocks = uint32_t((cnt + 255) / 256);
+        hipLaunchKernelGGL(transpose_level_kernel, dim3(blocks), dim3(256), 0, 0, d.maps + g->lev_off[l],
+                           d.maps_t + g->lev_off[l], X, Y, Z);
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipDeviceSynchronize());
+    return MG_OK;
+}
+
+void dev_free(Graph *g)
+{
+    DeviceState &d = g->dev;
+    if (d.device < 0 && !d.nodes && !d.maps) return;
+    DeviceGuard guard;
+    if (d.device >= 0) (void)hipSetDevice(d.device);
+    if (d.nodes) (void)hipFree(d.nodes);
+    if (d.step_ptr) (void)hipFree(d.step_ptr);
+    if (d.maps) (void)hipFree(d.maps);
+    for (void *e : d.ev_start) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
+    for (void *e : d.ev_stop) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
+    d = DeviceState();
+}
+
+uint64_t dev_workspace_bytes(const Graph &g, uint32_t max_boxes)
+{
+    return carve(g, nullptr, std::max<uint32_t>(max_boxes, 1)).bytes;
+}
+
+int dev_workspace_init(Graph *g, void *work, uint64_t bytes, void *stream, std::string *err)
+{
+    int rc = check_device(g, err);
+    if (rc) return rc;
+    // the workspace fixes its box capacity: find the largest max_boxes that fits
+    Workspace w = carve(*g, static_cast<char *>(work), 1);
+    if (bytes < w.bytes) {
+        *err = "workspace smaller than mg_workspace_bytes(g, 1)";
+        return MG_EINVAL;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const uint64_t hs = uint64_t(kFallbackWorkers) * kHashGlobal;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, w.g_keys, hs, kEmpty);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, w.g_cnt, hs, 0u);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_hi), hs, 0u);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_lo), hs, 0u);
+    const uint64_t ss = uint64_t(kFallbackWorkers) * g->nseg;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, w.g_seg_cnt, ss, 0u);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_seg_hi), ss, 0u);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_seg_lo), ss, 0u);
+    HIP_TRY(hipGetLastError());
+    return MG_OK;
+}
+
+int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *work, uint64_t bytes, void *stream,
+              int variant, uint32_t *stats, std::string *err)
+{
+    DeviceGuard guard;
+    int rc = check_device(g, err);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const uint64_t need = dev_workspace_bytes(*g, n);
+    if (bytes < need) {
+        *err = "workspace of " + std::to_string(bytes) + " bytes is smaller than the " + std::to_string(need) +
+               " bytes that " + std::to_string(n) + " boxes need";
+        return MG_EINVAL;
+    }
+    if (g->depth > kMaxSteps) {
+        *err = "graph depth " + std::to_string(g->depth) + " beyond the kernels' step table (" +
+               std::to_string(kMaxSteps) + ")";
+        return MG_ELIMIT;
+    }
+    if (g->n_levels > kMaxLevelsDev) {
+        *err = "more than " + std::to_string(kMaxLevelsDev) + " mip levels";
+        return MG_ELIMIT;
+    }
+    Workspace w = carve(*g, static_cast<char *>(work), n);
+    const LevelTable lt = level_table(*g);
+
+    if (variant == kQueryNaive) {
+        if (g->nseg > 16384) {
+            *err = "naive scan keeps per-source counts in LDS: at most 16384 sources";
+            return MG_ELIMIT;
+        }
+        NaiveArgs A;
+        A.lt = lt;
+        A.boxes = boxes;
+        A.out = out;
+        A.map0 = g->dev.maps;
+        A.nseg = g->nseg;
+        A.n = n;
+        rc = timing_begin(g, s, err);
+        if (rc) return rc;
+        hipLaunchKernelGGL(naive_kernel, dim3(n), dim3(kBlock), g->nseg * 4, s, A);
+        HIP_TRY(hipGetLastError());
+        return timing_end(g, s, err);
+    }
+
+    if (g->nseg > kSegLdsMax) {
+        *err = "query kernels keep per-source state in LDS: at most " + std::to_string(kSegLdsMax) + " sources";
+        return MG_ELIMIT;
+    }
+    QueryArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.lt = lt;
+    A.boxes = boxes;
+    A.out = out;
+    A.maps = g->dev.maps;
+    A.nodes = g->dev.nodes;
+    A.step_ptr = g->dev.step_ptr;
+    A.nseg = g->nseg;
+    A.depth = g->depth;
+    A.n = n;
+    A.counters = w.counters;
+    A.overflow = w.overflow;
+    A.stats = stats;
+    A.g_keys = w.g_keys, A.g_cnt = w.g_cnt, A.g_used = w.g_used, A.g_hi = w.g_hi, A.g_lo = w.g_lo;
+    A.g_seg_cnt = w.g_seg_cnt, A.g_seg_hi = w.g_seg_hi, A.g_seg_lo = w.g_seg_lo;
+    const LdsLayout L = LdsLayout::make(g->nseg, false, false);
+
+    int lds_max = 0;
+    HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, g->dev.device));
+    if (L.total + sizeof(QueryShared) > uint64_t(lds_max)) {
+        *err = "query state of " + std::to_string(L.total + sizeof(QueryShared)) + " bytes exceeds the " +
+               std::to_string(lds_max) + " bytes of LDS per workgroup";
+        return MG_ELIMIT;
+    }
+    const void *kern = variant == kQueryBatched ? reinterpret_cast<const void *>(query_batched_kernel)
+                                                : reinterpret_cast<const void *>(query_plain_kernel);
+    HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(L.total)));
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, w.counters, 64u);
+    if (variant == kQueryBatched) {
+        hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, w.buckets, 64u);
+        const uint32_t blocks = (n + 255) / 256;
+        hipLaunchKernelGGL(query_size_kernel, dim3(blocks), dim3(256), 0, s, lt, boxes, n, w.bucket_of, w.buckets);
+        hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(64), 0, s, w.buckets);
+        hipLaunchKernelGGL(query_order_kernel, dim3(blocks), dim3(256), 0, s, w.bucket_of, n, w.buckets, w.order);
+        A.order = w.order;
+        int ncu = 256, per_cu = 1;
+        HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, g->dev.device));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(query_batched_kernel),
+                                                             kBlock, L.total));
+        const uint32_t workers = std::max(1u, std::min<uint32_t>(n, uint32_t(ncu) * uint32_t(std::max(per_cu, 1))));
+        rc = timing_begin(g, s, err);
+        if (rc) return rc;
+        hipLaunchKernelGGL(query_batched_kernel, dim3(workers), dim3(kBlock), L.total, s, A);
+        HIP_TRY(hipGetLastError());
+        rc = timing_end(g, s, err);
+        if (rc) return rc;
+    } else {
+        rc = timing_begin(g, s, err);
+        if (rc) return rc;
+        hipLaunchKernelGGL(query_plain_kernel, dim3(n), dim3(kBlock), L.total, s, A);
+        HIP_TRY(hipGetLastError());
+        rc = timing_end(g, s, err);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(query_fallback_kernel, dim3(kFallbackWorkers), dim3(kBlock), 0, s, A);
+    HIP_TRY(hipGetLastError());
+    return MG_OK;
+}
+
+int dev_footprint(Graph *g, const uint32_t *boxes, uint32_t n, uint32_t *level_counts, uint32_t *cubes, uint32_t cap,
+                  uint32_t *count, void *stream, std::string *err)
+{
+    DeviceGuard guard;
+    int rc = check_device(g, err);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const LevelTable lt = level_table(*g);
+    hipLaunchKernelGGL(footprint_kernel, dim3(n), dim3(kBlock), 0, s, lt, boxes, n, g->dev.maps, level_counts, cubes,
+                       cap, count);
+    HIP_TRY(hipGetLastError());
+    return MG_OK;
+}
+
+int dev_propagate_tf(Graph *g, const uint8_t *tf, uint32_t T, float *out, void *stream, std::string *err)
+{
+    DeviceGuard guard;
+    int rc = check_device(g, err);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float4 *o = reinterpret_cast<float4 *>(out);
+    const uint64_t src = uint64_t(T) * g->nseg;
+    hipLaunchKernelGGL(tf_sources_kernel, dim3(uint32_t((src + 255) / 256)), dim3(256), 0, s, tf, T, g->nseg,
+                       g->n_nodes, o);
+    HIP_TRY(hipGetLastError());
+    rc = timing_begin(g, s, err);
+    if (rc) return rc;
+    for (uint32_t st = 1; st <= g->depth; ++st) {
+        const uint32_t lo = g->step_ptr[st], hi = g->step_ptr[st + 1];
+        if (hi <= lo) continue;
+        hipLaunchKernelGGL(tf_step_kernel, dim3((hi - lo + 255) / 256), dim3(256), 0, s, g->dev.nodes, lo, hi, T,
+                           g->n_nodes, o);
+        HIP_TRY(hipGetLastError());
+    }
+    return timing_end(g, s, err);
+}
+
+int dev_timing_enable(Graph *g, int enable, std::string *err)
+{
+    (void)err;
+    g->dev.timing = enable != 0;
+    return MG_OK;
+}
+
+int dev_timing_read(Graph *g, double *ms, uint32_t *launches, std::string *err)
+{
+    DeviceGuard guard;
+    int rc = check_device(g, err);
+    if (rc) return rc;
+    double tot = 0;
+    DeviceState &d = g->dev;
+    for (uint32_t i = 0; i < d.ev_used; ++i) {
+        HIP_TRY(hipEventSynchronize(static_cast<hipEvent_t>(d.ev_stop[i])));
+        float t = 0;
+        HIP_TRY(hipEventElapsedTime(&t, static_cast<hipEvent_t>(d.ev_start[i]), static_cast<hipEvent_t>(d.ev_stop[i])));
+        tot += t;
+    }
+    *ms = tot;
+    *launches = d.ev_used;
+    d.ev_used = 0;
+    return MG_OK;
+}
+
+}  // namespace mg

@@ -1,0 +1,74 @@
+// Internal types shared by the host builder (builder.cpp), the C ABI
+// (api.cpp) and the HIP launchers (kernels.hip). Not installed.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mg.h"
+
+namespace mg {
+
+// One internal node as the GPU reads it: node = (1 - w) * a + w * b.
+// 12 bytes, read with one dwordx3 load per visited node.
+struct NodeTriple {
+    uint32_t a;
+    uint32_t b;
+    float w;
+};
+static_assert(sizeof(NodeTriple) == 12, "NodeTriple must stay 12 bytes");
+
+struct DeviceState {
+    int device = -1;
+    NodeTriple *nodes = nullptr;   // [n_nodes]
+    uint32_t *step_ptr = nullptr;  // [depth + 2]
+    uint32_t *maps = nullptr;      // all levels, x fastest
+    uint32_t *maps_t = nullptr;    // all levels, y fastest then z then x
+    uint64_t bytes = 0;
+    bool timing = false;
+    std::vector<void *> ev_start, ev_stop;  // hipEvent_t pairs recorded around the dominant kernel
+    uint32_t ev_used = 0;
+};
+
+struct Graph {
+    uint32_t dims[3] = {0, 0, 0};
+    uint32_t nseg = 0;
+    uint32_t n_nodes = 0;
+    uint32_t depth = 0;
+    uint32_t n_levels = 0;
+    uint32_t max_mixture = 1;
+    std::vector<uint32_t> lev_dims;   // 3 per level
+    std::vector<uint64_t> lev_off;    // n_levels + 1 offsets into maps
+    std::vector<uint32_t> maps;       // node ID per mip voxel, all levels, x fastest
+    std::vector<uint32_t> seg_ids;    // source -> original volume ID
+    std::vector<uint32_t> child_a, child_b, rank, step;  // [n_nodes]
+    std::vector<float> alpha;                            // [n_nodes]
+    std::vector<uint64_t> wnum, wden;                    // [n_nodes]
+    std::vector<uint32_t> step_ptr;                      // [depth + 2]
+    DeviceState dev;
+};
+
+// Host builder (builder.cpp). Returns MG_OK or an MG_E* code with *err set.
+int build_graph(const uint32_t *ids, const mg_build_opts *opts, Graph *g, std::string *err);
+// Structural validation of a graph's host arrays (used by mg_load).
+int validate_graph(const Graph &g, std::string *err);
+// Level dimensions: halve with rounding up until 1^3.
+void level_dims(const uint32_t dims[3], std::vector<uint32_t> *out);
+
+// Device side (kernels.hip). All return MG_OK or an MG_E* code with *err set.
+int dev_upload(Graph *g, int device, std::string *err);
+void dev_free(Graph *g);
+uint64_t dev_workspace_bytes(const Graph &g, uint32_t max_boxes);
+int dev_workspace_init(Graph *g, void *work, uint64_t bytes, void *stream, std::string *err);
+int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *work, uint64_t bytes,
+              void *stream, int variant, uint32_t *stats, std::string *err);
+int dev_footprint(Graph *g, const uint32_t *boxes, uint32_t n, uint32_t *level_counts, uint32_t *cubes,
+                  uint32_t cap, uint32_t *count, void *stream, std::string *err);
+int dev_propagate_tf(Graph *g, const uint8_t *tf, uint32_t T, float *out, void *stream, std::string *err);
+int dev_timing_enable(Graph *g, int enable, std::string *err);
+int dev_timing_read(Graph *g, double *ms, uint32_t *launches, std::string *err);
+
+enum QueryVariant { kQueryBatched = 0, kQueryPlain = 1, kQueryNaive = 2 };
+
+}  // namespace mg

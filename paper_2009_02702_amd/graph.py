@@ -1,0 +1,211 @@
+"""Python binding of the Mixture Graph library: the same calls as include/mg.h.
+
+Host arrays are NumPy; device buffers are torch tensors (PyTorch provides
+device memory and streams only). Query and propagation calls enqueue HIP
+kernels on the current torch stream and return without synchronising.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+
+from . import _lib
+from ._lib import BuildOpts, Info, check
+
+VARIANTS = ("batched", "plain", "naive")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t) -> ctypes.c_void_p:
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Graph:
+    """A Mixture Graph built on the CPU and, after upload(), resident on one GPU."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self._h = handle
+        self._lib = _lib.load()
+        self._ws = None
+        self._ws_boxes = 0
+
+    # -------------------------------------------------------------- construction
+    @classmethod
+    def build(cls, volume: np.ndarray, defer: bool = True, max_depth: int = 0, threads: int = 0) -> "Graph":
+        """mg_build on a (nz, ny, nx) ID volume; uint8/uint16 volumes are widened to uint32."""
+        vol = np.asarray(volume)
+        if vol.ndim != 3:
+            raise ValueError("volume must be 3-D (nz, ny, nx)")
+        if vol.dtype != np.uint32:
+            if vol.dtype.kind not in "ui" or (vol.size and int(vol.min()) < 0):
+                raise ValueError("volume must hold non-negative integer IDs")
+            vol = vol.astype(np.uint32)
+        vol = np.ascontiguousarray(vol)
+        nz, ny, nx = vol.shape
+        o = BuildOpts(nx=nx, ny=ny, nz=nz, defer=1 if defer else 0, max_depth=max_depth, threads=threads)
+        h = ctypes.c_void_p()
+        check(_lib.load().mg_build(vol.ctypes.data_as(ctypes.c_void_p), ctypes.byref(o), ctypes.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def load(cls, path: str) -> "Graph":
+        h = ctypes.c_void_p()
+        check(_lib.load().mg_load(path.encode(), ctypes.byref(h)))
+        return cls(h)
+
+    def save(self, path: str) -> None:
+        check(self._lib.mg_save(self._h, path.encode()))
+
+    def close(self) -> None:
+        if self._h:
+            self._ws = None
+            self._lib.mg_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- host views
+    def info(self) -> dict:
+        i = Info()
+        check(self._lib.mg_info(self._h, ctypes.byref(i)))
+        return {
+            "nseg": i.nseg, "n_nodes": i.n_nodes, "depth": i.depth, "n_levels": i.n_levels,
+            "dims": [tuple(i.dims[l]) for l in range(i.n_levels)], "map_voxels": i.map_voxels,
+            "device_bytes": i.device_bytes, "device": i.device, "max_mixture": i.max_mixture,
+        }
+
+    def export_dag(self) -> dict:
+        inf = self.info()
+        n, d = inf["n_nodes"], inf["depth"]
+        out = {k: np.zeros(n, dtype=t) for k, t in (("child_a", np.uint32), ("child_b", np.uint32),
+                                                      ("alpha", np.float32), ("wnum", np.uint64),
+                                                      ("wden", np.uint64), ("rank", np.uint32),
+                                                      ("step", np.uint32))}
+        out["step_ptr"] = np.zeros(d + 2, dtype=np.uint32)
+        check(self._lib.mg_export_dag(self._h, *[out[k].ctypes.data_as(ctypes.c_void_p) for k in
+                                                 ("child_a", "child_b", "alpha", "wnum", "wden", "rank", "step",
+                                                  "step_ptr")]))
+        return out
+
+    def export_map(self, level: int) -> np.ndarray:
+        nx, ny, nz = self.info()["dims"][level]
+        out = np.zeros((nz, ny, nx), dtype=np.uint32)
+        check(self._lib.mg_export_map(self._h, level, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def segment_ids(self) -> np.ndarray:
+        out = np.zeros(self.info()["nseg"], dtype=np.uint32)
+        check(self._lib.mg_segment_ids(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    # -------------------------------------------------------------- device
+    def upload(self, device: int = 0) -> "Graph":
+        check(self._lib.mg_upload(self._h, int(device)))
+        self._device = int(device)
+        return self
+
+    def workspace_bytes(self, max_boxes: int) -> int:
+        b = ctypes.c_uint64()
+        check(self._lib.mg_workspace_bytes(self._h, int(max_boxes), ctypes.byref(b)))
+        return int(b.value)
+
+    def workspace(self, max_boxes: int, stream=None):
+        """Device workspace for up to max_boxes boxes per call (allocated by torch, initialised once)."""
+        torch = _torch()
+        if self._ws is None or self._ws_boxes < max_boxes:
+            nbytes = self.workspace_bytes(max_boxes)
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda:%d" % self._device)
+            check(self._lib.mg_workspace_init(self._h, _dptr(self._ws), nbytes, _stream_ptr(stream)))
+            self._ws_boxes = max_boxes
+        return self._ws
+
+    def query(self, boxes, out=None, variant: str = "batched", workspace=None, stream=None):
+        """Box histograms: boxes int32/uint32 device tensor [n, 6] -> fp32 [n, S] fractions."""
+        torch = _torch()
+        if boxes.dim() != 2 or boxes.shape[1] != 6 or boxes.element_size() != 4:
+            raise ValueError("boxes must be a 32-bit [n, 6] tensor")
+        n = boxes.shape[0]
+        S = self.info()["nseg"]
+        if out is None:
+            out = torch.empty((n, S), dtype=torch.float32, device=boxes.device)
+        if tuple(out.shape) != (n, S) or out.dtype != torch.float32:
+            raise ValueError("out must be fp32 [n, S]")
+        ws = workspace if workspace is not None else self.workspace(n, stream)
+        fn = {"batched": self._lib.mg_query_boxes, "plain": self._lib.mg_query_boxes_plain,
+              "naive": self._lib.mg_naive_boxes}[variant]
+        check(fn(self._h, _dptr(boxes), n, _dptr(out), _dptr(ws), ws.numel(), _stream_ptr(stream)))
+        return out
+
+    def query_stats(self, boxes, out=None, workspace=None, stream=None):
+        """Batched query that also returns int32 [n, 2] (cubes, graph nodes touched) per box."""
+        torch = _torch()
+        n = boxes.shape[0]
+        S = self.info()["nseg"]
+        if out is None:
+            out = torch.empty((n, S), dtype=torch.float32, device=boxes.device)
+        stats = torch.zeros((n, 2), dtype=torch.int32, device=boxes.device)
+        ws = workspace if workspace is not None else self.workspace(n, stream)
+        check(self._lib.mg_query_boxes_stats(self._h, _dptr(boxes), n, _dptr(out), _dptr(stats), _dptr(ws),
+                                             ws.numel(), _stream_ptr(stream)))
+        return out, stats
+
+    def footprint(self, boxes, cubes_cap: int = 0, stream=None):
+        """(level counts [n, L], cubes [m, 6] or None): the GPU decomposition of each box."""
+        torch = _torch()
+        n = boxes.shape[0]
+        L = self.info()["n_levels"]
+        counts = torch.zeros((n, L), dtype=torch.int32, device=boxes.device)
+        cubes = count = None
+        if cubes_cap:
+            cubes = torch.zeros((cubes_cap, 6), dtype=torch.int32, device=boxes.device)
+            count = torch.zeros(1, dtype=torch.int32, device=boxes.device)
+        check(self._lib.mg_footprint(self._h, _dptr(boxes), n, _dptr(counts),
+                                     _dptr(cubes) if cubes is not None else None, int(cubes_cap),
+                                     _dptr(count) if count is not None else None, _stream_ptr(stream)))
+        if cubes is not None:
+            m = int(count.item())
+            if m > cubes_cap:
+                raise RuntimeError("cube capacity %d too small (%d cubes)" % (cubes_cap, m))
+            cubes = cubes[:m]
+        return counts, cubes
+
+    def propagate_tf(self, tf, out=None, stream=None):
+        """RGBA8 device tensor [T, S, 4] -> fp32 [T, n_nodes, 4] node colours."""
+        torch = _torch()
+        T = tf.shape[0]
+        inf = self.info()
+        if tuple(tf.shape) != (T, inf["nseg"], 4) or tf.dtype != torch.uint8:
+            raise ValueError("tf must be uint8 [T, S, 4]")
+        if out is None:
+            out = torch.empty((T, inf["n_nodes"], 4), dtype=torch.float32, device=tf.device)
+        check(self._lib.mg_propagate_tf(self._h, _dptr(tf), T, _dptr(out), _stream_ptr(stream)))
+        return out
+
+    def timing(self, enable: bool) -> None:
+        check(self._lib.mg_timing_enable(self._h, 1 if enable else 0))
+
+    def timing_read(self):
+        ms = ctypes.c_double()
+        k = ctypes.c_uint32()
+        check(self._lib.mg_timing_read(self._h, ctypes.byref(ms), ctypes.byref(k)))
+        return float(ms.value), int(k.value)

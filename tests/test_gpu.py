@@ -1,0 +1,242 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerance (no precision is fixed by the paper; derivation): counts from cubes
+whose node is a source are exact integers; mass pushed through the DAG
+carries, per hop, the fp32 rounding of the weight, of 1 - w and of the
+product (3 units of 2^-24), and the compensated accumulation adds at most
+about one unit per node; the graph depth here is ceil(log2 S) <= 14, so the
+relative error per segment is below (5 * 14 + 2) * 2^-24 = 4.3e-6 < 1e-5.
+Segments absent from a box must come out exactly 0, and boxes whose cubes are
+all level-0 voxels must match the fp32-rounded oracle bit for bit.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import footprint as ofp
+from oracle import mipmap, scan
+from oracle import tf as otf
+from paper_2009_02702_amd import Graph, MGError, synth
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-5
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).cuda()
+
+
+def _compare(got, ref, level0_only=None, tag=""):
+    got = np.asarray(got, dtype=np.float64)
+    assert got.shape == ref.shape, tag
+    assert np.isfinite(got).all(), tag
+    assert np.array_equal(got == 0, ref == 0), "%s: support differs" % tag
+    nz = ref > 0
+    rel = np.abs(got[nz] - ref[nz]) / ref[nz]
+    assert rel.max(initial=0) <= REL_TOL, "%s: max rel err %g" % (tag, rel.max())
+    if level0_only is not None and level0_only.any():
+        a = got[level0_only].astype(np.float32)
+        b = ref[level0_only].astype(np.float32)
+        assert np.array_equal(a, b), "%s: level-0 boxes not bit-exact" % tag
+    return rel.max(initial=0)
+
+
+def _level0_only(g, dboxes):
+    counts, _ = g.footprint(dboxes)
+    c = counts.cpu().numpy()
+    return (c[:, 1:].sum(axis=1) == 0) & (c[:, 0] > 0)
+
+
+_GRAPHS = {}
+
+
+def _graph(key, vol):
+    if key not in _GRAPHS:
+        _GRAPHS[key] = Graph.build(vol).upload(0)
+    return _GRAPHS[key]
+
+
+def _check_workload(w, n=None, variants=("batched", "plain", "naive"), key=None):
+    vol = synth.make_volume(w)
+    boxes = synth.make_boxes(w, n)
+    g = _graph(key or (w.config, w.dims, w.segments), vol)
+    ids, vol_c = scan.compact(vol)
+    _, ref = scan.box_counts(vol_c, len(ids), boxes)
+    db = _dev(boxes)
+    l0 = _level0_only(g, db)
+    errs = {}
+    for v in variants:
+        out = g.query(db, variant=v)
+        torch.cuda.synchronize()
+        errs[v] = _compare(out.cpu().numpy(), ref, l0, "%s/%s" % (w.name, v))
+    return g, errs
+
+
+# ------------------------------------------------------------------ footprint (a1-a4)
+
+def test_footprint_cubes_and_nodes_match_oracle():
+    g0 = np.random.default_rng(21)
+    vol = g0.integers(0, 6, size=(41, 29, 37)).astype(np.uint32)
+    g = _graph("fp", vol)
+    nx, ny, nz = 37, 29, 41
+    boxes = np.concatenate([g0.integers(0, 45, size=(300, 3)), g0.integers(0, 40, size=(300, 3))], 1)
+    boxes[:20, 3:] = 1
+    boxes[20:30, :3] = 0
+    boxes[20:30, 3:] = [nx, ny, nz]
+    boxes = boxes.astype(np.uint32)
+    counts, cubes = g.footprint(_dev(boxes), cubes_cap=2_000_000)
+    counts = counts.cpu().numpy()
+    cubes = cubes.cpu().numpy().astype(np.int64)
+    maps = [g.export_map(l) for l in range(g.info()["n_levels"])]
+    by_box = {}
+    for q, l, x, y, z, node in cubes:
+        by_box.setdefault(int(q), []).append((int(l), (int(x), int(y), int(z))))
+        assert node == maps[l][z, y, x]
+    for q, b in enumerate(boxes):
+        want = sorted(ofp.assembly(b[:3], b[3:], (nx, ny, nz)))
+        assert sorted(by_box.get(q, [])) == want, q
+        hist = np.bincount([l for l, _ in want], minlength=len(maps)) if want else np.zeros(len(maps))
+        assert np.array_equal(counts[q], hist), q
+
+
+# ------------------------------------------------------------------ query parity (a1-a7, a10)
+
+def test_query_config1_full():
+    _, errs = _check_workload(synth.workload(1))
+    print(errs)
+
+
+@pytest.mark.parametrize("config,dims,segments,n", [
+    (2, (96, 80, 72), 353, 3000),
+    (3, (256, 256, 40), 1182, 2000),
+    (4, (123, 96, 100), 1500, 3000),
+    (5, (118, 113, 79), 353, 3000),
+])
+def test_query_reduced_recipes(config, dims, segments, n):
+    _, errs = _check_workload(synth.workload(config, dims=dims, segments=segments, n_boxes=n))
+    print(errs)
+
+
+def test_query_edge_cases():
+    vol = synth.make_volume(synth.workload(2, dims=(33, 35, 31), segments=25))
+    nx, ny, nz = 33, 35, 31
+    g = _graph("edge", vol)
+    M = 0xFFFFFFFF
+    boxes = np.array([
+        [0, 0, 0, nx, ny, nz],          # full volume
+        [5, 6, 7, 1, 1, 1],             # one voxel
+        [nx, 0, 0, 4, 4, 4],            # origin at the x extent: empty
+        [M, M, M, 4, 4, 4],             # far outside: empty
+        [3, 3, 3, 0, 5, 5],             # zero extent: empty
+        [10, 11, 12, M, M, M],          # huge extents clip
+        [0, 0, 0, 1, ny, nz],           # one-voxel-thick slab
+        [31, 0, 0, 2, 32, 16],          # aligned power-of-two block, clipped in x
+        [1, 1, 1, 31, 33, 29],
+    ], dtype=np.uint32)
+    ids, vol_c = scan.compact(vol)
+    _, ref = scan.box_counts(vol_c, len(ids), boxes)
+    for v in ("batched", "plain", "naive"):
+        out = g.query(_dev(boxes), variant=v).cpu().numpy()
+        _compare(out, ref, None, v)
+        assert (out[2:5] == 0).all()
+        assert out[1].tolist() == [1.0 if s == vol_c[7, 6, 5] else 0.0 for s in range(len(ids))]
+    # repeated calls with different sizes reuse the workspace
+    for n in (1, 3, 9, 2):
+        out = g.query(_dev(boxes[:n])).cpu().numpy()
+        _compare(out, ref[:n], None, "n=%d" % n)
+    empty = g.query(_dev(np.zeros((0, 6), dtype=np.uint32)))
+    assert tuple(empty.shape) == (0, len(ids))
+
+
+def test_query_bad_arguments():
+    vol = synth.make_volume(synth.workload(2, dims=(16, 16, 16), segments=5))
+    g = _graph("bad", vol)
+    boxes = _dev(np.zeros((4, 6), dtype=np.uint32))
+    out = torch.empty((4, g.info()["nseg"]), dtype=torch.float32, device="cuda")
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(MGError) as e:
+        g.query(boxes, out=out, workspace=small)
+    assert e.value.code == -1
+
+
+def test_query_full_config2_sampled():
+    """512^3, 100,000 boxes, batched as bench.py runs it; O1 on a sample that includes the largest boxes."""
+    w = synth.workload(2)
+    vol = synth.make_volume(w)
+    boxes = synth.make_boxes(w)
+    g = _graph("cfg2", vol)
+    db = _dev(boxes)
+    out = g.query(db, variant="batched")
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    vols = boxes[:, 3:].astype(np.float64).prod(axis=1)
+    sample = np.unique(np.concatenate([np.argsort(vols)[-40:], np.random.default_rng(7).choice(len(boxes), 160, replace=False)]))
+    ids, vol_c = scan.compact(vol)
+    _, ref = scan.box_counts(vol_c, len(ids), boxes[sample])
+    _compare(got[sample], ref, None, "cfg2 sample")
+    assert (got >= 0).all()
+    assert np.abs(got.astype(np.float64).sum(axis=1) - 1.0).max() < 1e-5
+    # the plain per-box kernel and the naive scan agree on the same sample
+    for v in ("plain", "naive"):
+        o = g.query(_dev(boxes[sample]), variant=v).cpu().numpy()
+        _compare(o, ref, None, "cfg2 sample " + v)
+
+
+# ------------------------------------------------------------------ TF propagation (a8)
+
+def test_tf_matches_oracle_every_mip_voxel():
+    vol = synth.make_volume(synth.workload(3, dims=(40, 36, 12), segments=30))
+    g = _graph("tf", vol)
+    inf = g.info()
+    S = inf["nseg"]
+    tfs = synth.make_tfs(synth.workload(3), S, 3)
+    col = g.propagate_tf(torch.from_numpy(tfs).cuda()).cpu().numpy().astype(np.float64)
+    ids, vol_c = scan.compact(vol)
+    atol = 4 * max(inf["depth"], 1) * 2.0 ** -24
+    for t in range(3):
+        for l in range(inf["n_levels"]):
+            want = otf.level_colours(vol_c, S, tfs[t], l)
+            node = g.export_map(l)
+            got = col[t][node]
+            assert np.abs(got - want).max() <= atol, (t, l, np.abs(got - want).max())
+
+
+def test_tf_constant_is_exact_and_one_hot_gives_mixture():
+    vol = synth.make_volume(synth.workload(2, dims=(30, 30, 30), segments=40))
+    g = _graph("tf2", vol)
+    inf = g.info()
+    S, N = inf["nseg"], inf["n_nodes"]
+    const = np.tile(np.array([[17, 99, 250, 3]], dtype=np.uint8), (S, 1))[None]
+    col = g.propagate_tf(torch.from_numpy(const).cuda()).cpu().numpy()
+    assert (col[0] == (const[0, 0].astype(np.float32) * np.float32(1 / 255))).all()
+    onehot = np.zeros((1, S, 4), dtype=np.uint8)
+    onehot[0, 7, 0] = 255
+    col = g.propagate_tf(torch.from_numpy(onehot).cuda()).cpu().numpy()[0, :, 0]
+    ids, vol_c = scan.compact(vol)
+    for l in range(inf["n_levels"]):
+        h = mipmap.mixtures_level(vol_c, S, l)[..., 7]
+        assert np.abs(col[g.export_map(l)] - h).max() <= 4 * inf["depth"] * 2.0 ** -24
+
+
+def test_adjoint_box_colour():
+    """Mean box colour two ways: sum_s p_s TF_s from the query, and sum over cubes of 8^l v_node / |box|
+    from the propagated palette (the push is the transpose of the propagation)."""
+    w = synth.workload(5, dims=(70, 64, 50), segments=60, n_boxes=300)
+    vol = synth.make_volume(w)
+    g = _graph("adj", vol)
+    S = g.info()["nseg"]
+    tf = synth.make_tfs(w, S, 1)
+    boxes = synth.make_boxes(w)
+    db = _dev(boxes)
+    p = g.query(db).cpu().numpy().astype(np.float64)
+    pal = g.propagate_tf(torch.from_numpy(tf).cuda()).cpu().numpy()[0].astype(np.float64)
+    _, cubes = g.footprint(db, cubes_cap=4_000_000)
+    cubes = cubes.cpu().numpy().astype(np.int64)
+    acc = np.zeros((len(boxes), 4))
+    np.add.at(acc, cubes[:, 0], (8.0 ** cubes[:, 1])[:, None] * pal[cubes[:, 5]])
+    vols = np.prod(np.minimum(boxes[:, :3].astype(np.int64) + boxes[:, 3:], [70, 64, 50]) - boxes[:, :3], axis=1)
+    lhs = p @ (tf[0].astype(np.float64) / 255.0)
+    rhs = acc / vols[:, None]
+    assert np.abs(lhs - rhs).max() < 1e-5
