@@ -56,7 +56,7 @@ extern "C" {
 typedef struct mg_graph mg_graph; /* opaque; owned by the library, freed by mg_free */
 
 typedef struct {
-    uint32_t nx, ny, nz;   /* level-0 dimensions, each >= 1, nx*ny*nz < 2^32       */
+    uint32_t nx, ny, nz;   /* level-0 dimensions, each >= 1, nx*ny*nz < 2^31       */
     uint32_t defer;        /* 1: deferred, load-balanced step schedule (Sec.
                               "Reconstruction"); 0: one step per topological level */
     uint32_t max_depth;    /* 0: no cap; else fail with MG_EDEPTH beyond it         */
@@ -84,21 +84,26 @@ typedef struct {
  * mip voxel's mixture is the exact normalized histogram of its level-0 support.
  * Each distinct mixture becomes one node, factored into binary lerps
  * n = (1 - w) a + w b with exact rational w in (0, 1/2]; nodes are numbered by
- * schedule step (sources first). On success *out owns host copies of the DAG
- * and of one node ID per mip voxel. `ids` is read only during the call. */
+ * topological level (sources first). On success *out owns host copies of the DAG
+ * and of one node ID per mip voxel. `ids` is read only during the call.
+ * Volumes of 2^31 voxels or more give MG_ELIMIT. */
 int mg_build(const uint32_t *ids, const mg_build_opts *opts, mg_graph **out);
 
 int mg_info(const mg_graph *g, mg_info_t *out);
 
-/* Host copies of the DAG, each array n_nodes long (NULL skips it): for node n,
+/* Host copies of the DAG (NULL skips an array). Per node (n_nodes entries):
  * child_a/child_b are its two predecessors and w[n] = wnum[n]/wden[n] the
- * weight of child_b, alpha[n] = w rounded to fp32; sources have a = b = n,
- * w = 0. rank[n] is the topological level (Sec. "Reconstruction"), step[n]
- * the step it runs in; step_ptr (depth + 2 entries) delimits the nodes of each
- * step: step s holds IDs [step_ptr[s], step_ptr[s+1]), step 0 the sources. */
+ * weight of child_b (n = (1 - w) a + w b), alpha[n] = w rounded to fp32;
+ * sources have a = b = n, w = 0. rank[n] is the topological level (Sec.
+ * "Reconstruction"); node IDs are sorted by rank, and rank_ptr (depth + 2
+ * entries) delimits them: rank r holds IDs [rank_ptr[r], rank_ptr[r+1]).
+ * step[n] is the step the deferred schedule runs n in (Sec.
+ * "Reconstruction"); sched (n_nodes entries) lists the IDs in execution order
+ * and step_ptr (depth + 2 entries) delimits each step in it, step 0 holding
+ * the sources. */
 int mg_export_dag(const mg_graph *g, uint32_t *child_a, uint32_t *child_b, float *alpha,
-                  uint64_t *wnum, uint64_t *wden, uint32_t *rank, uint32_t *step,
-                  uint32_t *step_ptr);
+                  uint64_t *wnum, uint64_t *wden, uint32_t *rank, uint32_t *rank_ptr,
+                  uint32_t *step, uint32_t *sched, uint32_t *step_ptr);
 
 /* Host copy of level `level`'s node IDs, x fastest, dims[level] voxels. */
 int mg_export_map(const mg_graph *g, uint32_t level, uint32_t *out);

@@ -63,7 +63,7 @@ def load() -> ctypes.CDLL:
     sig = {
         "mg_build": ([vp, ctypes.POINTER(BuildOpts), ctypes.POINTER(G)], i32),
         "mg_info": ([G, ctypes.POINTER(Info)], i32),
-        "mg_export_dag": ([G, vp, vp, vp, vp, vp, vp, vp, vp], i32),
+        "mg_export_dag": ([G, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp], i32),
         "mg_export_map": ([G, u32, vp], i32),
         "mg_segment_ids": ([G, vp], i32),
         "mg_upload": ([G, i32], i32),

@@ -28,7 +28,7 @@ int done(int code, const std::string &msg)
 }
 
 // ---- save / load: "MGRAPH01" + header + arrays, each followed by FNV-1a 64
-constexpr char kMagic[8] = {'M', 'G', 'R', 'A', 'P', 'H', '0', '1'};
+constexpr char kMagic[8] = {'M', 'G', 'R', 'A', 'P', 'H', '0', '2'};
 
 uint64_t fnv(const void *p, size_t n, uint64_t h = 0xcbf29ce484222325ULL)
 {
@@ -83,8 +83,8 @@ int mg_build(const uint32_t *ids, const mg_build_opts *opts, mg_graph **out)
     *out = nullptr;
     if (opts->nx == 0 || opts->ny == 0 || opts->nz == 0) return fail(MG_EINVAL, "mg_build: zero dimension");
     const uint64_t nvox = uint64_t(opts->nx) * opts->ny * opts->nz;
-    if (nvox >= (1ull << 32))
-        return fail(MG_ELIMIT, "mg_build: volumes of 2^32 voxels or more are not supported (32-bit counters)");
+    if (nvox >= (1ull << 31))
+        return fail(MG_ELIMIT, "mg_build: volumes of 2^31 voxels or more are not supported (31-bit offsets)");
     for (uint32_t r : opts->reserved)
         if (r) return fail(MG_EINVAL, "mg_build: reserved fields must be 0");
     if (opts->defer > 1) return fail(MG_EINVAL, "mg_build: defer must be 0 or 1");
@@ -126,7 +126,8 @@ int mg_info(const mg_graph *h, mg_info_t *out)
 }
 
 int mg_export_dag(const mg_graph *h, uint32_t *child_a, uint32_t *child_b, float *alpha, uint64_t *wnum,
-                  uint64_t *wden, uint32_t *rank, uint32_t *step, uint32_t *step_ptr)
+                  uint64_t *wden, uint32_t *rank, uint32_t *rank_ptr, uint32_t *step, uint32_t *sched,
+                  uint32_t *step_ptr)
 {
     if (!h) return fail(MG_EINVAL, "mg_export_dag: null graph");
     const mg::Graph &g = h->g;
@@ -138,6 +139,8 @@ int mg_export_dag(const mg_graph *h, uint32_t *child_a, uint32_t *child_b, float
     if (wden) std::memcpy(wden, g.wden.data(), n * 8);
     if (rank) std::memcpy(rank, g.rank.data(), n * 4);
     if (step) std::memcpy(step, g.step.data(), n * 4);
+    if (rank_ptr) std::memcpy(rank_ptr, g.rank_ptr.data(), g.rank_ptr.size() * 4);
+    if (sched) std::memcpy(sched, g.sched.data(), n * 4);
     if (step_ptr) std::memcpy(step_ptr, g.step_ptr.data(), g.step_ptr.size() * 4);
     return MG_OK;
 }
@@ -260,7 +263,8 @@ int mg_save(const mg_graph *h, const char *path)
     uint32_t hdr[8] = {g.dims[0], g.dims[1], g.dims[2], g.nseg, g.n_nodes, g.depth, g.n_levels, g.max_mixture};
     bool ok = wr(f, kMagic, 8) && wr(f, hdr, sizeof(hdr)) && wr_vec(f, g.seg_ids) && wr_vec(f, g.child_a) &&
               wr_vec(f, g.child_b) && wr_vec(f, g.alpha) && wr_vec(f, g.wnum) && wr_vec(f, g.wden) &&
-              wr_vec(f, g.rank) && wr_vec(f, g.step) && wr_vec(f, g.step_ptr) && wr_vec(f, g.lev_off) &&
+              wr_vec(f, g.rank) && wr_vec(f, g.step) && wr_vec(f, g.rank_ptr) && wr_vec(f, g.sched) &&
+              wr_vec(f, g.step_ptr) && wr_vec(f, g.lev_off) &&
               wr_vec(f, g.maps);
     ok = (std::fclose(f) == 0) && ok;
     return ok ? MG_OK : fail(MG_EIO, std::string("mg_save: write failed for ") + path);
@@ -288,7 +292,7 @@ int mg_load(const char *path, mg_graph **out)
         g.nseg = hdr[3], g.n_nodes = hdr[4], g.depth = hdr[5], g.n_levels = hdr[6], g.max_mixture = hdr[7];
         const uint64_t nvox = uint64_t(g.dims[0]) * g.dims[1] * g.dims[2];
         const uint64_t N = g.n_nodes, lim_maps = 2 * nvox + 64;
-        if (g.dims[0] == 0 || g.dims[1] == 0 || g.dims[2] == 0 || nvox >= (1ull << 32) ||
+        if (g.dims[0] == 0 || g.dims[1] == 0 || g.dims[2] == 0 || nvox >= (1ull << 31) ||
             g.n_levels > MG_MAX_LEVELS)
             rc = MG_EFORMAT;
         if (rc == MG_OK) rc = rd_vec(f, &g.seg_ids, N);
@@ -299,6 +303,8 @@ int mg_load(const char *path, mg_graph **out)
         if (rc == MG_OK) rc = rd_vec(f, &g.wden, N);
         if (rc == MG_OK) rc = rd_vec(f, &g.rank, N);
         if (rc == MG_OK) rc = rd_vec(f, &g.step, N);
+        if (rc == MG_OK) rc = rd_vec(f, &g.rank_ptr, uint64_t(g.depth) + 2);
+        if (rc == MG_OK) rc = rd_vec(f, &g.sched, N);
         if (rc == MG_OK) rc = rd_vec(f, &g.step_ptr, uint64_t(g.depth) + 2);
         if (rc == MG_OK) rc = rd_vec(f, &g.lev_off, uint64_t(MG_MAX_LEVELS) + 1);
         if (rc == MG_OK) rc = rd_vec(f, &g.maps, lim_maps);

@@ -513,17 +513,18 @@ int build_graph(const uint32_t *ids, const mg_build_opts *o, Graph *g, std::stri
         for (uint32_t n = g->nseg; n < N; ++n) step[n] = rank[n];
     }
 
-    // ---- renumber by (step, creation order); sources keep 0 .. S-1
+    // ---- renumber by (rank, creation order); sources keep 0 .. S-1. Nodes whose
+    // predecessors are both sources (rank 1) are then one contiguous ID range.
     std::vector<uint32_t> cnt(depth + 2, 0);
-    for (uint32_t n = g->nseg; n < N; ++n) cnt[step[n]]++;
-    g->step_ptr.assign(depth + 2, 0);
-    g->step_ptr[0] = 0;
-    g->step_ptr[1] = g->nseg;
-    for (uint32_t s = 1; s <= depth; ++s) g->step_ptr[s + 1] = g->step_ptr[s] + cnt[s];
-    std::vector<uint32_t> pos(g->step_ptr.begin(), g->step_ptr.end());
+    for (uint32_t n = g->nseg; n < N; ++n) cnt[rank[n]]++;
+    g->rank_ptr.assign(depth + 2, 0);
+    g->rank_ptr[0] = 0;
+    g->rank_ptr[1] = g->nseg;
+    for (uint32_t r = 1; r <= depth; ++r) g->rank_ptr[r + 1] = g->rank_ptr[r] + cnt[r];
+    std::vector<uint32_t> pos(g->rank_ptr.begin(), g->rank_ptr.end());
     std::vector<uint32_t> perm(N);
     for (uint32_t n = 0; n < g->nseg; ++n) perm[n] = n;
-    for (uint32_t n = g->nseg; n < N; ++n) perm[n] = pos[step[n]]++;
+    for (uint32_t n = g->nseg; n < N; ++n) perm[n] = pos[rank[n]]++;
 
     g->n_nodes = N;
     g->depth = depth;
@@ -545,6 +546,16 @@ int build_graph(const uint32_t *ids, const mg_build_opts *o, Graph *g, std::stri
         g->rank[p] = rank[n];
         g->step[p] = step[n];
     }
+    // ---- execution order of the step schedule: sources, then step 1, 2, ...
+    std::vector<uint32_t> scnt(depth + 2, 0);
+    for (uint32_t n = g->nseg; n < N; ++n) scnt[g->step[n]]++;
+    g->step_ptr.assign(depth + 2, 0);
+    g->step_ptr[1] = g->nseg;
+    for (uint32_t s = 1; s <= depth; ++s) g->step_ptr[s + 1] = g->step_ptr[s] + scnt[s];
+    std::vector<uint32_t> spos(g->step_ptr.begin(), g->step_ptr.end());
+    g->sched.assign(N, 0);
+    for (uint32_t n = 0; n < g->nseg; ++n) g->sched[n] = n;
+    for (uint32_t n = g->nseg; n < N; ++n) g->sched[spos[g->step[n]]++] = n;
     const uint64_t total = g->maps.size();
     uint32_t *mp = g->maps.data();
     const uint64_t first_internal = g->lev_off[1];
@@ -563,34 +574,41 @@ int validate_graph(const Graph &g, std::string *err)
         *err = "graph arrays have inconsistent sizes";
         return MG_EFORMAT;
     }
-    if (g.step_ptr[0] != 0 || g.step_ptr[1] != S || g.step_ptr[g.depth + 1] != N) {
-        *err = "step_ptr does not delimit the nodes";
+    if (g.rank_ptr.size() != size_t(g.depth) + 2 || g.sched.size() != N) {
+        *err = "rank_ptr / sched have inconsistent sizes";
         return MG_EFORMAT;
     }
-    for (uint32_t s = 0; s <= g.depth; ++s)
-        if (g.step_ptr[s] > g.step_ptr[s + 1]) {
-            *err = "step_ptr is not monotone";
+    for (const std::vector<uint32_t> *ptr : {&g.step_ptr, &g.rank_ptr}) {
+        const std::vector<uint32_t> &p = *ptr;
+        if (p[0] != 0 || p[1] != S || p[g.depth + 1] != N) {
+            *err = "step_ptr / rank_ptr do not delimit the nodes";
             return MG_EFORMAT;
         }
+        for (uint32_t s = 0; s <= g.depth; ++s)
+            if (p[s] > p[s + 1]) {
+                *err = "step_ptr / rank_ptr are not monotone";
+                return MG_EFORMAT;
+            }
+    }
     for (uint32_t s = 1; s < S; ++s)
         if (g.seg_ids[s] <= g.seg_ids[s - 1]) {
             *err = "segment IDs are not increasing";
             return MG_EFORMAT;
         }
-    uint32_t st = 1;
+    uint32_t rk = 1;
     for (uint32_t n = S; n < N; ++n) {
-        while (n >= g.step_ptr[st + 1]) ++st;
+        while (n >= g.rank_ptr[rk + 1]) ++rk;
         const uint32_t a = g.child_a[n], b = g.child_b[n];
         if (a >= n || b >= n || a == b) {
             *err = "node " + std::to_string(n) + " has a predecessor that is not an earlier node";
             return MG_EFORMAT;
         }
-        if (g.step[n] != st || g.step[a] >= st || g.step[b] >= st) {
-            *err = "node " + std::to_string(n) + " runs before one of its predecessors";
+        if (g.rank[n] != rk || g.rank[n] != std::max(g.rank[a], g.rank[b]) + 1) {
+            *err = "node " + std::to_string(n) + " has an inconsistent topological level";
             return MG_EFORMAT;
         }
-        if (g.rank[n] != std::max(g.rank[a], g.rank[b]) + 1 || g.rank[n] > st) {
-            *err = "node " + std::to_string(n) + " has an inconsistent topological level";
+        if (g.step[n] < g.rank[n] || g.step[n] > g.depth || g.step[a] >= g.step[n] || g.step[b] >= g.step[n]) {
+            *err = "node " + std::to_string(n) + " runs before one of its predecessors";
             return MG_EFORMAT;
         }
         if (g.wnum[n] == 0 || 2 * g.wnum[n] > g.wden[n]) {
@@ -601,6 +619,18 @@ int validate_graph(const Graph &g, std::string *err)
             *err = "node " + std::to_string(n) + " has an fp32 weight that does not match its ratio";
             return MG_EFORMAT;
         }
+    }
+    {
+        std::vector<uint8_t> seen(N, 0);
+        for (uint32_t st = 0; st <= g.depth; ++st)
+            for (uint32_t i = g.step_ptr[st]; i < g.step_ptr[st + 1]; ++i) {
+                const uint32_t n = g.sched[i];
+                if (n >= N || seen[n] || (st == 0 ? n >= S : (n < S || g.step[n] != st))) {
+                    *err = "sched is not the step order of the nodes";
+                    return MG_EFORMAT;
+                }
+                seen[n] = 1;
+            }
     }
     std::vector<uint32_t> ld;
     level_dims(g.dims, &ld);

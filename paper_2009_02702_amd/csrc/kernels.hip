@@ -40,9 +40,9 @@ constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kMaxLevelsDev = 16;          // dims up to 32768 per axis
 constexpr int kMaxSlabs = 6 * kMaxLevelsDev;
 constexpr uint32_t kHashLds = 2048;           // per-query hash slots in LDS
-constexpr uint32_t kHashGlobal = 1u << 18;    // per-worker hash slots in the fallback tables
+constexpr uint32_t kHashGlobal = 1u << 16;    // per-worker hash slots in the fallback tables
 constexpr uint32_t kSegLdsMax = 2048;         // sources kept in LDS
-constexpr uint32_t kFallbackWorkers = 64;     // workers of the global-table kernel
+constexpr uint32_t kFallbackWorkers = 128;    // workers of the global-table kernel
 constexpr int kUnroll = 4;
 constexpr uint32_t kMaxSteps = 64;              // graph depth the step table holds
 
@@ -229,20 +229,30 @@ __device__ inline void build_slabs(const LevelTable &lt, const uint32_t lo[3], c
 
 // ---------------------------------------------------------------- per-query state
 
-// Table of internal nodes touched by one query, plus per-source accumulators.
-// Pointers are into LDS or into a global per-worker region; the same code
-// serves both (the compiler resolves the address space after inlining).
+// Per-query accumulators. Sources keep an exact integer count (cubes whose
+// node is a source) plus pushed fp32 mass with its compensation term. Internal
+// nodes of rank >= 2 live in an open-addressing table (key, mass, compensation);
+// rank-1 nodes (both predecessors are sources) never enter it: their mass goes
+// straight to their two sources. Pointers are into LDS or into a global
+// per-worker region; the same code serves both (the compiler resolves the
+// address space after inlining).
 struct QueryState {
     uint32_t *keys;     // [cap] node ID or kEmpty
-    uint32_t *cnt;      // [cap] integer voxel count scattered from cubes
-    float *hi, *lo;     // [cap] pushed mass and its compensation
+    float *hi, *lo;     // [cap] mass and its compensation
     uint32_t *used;     // [cap] slots in insertion order
     uint32_t *n_used;   // scalar
     uint32_t *flags;    // scalar: bit 0 = overflow
+    uint32_t *max_key;  // scalar: largest node ID inserted
     uint32_t cap;       // power of two
     uint32_t limit;     // load-factor cap on n_used
     uint32_t *seg_cnt;  // [S] exact integer counts
     float *seg_hi, *seg_lo;  // [S] pushed mass and its compensation
+};
+
+struct GraphView {
+    const NodeTriple *__restrict__ nodes;
+    uint32_t nseg;     // sources are IDs [0, nseg)
+    uint32_t r1_end;   // rank-1 nodes are IDs [nseg, r1_end)
 };
 
 // Loads of per-query state written by other threads of the block: relaxed
@@ -270,13 +280,14 @@ __device__ inline uint32_t table_slot(const QueryState &st, uint32_t key)
     const uint32_t mask = st.cap - 1;
     uint32_t slot = hash_node(key) & mask;
     for (uint32_t probe = 0; probe < st.cap; ++probe) {
-        uint32_t k = ld(&st.keys[slot]);
+        const uint32_t k = ld(&st.keys[slot]);
         if (k == key) return slot;
         if (k == kEmpty) {
             const uint32_t old = atomicCAS(&st.keys[slot], kEmpty, key);
             if (old == kEmpty) {
                 const uint32_t idx = atomicAdd(st.n_used, 1u);
                 st.used[idx] = slot;
+                atomicMax(st.max_key, key);
                 if (idx >= st.limit) atomicOr(st.flags, 1u);
                 return slot;
             }
@@ -286,16 +297,6 @@ __device__ inline uint32_t table_slot(const QueryState &st, uint32_t key)
     }
     atomicOr(st.flags, 1u);
     return kEmpty;
-}
-
-__device__ inline void add_count(const QueryState &st, uint32_t nseg, uint32_t node, uint32_t c)
-{
-    if (node < nseg) {
-        atomicAdd(&st.seg_cnt[node], c);
-    } else {
-        const uint32_t slot = table_slot(st, node);
-        if (slot != kEmpty) atomicAdd(&st.cnt[slot], c);
-    }
 }
 
 // Compensated accumulation: the atomic returns the value it added to, so the
@@ -310,87 +311,146 @@ __device__ inline void add_mass_at(float *hi, float *lo, float h, float l)
     atomicAdd(lo, e + l);
 }
 
-__device__ inline void add_mass(const QueryState &st, uint32_t nseg, uint32_t node, float h, float l)
+// w * (h + l) as an unevaluated pair: exact product error via fma, plus w * l.
+__device__ inline void scale_pair(float w, float h, float l, float *oh, float *ol)
 {
-    if (node < nseg) {
+    const float p = w * h;
+    *oh = p;
+    *ol = fmaf(w, h, -p) + w * l;
+}
+
+// Mass (h, l) on a rank-1 node with predecessors (a, b), both sources.
+__device__ inline void push_pair(const QueryState &st, const NodeTriple &t, float h, float l)
+{
+    float ah, al, bh, bl;
+    scale_pair(1.0f - t.w, h, l, &ah, &al);
+    scale_pair(t.w, h, l, &bh, &bl);
+    add_mass_at(&st.seg_hi[t.a], &st.seg_lo[t.a], ah, al);
+    add_mass_at(&st.seg_hi[t.b], &st.seg_lo[t.b], bh, bl);
+}
+
+// Mass pushed into `node` during the reverse push.
+__device__ inline void route_mass(const QueryState &st, const GraphView &gv, uint32_t node, float h, float l)
+{
+    if (node < gv.nseg) {
         add_mass_at(&st.seg_hi[node], &st.seg_lo[node], h, l);
+    } else if (node < gv.r1_end) {
+        push_pair(st, gv.nodes[node], h, l);
     } else {
         const uint32_t slot = table_slot(st, node);
         if (slot != kEmpty) add_mass_at(&st.hi[slot], &st.lo[slot], h, l);
     }
 }
 
-// Scatter: every cube of every slab adds 8^level to its node. Lanes holding
-// the same node are merged first (one ballot per distinct node in the wave;
-// all cubes of a slab share the level, so the sum is popcount * 8^level).
+// Integer voxel count c (< 2^32) scattered onto `node` by cubes.
+__device__ inline void scatter_count(const QueryState &st, const GraphView &gv, uint32_t node, uint32_t c)
+{
+    if (node < gv.nseg) {
+        atomicAdd(&st.seg_cnt[node], c);
+        return;
+    }
+    const float h = float(c & 0xFFFFFF00u), l = float(c & 0xFFu);  // both exact in fp32
+    if (node < gv.r1_end) {
+        push_pair(st, gv.nodes[node], h, l);
+    } else {
+        const uint32_t slot = table_slot(st, node);
+        if (slot != kEmpty) add_mass_at(&st.hi[slot], &st.lo[slot], h, l);
+    }
+}
+
+// Run-length merge of equal neighbours in a wave: lane i starts a run when its
+// value differs from lane i-1's (DPP wave shift right by one lane); the run
+// length is the distance to the next run start. Returns the run length at run
+// starts and 0 elsewhere. Values must be kEmpty exactly on a tail of lanes.
+__device__ inline uint32_t run_length(uint32_t v)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    // lane 0 has no source lane and keeps `old` (~v), so it always starts a run
+    const uint32_t prev = uint32_t(__builtin_amdgcn_update_dpp(int(~v), int(v), 0x138, 0xF, 0xF, false));
+    const bool head = v != prev;
+    const uint64_t heads = __ballot(head);
+    if (!head || v == kEmpty) return 0;
+    const uint64_t above = lane == 63 ? 0 : heads & (~uint64_t(0) << (lane + 1));
+    const uint32_t next = above ? uint32_t(__builtin_ctzll(above)) : 64u;
+    return next - lane;
+}
+
+__device__ inline uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// n / d for n < 2^31 (the sum below then stays below 2^32).
+__device__ inline uint32_t fdiv31(uint32_t n, uint32_t m, uint32_t s) { return (__umulhi(n, m) + n) >> s; }
+
+// Scatter: every cube of every slab adds 8^level to its node. Neighbouring
+// lanes usually hold the same node (mixtures are spatially coherent), so each
+// run of equal nodes in a wave adds once: run length * 8^level. Slab
+// parameters are wave-uniform (scalar registers); the kUnroll node-ID loads
+// of a lane are unconditional (the index is clamped into the slab) so they are
+// all in flight together.
 __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint32_t *__restrict__ maps,
-                                     const QueryState &st, uint32_t nseg)
+                                     const QueryState &st, const GraphView &gv, const uint32_t *flags_lds)
 {
     const uint32_t lane = threadIdx.x & 63;
     for (int si = 0; si < n_slabs; ++si) {
-        const Slab sl = slabs[si];
-        const uint32_t w8 = 1u << (3 * sl.level);
-        for (uint32_t b0 = threadIdx.x & ~63u; b0 < sl.count; b0 += kUnroll * kBlock) {
+        if (uni(*flags_lds) & 1u) return;  // overflowed: this block gives the box to the fallback
+        const Slab &sp = slabs[si];
+        const uint32_t count = uni(sp.count);
+        const uint32_t w8 = 1u << (3 * uni(sp.level));
+        const uint32_t d0 = uni(sp.e0.d), m0 = uni(sp.e0.m), s0 = uni(sp.e0.s);
+        const uint32_t d1 = uni(sp.e1.d), m1 = uni(sp.e1.m), s1s = uni(sp.e1.s);
+        const uint32_t str1 = uni(sp.s1), str2 = uni(uint32_t(sp.s2));
+        const uint64_t base = (uint64_t(uni(uint32_t(sp.base >> 32))) << 32) | uni(uint32_t(sp.base));
+        const uint32_t *__restrict__ p = maps + base;
+        const uint32_t last = count - 1;
+        uint32_t iter = 0;
+        for (uint32_t b0 = threadIdx.x & ~63u; b0 < count; b0 += kUnroll * kBlock) {
+            if ((++iter & 7u) == 0 && (uni(*flags_lds) & 1u)) return;
             uint32_t node[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const uint32_t r = b0 + lane + u * kBlock;
-                node[u] = r < sl.count ? maps[slab_addr(sl, r)] : kEmpty;
+                const uint32_t r = min(b0 + lane + u * kBlock, last);
+                const uint32_t q = fdiv31(r, m0, s0);
+                const uint32_t i0 = r - q * d0;
+                const uint32_t i2 = fdiv31(q, m1, s1s);
+                const uint32_t i1 = q - i2 * d1;
+                node[u] = p[i0 + i1 * str1 + i2 * str2];
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                uint64_t pending = __ballot(node[u] != kEmpty);
-                while (pending) {
-                    const int leader = __ffsll((unsigned long long)pending) - 1;
-                    const uint32_t key = __shfl(node[u], leader, 64);
-                    const uint64_t match = __ballot(node[u] == key) & pending;
-                    if (int(lane) == leader) add_count(st, nseg, key, uint32_t(__popcll(match)) * w8);
-                    pending &= ~match;
-                }
+                const uint32_t v = (b0 + lane + u * kBlock) < count ? node[u] : kEmpty;
+                const uint32_t len = run_length(v);
+                if (len) scatter_count(st, gv, v, len * w8);
             }
         }
     }
 }
 
-// Convert integer counts to (hi, lo) mass and push down the DAG, step by step
-// from the highest step present. All threads of the block must call.
-__device__ inline void push_mass(const QueryState &st, uint32_t nseg, const NodeTriple *__restrict__ nodes,
-                                 const uint32_t *step_ptr_lds, uint32_t depth, uint32_t *max_step_lds)
+// Reverse push through the nodes of rank >= 2 in the table, rank by rank from
+// the highest present. All threads of the block must call.
+__device__ inline void push_mass(const QueryState &st, const GraphView &gv, const uint32_t *rank_ptr_lds,
+                                 uint32_t depth)
 {
-    const uint32_t nu = *st.n_used;
-    if (nu == 0) return;  // uniform
-    uint32_t my_max = 0;
-    for (uint32_t i = threadIdx.x; i < nu; i += kBlock) {
-        const uint32_t slot = ld(&st.used[i]);
-        const uint32_t c = ld(&st.cnt[slot]);
-        st.hi[slot] = float(c & 0xFFFFFF00u);  // both parts exact in fp32
-        st.lo[slot] = float(c & 0xFFu);
-        const uint32_t key = ld(&st.keys[slot]);
-        uint32_t s = 1;
-        while (s < depth && key >= step_ptr_lds[s + 1]) ++s;
-        my_max = max(my_max, s);
-    }
-    atomicMax(max_step_lds, my_max);
-    __syncthreads();
-    const uint32_t top = *max_step_lds;
-    for (uint32_t s = top; s >= 1; --s) {
-        const uint32_t lo_id = step_ptr_lds[s], hi_id = step_ptr_lds[s + 1];
+    const uint32_t nu = ld(st.n_used);
+    if (nu == 0 || (ld(st.flags) & 1u)) return;  // uniform
+    const uint32_t top_key = ld(st.max_key);
+    uint32_t r = depth;
+    while (r > 2 && rank_ptr_lds[r] > top_key) --r;
+    for (; r >= 2; --r) {
+        const uint32_t lo_id = rank_ptr_lds[r], hi_id = rank_ptr_lds[r + 1];
         const uint32_t n_now = ld(st.n_used);
-        __syncthreads();  // every thread has read n_now before any insert of this step
+        __syncthreads();  // every thread has read n_now before any insert of this rank
         for (uint32_t i = threadIdx.x; i < n_now; i += kBlock) {
             const uint32_t slot = ld(&st.used[i]);
             const uint32_t key = ld(&st.keys[slot]);
             if (key < lo_id || key >= hi_id) continue;
             const float mh = ld(&st.hi[slot]), ml = ld(&st.lo[slot]);
-            const NodeTriple t = nodes[key];
-            const float wb = t.w, wa = 1.0f - t.w;
-            const float ah = wa * mh, al = fmaf(wa, mh, -ah) + wa * ml;
-            const float bh = wb * mh, bl = fmaf(wb, mh, -bh) + wb * ml;
-            add_mass(st, nseg, t.a, ah, al);
-            add_mass(st, nseg, t.b, bh, bl);
+            const NodeTriple t = gv.nodes[key];
+            float ah, al, bh, bl;
+            scale_pair(1.0f - t.w, mh, ml, &ah, &al);
+            scale_pair(t.w, mh, ml, &bh, &bl);
+            route_mass(st, gv, t.a, ah, al);
+            route_mass(st, gv, t.b, bh, bl);
         }
         __syncthreads();
-        if (s == 1) break;
     }
 }
 
@@ -399,9 +459,8 @@ struct QueryArgs {
     const uint32_t *boxes;
     float *out;
     const uint32_t *maps;         // maps then maps_t
-    const NodeTriple *nodes;
-    const uint32_t *step_ptr;     // [depth + 2]
-    uint32_t nseg;
+    GraphView gv;
+    const uint32_t *rank_ptr;     // [depth + 2]
     uint32_t depth;
     uint32_t n;
     const uint32_t *order;        // query order (batched) or nullptr (identity)
@@ -409,32 +468,22 @@ struct QueryArgs {
     uint32_t *overflow;           // overflowed query indices
     uint32_t *stats;              // optional [n][2]: cubes, table entries (graph nodes) touched
     // fallback global regions (per worker)
-    uint32_t *g_keys, *g_cnt, *g_used;
+    uint32_t *g_keys, *g_used;
     float *g_hi, *g_lo;
     uint32_t *g_seg_cnt;
     float *g_seg_hi, *g_seg_lo;
 };
 
-// LDS layout of the query kernels (dynamic shared memory).
-struct LdsLayout {
-    uint32_t seg_bytes, table_bytes, total;
-    __host__ __device__ static LdsLayout make(uint32_t nseg, bool seg_global, bool table_global)
-    {
-        LdsLayout L;
-        L.seg_bytes = seg_global ? 0 : nseg * 12u;
-        L.table_bytes = table_global ? 0 : kHashLds * 20u;
-        L.total = L.seg_bytes + L.table_bytes;
-        return L;
-    }
-};
+// LDS bytes of the query kernels' dynamic shared memory.
+__host__ __device__ inline uint32_t lds_bytes(uint32_t nseg) { return nseg * 12u + kHashLds * 16u; }
 
 struct QueryShared {
     Slab slabs[kMaxSlabs];
-    uint32_t step_ptr[kMaxSteps + 2];
+    uint32_t rank_ptr[kMaxSteps + 2];
     int n_slabs;
     uint32_t n_used;
     uint32_t flags;
-    uint32_t max_step;
+    uint32_t max_key;
     uint32_t q;
 };
 
@@ -447,15 +496,15 @@ __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const Quer
     if (threadIdx.x == 0) {
         sh.n_used = 0;
         sh.flags = 0;
-        sh.max_step = 1;
+        sh.max_key = 0;
         sh.n_slabs = 0;
     }
     __syncthreads();
     if (nonempty) build_slabs(A.lt, lo, hi, sh.slabs, &sh.n_slabs);
     __syncthreads();
-    scatter_slabs(sh.slabs, sh.n_slabs, A.maps, st, A.nseg);
+    scatter_slabs(sh.slabs, sh.n_slabs, A.maps, st, A.gv, &sh.flags);
     __syncthreads();
-    if (A.depth > 0) push_mass(st, A.nseg, A.nodes, sh.step_ptr, A.depth, &sh.max_step);
+    push_mass(st, A.gv, sh.rank_ptr, A.depth);
     __syncthreads();
     const bool overflow = (sh.flags & 1u) != 0;
     if (A.stats && threadIdx.x == 0 && (!overflow || !report_overflow)) {
@@ -464,10 +513,11 @@ __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const Quer
         A.stats[2 * uint64_t(q)] = cubes;
         A.stats[2 * uint64_t(q) + 1] = sh.n_used;
     }
+    const uint32_t nseg = A.gv.nseg;
     if (!overflow) {
         const double vol = nonempty ? double(hi[0] - lo[0]) * double(hi[1] - lo[1]) * double(hi[2] - lo[2]) : 0.0;
-        float *o = A.out + uint64_t(q) * A.nseg;
-        for (uint32_t s = threadIdx.x; s < A.nseg; s += kBlock) {
+        float *o = A.out + uint64_t(q) * nseg;
+        for (uint32_t s = threadIdx.x; s < nseg; s += kBlock) {
             const double c = double(ld(&st.seg_cnt[s])) + double(ld(&st.seg_hi[s])) + double(ld(&st.seg_lo[s]));
             o[s] = nonempty ? float(c / vol) : 0.0f;
         }
@@ -478,19 +528,18 @@ __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const Quer
         }
     } else {
         // even the per-worker global table overflowed: make the failure visible
-        float *o = A.out + uint64_t(q) * A.nseg;
-        for (uint32_t s = threadIdx.x; s < A.nseg; s += kBlock) o[s] = __builtin_nanf("");
+        float *o = A.out + uint64_t(q) * nseg;
+        for (uint32_t s = threadIdx.x; s < nseg; s += kBlock) o[s] = __builtin_nanf("");
     }
     // restore a clean state for the next query
     const uint32_t nu = min(sh.n_used, st.cap);
     for (uint32_t i = threadIdx.x; i < nu; i += kBlock) {
         const uint32_t slot = ld(&st.used[i]);
         st.keys[slot] = kEmpty;
-        st.cnt[slot] = 0;
         st.hi[slot] = 0.f;
         st.lo[slot] = 0.f;
     }
-    for (uint32_t s = threadIdx.x; s < A.nseg; s += kBlock) {
+    for (uint32_t s = threadIdx.x; s < nseg; s += kBlock) {
         st.seg_cnt[s] = 0;
         st.seg_hi[s] = 0.f;
         st.seg_lo[s] = 0.f;
@@ -498,29 +547,28 @@ __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const Quer
     __syncthreads();
 }
 
-__device__ inline void load_step_ptr(const QueryArgs &A, QueryShared &sh)
+__device__ inline void load_rank_ptr(const QueryArgs &A, QueryShared &sh)
 {
-    for (uint32_t i = threadIdx.x; i < A.depth + 2; i += kBlock) sh.step_ptr[i] = A.step_ptr[i];
+    for (uint32_t i = threadIdx.x; i < A.depth + 2; i += kBlock) sh.rank_ptr[i] = A.rank_ptr[i];
 }
 
 __device__ inline QueryState lds_state(char *dyn, QueryShared &sh, uint32_t nseg)
 {
     QueryState st;
-    const LdsLayout L = LdsLayout::make(nseg, false, false);
     uint32_t *seg = reinterpret_cast<uint32_t *>(dyn);
     st.seg_cnt = seg;
     st.seg_hi = reinterpret_cast<float *>(seg + nseg);
     st.seg_lo = reinterpret_cast<float *>(seg + 2 * nseg);
-    uint32_t *t = reinterpret_cast<uint32_t *>(dyn + L.seg_bytes);
+    uint32_t *t = seg + 3 * nseg;
     st.keys = t;
-    st.cnt = t + kHashLds;
-    st.hi = reinterpret_cast<float *>(t + 2 * kHashLds);
-    st.lo = reinterpret_cast<float *>(t + 3 * kHashLds);
-    st.used = t + 4 * kHashLds;
+    st.hi = reinterpret_cast<float *>(t + kHashLds);
+    st.lo = reinterpret_cast<float *>(t + 2 * kHashLds);
+    st.used = t + 3 * kHashLds;
     st.cap = kHashLds;
-    st.limit = kHashLds / 2;
+    st.limit = kHashLds / 4 * 3;
     st.n_used = &sh.n_used;
     st.flags = &sh.flags;
+    st.max_key = &sh.max_key;
     return st;
 }
 
@@ -528,7 +576,6 @@ __device__ inline void clear_lds_state(const QueryState &st, uint32_t nseg)
 {
     for (uint32_t i = threadIdx.x; i < st.cap; i += kBlock) {
         st.keys[i] = kEmpty;
-        st.cnt[i] = 0;
         st.hi[i] = 0.f;
         st.lo[i] = 0.f;
     }
@@ -544,9 +591,9 @@ __global__ __launch_bounds__(kBlock) void query_plain_kernel(QueryArgs A)
 {
     extern __shared__ __align__(16) char dyn[];
     __shared__ QueryShared sh;
-    const QueryState st = lds_state(dyn, sh, A.nseg);
-    load_step_ptr(A, sh);
-    clear_lds_state(st, A.nseg);
+    const QueryState st = lds_state(dyn, sh, A.gv.nseg);
+    load_rank_ptr(A, sh);
+    clear_lds_state(st, A.gv.nseg);
     __syncthreads();
     run_query(A, sh, st, blockIdx.x, true);
 }
@@ -556,9 +603,9 @@ __global__ __launch_bounds__(kBlock) void query_batched_kernel(QueryArgs A)
 {
     extern __shared__ __align__(16) char dyn[];
     __shared__ QueryShared sh;
-    const QueryState st = lds_state(dyn, sh, A.nseg);
-    load_step_ptr(A, sh);
-    clear_lds_state(st, A.nseg);
+    const QueryState st = lds_state(dyn, sh, A.gv.nseg);
+    load_rank_ptr(A, sh);
+    clear_lds_state(st, A.gv.nseg);
     for (;;) {
         if (threadIdx.x == 0) sh.q = atomicAdd(&A.counters[0], 1u);
         __syncthreads();
@@ -576,18 +623,18 @@ __global__ __launch_bounds__(kBlock) void query_fallback_kernel(QueryArgs A)
     QueryState st;
     const uint64_t w = blockIdx.x;
     st.keys = A.g_keys + w * kHashGlobal;
-    st.cnt = A.g_cnt + w * kHashGlobal;
     st.hi = A.g_hi + w * kHashGlobal;
     st.lo = A.g_lo + w * kHashGlobal;
     st.used = A.g_used + w * kHashGlobal;
     st.cap = kHashGlobal;
-    st.limit = kHashGlobal;
+    st.limit = kHashGlobal / 4 * 3;
     st.n_used = &sh.n_used;
     st.flags = &sh.flags;
-    st.seg_cnt = A.g_seg_cnt + w * A.nseg;
-    st.seg_hi = A.g_seg_hi + w * A.nseg;
-    st.seg_lo = A.g_seg_lo + w * A.nseg;
-    load_step_ptr(A, sh);
+    st.max_key = &sh.max_key;
+    st.seg_cnt = A.g_seg_cnt + w * A.gv.nseg;
+    st.seg_hi = A.g_seg_hi + w * A.gv.nseg;
+    st.seg_lo = A.g_seg_lo + w * A.gv.nseg;
+    load_rank_ptr(A, sh);
     __syncthreads();
     const uint32_t n_over = ld(&A.counters[1]);
     for (;;) {
@@ -629,7 +676,7 @@ __global__ void query_size_kernel(LevelTable lt, const uint32_t *boxes, uint32_t
 
 __global__ void query_order_kernel(const uint32_t *bucket_of, uint32_t n, uint32_t *bucket_count, uint32_t *order)
 {
-    // bucket_count holds, on entry, exclusive offsets prepared by the scan below
+    // bucket_count[32 + b] holds, on entry, the first position of bucket b
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
     const uint32_t pos = atomicAdd(&bucket_count[32 + bucket_of[q]], 1u);
@@ -663,7 +710,8 @@ struct NaiveArgs {
     uint32_t n;
 };
 
-// Naive range query: every level-0 voxel of the box is read and counted.
+// Naive range query: every level-0 voxel of the box is read and counted
+// (same wave-level run merging and unconditional loads as the graph path).
 __global__ __launch_bounds__(kBlock) void naive_kernel(NaiveArgs A)
 {
     extern __shared__ __align__(16) char dyn[];
@@ -676,37 +724,27 @@ __global__ __launch_bounds__(kBlock) void naive_kernel(NaiveArgs A)
     if (nonempty) {
         const uint32_t ex = hi[0] - lo[0], ey = hi[1] - lo[1], ez = hi[2] - lo[2];
         const FastDiv fx = make_fastdiv(ex), fy = make_fastdiv(ey);
-        const uint64_t X = A.lt.vol[0], XY = uint64_t(A.lt.vol[0]) * A.lt.vol[1];
-        const uint64_t base = lo[0] + X * lo[1] + XY * lo[2];
-        const uint64_t total = uint64_t(ex) * ey * ez;
+        const uint32_t X = A.lt.vol[0], XY = A.lt.vol[0] * A.lt.vol[1];
+        const uint32_t *__restrict__ p = A.map0 + (lo[0] + uint64_t(X) * lo[1] + uint64_t(XY) * lo[2]);
+        const uint32_t total = ex * ey * ez;  // < 2^31: the whole volume is
+        const uint32_t last = total - 1;
         const uint32_t lane = threadIdx.x & 63;
-        // the box is one flat range of voxels (fewer than 2^32: the volume is)
-        for (uint64_t b0 = threadIdx.x & ~63u; b0 < total; b0 += kUnroll * kBlock) {
+        for (uint32_t b0 = threadIdx.x & ~63u; b0 < total; b0 += kUnroll * kBlock) {
             uint32_t v[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const uint64_t r = b0 + lane + u * kBlock;
-                if (r < total) {
-                    const uint32_t rr = uint32_t(r);
-                    const uint32_t qy = fdiv(rr, fx);
-                    const uint32_t ix = rr - qy * ex;
-                    const uint32_t iz = fdiv(qy, fy);
-                    const uint32_t iy = qy - iz * ey;
-                    v[u] = A.map0[base + ix + X * iy + XY * iz];
-                } else {
-                    v[u] = kEmpty;
-                }
+                const uint32_t r = min(b0 + lane + u * kBlock, last);
+                const uint32_t qy = fdiv31(r, fx.m, fx.s);
+                const uint32_t ix = r - qy * ex;
+                const uint32_t iz = fdiv31(qy, fy.m, fy.s);
+                const uint32_t iy = qy - iz * ey;
+                v[u] = p[ix + X * iy + XY * iz];
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                uint64_t pending = __ballot(v[u] != kEmpty);
-                while (pending) {
-                    const int leader = __ffsll((unsigned long long)pending) - 1;
-                    const uint32_t key = __shfl(v[u], leader, 64);
-                    const uint64_t match = __ballot(v[u] == key) & pending;
-                    if (int(lane) == leader) atomicAdd(&cnt[key], uint32_t(__popcll(match)));
-                    pending &= ~match;
-                }
+                const uint32_t val = (b0 + lane + u * kBlock) < total ? v[u] : kEmpty;
+                const uint32_t len = run_length(val);
+                if (len) atomicAdd(&cnt[val], len);
             }
         }
     }
@@ -764,12 +802,12 @@ __global__ void tf_sources_kernel(const uint8_t *tf, uint32_t T, uint32_t nseg, 
     out[uint64_t(t) * n_nodes + s] = make_float4(float(c.x) * k, float(c.y) * k, float(c.z) * k, float(c.w) * k);
 }
 
-__global__ void tf_step_kernel(const NodeTriple *__restrict__ nodes, uint32_t lo_id, uint32_t hi_id, uint32_t T,
+__global__ void tf_step_kernel(const SchedNode *__restrict__ sched, uint32_t lo_i, uint32_t hi_i, uint32_t T,
                                uint32_t n_nodes, float4 *out)
 {
-    const uint32_t n = lo_id + blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= hi_id) return;
-    const NodeTriple t = nodes[n];
+    const uint32_t i = lo_i + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= hi_i) return;
+    const SchedNode t = sched[i];
     for (uint32_t k = 0; k < T; ++k) {
         float4 *o = out + uint64_t(k) * n_nodes;
         const float4 va = o[t.a], vb = o[t.b];
@@ -778,7 +816,7 @@ __global__ void tf_step_kernel(const NodeTriple *__restrict__ nodes, uint32_t lo
         r.y = fmaf(t.w, vb.y - va.y, va.y);
         r.z = fmaf(t.w, vb.z - va.z, va.z);
         r.w = fmaf(t.w, vb.w - va.w, va.w);
-        o[n] = r;
+        o[t.id] = r;
     }
 }
 
@@ -824,7 +862,7 @@ struct Workspace {
     uint32_t *bucket_of;  // [max_boxes]
     uint32_t *order;      // [max_boxes]
     uint32_t *overflow;   // [max_boxes]
-    uint32_t *g_keys, *g_cnt, *g_used;
+    uint32_t *g_keys, *g_used;
     float *g_hi, *g_lo;
     uint32_t *g_seg_cnt;
     float *g_seg_hi, *g_seg_lo;
@@ -849,7 +887,6 @@ Workspace carve(const Graph &g, char *base, uint32_t max_boxes)
     w.buckets = reinterpret_cast<uint32_t *>(take(64 * 4));
     const uint64_t hs = uint64_t(kFallbackWorkers) * kHashGlobal;
     w.g_keys = reinterpret_cast<uint32_t *>(take(hs * 4));
-    w.g_cnt = reinterpret_cast<uint32_t *>(take(hs * 4));
     w.g_used = reinterpret_cast<uint32_t *>(take(hs * 4));
     w.g_hi = reinterpret_cast<float *>(take(hs * 4));
     w.g_lo = reinterpret_cast<float *>(take(hs * 4));
@@ -928,11 +965,18 @@ int dev_upload(Graph *g, int device, std::string *err)
     DeviceState &d = g->dev;
     const uint64_t nmap = g->lev_off[g->n_levels];
     const uint64_t bytes_nodes = uint64_t(g->n_nodes) * sizeof(NodeTriple);
+    const uint64_t bytes_sched = uint64_t(g->n_nodes) * sizeof(SchedNode);
+    const uint64_t bytes_rp = g->rank_ptr.size() * 4;
     const uint64_t bytes_maps = 2 * nmap * 4;
     std::vector<NodeTriple> nodes(g->n_nodes);
     for (uint32_t n = 0; n < g->n_nodes; ++n) nodes[n] = NodeTriple{g->child_a[n], g->child_b[n], g->alpha[n]};
-    if (hipMalloc(&d.nodes, bytes_nodes) != hipSuccess || hipMalloc(&d.step_ptr, g->step_ptr.size() * 4) != hipSuccess ||
-        hipMalloc(&d.maps, bytes_maps) != hipSuccess) {
+    std::vector<SchedNode> sched(g->n_nodes);
+    for (uint32_t i = 0; i < g->n_nodes; ++i) {
+        const uint32_t n = g->sched[i];
+        sched[i] = SchedNode{g->child_a[n], g->child_b[n], g->alpha[n], n};
+    }
+    if (hipMalloc(&d.nodes, bytes_nodes) != hipSuccess || hipMalloc(&d.sched, bytes_sched) != hipSuccess ||
+        hipMalloc(&d.rank_ptr, bytes_rp) != hipSuccess || hipMalloc(&d.maps, bytes_maps) != hipSuccess) {
         (void)hipGetLastError();
         dev_free(g);
         *err = "mg_upload: device allocation failed";
@@ -940,9 +984,10 @@ int dev_upload(Graph *g, int device, std::string *err)
     }
     d.maps_t = d.maps + nmap;
     d.device = device;
-    d.bytes = bytes_nodes + g->step_ptr.size() * 4 + bytes_maps;
+    d.bytes = bytes_nodes + bytes_sched + bytes_rp + bytes_maps;
     HIP_TRY(hipMemcpy(d.nodes, nodes.data(), bytes_nodes, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(d.step_ptr, g->step_ptr.data(), g->step_ptr.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d.sched, sched.data(), bytes_sched, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d.rank_ptr, g->rank_ptr.data(), bytes_rp, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(d.maps, g->maps.data(), nmap * 4, hipMemcpyHostToDevice));
     for (uint32_t l = 0; l < g->n_levels; ++l) {
         const uint32_t X = g->lev_dims[3 * l], Y = g->lev_dims[3 * l + 1], Z = g->lev_dims[3 * l + 2];
@@ -963,7 +1008,8 @@ void dev_free(Graph *g)
     DeviceGuard guard;
     if (d.device >= 0) (void)hipSetDevice(d.device);
     if (d.nodes) (void)hipFree(d.nodes);
-    if (d.step_ptr) (void)hipFree(d.step_ptr);
+    if (d.sched) (void)hipFree(d.sched);
+    if (d.rank_ptr) (void)hipFree(d.rank_ptr);
     if (d.maps) (void)hipFree(d.maps);
     for (void *e : d.ev_start) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
     for (void *e : d.ev_stop) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
@@ -988,7 +1034,6 @@ int dev_workspace_init(Graph *g, void *work, uint64_t bytes, void *stream, std::
     hipStream_t s = static_cast<hipStream_t>(stream);
     const uint64_t hs = uint64_t(kFallbackWorkers) * kHashGlobal;
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, w.g_keys, hs, kEmpty);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, w.g_cnt, hs, 0u);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_hi), hs, 0u);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_lo), hs, 0u);
     const uint64_t ss = uint64_t(kFallbackWorkers) * g->nseg;
@@ -1053,28 +1098,29 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *wor
     A.boxes = boxes;
     A.out = out;
     A.maps = g->dev.maps;
-    A.nodes = g->dev.nodes;
-    A.step_ptr = g->dev.step_ptr;
-    A.nseg = g->nseg;
+    A.gv.nodes = g->dev.nodes;
+    A.gv.nseg = g->nseg;
+    A.gv.r1_end = g->depth >= 1 ? g->rank_ptr[2] : g->nseg;
+    A.rank_ptr = g->dev.rank_ptr;
     A.depth = g->depth;
     A.n = n;
     A.counters = w.counters;
     A.overflow = w.overflow;
     A.stats = stats;
-    A.g_keys = w.g_keys, A.g_cnt = w.g_cnt, A.g_used = w.g_used, A.g_hi = w.g_hi, A.g_lo = w.g_lo;
+    A.g_keys = w.g_keys, A.g_used = w.g_used, A.g_hi = w.g_hi, A.g_lo = w.g_lo;
     A.g_seg_cnt = w.g_seg_cnt, A.g_seg_hi = w.g_seg_hi, A.g_seg_lo = w.g_seg_lo;
-    const LdsLayout L = LdsLayout::make(g->nseg, false, false);
+    const uint32_t dyn_lds = lds_bytes(g->nseg);
 
     int lds_max = 0;
     HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, g->dev.device));
-    if (L.total + sizeof(QueryShared) > uint64_t(lds_max)) {
-        *err = "query state of " + std::to_string(L.total + sizeof(QueryShared)) + " bytes exceeds the " +
+    if (dyn_lds + sizeof(QueryShared) > uint64_t(lds_max)) {
+        *err = "query state of " + std::to_string(dyn_lds + sizeof(QueryShared)) + " bytes exceeds the " +
                std::to_string(lds_max) + " bytes of LDS per workgroup";
         return MG_ELIMIT;
     }
     const void *kern = variant == kQueryBatched ? reinterpret_cast<const void *>(query_batched_kernel)
                                                 : reinterpret_cast<const void *>(query_plain_kernel);
-    HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(L.total)));
+    HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(dyn_lds)));
     hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, w.counters, 64u);
     if (variant == kQueryBatched) {
         hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, w.buckets, 64u);
@@ -1086,18 +1132,18 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *wor
         int ncu = 256, per_cu = 1;
         HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, g->dev.device));
         HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(query_batched_kernel),
-                                                             kBlock, L.total));
+                                                             kBlock, dyn_lds));
         const uint32_t workers = std::max(1u, std::min<uint32_t>(n, uint32_t(ncu) * uint32_t(std::max(per_cu, 1))));
         rc = timing_begin(g, s, err);
         if (rc) return rc;
-        hipLaunchKernelGGL(query_batched_kernel, dim3(workers), dim3(kBlock), L.total, s, A);
+        hipLaunchKernelGGL(query_batched_kernel, dim3(workers), dim3(kBlock), dyn_lds, s, A);
         HIP_TRY(hipGetLastError());
         rc = timing_end(g, s, err);
         if (rc) return rc;
     } else {
         rc = timing_begin(g, s, err);
         if (rc) return rc;
-        hipLaunchKernelGGL(query_plain_kernel, dim3(n), dim3(kBlock), L.total, s, A);
+        hipLaunchKernelGGL(query_plain_kernel, dim3(n), dim3(kBlock), dyn_lds, s, A);
         HIP_TRY(hipGetLastError());
         rc = timing_end(g, s, err);
         if (rc) return rc;
@@ -1137,7 +1183,7 @@ int dev_propagate_tf(Graph *g, const uint8_t *tf, uint32_t T, float *out, void *
     for (uint32_t st = 1; st <= g->depth; ++st) {
         const uint32_t lo = g->step_ptr[st], hi = g->step_ptr[st + 1];
         if (hi <= lo) continue;
-        hipLaunchKernelGGL(tf_step_kernel, dim3((hi - lo + 255) / 256), dim3(256), 0, s, g->dev.nodes, lo, hi, T,
+        hipLaunchKernelGGL(tf_step_kernel, dim3((hi - lo + 255) / 256), dim3(256), 0, s, g->dev.sched, lo, hi, T,
                            g->n_nodes, o);
         HIP_TRY(hipGetLastError());
     }

@@ -19,10 +19,19 @@ struct NodeTriple {
 };
 static_assert(sizeof(NodeTriple) == 12, "NodeTriple must stay 12 bytes");
 
+// A node in step-schedule order, for the propagation kernel (16 bytes).
+struct SchedNode {
+    uint32_t a;
+    uint32_t b;
+    float w;
+    uint32_t id;
+};
+
 struct DeviceState {
     int device = -1;
     NodeTriple *nodes = nullptr;   // [n_nodes]
-    uint32_t *step_ptr = nullptr;  // [depth + 2]
+    uint32_t *rank_ptr = nullptr;  // [depth + 2]
+    SchedNode *sched = nullptr;    // [n_nodes] in step order
     uint32_t *maps = nullptr;      // all levels, x fastest
     uint32_t *maps_t = nullptr;    // all levels, y fastest then z then x
     uint64_t bytes = 0;
@@ -45,7 +54,9 @@ struct Graph {
     std::vector<uint32_t> child_a, child_b, rank, step;  // [n_nodes]
     std::vector<float> alpha;                            // [n_nodes]
     std::vector<uint64_t> wnum, wden;                    // [n_nodes]
-    std::vector<uint32_t> step_ptr;                      // [depth + 2]
+    std::vector<uint32_t> rank_ptr;                      // [depth + 2] IDs of each rank
+    std::vector<uint32_t> step_ptr;                      // [depth + 2] into sched
+    std::vector<uint32_t> sched;                         // [n_nodes] IDs in step order
     DeviceState dev;
 };
 

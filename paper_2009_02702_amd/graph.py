@@ -97,14 +97,12 @@ class Graph:
     def export_dag(self) -> dict:
         inf = self.info()
         n, d = inf["n_nodes"], inf["depth"]
-        out = {k: np.zeros(n, dtype=t) for k, t in (("child_a", np.uint32), ("child_b", np.uint32),
-                                                      ("alpha", np.float32), ("wnum", np.uint64),
-                                                      ("wden", np.uint64), ("rank", np.uint32),
-                                                      ("step", np.uint32))}
-        out["step_ptr"] = np.zeros(d + 2, dtype=np.uint32)
-        check(self._lib.mg_export_dag(self._h, *[out[k].ctypes.data_as(ctypes.c_void_p) for k in
-                                                 ("child_a", "child_b", "alpha", "wnum", "wden", "rank", "step",
-                                                  "step_ptr")]))
+        spec = (("child_a", np.uint32, n), ("child_b", np.uint32, n), ("alpha", np.float32, n),
+                ("wnum", np.uint64, n), ("wden", np.uint64, n), ("rank", np.uint32, n),
+                ("rank_ptr", np.uint32, d + 2), ("step", np.uint32, n), ("sched", np.uint32, n),
+                ("step_ptr", np.uint32, d + 2))
+        out = {k: np.zeros(m, dtype=t) for k, t, m in spec}
+        check(self._lib.mg_export_dag(self._h, *[out[k].ctypes.data_as(ctypes.c_void_p) for k, _, _ in spec]))
         return out
 
     def export_map(self, level: int) -> np.ndarray:

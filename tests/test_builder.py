@@ -57,10 +57,17 @@ def _invariants(g, d):
     first, last = dag.defer_window(S, a[S:], b[S:])
     st = d["step"].astype(np.int64)
     assert (st[internal] >= first[internal]).all() and (st[internal] <= last[internal]).all()
+    rp = d["rank_ptr"].astype(np.int64)
+    assert rp[0] == 0 and rp[1] == S and rp[-1] == N
+    for r in range(1, inf["depth"] + 1):
+        assert (d["rank"][rp[r]:rp[r + 1]] == r).all()          # IDs sorted by rank
     sp = d["step_ptr"].astype(np.int64)
+    sched = d["sched"].astype(np.int64)
     assert sp[0] == 0 and sp[1] == S and sp[-1] == N
+    assert np.array_equal(np.sort(sched), np.arange(N))
+    assert np.array_equal(sched[:S], np.arange(S))
     for s in range(1, inf["depth"] + 1):
-        assert (st[sp[s]:sp[s + 1]] == s).all()
+        assert (st[sched[sp[s]:sp[s + 1]]] == s).all()
 
 
 def _rand(shape, nseg, seed):
