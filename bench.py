@@ -58,6 +58,10 @@ def main():
     ap.add_argument("--competitor-steps", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", choices=("full", "query", "copy"), default="full",
+                    help="full: the JSON line; query: only the timed batched launches (for profilers); "
+                         "copy: one device copy of --copy-mib MiB (calibrates HBM byte counters)")
+    ap.add_argument("--copy-mib", type=int, default=1024)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -70,6 +74,15 @@ def main():
     from paper_2009_02702_amd import Graph, synth
 
     dev = torch.device("cuda:0")
+    if args.mode == "copy":
+        n_el = args.copy_mib * (1 << 20) // 4
+        src = torch.ones(n_el, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read": n_el * 4, "bytes_written": n_el * 4}), flush=True)
+        return
     w = synth.workload(args.config)
     t0 = time.perf_counter()
     vol = synth.make_volume(w)
@@ -87,6 +100,20 @@ def main():
     dboxes = torch.from_numpy(boxes.view(np.int32)).to(dev)
     out = torch.empty((n, S), dtype=torch.float32, device=dev)
     ws = g.workspace(n)
+    torch.cuda.synchronize()
+
+    if args.mode == "query":
+        for _ in range(args.warmup):
+            g.query(dboxes, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.query(dboxes, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        print(json.dumps({"mode": "query", "workload": w.name, "steps": args.steps,
+                          "ms_per_step": 1e3 * el / args.steps}), flush=True)
+        return
 
     # accounting pass: per-box cubes and graph nodes touched (not timed)
     _, stats = g.query_stats(dboxes, out=out, workspace=ws)
@@ -131,10 +158,11 @@ def main():
         print("[bench] %s: %.3f ms/step" % (v, comp[v]["ms_per_step"]), file=sys.stderr, flush=True)
 
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
-    traffic = read_traffic("query_batched_kernel", w.name, alg_bytes)
+    traffic = read_traffic("query_tier_kernel", w.name, alg_bytes)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "query_batched_kernel", "kernel_ms": kern_ms,
+                "kernel": "query_tier_kernel (big-box tier + small-box tier, timed together)",
+                "kernel_ms": kern_ms,
                 "alg_bytes_per_launch": alg_bytes,
                 "alg_bytes_formula": "sum over boxes of 24 + 4*cubes + 12*graph nodes touched + 4*S (dense output)"}
 
@@ -144,15 +172,15 @@ def main():
         from oracle import scan
         ids, vol_c = scan.compact(vol)
         threads = scan.max_threads()
-        # calibrate on a small prefix, then time a prefix sized for about --cpu-seconds
-        m0 = min(n, 200)
-        t0 = time.perf_counter()
-        scan.box_counts(vol_c, len(ids), boxes[:m0], threads=threads)
-        rate = m0 / max(time.perf_counter() - t0, 1e-6)
-        m = int(min(n, max(m0, rate * args.cpu_seconds)))
-        t0 = time.perf_counter()
-        _, ref = scan.box_counts(vol_c, len(ids), boxes[:m], threads=threads)
-        el_cpu = time.perf_counter() - t0
+        # time consecutive chunks of the box list until about --cpu-seconds have passed
+        chunk, m, el_cpu, refs = 2000, 0, 0.0, []
+        while m < n and el_cpu < args.cpu_seconds:
+            t0 = time.perf_counter()
+            _, r = scan.box_counts(vol_c, len(ids), boxes[m:m + chunk], threads=threads)
+            el_cpu += time.perf_counter() - t0
+            refs.append(r)
+            m += len(r)
+        ref = np.concatenate(refs)
         cpu = {"value": m / el_cpu, "unit": "queries/s", "cores": threads, "kind": "oracle",
                "sample": "first %d of the %d boxes (%.1f s, %d OpenMP threads)" % (m, n, el_cpu, threads)}
         got = res_main[:m].astype(np.float64)

@@ -34,12 +34,15 @@
 namespace mg {
 namespace {
 
-constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / 64;
+constexpr int kBlock = 256;                    // plain / fallback / naive workgroup size
+constexpr int kBlockBig = 512;                 // big-box tier workgroup size
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kMaxLevelsDev = 16;          // dims up to 32768 per axis
 constexpr int kMaxSlabs = 6 * kMaxLevelsDev;
-constexpr uint32_t kHashLds = 2048;           // per-query hash slots in LDS
+constexpr uint32_t kHashPlain = 2048;         // per-box hash slots in LDS, plain kernel
+constexpr uint32_t kHashSmall = 1024;         // small-box tier
+constexpr uint32_t kHashBig = 4096;           // big-box tier
+constexpr uint32_t kBigLog2 = 16;             // boxes of >= 2^16 cubes go to the big tier
 constexpr uint32_t kHashGlobal = 1u << 16;    // per-worker hash slots in the fallback tables
 constexpr uint32_t kSegLdsMax = 2048;         // sources kept in LDS
 constexpr uint32_t kFallbackWorkers = 128;    // workers of the global-table kernel
@@ -386,14 +389,19 @@ __device__ inline uint32_t fdiv31(uint32_t n, uint32_t m, uint32_t s) { return (
 // parameters are wave-uniform (scalar registers); the kUnroll node-ID loads
 // of a lane are unconditional (the index is clamped into the slab) so they are
 // all in flight together.
+template <int BLOCK>
 __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint32_t *__restrict__ maps,
                                      const QueryState &st, const GraphView &gv, const uint32_t *flags_lds)
 {
-    const uint32_t lane = threadIdx.x & 63;
+    constexpr uint32_t kWaves = BLOCK / 64;
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int si = 0; si < n_slabs; ++si) {
-        if (uni(*flags_lds) & 1u) return;  // overflowed: this block gives the box to the fallback
         const Slab &sp = slabs[si];
         const uint32_t count = uni(sp.count);
+        // a slab that one wave covers in one pass is taken by one wave only
+        const bool one_wave = count <= 64u * kUnroll;
+        if (one_wave && (uint32_t(si) % kWaves) != wave) continue;
+        if (uni(*flags_lds) & 1u) return;  // overflowed: this block gives the box to the fallback
         const uint32_t w8 = 1u << (3 * uni(sp.level));
         const uint32_t d0 = uni(sp.e0.d), m0 = uni(sp.e0.m), s0 = uni(sp.e0.s);
         const uint32_t d1 = uni(sp.e1.d), m1 = uni(sp.e1.m), s1s = uni(sp.e1.s);
@@ -401,13 +409,15 @@ __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint3
         const uint64_t base = (uint64_t(uni(uint32_t(sp.base >> 32))) << 32) | uni(uint32_t(sp.base));
         const uint32_t *__restrict__ p = maps + base;
         const uint32_t last = count - 1;
+        const uint32_t step = one_wave ? 64u : uint32_t(BLOCK);
+        const uint32_t start = one_wave ? 0u : (threadIdx.x & ~63u);
         uint32_t iter = 0;
-        for (uint32_t b0 = threadIdx.x & ~63u; b0 < count; b0 += kUnroll * kBlock) {
+        for (uint32_t b0 = start; b0 < count; b0 += kUnroll * step) {
             if ((++iter & 7u) == 0 && (uni(*flags_lds) & 1u)) return;
             uint32_t node[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const uint32_t r = min(b0 + lane + u * kBlock, last);
+                const uint32_t r = min(b0 + lane + u * step, last);
                 const uint32_t q = fdiv31(r, m0, s0);
                 const uint32_t i0 = r - q * d0;
                 const uint32_t i2 = fdiv31(q, m1, s1s);
@@ -416,7 +426,7 @@ __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint3
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const uint32_t v = (b0 + lane + u * kBlock) < count ? node[u] : kEmpty;
+                const uint32_t v = (b0 + lane + u * step) < count ? node[u] : kEmpty;
                 const uint32_t len = run_length(v);
                 if (len) scatter_count(st, gv, v, len * w8);
             }
@@ -426,6 +436,7 @@ __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint3
 
 // Reverse push through the nodes of rank >= 2 in the table, rank by rank from
 // the highest present. All threads of the block must call.
+template <int BLOCK>
 __device__ inline void push_mass(const QueryState &st, const GraphView &gv, const uint32_t *rank_ptr_lds,
                                  uint32_t depth)
 {
@@ -438,7 +449,7 @@ __device__ inline void push_mass(const QueryState &st, const GraphView &gv, cons
         const uint32_t lo_id = rank_ptr_lds[r], hi_id = rank_ptr_lds[r + 1];
         const uint32_t n_now = ld(st.n_used);
         __syncthreads();  // every thread has read n_now before any insert of this rank
-        for (uint32_t i = threadIdx.x; i < n_now; i += kBlock) {
+        for (uint32_t i = threadIdx.x; i < n_now; i += BLOCK) {
             const uint32_t slot = ld(&st.used[i]);
             const uint32_t key = ld(&st.keys[slot]);
             if (key < lo_id || key >= hi_id) continue;
@@ -464,7 +475,9 @@ struct QueryArgs {
     uint32_t depth;
     uint32_t n;
     const uint32_t *order;        // query order (batched) or nullptr (identity)
-    uint32_t *counters;           // [0] next query, [1] overflow count, [2] next fallback query
+    uint32_t *counters;           // [0] next big-tier query, [1] overflow count, [2] next fallback
+                                  // query, [3] next small-tier query, [8] number of big-tier queries
+    uint32_t table_cap;           // LDS hash slots of this launch
     uint32_t *overflow;           // overflowed query indices
     uint32_t *stats;              // optional [n][2]: cubes, table entries (graph nodes) touched
     // fallback global regions (per worker)
@@ -475,7 +488,7 @@ struct QueryArgs {
 };
 
 // LDS bytes of the query kernels' dynamic shared memory.
-__host__ __device__ inline uint32_t lds_bytes(uint32_t nseg) { return nseg * 12u + kHashLds * 16u; }
+__host__ __device__ inline uint32_t lds_bytes(uint32_t nseg, uint32_t cap) { return nseg * 12u + cap * 16u; }
 
 struct QueryShared {
     Slab slabs[kMaxSlabs];
@@ -488,6 +501,7 @@ struct QueryShared {
 };
 
 // One query, by the whole block. `st` must be clean (keys empty, values 0).
+template <int BLOCK>
 __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const QueryState &st, uint32_t q,
                                  bool report_overflow)
 {
@@ -502,9 +516,9 @@ __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const Quer
     __syncthreads();
     if (nonempty) build_slabs(A.lt, lo, hi, sh.slabs, &sh.n_slabs);
     __syncthreads();
-    scatter_slabs(sh.slabs, sh.n_slabs, A.maps, st, A.gv, &sh.flags);
+    scatter_slabs<BLOCK>(sh.slabs, sh.n_slabs, A.maps, st, A.gv, &sh.flags);
     __syncthreads();
-    push_mass(st, A.gv, sh.rank_ptr, A.depth);
+    push_mass<BLOCK>(st, A.gv, sh.rank_ptr, A.depth);
     __syncthreads();
     const bool overflow = (sh.flags & 1u) != 0;
     if (A.stats && threadIdx.x == 0 && (!overflow || !report_overflow)) {
@@ -517,7 +531,7 @@ __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const Quer
     if (!overflow) {
         const double vol = nonempty ? double(hi[0] - lo[0]) * double(hi[1] - lo[1]) * double(hi[2] - lo[2]) : 0.0;
         float *o = A.out + uint64_t(q) * nseg;
-        for (uint32_t s = threadIdx.x; s < nseg; s += kBlock) {
+        for (uint32_t s = threadIdx.x; s < nseg; s += BLOCK) {
             const double c = double(ld(&st.seg_cnt[s])) + double(ld(&st.seg_hi[s])) + double(ld(&st.seg_lo[s]));
             o[s] = nonempty ? float(c / vol) : 0.0f;
         }
@@ -529,17 +543,17 @@ __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const Quer
     } else {
         // even the per-worker global table overflowed: make the failure visible
         float *o = A.out + uint64_t(q) * nseg;
-        for (uint32_t s = threadIdx.x; s < nseg; s += kBlock) o[s] = __builtin_nanf("");
+        for (uint32_t s = threadIdx.x; s < nseg; s += BLOCK) o[s] = __builtin_nanf("");
     }
     // restore a clean state for the next query
     const uint32_t nu = min(sh.n_used, st.cap);
-    for (uint32_t i = threadIdx.x; i < nu; i += kBlock) {
+    for (uint32_t i = threadIdx.x; i < nu; i += BLOCK) {
         const uint32_t slot = ld(&st.used[i]);
         st.keys[slot] = kEmpty;
         st.hi[slot] = 0.f;
         st.lo[slot] = 0.f;
     }
-    for (uint32_t s = threadIdx.x; s < nseg; s += kBlock) {
+    for (uint32_t s = threadIdx.x; s < nseg; s += BLOCK) {
         st.seg_cnt[s] = 0;
         st.seg_hi[s] = 0.f;
         st.seg_lo[s] = 0.f;
@@ -547,12 +561,13 @@ __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const Quer
     __syncthreads();
 }
 
+template <int BLOCK>
 __device__ inline void load_rank_ptr(const QueryArgs &A, QueryShared &sh)
 {
-    for (uint32_t i = threadIdx.x; i < A.depth + 2; i += kBlock) sh.rank_ptr[i] = A.rank_ptr[i];
+    for (uint32_t i = threadIdx.x; i < A.depth + 2; i += BLOCK) sh.rank_ptr[i] = A.rank_ptr[i];
 }
 
-__device__ inline QueryState lds_state(char *dyn, QueryShared &sh, uint32_t nseg)
+__device__ inline QueryState lds_state(char *dyn, QueryShared &sh, uint32_t nseg, uint32_t cap)
 {
     QueryState st;
     uint32_t *seg = reinterpret_cast<uint32_t *>(dyn);
@@ -561,25 +576,26 @@ __device__ inline QueryState lds_state(char *dyn, QueryShared &sh, uint32_t nseg
     st.seg_lo = reinterpret_cast<float *>(seg + 2 * nseg);
     uint32_t *t = seg + 3 * nseg;
     st.keys = t;
-    st.hi = reinterpret_cast<float *>(t + kHashLds);
-    st.lo = reinterpret_cast<float *>(t + 2 * kHashLds);
-    st.used = t + 3 * kHashLds;
-    st.cap = kHashLds;
-    st.limit = kHashLds / 4 * 3;
+    st.hi = reinterpret_cast<float *>(t + cap);
+    st.lo = reinterpret_cast<float *>(t + 2 * cap);
+    st.used = t + 3 * cap;
+    st.cap = cap;
+    st.limit = cap / 4 * 3;
     st.n_used = &sh.n_used;
     st.flags = &sh.flags;
     st.max_key = &sh.max_key;
     return st;
 }
 
+template <int BLOCK>
 __device__ inline void clear_lds_state(const QueryState &st, uint32_t nseg)
 {
-    for (uint32_t i = threadIdx.x; i < st.cap; i += kBlock) {
+    for (uint32_t i = threadIdx.x; i < st.cap; i += BLOCK) {
         st.keys[i] = kEmpty;
         st.hi[i] = 0.f;
         st.lo[i] = 0.f;
     }
-    for (uint32_t s = threadIdx.x; s < nseg; s += kBlock) {
+    for (uint32_t s = threadIdx.x; s < nseg; s += BLOCK) {
         st.seg_cnt[s] = 0;
         st.seg_hi[s] = 0.f;
         st.seg_lo[s] = 0.f;
@@ -591,27 +607,31 @@ __global__ __launch_bounds__(kBlock) void query_plain_kernel(QueryArgs A)
 {
     extern __shared__ __align__(16) char dyn[];
     __shared__ QueryShared sh;
-    const QueryState st = lds_state(dyn, sh, A.gv.nseg);
-    load_rank_ptr(A, sh);
-    clear_lds_state(st, A.gv.nseg);
+    const QueryState st = lds_state(dyn, sh, A.gv.nseg, A.table_cap);
+    load_rank_ptr<kBlock>(A, sh);
+    clear_lds_state<kBlock>(st, A.gv.nseg);
     __syncthreads();
-    run_query(A, sh, st, blockIdx.x, true);
+    run_query<kBlock>(A, sh, st, blockIdx.x, true);
 }
 
-// Batched: persistent blocks take queries in the given order from a counter.
-__global__ __launch_bounds__(kBlock) void query_batched_kernel(QueryArgs A)
+// Batched tiers: persistent blocks take queries from the largest-first order.
+// BIG: positions [0, counters[8]); otherwise [counters[8], n).
+template <int BLOCK, bool BIG>
+__global__ __launch_bounds__(BLOCK) void query_tier_kernel(QueryArgs A)
 {
     extern __shared__ __align__(16) char dyn[];
     __shared__ QueryShared sh;
-    const QueryState st = lds_state(dyn, sh, A.gv.nseg);
-    load_rank_ptr(A, sh);
-    clear_lds_state(st, A.gv.nseg);
+    const QueryState st = lds_state(dyn, sh, A.gv.nseg, A.table_cap);
+    load_rank_ptr<BLOCK>(A, sh);
+    clear_lds_state<BLOCK>(st, A.gv.nseg);
+    const uint32_t split = ld(&A.counters[8]);
+    const uint32_t begin = BIG ? 0u : split, end = BIG ? split : A.n;
     for (;;) {
-        if (threadIdx.x == 0) sh.q = atomicAdd(&A.counters[0], 1u);
+        if (threadIdx.x == 0) sh.q = begin + atomicAdd(&A.counters[BIG ? 0 : 3], 1u);
         __syncthreads();
         const uint32_t k = sh.q;
-        if (k >= A.n) break;  // uniform
-        run_query(A, sh, st, A.order ? A.order[k] : k, true);
+        if (k >= end) break;  // uniform
+        run_query<BLOCK>(A, sh, st, A.order[k], true);
     }
 }
 
@@ -634,7 +654,7 @@ __global__ __launch_bounds__(kBlock) void query_fallback_kernel(QueryArgs A)
     st.seg_cnt = A.g_seg_cnt + w * A.gv.nseg;
     st.seg_hi = A.g_seg_hi + w * A.gv.nseg;
     st.seg_lo = A.g_seg_lo + w * A.gv.nseg;
-    load_rank_ptr(A, sh);
+    load_rank_ptr<kBlock>(A, sh);
     __syncthreads();
     const uint32_t n_over = ld(&A.counters[1]);
     for (;;) {
@@ -642,7 +662,7 @@ __global__ __launch_bounds__(kBlock) void query_fallback_kernel(QueryArgs A)
         __syncthreads();
         const uint32_t k = sh.q;
         if (k >= n_over) break;
-        run_query(A, sh, st, A.overflow[k], false);
+        run_query<kBlock>(A, sh, st, A.overflow[k], false);
     }
 }
 
@@ -683,11 +703,12 @@ __global__ void query_order_kernel(const uint32_t *bucket_of, uint32_t n, uint32
     order[pos] = q;
 }
 
-__global__ void bucket_scan_kernel(uint32_t *bucket_count)
+__global__ void bucket_scan_kernel(uint32_t *bucket_count, uint32_t *counters)
 {
     if (threadIdx.x == 0) {
         uint32_t acc = 0;
         for (int b = 0; b < 32; ++b) {
+            if (b == 31 - int(kBigLog2) + 1) counters[8] = acc;  // boxes of >= 2^kBigLog2 cubes come first
             bucket_count[32 + b] = acc;
             acc += bucket_count[b];
         }
@@ -1109,41 +1130,54 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *wor
     A.stats = stats;
     A.g_keys = w.g_keys, A.g_used = w.g_used, A.g_hi = w.g_hi, A.g_lo = w.g_lo;
     A.g_seg_cnt = w.g_seg_cnt, A.g_seg_hi = w.g_seg_hi, A.g_seg_lo = w.g_seg_lo;
-    const uint32_t dyn_lds = lds_bytes(g->nseg);
-
-    int lds_max = 0;
+    int lds_max = 0, ncu = 256;
     HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, g->dev.device));
-    if (dyn_lds + sizeof(QueryShared) > uint64_t(lds_max)) {
-        *err = "query state of " + std::to_string(dyn_lds + sizeof(QueryShared)) + " bytes exceeds the " +
-               std::to_string(lds_max) + " bytes of LDS per workgroup";
-        return MG_ELIMIT;
-    }
-    const void *kern = variant == kQueryBatched ? reinterpret_cast<const void *>(query_batched_kernel)
-                                                : reinterpret_cast<const void *>(query_plain_kernel);
-    HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(dyn_lds)));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, g->dev.device));
+    auto fits = [&](uint32_t cap, const void *kern, std::string *e) -> int {
+        const uint32_t dyn = lds_bytes(g->nseg, cap);
+        if (dyn + sizeof(QueryShared) > uint64_t(lds_max)) {
+            *e = "query state of " + std::to_string(dyn + sizeof(QueryShared)) + " bytes exceeds the " +
+                 std::to_string(lds_max) + " bytes of LDS per workgroup";
+            return MG_ELIMIT;
+        }
+        HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(dyn)));
+        return MG_OK;
+    };
     hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, w.counters, 64u);
     if (variant == kQueryBatched) {
+        const void *kbig = reinterpret_cast<const void *>(query_tier_kernel<kBlockBig, true>);
+        const void *ksmall = reinterpret_cast<const void *>(query_tier_kernel<kBlock, false>);
+        if ((rc = fits(kHashBig, kbig, err)) || (rc = fits(kHashSmall, ksmall, err))) return rc;
         hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, w.buckets, 64u);
         const uint32_t blocks = (n + 255) / 256;
         hipLaunchKernelGGL(query_size_kernel, dim3(blocks), dim3(256), 0, s, lt, boxes, n, w.bucket_of, w.buckets);
-        hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(64), 0, s, w.buckets);
+        hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(64), 0, s, w.buckets, w.counters);
         hipLaunchKernelGGL(query_order_kernel, dim3(blocks), dim3(256), 0, s, w.bucket_of, n, w.buckets, w.order);
         A.order = w.order;
-        int ncu = 256, per_cu = 1;
-        HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, g->dev.device));
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(query_batched_kernel),
-                                                             kBlock, dyn_lds));
-        const uint32_t workers = std::max(1u, std::min<uint32_t>(n, uint32_t(ncu) * uint32_t(std::max(per_cu, 1))));
+        int per_big = 1, per_small = 1;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_big, kbig, kBlockBig, lds_bytes(g->nseg, kHashBig)));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_small, ksmall, kBlock, lds_bytes(g->nseg, kHashSmall)));
+        const uint32_t wbig = std::max(1u, std::min<uint32_t>(n, uint32_t(ncu) * uint32_t(std::max(per_big, 1))));
+        const uint32_t wsmall = std::max(1u, std::min<uint32_t>(n, uint32_t(ncu) * uint32_t(std::max(per_small, 1))));
         rc = timing_begin(g, s, err);
         if (rc) return rc;
-        hipLaunchKernelGGL(query_batched_kernel, dim3(workers), dim3(kBlock), dyn_lds, s, A);
+        A.table_cap = kHashBig;
+        hipLaunchKernelGGL((query_tier_kernel<kBlockBig, true>), dim3(wbig), dim3(kBlockBig),
+                           lds_bytes(g->nseg, kHashBig), s, A);
+        HIP_TRY(hipGetLastError());
+        A.table_cap = kHashSmall;
+        hipLaunchKernelGGL((query_tier_kernel<kBlock, false>), dim3(wsmall), dim3(kBlock),
+                           lds_bytes(g->nseg, kHashSmall), s, A);
         HIP_TRY(hipGetLastError());
         rc = timing_end(g, s, err);
         if (rc) return rc;
     } else {
+        const void *kplain = reinterpret_cast<const void *>(query_plain_kernel);
+        if ((rc = fits(kHashPlain, kplain, err))) return rc;
+        A.table_cap = kHashPlain;
         rc = timing_begin(g, s, err);
         if (rc) return rc;
-        hipLaunchKernelGGL(query_plain_kernel, dim3(n), dim3(kBlock), dyn_lds, s, A);
+        hipLaunchKernelGGL(query_plain_kernel, dim3(n), dim3(kBlock), lds_bytes(g->nseg, kHashPlain), s, A);
         HIP_TRY(hipGetLastError());
         rc = timing_end(g, s, err);
         if (rc) return rc;
