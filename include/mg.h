@@ -167,6 +167,26 @@ int mg_footprint(mg_graph *g, const uint32_t *d_boxes, uint32_t n, uint32_t *d_l
 int mg_propagate_tf(mg_graph *g, const uint8_t *d_tf, uint32_t T, float *d_node_rgba,
                     void *stream);
 
+/* Launch configuration of the GPU kernels (per graph, after mg_upload).
+ * Defaults: 8, 8, 8, 256. */
+typedef struct {
+    uint32_t unroll_big;    /* node-ID loads in flight per lane, boxes of >= 2^16 cubes: 4, 8 or 16 */
+    uint32_t unroll_small;  /* the same for smaller boxes: 4, 8 or 16 */
+    uint32_t unroll_naive;  /* level-0 loads in flight per lane of the naive scan: 4, 8 or 16 */
+    uint32_t tf_block;      /* threads per workgroup of the propagation kernel: 64, 128, 256, 512, 1024 */
+    uint32_t reserved[4];   /* must be 0 */
+} mg_launch_cfg;
+
+int mg_get_launch(const mg_graph *g, mg_launch_cfg *out);
+int mg_set_launch(mg_graph *g, const mg_launch_cfg *cfg); /* MG_EINVAL for unsupported values */
+
+/* Autotuner: runs mg_query_boxes and mg_naive_boxes on the caller's boxes with
+ * every supported unroll choice, `reps` timed repetitions each (HIP events on
+ * `stream`), keeps the fastest configuration in the graph and returns it in
+ * *chosen. Synchronises `stream`; d_out and d_work as for mg_query_boxes. */
+int mg_autotune(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *d_out, void *d_work,
+                uint64_t work_bytes, uint32_t reps, void *stream, mg_launch_cfg *chosen);
+
 /* Persist / restore the host graph (raw arrays with a header and checksums;
  * not the paper's bit-packed stream). mg_load validates the arrays (IDs in
  * range, children before parents, weights in (0, 1/2]) and returns

@@ -39,13 +39,19 @@ class Info(ctypes.Structure):
                 ("max_mixture", ctypes.c_uint32)]
 
 
+class LaunchCfg(ctypes.Structure):
+    _fields_ = [("unroll_big", ctypes.c_uint32), ("unroll_small", ctypes.c_uint32),
+                ("unroll_naive", ctypes.c_uint32), ("tf_block", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 4)]
+
+
 _lib = None
 
 SYMBOLS = [
     "mg_build", "mg_info", "mg_export_dag", "mg_export_map", "mg_segment_ids", "mg_upload",
     "mg_workspace_bytes", "mg_workspace_init", "mg_query_boxes", "mg_query_boxes_plain", "mg_query_boxes_stats",
     "mg_naive_boxes",
-    "mg_footprint", "mg_propagate_tf", "mg_save", "mg_load", "mg_timing_enable", "mg_timing_read",
+    "mg_footprint", "mg_propagate_tf", "mg_get_launch", "mg_set_launch", "mg_autotune",
+    "mg_save", "mg_load", "mg_timing_enable", "mg_timing_read",
     "mg_last_error", "mg_free",
 ]
 
@@ -75,6 +81,9 @@ def load() -> ctypes.CDLL:
         "mg_naive_boxes": ([G, vp, u32, vp, vp, u64, vp], i32),
         "mg_footprint": ([G, vp, u32, vp, vp, u32, vp, vp], i32),
         "mg_propagate_tf": ([G, vp, u32, vp, vp], i32),
+        "mg_get_launch": ([G, ctypes.POINTER(LaunchCfg)], i32),
+        "mg_set_launch": ([G, ctypes.POINTER(LaunchCfg)], i32),
+        "mg_autotune": ([G, vp, u32, vp, vp, u64, u32, vp, ctypes.POINTER(LaunchCfg)], i32),
         "mg_save": ([G, ctypes.c_char_p], i32),
         "mg_load": ([ctypes.c_char_p, ctypes.POINTER(G)], i32),
         "mg_timing_enable": ([G, i32], i32),

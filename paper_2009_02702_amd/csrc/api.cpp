@@ -240,6 +240,30 @@ int mg_propagate_tf(mg_graph *h, const uint8_t *d_tf, uint32_t T, float *d_node_
     return done(mg::dev_propagate_tf(&h->g, d_tf, T, d_node_rgba, stream, &err), err);
 }
 
+int mg_get_launch(const mg_graph *h, mg_launch_cfg *out)
+{
+    if (!h || !out) return fail(MG_EINVAL, "mg_get_launch: null argument");
+    *out = h->g.dev.cfg;
+    return MG_OK;
+}
+
+int mg_set_launch(mg_graph *h, const mg_launch_cfg *cfg)
+{
+    if (!h || !cfg) return fail(MG_EINVAL, "mg_set_launch: null argument");
+    std::string err;
+    return done(mg::dev_set_launch(&h->g, cfg, &err), err);
+}
+
+int mg_autotune(mg_graph *h, const uint32_t *d_boxes, uint32_t n, float *d_out, void *d_work, uint64_t work_bytes,
+                uint32_t reps, void *stream, mg_launch_cfg *chosen)
+{
+    if (!h) return fail(MG_EINVAL, "mg_autotune: null graph");
+    if (n == 0 || !d_boxes || !d_out || !d_work) return fail(MG_EINVAL, "mg_autotune: needs boxes, output, workspace");
+    std::string err;
+    return done(mg::dev_autotune(&h->g, d_boxes, n, d_out, d_work, work_bytes, reps ? reps : 3, stream, chosen, &err),
+                err);
+}
+
 int mg_timing_enable(mg_graph *h, int enable)
 {
     if (!h) return fail(MG_EINVAL, "mg_timing_enable: null graph");

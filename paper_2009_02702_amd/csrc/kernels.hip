@@ -46,7 +46,7 @@ constexpr uint32_t kBigLog2 = 16;             // boxes of >= 2^16 cubes go to th
 constexpr uint32_t kHashGlobal = 1u << 16;    // per-worker hash slots in the fallback tables
 constexpr uint32_t kSegLdsMax = 2048;         // sources kept in LDS
 constexpr uint32_t kFallbackWorkers = 128;    // workers of the global-table kernel
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 4;                     // node-ID loads in flight per lane (plain, fallback)
 constexpr uint32_t kMaxSteps = 64;              // graph depth the step table holds
 
 #define HIP_TRY(expr)                                                                  \
@@ -386,10 +386,10 @@ __device__ inline uint32_t fdiv31(uint32_t n, uint32_t m, uint32_t s) { return (
 // Scatter: every cube of every slab adds 8^level to its node. Neighbouring
 // lanes usually hold the same node (mixtures are spatially coherent), so each
 // run of equal nodes in a wave adds once: run length * 8^level. Slab
-// parameters are wave-uniform (scalar registers); the kUnroll node-ID loads
+// parameters are wave-uniform (scalar registers); the UNROLL node-ID loads
 // of a lane are unconditional (the index is clamped into the slab) so they are
 // all in flight together.
-template <int BLOCK>
+template <int BLOCK, int UNROLL>
 __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint32_t *__restrict__ maps,
                                      const QueryState &st, const GraphView &gv, const uint32_t *flags_lds)
 {
@@ -399,7 +399,7 @@ __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint3
         const Slab &sp = slabs[si];
         const uint32_t count = uni(sp.count);
         // a slab that one wave covers in one pass is taken by one wave only
-        const bool one_wave = count <= 64u * kUnroll;
+        const bool one_wave = count <= 64u * UNROLL;
         if (one_wave && (uint32_t(si) % kWaves) != wave) continue;
         if (uni(*flags_lds) & 1u) return;  // overflowed: this block gives the box to the fallback
         const uint32_t w8 = 1u << (3 * uni(sp.level));
@@ -412,11 +412,11 @@ __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint3
         const uint32_t step = one_wave ? 64u : uint32_t(BLOCK);
         const uint32_t start = one_wave ? 0u : (threadIdx.x & ~63u);
         uint32_t iter = 0;
-        for (uint32_t b0 = start; b0 < count; b0 += kUnroll * step) {
+        for (uint32_t b0 = start; b0 < count; b0 += UNROLL * step) {
             if ((++iter & 7u) == 0 && (uni(*flags_lds) & 1u)) return;
-            uint32_t node[kUnroll];
+            uint32_t node[UNROLL];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
+            for (int u = 0; u < UNROLL; ++u) {
                 const uint32_t r = min(b0 + lane + u * step, last);
                 const uint32_t q = fdiv31(r, m0, s0);
                 const uint32_t i0 = r - q * d0;
@@ -425,7 +425,7 @@ __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint3
                 node[u] = p[i0 + i1 * str1 + i2 * str2];
             }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
+            for (int u = 0; u < UNROLL; ++u) {
                 const uint32_t v = (b0 + lane + u * step) < count ? node[u] : kEmpty;
                 const uint32_t len = run_length(v);
                 if (len) scatter_count(st, gv, v, len * w8);
@@ -501,7 +501,7 @@ struct QueryShared {
 };
 
 // One query, by the whole block. `st` must be clean (keys empty, values 0).
-template <int BLOCK>
+template <int BLOCK, int UNROLL>
 __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const QueryState &st, uint32_t q,
                                  bool report_overflow)
 {
@@ -516,7 +516,7 @@ __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const Quer
     __syncthreads();
     if (nonempty) build_slabs(A.lt, lo, hi, sh.slabs, &sh.n_slabs);
     __syncthreads();
-    scatter_slabs<BLOCK>(sh.slabs, sh.n_slabs, A.maps, st, A.gv, &sh.flags);
+    scatter_slabs<BLOCK, UNROLL>(sh.slabs, sh.n_slabs, A.maps, st, A.gv, &sh.flags);
     __syncthreads();
     push_mass<BLOCK>(st, A.gv, sh.rank_ptr, A.depth);
     __syncthreads();
@@ -525,7 +525,8 @@ __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const Quer
         uint32_t cubes = 0;
         for (int i = 0; i < sh.n_slabs; ++i) cubes += sh.slabs[i].count;
         A.stats[2 * uint64_t(q)] = cubes;
-        A.stats[2 * uint64_t(q) + 1] = sh.n_used;
+        // bit 31 marks a box answered by the global-table fallback
+        A.stats[2 * uint64_t(q) + 1] = sh.n_used | (report_overflow ? 0u : 0x80000000u);
     }
     const uint32_t nseg = A.gv.nseg;
     if (!overflow) {
@@ -611,12 +612,12 @@ __global__ __launch_bounds__(kBlock) void query_plain_kernel(QueryArgs A)
     load_rank_ptr<kBlock>(A, sh);
     clear_lds_state<kBlock>(st, A.gv.nseg);
     __syncthreads();
-    run_query<kBlock>(A, sh, st, blockIdx.x, true);
+    run_query<kBlock, kUnroll>(A, sh, st, blockIdx.x, true);
 }
 
 // Batched tiers: persistent blocks take queries from the largest-first order.
 // BIG: positions [0, counters[8]); otherwise [counters[8], n).
-template <int BLOCK, bool BIG>
+template <int BLOCK, bool BIG, int UNROLL>
 __global__ __launch_bounds__(BLOCK) void query_tier_kernel(QueryArgs A)
 {
     extern __shared__ __align__(16) char dyn[];
@@ -631,7 +632,7 @@ __global__ __launch_bounds__(BLOCK) void query_tier_kernel(QueryArgs A)
         __syncthreads();
         const uint32_t k = sh.q;
         if (k >= end) break;  // uniform
-        run_query<BLOCK>(A, sh, st, A.order[k], true);
+        run_query<BLOCK, UNROLL>(A, sh, st, A.order[k], true);
     }
 }
 
@@ -662,8 +663,21 @@ __global__ __launch_bounds__(kBlock) void query_fallback_kernel(QueryArgs A)
         __syncthreads();
         const uint32_t k = sh.q;
         if (k >= n_over) break;
-        run_query<kBlock>(A, sh, st, A.overflow[k], false);
+        run_query<kBlock, kUnroll>(A, sh, st, A.overflow[k], false);
     }
+}
+
+// Per-block histogram of 32 buckets, merged with one global atomic per
+// non-empty bucket (instead of one contended atomic per box). Every thread of
+// the block must call it.
+__device__ inline void block_histogram_add(uint32_t bkt, uint32_t *bucket_count)
+{
+    __shared__ uint32_t h[32];
+    if (threadIdx.x < 32) h[threadIdx.x] = 0;
+    __syncthreads();
+    if (bkt < 32) atomicAdd(&h[bkt], 1u);
+    __syncthreads();
+    if (threadIdx.x < 32 && h[threadIdx.x]) atomicAdd(&bucket_count[threadIdx.x], h[threadIdx.x]);
 }
 
 // Per-query work estimate (cubes) and log2 bucket for the largest-first order.
@@ -671,10 +685,9 @@ __global__ void query_size_kernel(LevelTable lt, const uint32_t *boxes, uint32_t
                                   uint32_t *bucket_count)
 {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
     uint32_t lo[3], hi[3];
     uint64_t cubes = 0;
-    if (clip_box(boxes + 6 * uint64_t(q), lt, lo, hi)) {
+    if (q < n && clip_box(boxes + 6 * uint64_t(q), lt, lo, hi)) {
         for (uint32_t l = 0; l < lt.n_levels; ++l) {
             uint64_t outer = 1, inner = 1;
             for (int d = 0; d < 3; ++d) {
@@ -689,18 +702,25 @@ __global__ void query_size_kernel(LevelTable lt, const uint32_t *boxes, uint32_t
     }
     // 32 buckets, largest work first: bucket 0 holds >= 2^31 cubes
     const uint32_t lg = cubes ? 63 - __clzll(cubes) : 0;
-    const uint32_t bkt = 31 - min(lg, 31u);
-    bucket_of[q] = bkt;
-    atomicAdd(&bucket_count[bkt], 1u);
+    const uint32_t bkt = q < n ? 31 - min(lg, 31u) : 32u;
+    if (q < n) bucket_of[q] = bkt;
+    block_histogram_add(bkt, bucket_count);  // every thread, one call site: the barriers match
 }
 
 __global__ void query_order_kernel(const uint32_t *bucket_of, uint32_t n, uint32_t *bucket_count, uint32_t *order)
 {
-    // bucket_count[32 + b] holds, on entry, the first position of bucket b
+    // bucket_count[32 + b] holds, on entry, the first free position of bucket b;
+    // each block reserves one range per bucket and ranks its boxes inside it
+    __shared__ uint32_t h[32], base[32];
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
-    const uint32_t pos = atomicAdd(&bucket_count[32 + bucket_of[q]], 1u);
-    order[pos] = q;
+    if (threadIdx.x < 32) h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t bkt = q < n ? bucket_of[q] : 32u;
+    const uint32_t local = bkt < 32 ? atomicAdd(&h[bkt], 1u) : 0u;
+    __syncthreads();
+    if (threadIdx.x < 32 && h[threadIdx.x]) base[threadIdx.x] = atomicAdd(&bucket_count[32 + threadIdx.x], h[threadIdx.x]);
+    __syncthreads();
+    if (bkt < 32) order[base[bkt] + local] = q;
 }
 
 __global__ void bucket_scan_kernel(uint32_t *bucket_count, uint32_t *counters)
@@ -733,6 +753,7 @@ struct NaiveArgs {
 
 // Naive range query: every level-0 voxel of the box is read and counted
 // (same wave-level run merging and unconditional loads as the graph path).
+template <int UNROLL>
 __global__ __launch_bounds__(kBlock) void naive_kernel(NaiveArgs A)
 {
     extern __shared__ __align__(16) char dyn[];
@@ -750,10 +771,10 @@ __global__ __launch_bounds__(kBlock) void naive_kernel(NaiveArgs A)
         const uint32_t total = ex * ey * ez;  // < 2^31: the whole volume is
         const uint32_t last = total - 1;
         const uint32_t lane = threadIdx.x & 63;
-        for (uint32_t b0 = threadIdx.x & ~63u; b0 < total; b0 += kUnroll * kBlock) {
-            uint32_t v[kUnroll];
+        for (uint32_t b0 = threadIdx.x & ~63u; b0 < total; b0 += UNROLL * kBlock) {
+            uint32_t v[UNROLL];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
+            for (int u = 0; u < UNROLL; ++u) {
                 const uint32_t r = min(b0 + lane + u * kBlock, last);
                 const uint32_t qy = fdiv31(r, fx.m, fx.s);
                 const uint32_t ix = r - qy * ex;
@@ -762,7 +783,7 @@ __global__ __launch_bounds__(kBlock) void naive_kernel(NaiveArgs A)
                 v[u] = p[ix + X * iy + XY * iz];
             }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
+            for (int u = 0; u < UNROLL; ++u) {
                 const uint32_t val = (b0 + lane + u * kBlock) < total ? v[u] : kEmpty;
                 const uint32_t len = run_length(val);
                 if (len) atomicAdd(&cnt[val], len);
@@ -968,6 +989,52 @@ int timing_end(Graph *g, hipStream_t s, std::string *err)
     return MG_OK;
 }
 
+using QueryKernel = void (*)(QueryArgs);
+using NaiveKernel = void (*)(NaiveArgs);
+
+template <int BLOCK, bool BIG>
+QueryKernel tier_kernel(uint32_t unroll)
+{
+    switch (unroll) {
+    case 4: return query_tier_kernel<BLOCK, BIG, 4>;
+    case 8: return query_tier_kernel<BLOCK, BIG, 8>;
+    default: return query_tier_kernel<BLOCK, BIG, 16>;
+    }
+}
+
+NaiveKernel naive_variant(uint32_t unroll)
+{
+    switch (unroll) {
+    case 4: return naive_kernel<4>;
+    case 8: return naive_kernel<8>;
+    default: return naive_kernel<16>;
+    }
+}
+
+bool valid_unroll(uint32_t u) { return u == 4 || u == 8 || u == 16; }
+
+// Blocks per CU of a kernel variant (queried once, cached per device); also
+// raises the kernel's dynamic LDS limit.
+int occupancy(DeviceState &d, const void *k, int block, uint32_t dyn, int *out, std::string *err)
+{
+    for (const auto &e : d.occupancy)
+        if (e.first == k) {
+            *out = e.second;
+            return MG_OK;
+        }
+    if (dyn + sizeof(QueryShared) > uint64_t(d.lds_max)) {
+        *err = "kernel state of " + std::to_string(dyn + sizeof(QueryShared)) + " bytes exceeds the " +
+               std::to_string(d.lds_max) + " bytes of LDS per workgroup";
+        return MG_ELIMIT;
+    }
+    HIP_TRY(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(dyn)));
+    int occ = 1;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, block, dyn));
+    d.occupancy.emplace_back(k, std::max(occ, 1));
+    *out = std::max(occ, 1);
+    return MG_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- entry points
@@ -1089,6 +1156,11 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *wor
     }
     Workspace w = carve(*g, static_cast<char *>(work), n);
     const LevelTable lt = level_table(*g);
+    if (!g->dev.launch_ready) {
+        HIP_TRY(hipDeviceGetAttribute(&g->dev.lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, g->dev.device));
+        HIP_TRY(hipDeviceGetAttribute(&g->dev.ncu, hipDeviceAttributeMultiprocessorCount, g->dev.device));
+        g->dev.launch_ready = true;
+    }
 
     if (variant == kQueryNaive) {
         if (g->nseg > 16384) {
@@ -1104,7 +1176,7 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *wor
         A.n = n;
         rc = timing_begin(g, s, err);
         if (rc) return rc;
-        hipLaunchKernelGGL(naive_kernel, dim3(n), dim3(kBlock), g->nseg * 4, s, A);
+        hipLaunchKernelGGL(naive_variant(g->dev.cfg.unroll_naive), dim3(n), dim3(kBlock), g->nseg * 4, s, A);
         HIP_TRY(hipGetLastError());
         return timing_end(g, s, err);
     }
@@ -1130,54 +1202,41 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *wor
     A.stats = stats;
     A.g_keys = w.g_keys, A.g_used = w.g_used, A.g_hi = w.g_hi, A.g_lo = w.g_lo;
     A.g_seg_cnt = w.g_seg_cnt, A.g_seg_hi = w.g_seg_hi, A.g_seg_lo = w.g_seg_lo;
-    int lds_max = 0, ncu = 256;
-    HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, g->dev.device));
-    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, g->dev.device));
-    auto fits = [&](uint32_t cap, const void *kern, std::string *e) -> int {
-        const uint32_t dyn = lds_bytes(g->nseg, cap);
-        if (dyn + sizeof(QueryShared) > uint64_t(lds_max)) {
-            *e = "query state of " + std::to_string(dyn + sizeof(QueryShared)) + " bytes exceeds the " +
-                 std::to_string(lds_max) + " bytes of LDS per workgroup";
-            return MG_ELIMIT;
-        }
-        HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(dyn)));
-        return MG_OK;
-    };
+    DeviceState &d = g->dev;
+    const QueryKernel kbig = tier_kernel<kBlockBig, true>(d.cfg.unroll_big);
+    const QueryKernel ksmall = tier_kernel<kBlock, false>(d.cfg.unroll_small);
+    const uint32_t dyn_big = lds_bytes(g->nseg, kHashBig), dyn_small = lds_bytes(g->nseg, kHashSmall),
+                   dyn_plain = lds_bytes(g->nseg, kHashPlain);
+    int occ_big = 1, occ_small = 1, occ_plain = 1;
+    if ((rc = occupancy(d, reinterpret_cast<const void *>(kbig), kBlockBig, dyn_big, &occ_big, err)) ||
+        (rc = occupancy(d, reinterpret_cast<const void *>(ksmall), kBlock, dyn_small, &occ_small, err)) ||
+        (rc = occupancy(d, reinterpret_cast<const void *>(query_plain_kernel), kBlock, dyn_plain, &occ_plain, err)))
+        return rc;
     hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, w.counters, 64u);
     if (variant == kQueryBatched) {
-        const void *kbig = reinterpret_cast<const void *>(query_tier_kernel<kBlockBig, true>);
-        const void *ksmall = reinterpret_cast<const void *>(query_tier_kernel<kBlock, false>);
-        if ((rc = fits(kHashBig, kbig, err)) || (rc = fits(kHashSmall, ksmall, err))) return rc;
         hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, w.buckets, 64u);
         const uint32_t blocks = (n + 255) / 256;
         hipLaunchKernelGGL(query_size_kernel, dim3(blocks), dim3(256), 0, s, lt, boxes, n, w.bucket_of, w.buckets);
         hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(64), 0, s, w.buckets, w.counters);
         hipLaunchKernelGGL(query_order_kernel, dim3(blocks), dim3(256), 0, s, w.bucket_of, n, w.buckets, w.order);
         A.order = w.order;
-        int per_big = 1, per_small = 1;
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_big, kbig, kBlockBig, lds_bytes(g->nseg, kHashBig)));
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_small, ksmall, kBlock, lds_bytes(g->nseg, kHashSmall)));
-        const uint32_t wbig = std::max(1u, std::min<uint32_t>(n, uint32_t(ncu) * uint32_t(std::max(per_big, 1))));
-        const uint32_t wsmall = std::max(1u, std::min<uint32_t>(n, uint32_t(ncu) * uint32_t(std::max(per_small, 1))));
+        const uint32_t wbig = std::max(1u, std::min<uint32_t>(n, uint32_t(d.ncu) * uint32_t(occ_big)));
+        const uint32_t wsmall = std::max(1u, std::min<uint32_t>(n, uint32_t(d.ncu) * uint32_t(occ_small)));
         rc = timing_begin(g, s, err);
         if (rc) return rc;
         A.table_cap = kHashBig;
-        hipLaunchKernelGGL((query_tier_kernel<kBlockBig, true>), dim3(wbig), dim3(kBlockBig),
-                           lds_bytes(g->nseg, kHashBig), s, A);
+        hipLaunchKernelGGL(kbig, dim3(wbig), dim3(kBlockBig), dyn_big, s, A);
         HIP_TRY(hipGetLastError());
         A.table_cap = kHashSmall;
-        hipLaunchKernelGGL((query_tier_kernel<kBlock, false>), dim3(wsmall), dim3(kBlock),
-                           lds_bytes(g->nseg, kHashSmall), s, A);
+        hipLaunchKernelGGL(ksmall, dim3(wsmall), dim3(kBlock), dyn_small, s, A);
         HIP_TRY(hipGetLastError());
         rc = timing_end(g, s, err);
         if (rc) return rc;
     } else {
-        const void *kplain = reinterpret_cast<const void *>(query_plain_kernel);
-        if ((rc = fits(kHashPlain, kplain, err))) return rc;
         A.table_cap = kHashPlain;
         rc = timing_begin(g, s, err);
         if (rc) return rc;
-        hipLaunchKernelGGL(query_plain_kernel, dim3(n), dim3(kBlock), lds_bytes(g->nseg, kHashPlain), s, A);
+        hipLaunchKernelGGL(query_plain_kernel, dim3(n), dim3(kBlock), dyn_plain, s, A);
         HIP_TRY(hipGetLastError());
         rc = timing_end(g, s, err);
         if (rc) return rc;
@@ -1217,11 +1276,85 @@ int dev_propagate_tf(Graph *g, const uint8_t *tf, uint32_t T, float *out, void *
     for (uint32_t st = 1; st <= g->depth; ++st) {
         const uint32_t lo = g->step_ptr[st], hi = g->step_ptr[st + 1];
         if (hi <= lo) continue;
-        hipLaunchKernelGGL(tf_step_kernel, dim3((hi - lo + 255) / 256), dim3(256), 0, s, g->dev.sched, lo, hi, T,
+        const uint32_t tb = g->dev.cfg.tf_block;
+        hipLaunchKernelGGL(tf_step_kernel, dim3((hi - lo + tb - 1) / tb), dim3(tb), 0, s, g->dev.sched, lo, hi, T,
                            g->n_nodes, o);
         HIP_TRY(hipGetLastError());
     }
     return timing_end(g, s, err);
+}
+
+int dev_set_launch(Graph *g, const mg_launch_cfg *cfg, std::string *err)
+{
+    for (uint32_t r : cfg->reserved)
+        if (r) {
+            *err = "mg_set_launch: reserved fields must be 0";
+            return MG_EINVAL;
+        }
+    const uint32_t tb = cfg->tf_block;
+    if (!valid_unroll(cfg->unroll_big) || !valid_unroll(cfg->unroll_small) || !valid_unroll(cfg->unroll_naive) ||
+        !(tb == 64 || tb == 128 || tb == 256 || tb == 512 || tb == 1024)) {
+        *err = "mg_set_launch: unroll must be 4, 8 or 16 and tf_block a power of two in [64, 1024]";
+        return MG_EINVAL;
+    }
+    g->dev.cfg = *cfg;
+    return MG_OK;
+}
+
+int dev_autotune(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *work, uint64_t bytes, uint32_t reps,
+                 void *stream, mg_launch_cfg *chosen, std::string *err)
+{
+    DeviceGuard guard;
+    int rc = check_device(g, err);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const mg_launch_cfg saved = g->dev.cfg;
+    const bool timing = g->dev.timing;
+    g->dev.timing = false;
+    auto time_variant = [&](int variant, float *best_ms) -> int {
+        float best = 1e30f;
+        for (uint32_t r = 0; r <= reps; ++r) {  // the first run warms up
+            HIP_TRY(hipEventRecord(e0, s));
+            int rc2 = dev_query(g, boxes, n, out, work, bytes, stream, variant, nullptr, err);
+            if (rc2) return rc2;
+            HIP_TRY(hipEventRecord(e1, s));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (r > 0) best = std::min(best, ms);
+        }
+        *best_ms = best;
+        return MG_OK;
+    };
+    const uint32_t us[3] = {4, 8, 16};
+    mg_launch_cfg best_cfg = saved;
+    float best = 1e30f;
+    for (uint32_t ub : us)
+        for (uint32_t usm : us) {
+            g->dev.cfg.unroll_big = ub;
+            g->dev.cfg.unroll_small = usm;
+            float ms = 0;
+            if ((rc = time_variant(kQueryBatched, &ms))) break;
+            if (ms < best) best = ms, best_cfg.unroll_big = ub, best_cfg.unroll_small = usm;
+        }
+    float best_naive = 1e30f;
+    for (uint32_t u : us) {
+        if (rc) break;
+        g->dev.cfg = best_cfg;
+        g->dev.cfg.unroll_naive = u;
+        float ms = 0;
+        if ((rc = time_variant(kQueryNaive, &ms))) break;
+        if (ms < best_naive) best_naive = ms, best_cfg.unroll_naive = u;
+    }
+    g->dev.timing = timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g->dev.cfg = rc ? saved : best_cfg;
+    if (!rc && chosen) *chosen = best_cfg;
+    return rc;
 }
 
 int dev_timing_enable(Graph *g, int enable, std::string *err)

@@ -35,6 +35,11 @@ struct DeviceState {
     uint32_t *maps = nullptr;      // all levels, x fastest
     uint32_t *maps_t = nullptr;    // all levels, y fastest then z then x
     uint64_t bytes = 0;
+    // launch parameters, queried once per device and graph
+    bool launch_ready = false;
+    int ncu = 0, lds_max = 0;
+    std::vector<std::pair<const void *, int>> occupancy;  // blocks per CU of each kernel variant
+    mg_launch_cfg cfg = {8, 8, 8, 256, {0, 0, 0, 0}};
     bool timing = false;
     std::vector<void *> ev_start, ev_stop;  // hipEvent_t pairs recorded around the dominant kernel
     uint32_t ev_used = 0;
@@ -78,6 +83,9 @@ int dev_footprint(Graph *g, const uint32_t *boxes, uint32_t n, uint32_t *level_c
                   uint32_t cap, uint32_t *count, void *stream, std::string *err);
 int dev_propagate_tf(Graph *g, const uint8_t *tf, uint32_t T, float *out, void *stream, std::string *err);
 int dev_timing_enable(Graph *g, int enable, std::string *err);
+int dev_set_launch(Graph *g, const mg_launch_cfg *cfg, std::string *err);
+int dev_autotune(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *work, uint64_t bytes, uint32_t reps,
+                 void *stream, mg_launch_cfg *chosen, std::string *err);
 int dev_timing_read(Graph *g, double *ms, uint32_t *launches, std::string *err);
 
 enum QueryVariant { kQueryBatched = 0, kQueryPlain = 1, kQueryNaive = 2 };

@@ -12,7 +12,7 @@ from typing import Optional
 import numpy as np
 
 from . import _lib
-from ._lib import BuildOpts, Info, check
+from ._lib import BuildOpts, Info, LaunchCfg, check
 
 VARIANTS = ("batched", "plain", "naive")
 
@@ -198,6 +198,30 @@ class Graph:
             out = torch.empty((T, inf["n_nodes"], 4), dtype=torch.float32, device=tf.device)
         check(self._lib.mg_propagate_tf(self._h, _dptr(tf), T, _dptr(out), _stream_ptr(stream)))
         return out
+
+    def launch_config(self) -> dict:
+        c = LaunchCfg()
+        check(self._lib.mg_get_launch(self._h, ctypes.byref(c)))
+        return {"unroll_big": c.unroll_big, "unroll_small": c.unroll_small, "unroll_naive": c.unroll_naive,
+                "tf_block": c.tf_block}
+
+    def set_launch_config(self, **kw) -> None:
+        cur = self.launch_config()
+        cur.update(kw)
+        c = LaunchCfg(**cur)
+        check(self._lib.mg_set_launch(self._h, ctypes.byref(c)))
+
+    def autotune(self, boxes, out=None, reps: int = 3, workspace=None, stream=None) -> dict:
+        """mg_autotune on these boxes: keeps and returns the fastest launch configuration."""
+        torch = _torch()
+        n = boxes.shape[0]
+        if out is None:
+            out = torch.empty((n, self.info()["nseg"]), dtype=torch.float32, device=boxes.device)
+        ws = workspace if workspace is not None else self.workspace(n, stream)
+        c = LaunchCfg()
+        check(self._lib.mg_autotune(self._h, _dptr(boxes), n, _dptr(out), _dptr(ws), ws.numel(), int(reps),
+                                    _stream_ptr(stream), ctypes.byref(c)))
+        return self.launch_config()
 
     def timing(self, enable: bool) -> None:
         check(self._lib.mg_timing_enable(self._h, 1 if enable else 0))

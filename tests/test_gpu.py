@@ -240,3 +240,39 @@ def test_adjoint_box_colour():
     lhs = p @ (tf[0].astype(np.float64) / 255.0)
     rhs = acc / vols[:, None]
     assert np.abs(lhs - rhs).max() < 1e-5
+
+
+# ------------------------------------------------------------------ launch configurations (autotuner)
+
+@pytest.mark.parametrize("ub,us,un", [(4, 16, 4), (16, 4, 16), (8, 8, 8)])
+def test_query_every_unroll_variant(ub, us, un):
+    w = synth.workload(2, dims=(150, 140, 130), segments=200, n_boxes=1500)
+    vol = synth.make_volume(w)
+    g = _graph(("unroll", ub, us, un), vol)
+    g.set_launch_config(unroll_big=ub, unroll_small=us, unroll_naive=un)
+    boxes = synth.make_boxes(w)
+    boxes[:5] = [0, 0, 0, 150, 140, 130]          # big-tier boxes
+    ids, vol_c = scan.compact(vol)
+    _, ref = scan.box_counts(vol_c, len(ids), boxes)
+    db = _dev(boxes)
+    for v in ("batched", "naive"):
+        _compare(g.query(db, variant=v).cpu().numpy(), ref, None, "%s u=%d/%d/%d" % (v, ub, us, un))
+
+
+def test_autotune_and_launch_validation():
+    w = synth.workload(2, dims=(64, 64, 64), segments=40, n_boxes=500)
+    vol = synth.make_volume(w)
+    g = _graph("tune", vol)
+    boxes = synth.make_boxes(w)
+    db = _dev(boxes)
+    cfg = g.autotune(db, reps=1)
+    assert cfg["unroll_big"] in (4, 8, 16) and cfg["unroll_small"] in (4, 8, 16)
+    ids, vol_c = scan.compact(vol)
+    _, ref = scan.box_counts(vol_c, len(ids), boxes)
+    _compare(g.query(db).cpu().numpy(), ref, None, "after autotune")
+    with pytest.raises(MGError) as e:
+        g.set_launch_config(unroll_big=5)
+    assert e.value.code == -1
+    with pytest.raises(MGError):
+        g.set_launch_config(tf_block=100)
+    assert g.launch_config() == cfg
