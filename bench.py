@@ -126,8 +126,9 @@ def main():
     torch.cuda.synchronize()
     st = stats.cpu().numpy().view(np.uint32)
     cubes = st[:, 0].astype(np.float64)
-    touched = (st[:, 1] & 0x7FFFFFFF).astype(np.float64)
+    touched = (st[:, 1] & 0x3FFFFFFF).astype(np.float64)
     fallback = (st[:, 1] >> 31).astype(bool)
+    retried = ((st[:, 1] >> 30) & 1).astype(bool)
     alg_bytes = float(np.sum(24.0 + 4.0 * cubes + 12.0 * touched + 4.0 * S))
 
     def run(variant, steps, warmup, timing):
@@ -218,6 +219,7 @@ def main():
                   "build_s": t_build, "volume_gen_s": t_gen, "device_bytes": inf["device_bytes"]},
         "work": {"cubes_mean": float(cubes.mean()), "nodes_touched_mean": float(touched.mean()),
                  "nodes_touched_max": int(touched.max()), "boxes_via_fallback": int(fallback.sum()),
+                 "boxes_via_retry": int(retried.sum()),
                  "cubes_share_via_fallback": float(cubes[fallback].sum() / max(cubes.sum(), 1.0)),
                  "touched_max_big_tier": int(touched[cubes >= 65536].max(initial=0)),
                  "touched_max_small_tier": int(touched[cubes < 65536].max(initial=0))},

@@ -147,6 +147,21 @@ int mg_query_boxes_plain(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float
 int mg_query_boxes_stats(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *d_out,
                          uint32_t *d_stats, void *d_work, uint64_t work_bytes, void *stream);
 
+/* Box histograms with sparse output, for many segments: the same path, with
+ * each box's non-zero segments appended to one entry buffer.
+ *   d_index  device uint32 [n][2]: first entry of the box and its number of
+ *            entries (its non-zero segments, in no particular order)
+ *   d_seg    device uint32 [capacity]: segment (source) of each entry
+ *   d_val    device fp32 [capacity]: fraction of the box's voxels
+ *   d_total  device uint32: reset by the call, then the entries produced. If
+ *            it exceeds `capacity` after the stream completes, entries at or
+ *            beyond `capacity` were not written (call again with more room).
+ * A box that no table could hold (never seen in the tested workloads) gets
+ * 0xFFFFFFFF in both index fields. */
+int mg_query_boxes_sparse(mg_graph *g, const uint32_t *d_boxes, uint32_t n, uint32_t *d_index,
+                          uint32_t *d_seg, float *d_val, uint32_t capacity, uint32_t *d_total,
+                          void *d_work, uint64_t work_bytes, void *stream);
+
 /* Competitor: the naive range query (Sec. "Results", range queries): every
  * level-0 voxel of the box is read and counted. Same output as above. */
 int mg_naive_boxes(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *d_out,
@@ -174,7 +189,12 @@ typedef struct {
     uint32_t unroll_small;  /* the same for smaller boxes: 4, 8 or 16 */
     uint32_t unroll_naive;  /* level-0 loads in flight per lane of the naive scan: 4, 8 or 16 */
     uint32_t tf_block;      /* threads per workgroup of the propagation kernel: 64, 128, 256, 512, 1024 */
-    uint32_t reserved[4];   /* must be 0 */
+    uint32_t table_big;     /* per-box LDS hash slots, big-box tier (0: 4096)                  */
+    uint32_t table_small;   /* small-box tier (0: 1024)                                         */
+    uint32_t table_retry;   /* retry of overflowed boxes (0: the largest of 8192 that fits)     */
+    uint32_t reserved;      /* must be 0. Table sizes are 0 or powers of two in [64, 8192];
+                               boxes that overflow every LDS table are answered from global
+                               memory, so smaller tables change speed, never results          */
 } mg_launch_cfg;
 
 int mg_get_launch(const mg_graph *g, mg_launch_cfg *out);

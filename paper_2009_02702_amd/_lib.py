@@ -41,7 +41,8 @@ class Info(ctypes.Structure):
 
 class LaunchCfg(ctypes.Structure):
     _fields_ = [("unroll_big", ctypes.c_uint32), ("unroll_small", ctypes.c_uint32),
-                ("unroll_naive", ctypes.c_uint32), ("tf_block", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 4)]
+                ("unroll_naive", ctypes.c_uint32), ("tf_block", ctypes.c_uint32), ("table_big", ctypes.c_uint32),
+                ("table_small", ctypes.c_uint32), ("table_retry", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 _lib = None
@@ -49,6 +50,7 @@ _lib = None
 SYMBOLS = [
     "mg_build", "mg_info", "mg_export_dag", "mg_export_map", "mg_segment_ids", "mg_upload",
     "mg_workspace_bytes", "mg_workspace_init", "mg_query_boxes", "mg_query_boxes_plain", "mg_query_boxes_stats",
+    "mg_query_boxes_sparse",
     "mg_naive_boxes",
     "mg_footprint", "mg_propagate_tf", "mg_get_launch", "mg_set_launch", "mg_autotune",
     "mg_save", "mg_load", "mg_timing_enable", "mg_timing_read",
@@ -78,6 +80,7 @@ def load() -> ctypes.CDLL:
         "mg_query_boxes": ([G, vp, u32, vp, vp, u64, vp], i32),
         "mg_query_boxes_plain": ([G, vp, u32, vp, vp, u64, vp], i32),
         "mg_query_boxes_stats": ([G, vp, u32, vp, vp, vp, u64, vp], i32),
+        "mg_query_boxes_sparse": ([G, vp, u32, vp, vp, vp, u32, vp, vp, u64, vp], i32),
         "mg_naive_boxes": ([G, vp, u32, vp, vp, u64, vp], i32),
         "mg_footprint": ([G, vp, u32, vp, vp, u32, vp, vp], i32),
         "mg_propagate_tf": ([G, vp, u32, vp, vp], i32),

@@ -190,7 +190,7 @@ static int query_common(mg_graph *h, const uint32_t *boxes, uint32_t n, float *o
     if (n == 0) return MG_OK;
     if (!boxes || !out || !work) return fail(MG_EINVAL, std::string(name) + ": null buffer");
     std::string err;
-    return done(mg::dev_query(&h->g, boxes, n, out, work, bytes, stream, variant, stats, &err), err);
+    return done(mg::dev_query(&h->g, boxes, n, out, nullptr, work, bytes, stream, variant, stats, &err), err);
 }
 
 int mg_query_boxes(mg_graph *h, const uint32_t *d_boxes, uint32_t n, float *d_out, void *d_work,
@@ -212,6 +212,21 @@ int mg_query_boxes_stats(mg_graph *h, const uint32_t *d_boxes, uint32_t n, float
     if (n && !d_stats) return fail(MG_EINVAL, "mg_query_boxes_stats: null stats buffer");
     return query_common(h, d_boxes, n, d_out, d_work, work_bytes, stream, mg::kQueryBatched,
                         "mg_query_boxes_stats", d_stats);
+}
+
+int mg_query_boxes_sparse(mg_graph *h, const uint32_t *d_boxes, uint32_t n, uint32_t *d_index, uint32_t *d_seg,
+                          float *d_val, uint32_t capacity, uint32_t *d_total, void *d_work, uint64_t work_bytes,
+                          void *stream)
+{
+    if (!h) return fail(MG_EINVAL, "mg_query_boxes_sparse: null graph");
+    if (n == 0) return MG_OK;
+    if (!d_boxes || !d_index || !d_total || !d_work || (capacity && (!d_seg || !d_val)))
+        return fail(MG_EINVAL, "mg_query_boxes_sparse: null buffer");
+    mg::SparseOut sp{d_index, d_seg, d_val, capacity, d_total};
+    std::string err;
+    return done(mg::dev_query(&h->g, d_boxes, n, nullptr, &sp, d_work, work_bytes, stream, mg::kQueryBatched, nullptr,
+                              &err),
+                err);
 }
 
 int mg_naive_boxes(mg_graph *h, const uint32_t *d_boxes, uint32_t n, float *d_out, void *d_work,

@@ -42,6 +42,7 @@ constexpr int kMaxSlabs = 6 * kMaxLevelsDev;
 constexpr uint32_t kHashPlain = 2048;         // per-box hash slots in LDS, plain kernel
 constexpr uint32_t kHashSmall = 1024;         // small-box tier
 constexpr uint32_t kHashBig = 4096;           // big-box tier
+constexpr uint32_t kHashRetry = 8192;         // boxes that overflowed a tier table
 constexpr uint32_t kBigLog2 = 16;             // boxes of >= 2^16 cubes go to the big tier
 constexpr uint32_t kHashGlobal = 1u << 16;    // per-worker hash slots in the fallback tables
 constexpr uint32_t kSegLdsMax = 2048;         // sources kept in LDS
@@ -232,15 +233,17 @@ __device__ inline void build_slabs(const LevelTable &lt, const uint32_t lo[3], c
 
 // ---------------------------------------------------------------- per-query state
 
-// Per-query accumulators. Sources keep an exact integer count (cubes whose
-// node is a source) plus pushed fp32 mass with its compensation term. Internal
-// nodes of rank >= 2 live in an open-addressing table (key, mass, compensation);
-// rank-1 nodes (both predecessors are sources) never enter it: their mass goes
-// straight to their two sources. Pointers are into LDS or into a global
-// per-worker region; the same code serves both (the compiler resolves the
-// address space after inlining).
+// Per-query accumulators. Internal nodes of rank >= 2 live in an
+// open-addressing table (key, mass, compensation); rank-1 nodes (both
+// predecessors are sources) never enter it: their mass goes straight to their
+// two sources. Sources keep an exact integer count (cubes whose node is a
+// source) plus pushed fp32 mass with its compensation term: in dense mode in
+// per-source arrays [S], in sparse mode (many sources) as entries of the same
+// table. Pointers are into LDS or into a global per-worker region; the same
+// code serves both (the compiler resolves the address space after inlining).
 struct QueryState {
     uint32_t *keys;     // [cap] node ID or kEmpty
+    uint32_t *cnt;      // [cap] exact integer counts of source entries (sparse mode)
     float *hi, *lo;     // [cap] mass and its compensation
     uint32_t *used;     // [cap] slots in insertion order
     uint32_t *n_used;   // scalar
@@ -248,8 +251,8 @@ struct QueryState {
     uint32_t *max_key;  // scalar: largest node ID inserted
     uint32_t cap;       // power of two
     uint32_t limit;     // load-factor cap on n_used
-    uint32_t *seg_cnt;  // [S] exact integer counts
-    float *seg_hi, *seg_lo;  // [S] pushed mass and its compensation
+    uint32_t *seg_cnt;  // [S] exact integer counts (dense mode)
+    float *seg_hi, *seg_lo;  // [S] pushed mass and its compensation (dense mode)
 };
 
 struct GraphView {
@@ -322,23 +325,47 @@ __device__ inline void scale_pair(float w, float h, float l, float *oh, float *o
     *ol = fmaf(w, h, -p) + w * l;
 }
 
+template <bool SPARSE>
+__device__ inline void add_source_count(const QueryState &st, uint32_t s, uint32_t c)
+{
+    if (SPARSE) {
+        const uint32_t slot = table_slot(st, s);
+        if (slot != kEmpty) atomicAdd(&st.cnt[slot], c);
+    } else {
+        atomicAdd(&st.seg_cnt[s], c);
+    }
+}
+
+template <bool SPARSE>
+__device__ inline void add_source_mass(const QueryState &st, uint32_t s, float h, float l)
+{
+    if (SPARSE) {
+        const uint32_t slot = table_slot(st, s);
+        if (slot != kEmpty) add_mass_at(&st.hi[slot], &st.lo[slot], h, l);
+    } else {
+        add_mass_at(&st.seg_hi[s], &st.seg_lo[s], h, l);
+    }
+}
+
 // Mass (h, l) on a rank-1 node with predecessors (a, b), both sources.
+template <bool SPARSE>
 __device__ inline void push_pair(const QueryState &st, const NodeTriple &t, float h, float l)
 {
     float ah, al, bh, bl;
     scale_pair(1.0f - t.w, h, l, &ah, &al);
     scale_pair(t.w, h, l, &bh, &bl);
-    add_mass_at(&st.seg_hi[t.a], &st.seg_lo[t.a], ah, al);
-    add_mass_at(&st.seg_hi[t.b], &st.seg_lo[t.b], bh, bl);
+    add_source_mass<SPARSE>(st, t.a, ah, al);
+    add_source_mass<SPARSE>(st, t.b, bh, bl);
 }
 
 // Mass pushed into `node` during the reverse push.
+template <bool SPARSE>
 __device__ inline void route_mass(const QueryState &st, const GraphView &gv, uint32_t node, float h, float l)
 {
     if (node < gv.nseg) {
-        add_mass_at(&st.seg_hi[node], &st.seg_lo[node], h, l);
+        add_source_mass<SPARSE>(st, node, h, l);
     } else if (node < gv.r1_end) {
-        push_pair(st, gv.nodes[node], h, l);
+        push_pair<SPARSE>(st, gv.nodes[node], h, l);
     } else {
         const uint32_t slot = table_slot(st, node);
         if (slot != kEmpty) add_mass_at(&st.hi[slot], &st.lo[slot], h, l);
@@ -346,15 +373,16 @@ __device__ inline void route_mass(const QueryState &st, const GraphView &gv, uin
 }
 
 // Integer voxel count c (< 2^32) scattered onto `node` by cubes.
+template <bool SPARSE>
 __device__ inline void scatter_count(const QueryState &st, const GraphView &gv, uint32_t node, uint32_t c)
 {
     if (node < gv.nseg) {
-        atomicAdd(&st.seg_cnt[node], c);
+        add_source_count<SPARSE>(st, node, c);
         return;
     }
     const float h = float(c & 0xFFFFFF00u), l = float(c & 0xFFu);  // both exact in fp32
     if (node < gv.r1_end) {
-        push_pair(st, gv.nodes[node], h, l);
+        push_pair<SPARSE>(st, gv.nodes[node], h, l);
     } else {
         const uint32_t slot = table_slot(st, node);
         if (slot != kEmpty) add_mass_at(&st.hi[slot], &st.lo[slot], h, l);
@@ -389,7 +417,7 @@ __device__ inline uint32_t fdiv31(uint32_t n, uint32_t m, uint32_t s) { return (
 // parameters are wave-uniform (scalar registers); the UNROLL node-ID loads
 // of a lane are unconditional (the index is clamped into the slab) so they are
 // all in flight together.
-template <int BLOCK, int UNROLL>
+template <int BLOCK, int UNROLL, bool SPARSE>
 __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint32_t *__restrict__ maps,
                                      const QueryState &st, const GraphView &gv, const uint32_t *flags_lds)
 {
@@ -428,7 +456,7 @@ __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint3
             for (int u = 0; u < UNROLL; ++u) {
                 const uint32_t v = (b0 + lane + u * step) < count ? node[u] : kEmpty;
                 const uint32_t len = run_length(v);
-                if (len) scatter_count(st, gv, v, len * w8);
+                if (len) scatter_count<SPARSE>(st, gv, v, len * w8);
             }
         }
     }
@@ -436,13 +464,14 @@ __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint3
 
 // Reverse push through the nodes of rank >= 2 in the table, rank by rank from
 // the highest present. All threads of the block must call.
-template <int BLOCK>
+template <int BLOCK, bool SPARSE>
 __device__ inline void push_mass(const QueryState &st, const GraphView &gv, const uint32_t *rank_ptr_lds,
                                  uint32_t depth)
 {
     const uint32_t nu = ld(st.n_used);
     if (nu == 0 || (ld(st.flags) & 1u)) return;  // uniform
     const uint32_t top_key = ld(st.max_key);
+    if (top_key < gv.r1_end) return;  // only sources in the table: nothing to push
     uint32_t r = depth;
     while (r > 2 && rank_ptr_lds[r] > top_key) --r;
     for (; r >= 2; --r) {
@@ -458,8 +487,8 @@ __device__ inline void push_mass(const QueryState &st, const GraphView &gv, cons
             float ah, al, bh, bl;
             scale_pair(1.0f - t.w, mh, ml, &ah, &al);
             scale_pair(t.w, mh, ml, &bh, &bl);
-            route_mass(st, gv, t.a, ah, al);
-            route_mass(st, gv, t.b, bh, bl);
+            route_mass<SPARSE>(st, gv, t.a, ah, al);
+            route_mass<SPARSE>(st, gv, t.b, bh, bl);
         }
         __syncthreads();
     }
@@ -468,27 +497,40 @@ __device__ inline void push_mass(const QueryState &st, const GraphView &gv, cons
 struct QueryArgs {
     LevelTable lt;
     const uint32_t *boxes;
-    float *out;
+    float *out;                   // dense output [n][S], or nullptr for sparse output
+    uint32_t *sp_index;           // sparse output: [n][2] (first entry, entries) per box
+    uint32_t *sp_seg;             // sparse output: source of each entry
+    float *sp_val;                // sparse output: fraction of each entry
+    uint32_t sp_cap;              // entries sp_seg / sp_val hold
+    uint32_t *sp_total;           // entries produced (may exceed sp_cap: then the rest are dropped)
     const uint32_t *maps;         // maps then maps_t
     GraphView gv;
     const uint32_t *rank_ptr;     // [depth + 2]
     uint32_t depth;
     uint32_t n;
     const uint32_t *order;        // query order (batched) or nullptr (identity)
-    uint32_t *counters;           // [0] next big-tier query, [1] overflow count, [2] next fallback
-                                  // query, [3] next small-tier query, [8] number of big-tier queries
+    uint32_t *counters;           // [0] next big-tier box, [1] boxes in list 1, [2] next box of the
+                                  // global fallback, [3] next small-tier box, [4] next retry box,
+                                  // [5] boxes in list 2, [8] number of big-tier boxes
     uint32_t table_cap;           // LDS hash slots of this launch
-    uint32_t *overflow;           // overflowed query indices
+    uint32_t *overflow;           // list 1: boxes whose tier table overflowed
+    uint32_t *overflow2;          // list 2: boxes whose retry table overflowed too
+    uint32_t *ovf_out;            // where this launch reports overflowed boxes (nullptr: mark NaN)
+    uint32_t ovf_out_idx;         // counters[] entry that counts them
+    uint32_t stats_tag;           // OR-ed into stats[q][1]: which launch answered the box
     uint32_t *stats;              // optional [n][2]: cubes, table entries (graph nodes) touched
     // fallback global regions (per worker)
-    uint32_t *g_keys, *g_used;
+    uint32_t *g_keys, *g_cnt, *g_used;
     float *g_hi, *g_lo;
     uint32_t *g_seg_cnt;
     float *g_seg_hi, *g_seg_lo;
 };
 
 // LDS bytes of the query kernels' dynamic shared memory.
-__host__ __device__ inline uint32_t lds_bytes(uint32_t nseg, uint32_t cap) { return nseg * 12u + cap * 16u; }
+__host__ __device__ inline uint32_t lds_bytes(uint32_t nseg, uint32_t cap, bool sparse)
+{
+    return sparse ? cap * 20u : nseg * 12u + cap * 16u;
+}
 
 struct QueryShared {
     Slab slabs[kMaxSlabs];
@@ -498,10 +540,80 @@ struct QueryShared {
     uint32_t flags;
     uint32_t max_key;
     uint32_t q;
+    uint32_t nnz;    // sparse output: entries of this box
+    uint32_t base;   // sparse output: first entry of this box
 };
 
+// Fraction of voxels of each source of one box, written to the dense row or
+// appended to the sparse output. All threads of the block must call.
+template <int BLOCK, bool SPARSE>
+__device__ inline void write_result(const QueryArgs &A, QueryShared &sh, const QueryState &st, uint32_t q,
+                                    bool nonempty, double vol)
+{
+    const uint32_t nseg = A.gv.nseg;
+    if (!SPARSE) {
+        float *o = A.out + uint64_t(q) * nseg;
+        for (uint32_t s = threadIdx.x; s < nseg; s += BLOCK) {
+            const double c = double(ld(&st.seg_cnt[s])) + double(ld(&st.seg_hi[s])) + double(ld(&st.seg_lo[s]));
+            o[s] = nonempty ? float(c / vol) : 0.0f;
+        }
+        return;
+    }
+    const uint32_t nu = min(sh.n_used, st.cap);
+    if (A.out) {
+        float *o = A.out + uint64_t(q) * nseg;
+        for (uint32_t s = threadIdx.x; s < nseg; s += BLOCK) o[s] = 0.0f;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < nu; i += BLOCK) {
+            const uint32_t slot = ld(&st.used[i]);
+            const uint32_t key = ld(&st.keys[slot]);
+            if (key >= nseg) continue;
+            const double c = double(ld(&st.cnt[slot])) + double(ld(&st.hi[slot])) + double(ld(&st.lo[slot]));
+            o[key] = float(c / vol);
+        }
+        return;
+    }
+    if (threadIdx.x == 0) sh.nnz = 0;
+    __syncthreads();
+    uint32_t mine = 0;
+    for (uint32_t i = threadIdx.x; i < nu; i += BLOCK) mine += ld(&st.keys[ld(&st.used[i])]) < nseg;
+    if (mine) atomicAdd(&sh.nnz, mine);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        sh.base = sh.nnz ? atomicAdd(A.sp_total, sh.nnz) : 0u;
+        A.sp_index[2 * uint64_t(q)] = sh.base;
+        A.sp_index[2 * uint64_t(q) + 1] = sh.nnz;
+        sh.nnz = 0;
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nu; i += BLOCK) {
+        const uint32_t slot = ld(&st.used[i]);
+        const uint32_t key = ld(&st.keys[slot]);
+        if (key >= nseg) continue;
+        const double c = double(ld(&st.cnt[slot])) + double(ld(&st.hi[slot])) + double(ld(&st.lo[slot]));
+        const uint32_t pos = sh.base + atomicAdd(&sh.nnz, 1u);
+        if (pos < A.sp_cap) {
+            A.sp_seg[pos] = key;
+            A.sp_val[pos] = float(c / vol);
+        }
+    }
+}
+
+// Marks a box that no table could hold: NaN row (dense) or a NaN entry count.
+template <int BLOCK>
+__device__ inline void write_failure(const QueryArgs &A, uint32_t q)
+{
+    if (A.out) {
+        float *o = A.out + uint64_t(q) * A.gv.nseg;
+        for (uint32_t s = threadIdx.x; s < A.gv.nseg; s += BLOCK) o[s] = __builtin_nanf("");
+    } else if (threadIdx.x == 0) {
+        A.sp_index[2 * uint64_t(q)] = 0xFFFFFFFFu;
+        A.sp_index[2 * uint64_t(q) + 1] = 0xFFFFFFFFu;
+    }
+}
+
 // One query, by the whole block. `st` must be clean (keys empty, values 0).
-template <int BLOCK, int UNROLL>
+template <int BLOCK, int UNROLL, bool SPARSE>
 __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const QueryState &st, uint32_t q,
                                  bool report_overflow)
 {
@@ -516,36 +628,31 @@ __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const Quer
     __syncthreads();
     if (nonempty) build_slabs(A.lt, lo, hi, sh.slabs, &sh.n_slabs);
     __syncthreads();
-    scatter_slabs<BLOCK, UNROLL>(sh.slabs, sh.n_slabs, A.maps, st, A.gv, &sh.flags);
+    scatter_slabs<BLOCK, UNROLL, SPARSE>(sh.slabs, sh.n_slabs, A.maps, st, A.gv, &sh.flags);
     __syncthreads();
-    push_mass<BLOCK>(st, A.gv, sh.rank_ptr, A.depth);
+    push_mass<BLOCK, SPARSE>(st, A.gv, sh.rank_ptr, A.depth);
     __syncthreads();
     const bool overflow = (sh.flags & 1u) != 0;
     if (A.stats && threadIdx.x == 0 && (!overflow || !report_overflow)) {
         uint32_t cubes = 0;
         for (int i = 0; i < sh.n_slabs; ++i) cubes += sh.slabs[i].count;
         A.stats[2 * uint64_t(q)] = cubes;
-        // bit 31 marks a box answered by the global-table fallback
-        A.stats[2 * uint64_t(q) + 1] = sh.n_used | (report_overflow ? 0u : 0x80000000u);
+        // bit 30: answered by the retry launch, bit 31: by the global-table fallback
+        A.stats[2 * uint64_t(q) + 1] = sh.n_used | A.stats_tag;
     }
     const uint32_t nseg = A.gv.nseg;
     if (!overflow) {
         const double vol = nonempty ? double(hi[0] - lo[0]) * double(hi[1] - lo[1]) * double(hi[2] - lo[2]) : 0.0;
-        float *o = A.out + uint64_t(q) * nseg;
-        for (uint32_t s = threadIdx.x; s < nseg; s += BLOCK) {
-            const double c = double(ld(&st.seg_cnt[s])) + double(ld(&st.seg_hi[s])) + double(ld(&st.seg_lo[s]));
-            o[s] = nonempty ? float(c / vol) : 0.0f;
-        }
+        write_result<BLOCK, SPARSE>(A, sh, st, q, nonempty, vol);
     } else if (report_overflow) {
         if (threadIdx.x == 0) {
-            const uint32_t k = atomicAdd(&A.counters[1], 1u);
-            A.overflow[k] = q;
+            const uint32_t k = atomicAdd(&A.counters[A.ovf_out_idx], 1u);
+            A.ovf_out[k] = q;
         }
     } else {
-        // even the per-worker global table overflowed: make the failure visible
-        float *o = A.out + uint64_t(q) * nseg;
-        for (uint32_t s = threadIdx.x; s < nseg; s += BLOCK) o[s] = __builtin_nanf("");
+        write_failure<BLOCK>(A, q);  // even the per-worker global table overflowed
     }
+    __syncthreads();
     // restore a clean state for the next query
     const uint32_t nu = min(sh.n_used, st.cap);
     for (uint32_t i = threadIdx.x; i < nu; i += BLOCK) {
@@ -553,12 +660,14 @@ __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const Quer
         st.keys[slot] = kEmpty;
         st.hi[slot] = 0.f;
         st.lo[slot] = 0.f;
+        if (SPARSE) st.cnt[slot] = 0;
     }
-    for (uint32_t s = threadIdx.x; s < nseg; s += BLOCK) {
-        st.seg_cnt[s] = 0;
-        st.seg_hi[s] = 0.f;
-        st.seg_lo[s] = 0.f;
-    }
+    if (!SPARSE)
+        for (uint32_t s = threadIdx.x; s < nseg; s += BLOCK) {
+            st.seg_cnt[s] = 0;
+            st.seg_hi[s] = 0.f;
+            st.seg_lo[s] = 0.f;
+        }
     __syncthreads();
 }
 
@@ -568,14 +677,22 @@ __device__ inline void load_rank_ptr(const QueryArgs &A, QueryShared &sh)
     for (uint32_t i = threadIdx.x; i < A.depth + 2; i += BLOCK) sh.rank_ptr[i] = A.rank_ptr[i];
 }
 
+template <bool SPARSE>
 __device__ inline QueryState lds_state(char *dyn, QueryShared &sh, uint32_t nseg, uint32_t cap)
 {
     QueryState st;
-    uint32_t *seg = reinterpret_cast<uint32_t *>(dyn);
-    st.seg_cnt = seg;
-    st.seg_hi = reinterpret_cast<float *>(seg + nseg);
-    st.seg_lo = reinterpret_cast<float *>(seg + 2 * nseg);
-    uint32_t *t = seg + 3 * nseg;
+    uint32_t *t = reinterpret_cast<uint32_t *>(dyn);
+    if (SPARSE) {
+        st.seg_cnt = nullptr;
+        st.seg_hi = st.seg_lo = nullptr;
+        st.cnt = t + 4 * cap;
+    } else {
+        st.seg_cnt = t;
+        st.seg_hi = reinterpret_cast<float *>(t + nseg);
+        st.seg_lo = reinterpret_cast<float *>(t + 2 * nseg);
+        t += 3 * nseg;
+        st.cnt = nullptr;
+    }
     st.keys = t;
     st.hi = reinterpret_cast<float *>(t + cap);
     st.lo = reinterpret_cast<float *>(t + 2 * cap);
@@ -588,43 +705,46 @@ __device__ inline QueryState lds_state(char *dyn, QueryShared &sh, uint32_t nseg
     return st;
 }
 
-template <int BLOCK>
+template <int BLOCK, bool SPARSE>
 __device__ inline void clear_lds_state(const QueryState &st, uint32_t nseg)
 {
     for (uint32_t i = threadIdx.x; i < st.cap; i += BLOCK) {
         st.keys[i] = kEmpty;
         st.hi[i] = 0.f;
         st.lo[i] = 0.f;
+        if (SPARSE) st.cnt[i] = 0;
     }
-    for (uint32_t s = threadIdx.x; s < nseg; s += BLOCK) {
-        st.seg_cnt[s] = 0;
-        st.seg_hi[s] = 0.f;
-        st.seg_lo[s] = 0.f;
-    }
+    if (!SPARSE)
+        for (uint32_t s = threadIdx.x; s < nseg; s += BLOCK) {
+            st.seg_cnt[s] = 0;
+            st.seg_hi[s] = 0.f;
+            st.seg_lo[s] = 0.f;
+        }
 }
 
 // Plain: one block per query in input order, state in LDS.
+template <bool SPARSE>
 __global__ __launch_bounds__(kBlock) void query_plain_kernel(QueryArgs A)
 {
     extern __shared__ __align__(16) char dyn[];
     __shared__ QueryShared sh;
-    const QueryState st = lds_state(dyn, sh, A.gv.nseg, A.table_cap);
+    const QueryState st = lds_state<SPARSE>(dyn, sh, A.gv.nseg, A.table_cap);
     load_rank_ptr<kBlock>(A, sh);
-    clear_lds_state<kBlock>(st, A.gv.nseg);
+    clear_lds_state<kBlock, SPARSE>(st, A.gv.nseg);
     __syncthreads();
-    run_query<kBlock, kUnroll>(A, sh, st, blockIdx.x, true);
+    run_query<kBlock, kUnroll, SPARSE>(A, sh, st, blockIdx.x, A.ovf_out != nullptr);
 }
 
 // Batched tiers: persistent blocks take queries from the largest-first order.
 // BIG: positions [0, counters[8]); otherwise [counters[8], n).
-template <int BLOCK, bool BIG, int UNROLL>
+template <int BLOCK, bool BIG, int UNROLL, bool SPARSE>
 __global__ __launch_bounds__(BLOCK) void query_tier_kernel(QueryArgs A)
 {
     extern __shared__ __align__(16) char dyn[];
     __shared__ QueryShared sh;
-    const QueryState st = lds_state(dyn, sh, A.gv.nseg, A.table_cap);
+    const QueryState st = lds_state<SPARSE>(dyn, sh, A.gv.nseg, A.table_cap);
     load_rank_ptr<BLOCK>(A, sh);
-    clear_lds_state<BLOCK>(st, A.gv.nseg);
+    clear_lds_state<BLOCK, SPARSE>(st, A.gv.nseg);
     const uint32_t split = ld(&A.counters[8]);
     const uint32_t begin = BIG ? 0u : split, end = BIG ? split : A.n;
     for (;;) {
@@ -632,18 +752,40 @@ __global__ __launch_bounds__(BLOCK) void query_tier_kernel(QueryArgs A)
         __syncthreads();
         const uint32_t k = sh.q;
         if (k >= end) break;  // uniform
-        run_query<BLOCK, UNROLL>(A, sh, st, A.order[k], true);
+        run_query<BLOCK, UNROLL, SPARSE>(A, sh, st, A.order[k], A.ovf_out != nullptr);
     }
 }
 
-// Fallback for overflowed queries: per-worker tables and source arrays in the
-// workspace (global memory), drained from the overflow list.
+// Retry of boxes whose tier table overflowed (list 1), with a larger LDS table;
+// what overflows again goes to list 2.
+template <int BLOCK, int UNROLL, bool SPARSE>
+__global__ __launch_bounds__(BLOCK) void query_retry_kernel(QueryArgs A)
+{
+    extern __shared__ __align__(16) char dyn[];
+    __shared__ QueryShared sh;
+    const QueryState st = lds_state<SPARSE>(dyn, sh, A.gv.nseg, A.table_cap);
+    load_rank_ptr<BLOCK>(A, sh);
+    clear_lds_state<BLOCK, SPARSE>(st, A.gv.nseg);
+    const uint32_t n_list = ld(&A.counters[1]);
+    for (;;) {
+        if (threadIdx.x == 0) sh.q = atomicAdd(&A.counters[4], 1u);
+        __syncthreads();
+        const uint32_t k = sh.q;
+        if (k >= n_list) break;  // uniform
+        run_query<BLOCK, UNROLL, SPARSE>(A, sh, st, A.overflow[k], true);
+    }
+}
+
+// Fallback for boxes that overflowed the retry table too (list 2): per-worker
+// tables and source arrays in the workspace (global memory).
+template <bool SPARSE>
 __global__ __launch_bounds__(kBlock) void query_fallback_kernel(QueryArgs A)
 {
     __shared__ QueryShared sh;
     QueryState st;
     const uint64_t w = blockIdx.x;
     st.keys = A.g_keys + w * kHashGlobal;
+    st.cnt = A.g_cnt + w * kHashGlobal;
     st.hi = A.g_hi + w * kHashGlobal;
     st.lo = A.g_lo + w * kHashGlobal;
     st.used = A.g_used + w * kHashGlobal;
@@ -652,18 +794,18 @@ __global__ __launch_bounds__(kBlock) void query_fallback_kernel(QueryArgs A)
     st.n_used = &sh.n_used;
     st.flags = &sh.flags;
     st.max_key = &sh.max_key;
-    st.seg_cnt = A.g_seg_cnt + w * A.gv.nseg;
-    st.seg_hi = A.g_seg_hi + w * A.gv.nseg;
-    st.seg_lo = A.g_seg_lo + w * A.gv.nseg;
+    st.seg_cnt = SPARSE ? nullptr : A.g_seg_cnt + w * A.gv.nseg;
+    st.seg_hi = SPARSE ? nullptr : A.g_seg_hi + w * A.gv.nseg;
+    st.seg_lo = SPARSE ? nullptr : A.g_seg_lo + w * A.gv.nseg;
     load_rank_ptr<kBlock>(A, sh);
     __syncthreads();
-    const uint32_t n_over = ld(&A.counters[1]);
+    const uint32_t n_over = ld(&A.counters[5]);
     for (;;) {
         if (threadIdx.x == 0) sh.q = atomicAdd(&A.counters[2], 1u);
         __syncthreads();
         const uint32_t k = sh.q;
         if (k >= n_over) break;
-        run_query<kBlock, kUnroll>(A, sh, st, A.overflow[k], false);
+        run_query<kBlock, kUnroll, SPARSE>(A, sh, st, A.overflow2[k], false);
     }
 }
 
@@ -904,7 +1046,8 @@ struct Workspace {
     uint32_t *bucket_of;  // [max_boxes]
     uint32_t *order;      // [max_boxes]
     uint32_t *overflow;   // [max_boxes]
-    uint32_t *g_keys, *g_used;
+    uint32_t *overflow2;  // [max_boxes]
+    uint32_t *g_keys, *g_cnt, *g_used;
     float *g_hi, *g_lo;
     uint32_t *g_seg_cnt;
     float *g_seg_hi, *g_seg_lo;
@@ -929,6 +1072,7 @@ Workspace carve(const Graph &g, char *base, uint32_t max_boxes)
     w.buckets = reinterpret_cast<uint32_t *>(take(64 * 4));
     const uint64_t hs = uint64_t(kFallbackWorkers) * kHashGlobal;
     w.g_keys = reinterpret_cast<uint32_t *>(take(hs * 4));
+    w.g_cnt = reinterpret_cast<uint32_t *>(take(hs * 4));
     w.g_used = reinterpret_cast<uint32_t *>(take(hs * 4));
     w.g_hi = reinterpret_cast<float *>(take(hs * 4));
     w.g_lo = reinterpret_cast<float *>(take(hs * 4));
@@ -939,6 +1083,7 @@ Workspace carve(const Graph &g, char *base, uint32_t max_boxes)
     w.bucket_of = reinterpret_cast<uint32_t *>(take(uint64_t(max_boxes) * 4));
     w.order = reinterpret_cast<uint32_t *>(take(uint64_t(max_boxes) * 4));
     w.overflow = reinterpret_cast<uint32_t *>(take(uint64_t(max_boxes) * 4));
+    w.overflow2 = reinterpret_cast<uint32_t *>(take(uint64_t(max_boxes) * 4));
     w.bytes = off;
     w.max_boxes = max_boxes;
     return w;
@@ -992,13 +1137,13 @@ int timing_end(Graph *g, hipStream_t s, std::string *err)
 using QueryKernel = void (*)(QueryArgs);
 using NaiveKernel = void (*)(NaiveArgs);
 
-template <int BLOCK, bool BIG>
+template <int BLOCK, bool BIG, bool SPARSE>
 QueryKernel tier_kernel(uint32_t unroll)
 {
     switch (unroll) {
-    case 4: return query_tier_kernel<BLOCK, BIG, 4>;
-    case 8: return query_tier_kernel<BLOCK, BIG, 8>;
-    default: return query_tier_kernel<BLOCK, BIG, 16>;
+    case 4: return query_tier_kernel<BLOCK, BIG, 4, SPARSE>;
+    case 8: return query_tier_kernel<BLOCK, BIG, 8, SPARSE>;
+    default: return query_tier_kernel<BLOCK, BIG, 16, SPARSE>;
     }
 }
 
@@ -1018,8 +1163,8 @@ bool valid_unroll(uint32_t u) { return u == 4 || u == 8 || u == 16; }
 int occupancy(DeviceState &d, const void *k, int block, uint32_t dyn, int *out, std::string *err)
 {
     for (const auto &e : d.occupancy)
-        if (e.first == k) {
-            *out = e.second;
+        if (e.kernel == k && e.dyn == dyn) {
+            *out = e.blocks;
             return MG_OK;
         }
     if (dyn + sizeof(QueryShared) > uint64_t(d.lds_max)) {
@@ -1027,10 +1172,14 @@ int occupancy(DeviceState &d, const void *k, int block, uint32_t dyn, int *out, 
                std::to_string(d.lds_max) + " bytes of LDS per workgroup";
         return MG_ELIMIT;
     }
-    HIP_TRY(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(dyn)));
+    // the attribute is the largest dynamic LDS any launch of this kernel uses
+    uint32_t dmax = dyn;
+    for (const auto &e : d.occupancy)
+        if (e.kernel == k) dmax = std::max(dmax, e.dyn);
+    HIP_TRY(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(dmax)));
     int occ = 1;
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, block, dyn));
-    d.occupancy.emplace_back(k, std::max(occ, 1));
+    d.occupancy.push_back(DeviceState::Occ{k, dyn, std::max(occ, 1)});
     *out = std::max(occ, 1);
     return MG_OK;
 }
@@ -1122,6 +1271,7 @@ int dev_workspace_init(Graph *g, void *work, uint64_t bytes, void *stream, std::
     hipStream_t s = static_cast<hipStream_t>(stream);
     const uint64_t hs = uint64_t(kFallbackWorkers) * kHashGlobal;
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, w.g_keys, hs, kEmpty);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, w.g_cnt, hs, 0u);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_hi), hs, 0u);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_lo), hs, 0u);
     const uint64_t ss = uint64_t(kFallbackWorkers) * g->nseg;
@@ -1132,8 +1282,82 @@ int dev_workspace_init(Graph *g, void *work, uint64_t bytes, void *stream, std::
     return MG_OK;
 }
 
-int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *work, uint64_t bytes, void *stream,
-              int variant, uint32_t *stats, std::string *err)
+template <bool SPARSE>
+int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &lt, uint32_t n, hipStream_t s,
+                 int variant, std::string *err)
+{
+    int rc = MG_OK;
+    DeviceState &d = g->dev;
+    const QueryKernel kbig = tier_kernel<kBlockBig, true, SPARSE>(d.cfg.unroll_big);
+    const QueryKernel ksmall = tier_kernel<kBlock, false, SPARSE>(d.cfg.unroll_small);
+    const QueryKernel kplain = query_plain_kernel<SPARSE>;
+    const uint32_t cap_big = d.cfg.table_big ? d.cfg.table_big : kHashBig;
+    const uint32_t cap_small = d.cfg.table_small ? d.cfg.table_small : (SPARSE ? kHashPlain : kHashSmall);
+    const uint32_t dyn_big = lds_bytes(g->nseg, cap_big, SPARSE), dyn_small = lds_bytes(g->nseg, cap_small, SPARSE),
+                   dyn_plain = lds_bytes(g->nseg, kHashPlain, SPARSE);
+    int occ_big = 1, occ_small = 1, occ_plain = 1;
+    if ((rc = occupancy(d, reinterpret_cast<const void *>(kbig), kBlockBig, dyn_big, &occ_big, err)) ||
+        (rc = occupancy(d, reinterpret_cast<const void *>(ksmall), kBlock, dyn_small, &occ_small, err)) ||
+        (rc = occupancy(d, reinterpret_cast<const void *>(kplain), kBlock, dyn_plain, &occ_plain, err)))
+        return rc;
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, w.counters, 64u);
+    if (A.sp_total) hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, A.sp_total, 1u);
+    if (variant == kQueryBatched) {
+        hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, w.buckets, 64u);
+        const uint32_t blocks = (n + 255) / 256;
+        hipLaunchKernelGGL(query_size_kernel, dim3(blocks), dim3(256), 0, s, lt, A.boxes, n, w.bucket_of, w.buckets);
+        hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(64), 0, s, w.buckets, w.counters);
+        hipLaunchKernelGGL(query_order_kernel, dim3(blocks), dim3(256), 0, s, w.bucket_of, n, w.buckets, w.order);
+        A.order = w.order;
+        const uint32_t wbig = std::max(1u, std::min<uint32_t>(n, uint32_t(d.ncu) * uint32_t(occ_big)));
+        const uint32_t wsmall = std::max(1u, std::min<uint32_t>(n, uint32_t(d.ncu) * uint32_t(occ_small)));
+        rc = timing_begin(g, s, err);
+        if (rc) return rc;
+        A.table_cap = cap_big;
+        hipLaunchKernelGGL(kbig, dim3(wbig), dim3(kBlockBig), dyn_big, s, A);
+        HIP_TRY(hipGetLastError());
+        A.table_cap = cap_small;
+        hipLaunchKernelGGL(ksmall, dim3(wsmall), dim3(kBlock), dyn_small, s, A);
+        HIP_TRY(hipGetLastError());
+        rc = timing_end(g, s, err);
+        if (rc) return rc;
+    } else {
+        A.table_cap = kHashPlain;
+        rc = timing_begin(g, s, err);
+        if (rc) return rc;
+        hipLaunchKernelGGL(kplain, dim3(n), dim3(kBlock), dyn_plain, s, A);
+        HIP_TRY(hipGetLastError());
+        rc = timing_end(g, s, err);
+        if (rc) return rc;
+    }
+    // boxes whose table overflowed: once more with a larger LDS table, then in global memory
+    const QueryKernel kretry = query_retry_kernel<kBlockBig, 8, SPARSE>;
+    uint32_t cap_retry = d.cfg.table_retry;
+    if (!cap_retry) {  // the largest table up to kHashRetry that fits the LDS of a workgroup
+        cap_retry = kHashRetry;
+        while (cap_retry > kHashBig &&
+               lds_bytes(g->nseg, cap_retry, SPARSE) + sizeof(QueryShared) > uint64_t(d.lds_max))
+            cap_retry /= 2;
+    }
+    const uint32_t dyn_retry = lds_bytes(g->nseg, cap_retry, SPARSE);
+    int occ_retry = 1;
+    if ((rc = occupancy(d, reinterpret_cast<const void *>(kretry), kBlockBig, dyn_retry, &occ_retry, err)))
+        return rc;
+    A.table_cap = cap_retry;
+    A.stats_tag = 0x40000000u;
+    A.ovf_out = w.overflow2;
+    A.ovf_out_idx = 5;
+    hipLaunchKernelGGL(kretry, dim3(uint32_t(d.ncu) * uint32_t(occ_retry)), dim3(kBlockBig), dyn_retry, s, A);
+    HIP_TRY(hipGetLastError());
+    A.ovf_out = nullptr;
+    A.stats_tag = 0x80000000u;
+    hipLaunchKernelGGL(query_fallback_kernel<SPARSE>, dim3(kFallbackWorkers), dim3(kBlock), 0, s, A);
+    HIP_TRY(hipGetLastError());
+    return MG_OK;
+}
+
+int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const SparseOut *sp, void *work,
+              uint64_t bytes, void *stream, int variant, uint32_t *stats, std::string *err)
 {
     DeviceGuard guard;
     int rc = check_device(g, err);
@@ -1167,6 +1391,10 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *wor
             *err = "naive scan keeps per-source counts in LDS: at most 16384 sources";
             return MG_ELIMIT;
         }
+        if (sp) {
+            *err = "the naive scan writes dense output only";
+            return MG_EINVAL;
+        }
         NaiveArgs A;
         A.lt = lt;
         A.boxes = boxes;
@@ -1181,15 +1409,18 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *wor
         return timing_end(g, s, err);
     }
 
-    if (g->nseg > kSegLdsMax) {
-        *err = "query kernels keep per-source state in LDS: at most " + std::to_string(kSegLdsMax) + " sources";
-        return MG_ELIMIT;
-    }
     QueryArgs A;
     std::memset(&A, 0, sizeof(A));
     A.lt = lt;
     A.boxes = boxes;
-    A.out = out;
+    A.out = sp ? nullptr : out;
+    if (sp) {
+        A.sp_index = sp->index;
+        A.sp_seg = sp->seg;
+        A.sp_val = sp->val;
+        A.sp_cap = sp->cap;
+        A.sp_total = sp->total;
+    }
     A.maps = g->dev.maps;
     A.gv.nodes = g->dev.nodes;
     A.gv.nseg = g->nseg;
@@ -1199,51 +1430,16 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *wor
     A.n = n;
     A.counters = w.counters;
     A.overflow = w.overflow;
+    A.overflow2 = w.overflow2;
+    A.ovf_out = w.overflow;
+    A.ovf_out_idx = 1;
     A.stats = stats;
-    A.g_keys = w.g_keys, A.g_used = w.g_used, A.g_hi = w.g_hi, A.g_lo = w.g_lo;
+    A.g_keys = w.g_keys, A.g_cnt = w.g_cnt, A.g_used = w.g_used, A.g_hi = w.g_hi, A.g_lo = w.g_lo;
     A.g_seg_cnt = w.g_seg_cnt, A.g_seg_hi = w.g_seg_hi, A.g_seg_lo = w.g_seg_lo;
-    DeviceState &d = g->dev;
-    const QueryKernel kbig = tier_kernel<kBlockBig, true>(d.cfg.unroll_big);
-    const QueryKernel ksmall = tier_kernel<kBlock, false>(d.cfg.unroll_small);
-    const uint32_t dyn_big = lds_bytes(g->nseg, kHashBig), dyn_small = lds_bytes(g->nseg, kHashSmall),
-                   dyn_plain = lds_bytes(g->nseg, kHashPlain);
-    int occ_big = 1, occ_small = 1, occ_plain = 1;
-    if ((rc = occupancy(d, reinterpret_cast<const void *>(kbig), kBlockBig, dyn_big, &occ_big, err)) ||
-        (rc = occupancy(d, reinterpret_cast<const void *>(ksmall), kBlock, dyn_small, &occ_small, err)) ||
-        (rc = occupancy(d, reinterpret_cast<const void *>(query_plain_kernel), kBlock, dyn_plain, &occ_plain, err)))
-        return rc;
-    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, w.counters, 64u);
-    if (variant == kQueryBatched) {
-        hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, w.buckets, 64u);
-        const uint32_t blocks = (n + 255) / 256;
-        hipLaunchKernelGGL(query_size_kernel, dim3(blocks), dim3(256), 0, s, lt, boxes, n, w.bucket_of, w.buckets);
-        hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(64), 0, s, w.buckets, w.counters);
-        hipLaunchKernelGGL(query_order_kernel, dim3(blocks), dim3(256), 0, s, w.bucket_of, n, w.buckets, w.order);
-        A.order = w.order;
-        const uint32_t wbig = std::max(1u, std::min<uint32_t>(n, uint32_t(d.ncu) * uint32_t(occ_big)));
-        const uint32_t wsmall = std::max(1u, std::min<uint32_t>(n, uint32_t(d.ncu) * uint32_t(occ_small)));
-        rc = timing_begin(g, s, err);
-        if (rc) return rc;
-        A.table_cap = kHashBig;
-        hipLaunchKernelGGL(kbig, dim3(wbig), dim3(kBlockBig), dyn_big, s, A);
-        HIP_TRY(hipGetLastError());
-        A.table_cap = kHashSmall;
-        hipLaunchKernelGGL(ksmall, dim3(wsmall), dim3(kBlock), dyn_small, s, A);
-        HIP_TRY(hipGetLastError());
-        rc = timing_end(g, s, err);
-        if (rc) return rc;
-    } else {
-        A.table_cap = kHashPlain;
-        rc = timing_begin(g, s, err);
-        if (rc) return rc;
-        hipLaunchKernelGGL(query_plain_kernel, dim3(n), dim3(kBlock), dyn_plain, s, A);
-        HIP_TRY(hipGetLastError());
-        rc = timing_end(g, s, err);
-        if (rc) return rc;
-    }
-    hipLaunchKernelGGL(query_fallback_kernel, dim3(kFallbackWorkers), dim3(kBlock), 0, s, A);
-    HIP_TRY(hipGetLastError());
-    return MG_OK;
+    // sources in LDS arrays while they fit, else as table entries (sparse mode)
+    const bool sparse = sp != nullptr || g->nseg > kSegLdsMax;
+    return sparse ? launch_query<true>(g, A, w, lt, n, s, variant, err)
+                  : launch_query<false>(g, A, w, lt, n, s, variant, err);
 }
 
 int dev_footprint(Graph *g, const uint32_t *boxes, uint32_t n, uint32_t *level_counts, uint32_t *cubes, uint32_t cap,
@@ -1286,9 +1482,13 @@ int dev_propagate_tf(Graph *g, const uint8_t *tf, uint32_t T, float *out, void *
 
 int dev_set_launch(Graph *g, const mg_launch_cfg *cfg, std::string *err)
 {
-    for (uint32_t r : cfg->reserved)
-        if (r) {
-            *err = "mg_set_launch: reserved fields must be 0";
+    if (cfg->reserved) {
+        *err = "mg_set_launch: reserved field must be 0";
+        return MG_EINVAL;
+    }
+    for (uint32_t t : {cfg->table_big, cfg->table_small, cfg->table_retry})
+        if (t != 0 && (t < 64 || t > 8192 || (t & (t - 1)) != 0)) {
+            *err = "mg_set_launch: table sizes must be 0 or a power of two in [64, 8192]";
             return MG_EINVAL;
         }
     const uint32_t tb = cfg->tf_block;
@@ -1318,7 +1518,7 @@ int dev_autotune(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *
         float best = 1e30f;
         for (uint32_t r = 0; r <= reps; ++r) {  // the first run warms up
             HIP_TRY(hipEventRecord(e0, s));
-            int rc2 = dev_query(g, boxes, n, out, work, bytes, stream, variant, nullptr, err);
+            int rc2 = dev_query(g, boxes, n, out, nullptr, work, bytes, stream, variant, nullptr, err);
             if (rc2) return rc2;
             HIP_TRY(hipEventRecord(e1, s));
             HIP_TRY(hipEventSynchronize(e1));

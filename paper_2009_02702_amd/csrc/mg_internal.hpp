@@ -38,8 +38,13 @@ struct DeviceState {
     // launch parameters, queried once per device and graph
     bool launch_ready = false;
     int ncu = 0, lds_max = 0;
-    std::vector<std::pair<const void *, int>> occupancy;  // blocks per CU of each kernel variant
-    mg_launch_cfg cfg = {8, 8, 8, 256, {0, 0, 0, 0}};
+    struct Occ {
+        const void *kernel;
+        uint32_t dyn;   // dynamic LDS bytes of the launch
+        int blocks;     // blocks per CU
+    };
+    std::vector<Occ> occupancy;  // per kernel variant and LDS size
+    mg_launch_cfg cfg = {8, 8, 8, 256, 0, 0, 0, 0};
     bool timing = false;
     std::vector<void *> ev_start, ev_stop;  // hipEvent_t pairs recorded around the dominant kernel
     uint32_t ev_used = 0;
@@ -77,8 +82,15 @@ int dev_upload(Graph *g, int device, std::string *err);
 void dev_free(Graph *g);
 uint64_t dev_workspace_bytes(const Graph &g, uint32_t max_boxes);
 int dev_workspace_init(Graph *g, void *work, uint64_t bytes, void *stream, std::string *err);
-int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *work, uint64_t bytes,
-              void *stream, int variant, uint32_t *stats, std::string *err);
+struct SparseOut {
+    uint32_t *index;   // [n][2] first entry, entries
+    uint32_t *seg;     // [cap]
+    float *val;        // [cap]
+    uint32_t cap;
+    uint32_t *total;   // device counter
+};
+int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const SparseOut *sp, void *work,
+              uint64_t bytes, void *stream, int variant, uint32_t *stats, std::string *err);
 int dev_footprint(Graph *g, const uint32_t *boxes, uint32_t n, uint32_t *level_counts, uint32_t *cubes,
                   uint32_t cap, uint32_t *count, void *stream, std::string *err);
 int dev_propagate_tf(Graph *g, const uint8_t *tf, uint32_t T, float *out, void *stream, std::string *err);

@@ -167,6 +167,24 @@ class Graph:
                                              ws.numel(), _stream_ptr(stream)))
         return out, stats
 
+    def query_sparse(self, boxes, capacity: int, workspace=None, stream=None):
+        """Sparse histograms: (index int32 [n, 2], seg int32 [capacity], val fp32 [capacity], total int32 [1]).
+
+        Box q's entries are seg/val[index[q,0] : index[q,0] + index[q,1]]; if total > capacity the
+        call must be repeated with more room."""
+        torch = _torch()
+        n = boxes.shape[0]
+        dev = boxes.device
+        index = torch.zeros((n, 2), dtype=torch.int32, device=dev)
+        seg = torch.zeros(max(capacity, 1), dtype=torch.int32, device=dev)
+        val = torch.zeros(max(capacity, 1), dtype=torch.float32, device=dev)
+        total = torch.zeros(1, dtype=torch.int32, device=dev)
+        ws = workspace if workspace is not None else self.workspace(n, stream)
+        check(self._lib.mg_query_boxes_sparse(self._h, _dptr(boxes), n, _dptr(index), _dptr(seg), _dptr(val),
+                                              int(capacity), _dptr(total), _dptr(ws), ws.numel(),
+                                              _stream_ptr(stream)))
+        return index, seg, val, total
+
     def footprint(self, boxes, cubes_cap: int = 0, stream=None):
         """(level counts [n, L], cubes [m, 6] or None): the GPU decomposition of each box."""
         torch = _torch()
@@ -203,7 +221,8 @@ class Graph:
         c = LaunchCfg()
         check(self._lib.mg_get_launch(self._h, ctypes.byref(c)))
         return {"unroll_big": c.unroll_big, "unroll_small": c.unroll_small, "unroll_naive": c.unroll_naive,
-                "tf_block": c.tf_block}
+                "tf_block": c.tf_block, "table_big": c.table_big, "table_small": c.table_small,
+                "table_retry": c.table_retry}
 
     def set_launch_config(self, **kw) -> None:
         cur = self.launch_config()

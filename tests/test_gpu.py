@@ -276,3 +276,93 @@ def test_autotune_and_launch_validation():
     with pytest.raises(MGError):
         g.set_launch_config(tf_block=100)
     assert g.launch_config() == cfg
+
+
+def test_overflow_retry_and_global_fallback_paths():
+    """Tiny LDS tables force boxes through the retry launch and the global-memory fallback;
+    results must not change (the table sizes are a launch knob set from the host)."""
+    w = synth.workload(2, dims=(160, 150, 140), segments=300, n_boxes=800)
+    vol = synth.make_volume(w)
+    g = _graph("ovf", vol)
+    boxes = synth.make_boxes(w)
+    boxes[:10] = [0, 0, 0, 160, 150, 140]
+    ids, vol_c = scan.compact(vol)
+    _, ref = scan.box_counts(vol_c, len(ids), boxes)
+    db = _dev(boxes)
+    for tb, ts, tr in ((64, 64, 8192), (64, 64, 64), (4096, 1024, 0)):
+        g.set_launch_config(table_big=tb, table_small=ts, table_retry=tr)
+        out, stats = g.query_stats(db)
+        st = stats.cpu().numpy().view(np.uint32)
+        _compare(out.cpu().numpy(), ref, None, "tables %d/%d/%d" % (tb, ts, tr))
+        via_retry = int(((st[:, 1] >> 30) & 1).sum())
+        via_global = int((st[:, 1] >> 31).sum())
+        if tr == 8192:
+            assert via_retry > 0 and via_global == 0
+        if tr == 64:
+            assert via_global > 0
+    for v in ("plain",):
+        g.set_launch_config(table_big=0, table_small=0, table_retry=64)
+        _compare(g.query(db, variant=v).cpu().numpy(), ref, None, "plain with tiny retry table")
+    g.set_launch_config(table_big=0, table_small=0, table_retry=0)
+
+
+# ------------------------------------------------------------------ many segments: sources in the table
+
+def _sparse_to_dense(index, seg, val, n, S):
+    out = np.zeros((n, S), dtype=np.float64)
+    index = index.astype(np.int64)
+    for q in range(n):
+        b, k = index[q]
+        assert b >= 0 and k >= 0
+        s_ = seg[b:b + k]
+        assert len(np.unique(s_)) == len(s_)           # each segment once per box
+        out[q, s_] = val[b:b + k]
+    return out
+
+
+def test_query_many_segments_dense_and_sparse():
+    """More sources than the LDS arrays hold (cylinder recipe, > 2048 segments): sources become table
+    entries; dense rows and the sparse entry list both match the oracle."""
+    w = synth.workload(4, dims=(160, 200, 150), segments=4000, n_boxes=1500)
+    vol = synth.make_volume(w)
+    g = _graph("many", vol)
+    S = g.info()["nseg"]
+    assert S > 2048
+    boxes = synth.make_boxes(w)
+    ids, vol_c = scan.compact(vol)
+    _, ref = scan.box_counts(vol_c, len(ids), boxes)
+    db = _dev(boxes)
+    l0 = _level0_only(g, db)
+    for v in ("batched", "plain", "naive"):
+        _compare(g.query(db, variant=v).cpu().numpy(), ref, l0, "many segments " + v)
+    nnz = int((ref > 0).sum())
+    index, seg, val, total = g.query_sparse(db, capacity=nnz + 10)
+    assert int(total.item()) == nnz
+    dense = _sparse_to_dense(index.cpu().numpy(), seg.cpu().numpy(), val.cpu().numpy(), len(boxes), S)
+    _compare(dense, ref, l0, "sparse output")
+
+
+def test_query_sparse_output_small_segment_count_and_truncation():
+    w = synth.workload(2, dims=(90, 80, 70), segments=120, n_boxes=700)
+    vol = synth.make_volume(w)
+    g = _graph("sparse_small", vol)
+    S = g.info()["nseg"]
+    boxes = synth.make_boxes(w)
+    ids, vol_c = scan.compact(vol)
+    _, ref = scan.box_counts(vol_c, len(ids), boxes)
+    db = _dev(boxes)
+    nnz = int((ref > 0).sum())
+    index, seg, val, total = g.query_sparse(db, capacity=nnz)
+    assert int(total.item()) == nnz
+    _compare(_sparse_to_dense(index.cpu().numpy(), seg.cpu().numpy(), val.cpu().numpy(), len(boxes), S), ref, None,
+             "sparse")
+    # too little room: the total still reports what was needed, and written entries are valid
+    cap = nnz // 3
+    index, seg, val, total = g.query_sparse(db, capacity=cap)
+    assert int(total.item()) == nnz
+    index, seg, val = index.cpu().numpy().astype(np.int64), seg.cpu().numpy(), val.cpu().numpy()
+    for q in range(len(boxes)):
+        b, k = index[q]
+        for j in range(b, min(b + k, cap)):
+            r = ref[q, seg[j]]
+            assert r > 0 and abs(val[j] - r) <= REL_TOL * r
