@@ -366,3 +366,52 @@ def test_query_sparse_output_small_segment_count_and_truncation():
         for j in range(b, min(b + k, cap)):
             r = ref[q, seg[j]]
             assert r > 0 and abs(val[j] - r) <= REL_TOL * r
+
+
+# ------------------------------------------------------------------ serving loop (continuous batching)
+
+def _served(w, n, qps, **kw):
+    from paper_2009_02702_amd.serve import Server
+    vol = synth.make_volume(w)
+    g = _graph(("serve", w.dims), vol)
+    S = g.info()["nseg"]
+    boxes = synth.make_boxes(w, n)
+    arrivals = synth.poisson_arrivals(w, n, qps)
+    tf_index = np.full(n, -1, dtype=np.int64)
+    tf_rows = np.arange(0, n, 10)
+    tf_index[tf_rows] = np.arange(len(tf_rows))
+    tfs = synth.make_tfs(w, S, len(tf_rows))
+    srv = Server(g, **kw)
+    res = np.zeros((n, S), dtype=np.float32)
+    stats = srv.serve(boxes, arrivals, tf_index, tfs, results=res)
+    return g, boxes, res, stats
+
+
+def test_serving_results_equal_alone_and_in_the_mix():
+    """Every served result (admitted in batches that overlap on several streams, replayed from
+    captured graphs) matches the same box queried alone, and the oracle."""
+    w = synth.workload(5, dims=(140, 130, 100), segments=80)
+    g, boxes, res, stats = _served(w, 3000, 20000.0, slots=3, max_batch=256, max_tf=8)
+    assert np.isfinite(stats.latency_s).all() and (stats.latency_s >= 0).all()
+    assert stats.batches > 1
+    ids, vol_c = scan.compact(synth.make_volume(w))
+    _, ref = scan.box_counts(vol_c, len(ids), boxes)
+    _compare(res, ref, None, "served")
+    alone = np.stack([g.query(_dev(boxes[i:i + 1])).cpu().numpy()[0] for i in range(0, 3000, 97)])
+    _compare(res[::97], alone.astype(np.float64), None, "served vs alone")
+    print(stats.summary())
+
+
+def test_serving_small_budget_queues_instead_of_failing():
+    from paper_2009_02702_amd.serve import Server
+    w = synth.workload(5, dims=(100, 90, 80), segments=40)
+    g = _graph(("serve", w.dims), synth.make_volume(w))
+    one = Server(g, slots=1, max_batch=1, max_tf=1, use_graphs=False).device_bytes
+    g2, boxes, res, stats = _served(w, 400, 50000.0, slots=4, max_batch=512, max_tf=4,
+                                    budget_bytes=one * 3, use_graphs=False)
+    assert max(stats.batch_sizes) <= 512
+    ids, vol_c = scan.compact(synth.make_volume(w))
+    _, ref = scan.box_counts(vol_c, len(ids), boxes)
+    _compare(res, ref, None, "small budget")
+    with pytest.raises(ValueError):
+        Server(g, budget_bytes=16)
