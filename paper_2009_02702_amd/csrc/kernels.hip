@@ -69,64 +69,31 @@ struct LevelTable {
     uint64_t total;                  // elements of one full copy (maps_t starts here)
 };
 
-// Unsigned division by a runtime-invariant divisor (Granlund and Montgomery,
-// "Division by Invariant Integers using Multiplication", PLDI 1994): with
-// s = ceil(log2 d) and m = floor(2^32 (2^s - d) / d) + 1, n / d equals
-// (umulhi(n, m) + n) >> s for every 32-bit n.
-struct FastDiv {
-    uint32_t d, m, s;
-};
-
-__host__ __device__ inline FastDiv make_fastdiv(uint32_t d)
-{
-    FastDiv f;
-    f.d = d;
-    uint32_t s = 0;
-    while ((uint64_t(1) << s) < d) ++s;
-    f.s = s;
-    f.m = uint32_t(((uint64_t(1) << 32) * ((uint64_t(1) << s) - d)) / d + 1);
-    return f;
-}
-
-__device__ inline uint32_t fdiv(uint32_t n, const FastDiv &f)
-{
-    const uint64_t t = uint64_t(__umulhi(n, f.m)) + n;
-    return uint32_t(t >> f.s);
-}
-
+// A slab of cubes at one level, as read from memory: the fast axis is the
+// contiguous one of the chosen copy (x in maps, y in maps_t); the other two are
+// ordered so that the slow axis is the thinner one. Lanes cover tiles of
+// 2^ltx cubes along the fast axis times 64 / 2^ltx rows along the mid axis.
 struct Slab {
     uint32_t count;      // cubes
     uint32_t level;
-    uint32_t transposed; // 1: read from maps_t (y fastest)
+    uint32_t e0, e1, e2; // extents along the fast, mid and slow axes
+    uint32_t s1, s2;     // element strides of the mid and slow axes (fast axis: 1)
+    uint32_t ltx;        // log2 of the tile width along the fast axis
+    uint32_t axes;       // fast | mid << 2 | slow << 4 (0 = x, 1 = y, 2 = z)
     uint32_t bx, by, bz; // first cube, level coordinates
-    FastDiv e0, e1;      // extents of the fastest and middle iteration axes
-    uint32_t s1;         // element stride of the middle axis
     uint32_t pad;
-    uint64_t s2;         // element stride of the slowest axis
     uint64_t base;       // element index of the first cube in the combined map buffer
 };
 
-// Element index and level coordinates of cube r of a slab.
-__device__ inline uint64_t slab_addr(const Slab &sl, uint32_t r)
+// Level coordinates of the cube at (fast, mid, slow) offsets (i0, i1, i2).
+__device__ inline void slab_coords(const Slab &sl, uint32_t i0, uint32_t i1, uint32_t i2, uint32_t *x,
+                                   uint32_t *y, uint32_t *z)
 {
-    const uint32_t q = fdiv(r, sl.e0);
-    const uint32_t i0 = r - q * sl.e0.d;
-    const uint32_t i2 = fdiv(q, sl.e1);
-    const uint32_t i1 = q - i2 * sl.e1.d;
-    return sl.base + i0 + uint64_t(i1) * sl.s1 + uint64_t(i2) * sl.s2;
-}
-
-__device__ inline void slab_coords(const Slab &sl, uint32_t r, uint32_t *x, uint32_t *y, uint32_t *z)
-{
-    const uint32_t q = fdiv(r, sl.e0);
-    const uint32_t i0 = r - q * sl.e0.d;
-    const uint32_t i2 = fdiv(q, sl.e1);
-    const uint32_t i1 = q - i2 * sl.e1.d;
-    if (sl.transposed) {
-        *x = sl.bx + i2, *y = sl.by + i0, *z = sl.bz + i1;
-    } else {
-        *x = sl.bx + i0, *y = sl.by + i1, *z = sl.bz + i2;
-    }
+    uint32_t c[3] = {sl.bx, sl.by, sl.bz};
+    c[sl.axes & 3] += i0;
+    c[(sl.axes >> 2) & 3] += i1;
+    c[(sl.axes >> 4) & 3] += i2;
+    *x = c[0], *y = c[1], *z = c[2];
 }
 
 // Clipped box: half-open ranges; returns false for an empty box.
@@ -158,22 +125,27 @@ __device__ inline void put_slab(Slab *out, int *n, const LevelTable &lt, uint32_
     s.level = lev;
     s.bx = x0, s.by = y0, s.bz = z0;
     s.pad = 0;
+    uint32_t f, m, w, ef, em, ew, sm, sw;
     if (ex < ey) {
         // rows along y in the transposed copy: index y + Y (z + Z x)
-        s.transposed = 1;
-        s.e0 = make_fastdiv(ey);
-        s.e1 = make_fastdiv(ez);
-        s.s1 = Y;
-        s.s2 = uint64_t(Y) * Z;
+        f = 1, ef = ey;
+        const uint32_t sz = Y, sx = Y * Z;
+        if (ez >= ex) m = 2, em = ez, sm = sz, w = 0, ew = ex, sw = sx;
+        else m = 0, em = ex, sm = sx, w = 2, ew = ez, sw = sz;
         s.base = lt.total + lt.off[lev] + y0 + uint64_t(Y) * (z0 + uint64_t(Z) * x0);
     } else {
-        s.transposed = 0;
-        s.e0 = make_fastdiv(ex);
-        s.e1 = make_fastdiv(ey);
-        s.s1 = X;
-        s.s2 = uint64_t(X) * Y;
+        f = 0, ef = ex;
+        const uint32_t sy = X, sz = X * Y;
+        if (ey >= ez) m = 1, em = ey, sm = sy, w = 2, ew = ez, sw = sz;
+        else m = 2, em = ez, sm = sz, w = 1, ew = ey, sw = sy;
         s.base = lt.off[lev] + x0 + uint64_t(X) * (y0 + uint64_t(Y) * z0);
     }
+    s.e0 = ef, s.e1 = em, s.e2 = ew;
+    s.s1 = sm, s.s2 = sw;
+    s.axes = f | (m << 2) | (w << 4);
+    uint32_t ltx = 0;
+    while (ltx < 6 && (1u << ltx) < ef) ++ltx;  // tile width: smallest power of two >= e0, at most 64
+    s.ltx = ltx;
     out[(*n)++] = s;
 }
 
@@ -408,57 +380,83 @@ __device__ inline uint32_t run_length(uint32_t v)
 
 __device__ inline uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// n / d for n < 2^31 (the sum below then stays below 2^32).
-__device__ inline uint32_t fdiv31(uint32_t n, uint32_t m, uint32_t s) { return (__umulhi(n, m) + n) >> s; }
+// Streams one slab of node IDs: a wave covers a block of UNROLL lane tiles;
+// lane (lx, ly) = (lane mod 2^ltx, lane / 2^ltx) reads element
+// (t0 * 2^ltx + lx, rb + u * 64/2^ltx + ly) of slow slice k2, u = 0 .. UNROLL-1,
+// so the UNROLL loads of a lane are independent and all in flight together
+// (lanes outside the slab read a clamped address and see kEmpty). Blocks
+// (k2, rb, t0) are dealt to waves round-robin starting at wave `first`;
+// `use(v, u)` consumes the UNROLL values of each block (every lane calls it).
+// Extents and strides are wave-uniform (scalar registers). Returns false if
+// `stop()` became true (checked every 8 blocks).
+template <int UNROLL, int WAVES, class Use, class Stop>
+__device__ inline bool stream_slab(const uint32_t *__restrict__ p, uint32_t e0, uint32_t e1, uint32_t e2, uint32_t s1,
+                                   uint32_t s2, uint32_t ltx, uint32_t first, Use use, Stop stop)
+{
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t ty = 64u >> ltx;                       // rows per tile
+    const uint32_t n_t0 = (e0 + (1u << ltx) - 1) >> ltx;  // tiles along the fast axis
+    const uint32_t rows = ty * UNROLL;                     // rows per block
+    const uint32_t n_rb = (e1 + rows - 1) / rows;          // blocks along the mid axis
+    const uint32_t n_blk = n_t0 * n_rb * e2;
+    const uint32_t lx = lane & ((1u << ltx) - 1), ly = lane >> ltx;
+    uint32_t fb = (wave + WAVES - first) % WAVES;
+    if (fb >= n_blk) return true;
+    uint32_t t0 = fb % n_t0, rest = fb / n_t0;
+    uint32_t rb = rest % n_rb, k2 = rest / n_rb;
+    const bool mul24 = s1 < (1u << 24);
+    uint32_t iter = 0;
+    for (; fb < n_blk; fb += WAVES) {
+        if ((++iter & 7u) == 0 && stop()) return false;
+        const uint32_t i0 = (t0 << ltx) + lx;
+        const uint32_t row0 = rb * rows + ly;
+        const uint32_t off0 = i0 + k2 * s2;
+        const bool col_ok = i0 < e0;
+        uint32_t v[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const uint32_t i1 = row0 + u * ty;
+            const bool ok = col_ok && i1 < e1;
+            const uint32_t off = (mul24 ? __umul24(i1, s1) : i1 * s1) + off0;
+            v[u] = p[ok ? off : 0u];
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const uint32_t i1 = row0 + u * ty;
+            use((col_ok && i1 < e1) ? v[u] : kEmpty);
+        }
+        // advance to this wave's next block
+        t0 += WAVES;
+        while (t0 >= n_t0) {
+            t0 -= n_t0;
+            if (++rb == n_rb) rb = 0, ++k2;
+        }
+    }
+    return true;
+}
 
 // Scatter: every cube of every slab adds 8^level to its node. Neighbouring
 // lanes usually hold the same node (mixtures are spatially coherent), so each
-// run of equal nodes in a wave adds once: run length * 8^level. Slab
-// parameters are wave-uniform (scalar registers); the UNROLL node-ID loads
-// of a lane are unconditional (the index is clamped into the slab) so they are
-// all in flight together.
+// run of equal nodes in a wave adds once: run length * 8^level.
 template <int BLOCK, int UNROLL, bool SPARSE>
 __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint32_t *__restrict__ maps,
                                      const QueryState &st, const GraphView &gv, const uint32_t *flags_lds)
 {
     constexpr uint32_t kWaves = BLOCK / 64;
-    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int si = 0; si < n_slabs; ++si) {
         const Slab &sp = slabs[si];
-        const uint32_t count = uni(sp.count);
-        // a slab that one wave covers in one pass is taken by one wave only
-        const bool one_wave = count <= 64u * UNROLL;
-        if (one_wave && (uint32_t(si) % kWaves) != wave) continue;
-        if (uni(*flags_lds) & 1u) return;  // overflowed: this block gives the box to the fallback
+        if (uni(*flags_lds) & 1u) return;  // overflowed: the box goes to the retry launch
         const uint32_t w8 = 1u << (3 * uni(sp.level));
-        const uint32_t d0 = uni(sp.e0.d), m0 = uni(sp.e0.m), s0 = uni(sp.e0.s);
-        const uint32_t d1 = uni(sp.e1.d), m1 = uni(sp.e1.m), s1s = uni(sp.e1.s);
-        const uint32_t str1 = uni(sp.s1), str2 = uni(uint32_t(sp.s2));
         const uint64_t base = (uint64_t(uni(uint32_t(sp.base >> 32))) << 32) | uni(uint32_t(sp.base));
-        const uint32_t *__restrict__ p = maps + base;
-        const uint32_t last = count - 1;
-        const uint32_t step = one_wave ? 64u : uint32_t(BLOCK);
-        const uint32_t start = one_wave ? 0u : (threadIdx.x & ~63u);
-        uint32_t iter = 0;
-        for (uint32_t b0 = start; b0 < count; b0 += UNROLL * step) {
-            if ((++iter & 7u) == 0 && (uni(*flags_lds) & 1u)) return;
-            uint32_t node[UNROLL];
-#pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
-                const uint32_t r = min(b0 + lane + u * step, last);
-                const uint32_t q = fdiv31(r, m0, s0);
-                const uint32_t i0 = r - q * d0;
-                const uint32_t i2 = fdiv31(q, m1, s1s);
-                const uint32_t i1 = q - i2 * d1;
-                node[u] = p[i0 + i1 * str1 + i2 * str2];
-            }
-#pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
-                const uint32_t v = (b0 + lane + u * step) < count ? node[u] : kEmpty;
+        const bool go = stream_slab<UNROLL, kWaves>(
+            maps + base, uni(sp.e0), uni(sp.e1), uni(sp.e2), uni(sp.s1), uni(sp.s2), uni(sp.ltx),
+            uint32_t(si) % kWaves,
+            [&](uint32_t v) {
                 const uint32_t len = run_length(v);
                 if (len) scatter_count<SPARSE>(st, gv, v, len * w8);
-            }
-        }
+            },
+            [&]() { return (uni(*flags_lds) & 1u) != 0; });
+        if (!go) return;
     }
 }
 
@@ -907,30 +905,17 @@ __global__ __launch_bounds__(kBlock) void naive_kernel(NaiveArgs A)
     __syncthreads();
     if (nonempty) {
         const uint32_t ex = hi[0] - lo[0], ey = hi[1] - lo[1], ez = hi[2] - lo[2];
-        const FastDiv fx = make_fastdiv(ex), fy = make_fastdiv(ey);
         const uint32_t X = A.lt.vol[0], XY = A.lt.vol[0] * A.lt.vol[1];
         const uint32_t *__restrict__ p = A.map0 + (lo[0] + uint64_t(X) * lo[1] + uint64_t(XY) * lo[2]);
-        const uint32_t total = ex * ey * ez;  // < 2^31: the whole volume is
-        const uint32_t last = total - 1;
-        const uint32_t lane = threadIdx.x & 63;
-        for (uint32_t b0 = threadIdx.x & ~63u; b0 < total; b0 += UNROLL * kBlock) {
-            uint32_t v[UNROLL];
-#pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
-                const uint32_t r = min(b0 + lane + u * kBlock, last);
-                const uint32_t qy = fdiv31(r, fx.m, fx.s);
-                const uint32_t ix = r - qy * ex;
-                const uint32_t iz = fdiv31(qy, fy.m, fy.s);
-                const uint32_t iy = qy - iz * ey;
-                v[u] = p[ix + X * iy + XY * iz];
-            }
-#pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
-                const uint32_t val = (b0 + lane + u * kBlock) < total ? v[u] : kEmpty;
-                const uint32_t len = run_length(val);
-                if (len) atomicAdd(&cnt[val], len);
-            }
-        }
+        uint32_t ltx = 0;
+        while (ltx < 6 && (1u << ltx) < ex) ++ltx;
+        stream_slab<UNROLL, kBlock / 64>(
+            p, ex, ey, ez, X, XY, ltx, 0u,
+            [&](uint32_t v) {
+                const uint32_t len = run_length(v);
+                if (len) atomicAdd(&cnt[v], len);
+            },
+            []() { return false; });
     }
     __syncthreads();
     const double vol = nonempty ? double(hi[0] - lo[0]) * double(hi[1] - lo[1]) * double(hi[2] - lo[2]) : 0.0;
@@ -960,9 +945,10 @@ __global__ __launch_bounds__(kBlock) void footprint_kernel(LevelTable lt, const 
         if (threadIdx.x == 0) atomicAdd(&per_level[sl.level], sl.count);
         if (!cubes) continue;
         for (uint32_t r = threadIdx.x; r < sl.count; r += kBlock) {
+            const uint32_t i0 = r % sl.e0, i1 = (r / sl.e0) % sl.e1, i2 = r / (sl.e0 * sl.e1);
             uint32_t x, y, z;
-            slab_coords(sl, r, &x, &y, &z);
-            const uint32_t node = maps[slab_addr(sl, r)];
+            slab_coords(sl, i0, i1, i2, &x, &y, &z);
+            const uint32_t node = maps[sl.base + i0 + uint64_t(i1) * sl.s1 + uint64_t(i2) * sl.s2];
             const uint32_t k = atomicAdd(count, 1u);
             if (k < cap) {
                 uint32_t *c = cubes + 6 * uint64_t(k);
