@@ -49,6 +49,64 @@ def read_traffic(kernel: str, workload: str, bytes_per_launch_alg: float):
     return float(e["hbm_bytes_per_launch"])
 
 
+def measure_tf(g, w, T, steps, warmup):
+    """Frames of T transfer functions propagated leaf -> node; HIP-event time of the step kernels."""
+    import numpy as np
+    import torch
+    from paper_2009_02702_amd import synth
+    inf = g.info()
+    S, N, D = inf["nseg"], inf["n_nodes"], inf["depth"]
+    tf = torch.from_numpy(synth.make_tfs(w, S, T)).cuda()
+    pal = torch.empty((T, N, 4), dtype=torch.float32, device="cuda")
+    for _ in range(warmup):
+        g.propagate_tf(tf, out=pal)
+    torch.cuda.synchronize()
+    g.timing_read()
+    g.timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.propagate_tf(tf, out=pal)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms, k = g.timing_read()
+    g.timing(False)
+    kern_ms = ms / max(k, 1)
+    internal = N - S
+    # per internal node: its 16-B schedule entry, T pairs of 16-B gathers and one 16-B store
+    alg = internal * (16.0 + 48.0 * T)
+    achieved = alg / (kern_ms * 1e-3) / 1e9
+    return {"frames_per_s": steps / el, "ms_per_frame": 1e3 * el / steps, "tfs_per_frame": T,
+            "nodes": N, "depth": D, "steps_launched": D,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "tf_step_kernel x depth",
+                         "kernel_ms": kern_ms, "alg_bytes_per_launch": alg,
+                         "alg_bytes_formula": "internal nodes x (16 + 48 T)"}}
+
+
+def measure_serve(g, w, qps_list, seconds):
+    """Poisson arrivals through the continuous-batching server; p50/p99 latency and achieved rate."""
+    import numpy as np
+    from paper_2009_02702_amd import synth
+    from paper_2009_02702_amd.serve import Server
+    S = g.info()["nseg"]
+    srv = Server(g, slots=4, max_batch=4096, max_tf=64)
+    out = []
+    for qps in qps_list:
+        n = max(1000, int(qps * seconds))
+        boxes = synth.make_boxes(w, n)
+        arr = synth.poisson_arrivals(w, n, qps)
+        tf_index = np.full(n, -1, dtype=np.int64)
+        rows = np.arange(0, n, 10)                     # 10% of the requests carry a TF
+        tf_index[rows] = np.arange(len(rows))
+        tfs = synth.make_tfs(w, S, len(rows))
+        st = srv.serve(boxes, arr, tf_index, tfs)
+        r = st.summary()
+        r["offered_qps"] = qps
+        out.append(r)
+        print("[bench] serve %s" % r, file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,10 +116,17 @@ def main():
     ap.add_argument("--competitor-steps", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=("full", "query", "copy"), default="full",
+    ap.add_argument("--mode", choices=("full", "query", "copy", "tf", "serve"), default="full",
                     help="full: the JSON line; query: only the timed batched launches (for profilers); "
-                         "copy: one device copy of --copy-mib MiB (calibrates HBM byte counters)")
+                         "copy: one device copy of --copy-mib MiB (calibrates HBM byte counters); "
+                         "tf: transfer-function propagation frames (8 TFs) on --config; "
+                         "serve: Poisson-arrival stream through the continuous-batching server on --config")
+    ap.add_argument("--tf-count", type=int, default=8)
+    ap.add_argument("--qps", type=str, default="5000,20000,50000,100000,200000")
+    ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--serve-qps", type=float, default=100000.0,
+                    help="full mode: offered rate of the short serving leg (per-request p50/p99); 0 skips it")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -102,6 +167,16 @@ def main():
     ws = g.workspace(n)
     torch.cuda.synchronize()
 
+    if args.mode == "tf":
+        r = measure_tf(g, w, args.tf_count, args.steps, args.warmup)
+        r.update({"mode": "tf", "workload": w.name})
+        print(json.dumps(r), flush=True)
+        return
+    if args.mode == "serve":
+        qps = [float(x) for x in args.qps.split(",") if x]
+        r = {"mode": "serve", "workload": w.name, "levels": measure_serve(g, w, qps, args.serve_seconds)}
+        print(json.dumps(r), flush=True)
+        return
     if args.mode == "query":
         for _ in range(args.warmup):
             g.query(dboxes, out=out, workspace=ws)
@@ -166,6 +241,16 @@ def main():
                    "kernel_ms": k2}
         print("[bench] %s: %.3f ms/step" % (v, comp[v]["ms_per_step"]), file=sys.stderr, flush=True)
 
+    tf_meas = measure_tf(g, w, args.tf_count, max(3, args.steps // 2), 1)
+    print("[bench] tf: %.3f ms per frame of %d TFs" % (tf_meas["ms_per_frame"], args.tf_count), file=sys.stderr,
+          flush=True)
+
+    serving = None
+    if args.serve_qps > 0:
+        serving = measure_serve(g, w, [args.serve_qps], args.serve_seconds)[0]
+        serving["what"] = ("per-request latency (completion - arrival) of Poisson arrivals through the "
+                           "continuous-batching server, 10% of requests with one TF")
+
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     traffic = read_traffic("query_tier_kernel", w.name, alg_bytes)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -211,7 +296,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "max_rel_err_vs_oracle": max_rel,
+        "serving": serving,
         "competitors": comp,
+        "tf_propagation": tf_meas,
         "speedup_vs_naive": value / comp["naive"]["value"],
         "speedup_vs_plain": value / comp["plain"]["value"],
         "launch": tuned,

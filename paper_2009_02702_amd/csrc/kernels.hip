@@ -145,6 +145,7 @@ __device__ inline void put_slab(Slab *out, int *n, const LevelTable &lt, uint32_
     s.axes = f | (m << 2) | (w << 4);
     uint32_t ltx = 0;
     while (ltx < 6 && (1u << ltx) < ef) ++ltx;  // tile width: smallest power of two >= e0, at most 64
+    if (sm >= (1u << 24)) ltx = 6;  // one row per tile: lane byte offsets stay below 2^32
     s.ltx = ltx;
     out[(*n)++] = s;
 }
@@ -362,20 +363,29 @@ __device__ inline void scatter_count(const QueryState &st, const GraphView &gv, 
 }
 
 // Run-length merge of equal neighbours in a wave: lane i starts a run when its
-// value differs from lane i-1's (DPP wave shift right by one lane); the run
-// length is the distance to the next run start. Returns the run length at run
-// starts and 0 elsewhere. Values must be kEmpty exactly on a tail of lanes.
-__device__ inline uint32_t run_length(uint32_t v)
+// value differs from lane i-1's (DPP wave shift right by one lane; lane 0 sees
+// kEmpty); the run length is the distance to the next run start. `above_lo` /
+// `above_hi` are this lane's masks of the higher lanes (zero for lane 63).
+// Returns the run length at run starts and 0 elsewhere; runs of kEmpty count 0.
+__device__ inline uint32_t run_length(uint32_t v, uint32_t above_lo, uint32_t above_hi)
 {
     const uint32_t lane = threadIdx.x & 63;
-    // lane 0 has no source lane and keeps `old` (~v), so it always starts a run
-    const uint32_t prev = uint32_t(__builtin_amdgcn_update_dpp(int(~v), int(v), 0x138, 0xF, 0xF, false));
+    const uint32_t prev = uint32_t(__builtin_amdgcn_update_dpp(int(kEmpty), int(v), 0x138, 0xF, 0xF, false));
     const bool head = v != prev;
     const uint64_t heads = __ballot(head);
     if (!head || v == kEmpty) return 0;
-    const uint64_t above = lane == 63 ? 0 : heads & (~uint64_t(0) << (lane + 1));
-    const uint32_t next = above ? uint32_t(__builtin_ctzll(above)) : 64u;
+    // first run start above this lane, 64 if none
+    const uint64_t m = heads & ((uint64_t(above_hi) << 32) | above_lo);
+    const uint32_t next = m ? uint32_t(__builtin_ctzll(m)) : 64u;
     return next - lane;
+}
+
+__device__ inline void lane_above_masks(uint32_t *lo, uint32_t *hi)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t m = lane == 63 ? 0 : (~uint64_t(0) << (lane + 1));
+    *lo = uint32_t(m);
+    *hi = uint32_t(m >> 32);
 }
 
 __device__ inline uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -386,45 +396,47 @@ __device__ inline uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstla
 // so the UNROLL loads of a lane are independent and all in flight together
 // (lanes outside the slab read a clamped address and see kEmpty). Blocks
 // (k2, rb, t0) are dealt to waves round-robin starting at wave `first`;
-// `use(v, u)` consumes the UNROLL values of each block (every lane calls it).
-// Extents and strides are wave-uniform (scalar registers). Returns false if
-// `stop()` became true (checked every 8 blocks).
+// `use(v)` consumes each of the UNROLL values of a block (every lane calls it).
+// The row base of every u is a wave-uniform pointer (scalar registers) and a
+// lane adds a 32-bit byte offset (< 64 rows of the mid stride), so a load
+// costs no 64-bit vector arithmetic. Returns false if `stop()` became true
+// (checked every 8 blocks).
 template <int UNROLL, int WAVES, class Use, class Stop>
 __device__ inline bool stream_slab(const uint32_t *__restrict__ p, uint32_t e0, uint32_t e1, uint32_t e2, uint32_t s1,
                                    uint32_t s2, uint32_t ltx, uint32_t first, Use use, Stop stop)
 {
-    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint32_t ty = 64u >> ltx;                       // rows per tile
+    const uint32_t lane = threadIdx.x & 63, wave = uni(threadIdx.x >> 6);  // the wave index is uniform
+    const uint32_t lty = 6u - ltx;
+    const uint32_t ty = 1u << lty;                        // rows per tile
     const uint32_t n_t0 = (e0 + (1u << ltx) - 1) >> ltx;  // tiles along the fast axis
     const uint32_t rows = ty * UNROLL;                     // rows per block
     const uint32_t n_rb = (e1 + rows - 1) / rows;          // blocks along the mid axis
     const uint32_t n_blk = n_t0 * n_rb * e2;
     const uint32_t lx = lane & ((1u << ltx) - 1), ly = lane >> ltx;
+    const uint32_t ly_bytes = ly * s1 * 4u;                // < 64 * s1 * 4 < 2^32 (s1 < 2^24)
+    const uint64_t row_step = uint64_t(ty) * s1 * 4u;      // bytes between the rows of u and u + 1
     uint32_t fb = (wave + WAVES - first) % WAVES;
     if (fb >= n_blk) return true;
     uint32_t t0 = fb % n_t0, rest = fb / n_t0;
     uint32_t rb = rest % n_rb, k2 = rest / n_rb;
-    const bool mul24 = s1 < (1u << 24);
     uint32_t iter = 0;
     for (; fb < n_blk; fb += WAVES) {
         if ((++iter & 7u) == 0 && stop()) return false;
         const uint32_t i0 = (t0 << ltx) + lx;
         const uint32_t row0 = rb * rows + ly;
-        const uint32_t off0 = i0 + k2 * s2;
-        const bool col_ok = i0 < e0;
+        // rows of this lane inside the slab: u < n_ok
+        const uint32_t n_ok = (i0 < e0 && row0 < e1) ? ((e1 - row0 + ty - 1) >> lty) : 0u;
+        const char *blk = reinterpret_cast<const char *>(p) +
+                          (uint64_t(rb) * rows * s1 + uint64_t(k2) * s2 + (t0 << ltx)) * 4u;
+        const uint32_t lane_bytes = ly_bytes + lx * 4u;
         uint32_t v[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            const uint32_t i1 = row0 + u * ty;
-            const bool ok = col_ok && i1 < e1;
-            const uint32_t off = (mul24 ? __umul24(i1, s1) : i1 * s1) + off0;
-            v[u] = p[ok ? off : 0u];
+            const char *row = blk + u * row_step;
+            v[u] = *reinterpret_cast<const uint32_t *>(row + (uint32_t(u) < n_ok ? lane_bytes : 0u));
         }
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-            const uint32_t i1 = row0 + u * ty;
-            use((col_ok && i1 < e1) ? v[u] : kEmpty);
-        }
+        for (int u = 0; u < UNROLL; ++u) use(uint32_t(u) < n_ok ? v[u] : kEmpty);
         // advance to this wave's next block
         t0 += WAVES;
         while (t0 >= n_t0) {
@@ -437,23 +449,45 @@ __device__ inline bool stream_slab(const uint32_t *__restrict__ p, uint32_t e0, 
 
 // Scatter: every cube of every slab adds 8^level to its node. Neighbouring
 // lanes usually hold the same node (mixtures are spatially coherent), so each
-// run of equal nodes in a wave adds once: run length * 8^level.
+// run of equal nodes in a wave adds once: run length * 8^level. Runs on
+// sources add to an integer counter; runs on internal nodes (rare) take a
+// branch that the whole wave skips when no lane needs it.
 template <int BLOCK, int UNROLL, bool SPARSE>
 __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint32_t *__restrict__ maps,
                                      const QueryState &st, const GraphView &gv, const uint32_t *flags_lds)
 {
     constexpr uint32_t kWaves = BLOCK / 64;
+    const uint32_t nseg = gv.nseg;
+    uint32_t alo, ahi;
+    lane_above_masks(&alo, &ahi);
+    const uint64_t above = (uint64_t(ahi) << 32) | alo;
+    const uint32_t lane = threadIdx.x & 63;
     for (int si = 0; si < n_slabs; ++si) {
         const Slab &sp = slabs[si];
         if (uni(*flags_lds) & 1u) return;  // overflowed: the box goes to the retry launch
-        const uint32_t w8 = 1u << (3 * uni(sp.level));
+        const uint32_t lw8 = 3 * uni(sp.level);
+        const uint32_t w8 = 1u << lw8;
         const uint64_t base = (uint64_t(uni(uint32_t(sp.base >> 32))) << 32) | uni(uint32_t(sp.base));
         const bool go = stream_slab<UNROLL, kWaves>(
             maps + base, uni(sp.e0), uni(sp.e1), uni(sp.e2), uni(sp.s1), uni(sp.s2), uni(sp.ltx),
             uint32_t(si) % kWaves,
             [&](uint32_t v) {
-                const uint32_t len = run_length(v);
-                if (len) scatter_count<SPARSE>(st, gv, v, len * w8);
+                if (SPARSE) {
+                    const uint32_t len = run_length(v, alo, ahi);
+                    if (len) scatter_count<SPARSE>(st, gv, v, len << lw8);
+                    return;
+                }
+                // run starts: value differs from the previous lane's (lane 0 sees kEmpty)
+                const uint32_t prev =
+                    uint32_t(__builtin_amdgcn_update_dpp(int(kEmpty), int(v), 0x138, 0xF, 0xF, false));
+                const uint64_t starts = __ballot(v != prev);
+                const bool head = v != prev && v != kEmpty;
+                const uint64_t m = starts & above;
+                const uint32_t len = (m ? uint32_t(__builtin_ctzll(m)) : 64u) - lane;
+                if (head && v < nseg) atomicAdd(&st.seg_cnt[v], len << lw8);
+                // runs on internal nodes: a branch the wave skips unless a lane needs it
+                if (__builtin_expect(__ballot(head && v >= nseg) != 0, 0))
+                    if (head && v >= nseg) scatter_count<SPARSE>(st, gv, v, len << lw8);
             },
             [&]() { return (uni(*flags_lds) & 1u) != 0; });
         if (!go) return;
@@ -909,10 +943,13 @@ __global__ __launch_bounds__(kBlock) void naive_kernel(NaiveArgs A)
         const uint32_t *__restrict__ p = A.map0 + (lo[0] + uint64_t(X) * lo[1] + uint64_t(XY) * lo[2]);
         uint32_t ltx = 0;
         while (ltx < 6 && (1u << ltx) < ex) ++ltx;
+        if (X >= (1u << 24)) ltx = 6;  // one row per tile: lane byte offsets stay below 2^32
+        uint32_t alo, ahi;
+        lane_above_masks(&alo, &ahi);
         stream_slab<UNROLL, kBlock / 64>(
             p, ex, ey, ez, X, XY, ltx, 0u,
             [&](uint32_t v) {
-                const uint32_t len = run_length(v);
+                const uint32_t len = run_length(v, alo, ahi);
                 if (len) atomicAdd(&cnt[v], len);
             },
             []() { return false; });
