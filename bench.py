@@ -255,7 +255,7 @@ def main():
     traffic = read_traffic("query_tier_kernel", w.name, alg_bytes)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "query_tier_kernel (big-box tier + small-box tier, timed together)",
+                "kernel": "query_tier_kernel big + small tiers, with query_retry_kernel and query_fallback_kernel (timed together)",
                 "kernel_ms": kern_ms,
                 "alg_bytes_per_launch": alg_bytes,
                 "alg_bytes_formula": "sum over boxes of 24 + 4*cubes + 12*graph nodes touched + 4*S (dense output)"}

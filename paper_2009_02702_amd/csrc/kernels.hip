@@ -362,30 +362,40 @@ __device__ inline void scatter_count(const QueryState &st, const GraphView &gv, 
     }
 }
 
-// Run-length merge of equal neighbours in a wave: lane i starts a run when its
-// value differs from lane i-1's (DPP wave shift right by one lane; lane 0 sees
-// kEmpty); the run length is the distance to the next run start. `above_lo` /
-// `above_hi` are this lane's masks of the higher lanes (zero for lane 63).
-// Returns the run length at run starts and 0 elsewhere; runs of kEmpty count 0.
-__device__ inline uint32_t run_length(uint32_t v, uint32_t above_lo, uint32_t above_hi)
+__device__ inline uint64_t lane_above_mask()
 {
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t prev = uint32_t(__builtin_amdgcn_update_dpp(int(kEmpty), int(v), 0x138, 0xF, 0xF, false));
-    const bool head = v != prev;
-    const uint64_t heads = __ballot(head);
-    if (!head || v == kEmpty) return 0;
-    // first run start above this lane, 64 if none
-    const uint64_t m = heads & ((uint64_t(above_hi) << 32) | above_lo);
-    const uint32_t next = m ? uint32_t(__builtin_ctzll(m)) : 64u;
-    return next - lane;
+    return lane == 63 ? 0 : (~uint64_t(0) << (lane + 1));
 }
 
-__device__ inline void lane_above_masks(uint32_t *lo, uint32_t *hi)
+// Run starts of a wave: lane 0, and every lane whose value differs from lane
+// i-1's (DPP wave shift right by one lane; the shift fills lane 0 with 0, and
+// lane 0 is a start regardless). Returned as the wave mask of start lanes,
+// taken straight from the vector compare.
+__device__ inline uint64_t run_starts(uint32_t v, uint32_t *prev_out)
+{
+    const uint32_t prev = uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x138, 0xF, 0xF, true));
+    *prev_out = prev;
+    return __builtin_amdgcn_uicmp(v, prev, 33 /* ne */) | 1u;
+}
+
+// Distance from this lane to the next run start above it (64 if none):
+// the length of the run this lane starts. `above` = lane_above_mask().
+__device__ inline uint32_t run_len(uint64_t starts, uint64_t above, uint32_t lane)
+{
+    const uint64_t m = starts & above;
+    return (m ? uint32_t(__builtin_ctzll(m)) : 64u) - lane;
+}
+
+// Run-length merge of equal neighbours in a wave: true at the start lane of a
+// run of a real value (not kEmpty), with the run's length in *len.
+__device__ inline bool run_head(uint32_t v, uint64_t above, uint32_t *len)
 {
     const uint32_t lane = threadIdx.x & 63;
-    const uint64_t m = lane == 63 ? 0 : (~uint64_t(0) << (lane + 1));
-    *lo = uint32_t(m);
-    *hi = uint32_t(m >> 32);
+    uint32_t prev;
+    const uint64_t starts = run_starts(v, &prev);
+    *len = run_len(starts, above, lane);
+    return (v != prev || lane == 0) && v != kEmpty;
 }
 
 __device__ inline uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -458,9 +468,7 @@ __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint3
 {
     constexpr uint32_t kWaves = BLOCK / 64;
     const uint32_t nseg = gv.nseg;
-    uint32_t alo, ahi;
-    lane_above_masks(&alo, &ahi);
-    const uint64_t above = (uint64_t(ahi) << 32) | alo;
+    const uint64_t above = lane_above_mask();
     const uint32_t lane = threadIdx.x & 63;
     for (int si = 0; si < n_slabs; ++si) {
         const Slab &sp = slabs[si];
@@ -473,21 +481,20 @@ __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint3
             uint32_t(si) % kWaves,
             [&](uint32_t v) {
                 if (SPARSE) {
-                    const uint32_t len = run_length(v, alo, ahi);
-                    if (len) scatter_count<SPARSE>(st, gv, v, len << lw8);
+                    uint32_t len;
+                    if (run_head(v, above, &len)) scatter_count<SPARSE>(st, gv, v, len << lw8);
                     return;
                 }
-                // run starts: value differs from the previous lane's (lane 0 sees kEmpty)
-                const uint32_t prev =
-                    uint32_t(__builtin_amdgcn_update_dpp(int(kEmpty), int(v), 0x138, 0xF, 0xF, false));
-                const uint64_t starts = __ballot(v != prev);
-                const bool head = v != prev && v != kEmpty;
-                const uint64_t m = starts & above;
-                const uint32_t len = (m ? uint32_t(__builtin_ctzll(m)) : 64u) - lane;
-                if (head && v < nseg) atomicAdd(&st.seg_cnt[v], len << lw8);
+                uint32_t prev;
+                const uint64_t starts = run_starts(v, &prev);
+                const bool start = v != prev || lane == 0;
+                const uint32_t len = run_len(starts, above, lane);
+                if (start && v < nseg) atomicAdd(&st.seg_cnt[v], len << lw8);
                 // runs on internal nodes: a branch the wave skips unless a lane needs it
-                if (__builtin_expect(__ballot(head && v >= nseg) != 0, 0))
-                    if (head && v >= nseg) scatter_count<SPARSE>(st, gv, v, len << lw8);
+                const uint64_t internal = starts & ~__builtin_amdgcn_uicmp(v, nseg, 36 /* ult */) &
+                                          __builtin_amdgcn_uicmp(v, kEmpty, 33 /* ne */);
+                if (__builtin_expect(internal != 0, 0))
+                    if (start && v >= nseg && v != kEmpty) scatter_count<SPARSE>(st, gv, v, len << lw8);
             },
             [&]() { return (uni(*flags_lds) & 1u) != 0; });
         if (!go) return;
@@ -944,13 +951,12 @@ __global__ __launch_bounds__(kBlock) void naive_kernel(NaiveArgs A)
         uint32_t ltx = 0;
         while (ltx < 6 && (1u << ltx) < ex) ++ltx;
         if (X >= (1u << 24)) ltx = 6;  // one row per tile: lane byte offsets stay below 2^32
-        uint32_t alo, ahi;
-        lane_above_masks(&alo, &ahi);
+        const uint64_t above = lane_above_mask();
         stream_slab<UNROLL, kBlock / 64>(
             p, ex, ey, ez, X, XY, ltx, 0u,
             [&](uint32_t v) {
-                const uint32_t len = run_length(v, alo, ahi);
-                if (len) atomicAdd(&cnt[v], len);
+                uint32_t len;
+                if (run_head(v, above, &len)) atomicAdd(&cnt[v], len);
             },
             []() { return false; });
     }
@@ -1342,16 +1348,12 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
         A.table_cap = cap_small;
         hipLaunchKernelGGL(ksmall, dim3(wsmall), dim3(kBlock), dyn_small, s, A);
         HIP_TRY(hipGetLastError());
-        rc = timing_end(g, s, err);
-        if (rc) return rc;
     } else {
         A.table_cap = kHashPlain;
         rc = timing_begin(g, s, err);
         if (rc) return rc;
         hipLaunchKernelGGL(kplain, dim3(n), dim3(kBlock), dyn_plain, s, A);
         HIP_TRY(hipGetLastError());
-        rc = timing_end(g, s, err);
-        if (rc) return rc;
     }
     // boxes whose table overflowed: once more with a larger LDS table, then in global memory
     const QueryKernel kretry = query_retry_kernel<kBlockBig, 8, SPARSE>;
@@ -1376,7 +1378,8 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
     A.stats_tag = 0x80000000u;
     hipLaunchKernelGGL(query_fallback_kernel<SPARSE>, dim3(kFallbackWorkers), dim3(kBlock), 0, s, A);
     HIP_TRY(hipGetLastError());
-    return MG_OK;
+    // the timed region: every kernel that answers boxes (tiers or plain, retry, fallback)
+    return timing_end(g, s, err);
 }
 
 int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const SparseOut *sp, void *work,
