@@ -182,6 +182,39 @@ int mg_footprint(mg_graph *g, const uint32_t *d_boxes, uint32_t n, uint32_t *d_l
 int mg_propagate_tf(mg_graph *g, const uint8_t *d_tf, uint32_t T, float *d_node_rgba,
                     void *stream);
 
+/* Per-voxel palette fetch (Sec. "Rendering": a voxel's node ID indexes the
+ * colour lookup table, like a paletted texture; the same fetch on a
+ * propagated visibility channel gives the visible fraction used for empty
+ * space skipping). d_palette device fp32 [T][n_nodes][4] as written by
+ * mg_propagate_tf; d_xyz device uint32 [n][3] voxel coordinates at mip
+ * `level`; d_out device fp32 [T][n][4] = palette of the voxel's node.
+ * Coordinates outside the level's dimensions give (0, 0, 0, 0).
+ * MG_EINVAL for level >= n_levels. */
+int mg_palette_fetch(mg_graph *g, const float *d_palette, uint32_t T, uint32_t level,
+                     const uint32_t *d_xyz, uint32_t n, float *d_out, void *stream);
+
+/* Mixture lookup table (Sec. "Decoder": one mixture per node, found by
+ * carrying each source's unit vector through the interpolations; Sec.
+ * "Range queries" answers boxes from it). Built on the host in fp64 from the
+ * exact weights and stored fp32; uploaded now if the graph is on a device,
+ * otherwise by mg_upload. `threads` 0 = all cores. *out_nnz (may be NULL)
+ * receives the number of entries. MG_ELIMIT beyond 2^34 entries. */
+int mg_lut_build(mg_graph *g, uint32_t threads, uint64_t *out_nnz);
+
+/* Host copy of the lookup table: ptr host uint64 [n_nodes + 1]; row n is
+ * seg/val[ptr[n] .. ptr[n+1]), sources in increasing order, fractions fp32.
+ * seg and val may be NULL (then only ptr is written). MG_ESTATE if the
+ * table was not built. */
+int mg_export_lut(const mg_graph *g, uint64_t *ptr, uint32_t *seg, float *val);
+
+/* Box histograms answered from the mixture lookup table (the paper's own
+ * query, Sec. "Range queries"): the same footprint and scatter as
+ * mg_query_boxes, then every scattered graph node adds count * mixture row
+ * to the segments, instead of the rank-by-rank push. Same arguments and
+ * output as mg_query_boxes; MG_ESTATE unless mg_lut_build ran. */
+int mg_query_boxes_lut(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *d_out,
+                       void *d_work, uint64_t work_bytes, void *stream);
+
 /* Launch configuration of the GPU kernels (per graph, after mg_upload).
  * Defaults: 8, 8, 8, 256. */
 typedef struct {

@@ -255,6 +255,46 @@ int mg_propagate_tf(mg_graph *h, const uint8_t *d_tf, uint32_t T, float *d_node_
     return done(mg::dev_propagate_tf(&h->g, d_tf, T, d_node_rgba, stream, &err), err);
 }
 
+int mg_palette_fetch(mg_graph *h, const float *d_palette, uint32_t T, uint32_t level, const uint32_t *d_xyz,
+                     uint32_t n, float *d_out, void *stream)
+{
+    if (!h) return fail(MG_EINVAL, "mg_palette_fetch: null graph");
+    if (level >= h->g.n_levels)
+        return fail(MG_EINVAL, "mg_palette_fetch: level " + std::to_string(level) + " of a graph with " +
+                                   std::to_string(h->g.n_levels) + " levels");
+    if (T == 0 || n == 0) return MG_OK;
+    if (!d_palette || !d_xyz || !d_out) return fail(MG_EINVAL, "mg_palette_fetch: null buffer");
+    std::string err;
+    return done(mg::dev_palette_fetch(&h->g, d_palette, T, level, d_xyz, n, d_out, stream, &err), err);
+}
+
+int mg_lut_build(mg_graph *h, uint32_t threads, uint64_t *out_nnz)
+{
+    if (!h) return fail(MG_EINVAL, "mg_lut_build: null graph");
+    std::string err;
+    int rc = mg::build_lut(&h->g, threads, &err);
+    if (rc == MG_OK && h->g.dev.device >= 0) rc = mg::dev_upload_lut(&h->g, &err);
+    if (rc == MG_OK && out_nnz) *out_nnz = h->g.lut_ptr.back();
+    return done(rc, err);
+}
+
+int mg_export_lut(const mg_graph *h, uint64_t *ptr, uint32_t *seg, float *val)
+{
+    if (!h || !ptr) return fail(MG_EINVAL, "mg_export_lut: null argument");
+    const mg::Graph &g = h->g;
+    if (g.lut_ptr.empty()) return fail(MG_ESTATE, "mg_export_lut: the lookup table was not built (mg_lut_build)");
+    std::memcpy(ptr, g.lut_ptr.data(), g.lut_ptr.size() * sizeof(uint64_t));
+    if (seg) std::memcpy(seg, g.lut_seg.data(), g.lut_seg.size() * sizeof(uint32_t));
+    if (val) std::memcpy(val, g.lut_val.data(), g.lut_val.size() * sizeof(float));
+    return MG_OK;
+}
+
+int mg_query_boxes_lut(mg_graph *h, const uint32_t *d_boxes, uint32_t n, float *d_out, void *d_work,
+                       uint64_t work_bytes, void *stream)
+{
+    return query_common(h, d_boxes, n, d_out, d_work, work_bytes, stream, mg::kQueryLut, "mg_query_boxes_lut");
+}
+
 int mg_get_launch(const mg_graph *h, mg_launch_cfg *out)
 {
     if (!h || !out) return fail(MG_EINVAL, "mg_get_launch: null argument");

@@ -652,4 +652,84 @@ int validate_graph(const Graph &g, std::string *err)
     return MG_OK;
 }
 
+// Mixture lookup table (Sec. "Decoder", mixture lookup; used by range queries in
+// Sec. "Range queries"): the mixture of every node over the segments, found by
+// carrying the unit vector of each source through the interpolations in rank
+// order, mu_n = (1 - w_n) mu_a + w_n mu_b, in fp64 from the exact rational
+// weights, then stored as fp32. Rows list sources in increasing order. The
+// paper also carries a variance per entry for quantized weights; the weights
+// here are exact, so the variance would be zero and is not stored.
+int build_lut(Graph *g, uint32_t threads, std::string *err)
+{
+    const uint32_t S = g->nseg, N = g->n_nodes;
+    const unsigned nt = resolve_threads(threads);
+    std::vector<uint64_t> ptr(uint64_t(N) + 1, 0);
+    std::vector<uint32_t> seg(S);
+    std::vector<double> val(S, 1.0);
+    for (uint32_t s = 0; s < S; ++s) {
+        ptr[s] = s;
+        seg[s] = s;
+    }
+    ptr[S] = S;
+    const uint64_t kMaxEntries = uint64_t(1) << 34;
+    for (uint32_t r = 1; r <= g->depth; ++r) {
+        const uint32_t lo = g->rank_ptr[r], hi = g->rank_ptr[r + 1];
+        std::vector<uint64_t> len(hi - lo);
+        // entries of each row: the union of its two predecessors' rows (children have lower rank)
+        parallel_chunks(hi - lo, nt, [&](uint64_t b, uint64_t e, unsigned) {
+            for (uint64_t i = b; i < e; ++i) {
+                const uint32_t n = lo + uint32_t(i);
+                uint64_t pa = ptr[g->child_a[n]], ea = ptr[g->child_a[n] + 1];
+                uint64_t pb = ptr[g->child_b[n]], eb = ptr[g->child_b[n] + 1];
+                uint64_t k = 0;
+                while (pa < ea || pb < eb) {
+                    if (pb == eb || (pa < ea && seg[pa] < seg[pb])) ++pa;
+                    else if (pa == ea || seg[pb] < seg[pa]) ++pb;
+                    else ++pa, ++pb;
+                    ++k;
+                }
+                len[i] = k;
+            }
+        });
+        for (uint32_t i = 0; i < hi - lo; ++i) ptr[lo + i + 1] = ptr[lo + i] + len[i];
+        if (ptr[hi] > kMaxEntries) {
+            *err = "mixture lookup table beyond 2^34 entries";
+            return MG_ELIMIT;
+        }
+        seg.resize(ptr[hi]);
+        val.resize(ptr[hi]);
+        parallel_chunks(hi - lo, nt, [&](uint64_t b, uint64_t e, unsigned) {
+            for (uint64_t i = b; i < e; ++i) {
+                const uint32_t n = lo + uint32_t(i);
+                const double wb = double(g->wnum[n]) / double(g->wden[n]);
+                const double wa = double(g->wden[n] - g->wnum[n]) / double(g->wden[n]);
+                uint64_t pa = ptr[g->child_a[n]], ea = ptr[g->child_a[n] + 1];
+                uint64_t pb = ptr[g->child_b[n]], eb = ptr[g->child_b[n] + 1];
+                uint64_t k = ptr[n];
+                while (pa < ea || pb < eb) {
+                    if (pb == eb || (pa < ea && seg[pa] < seg[pb])) {
+                        seg[k] = seg[pa];
+                        val[k] = wa * val[pa];
+                        ++pa;
+                    } else if (pa == ea || seg[pb] < seg[pa]) {
+                        seg[k] = seg[pb];
+                        val[k] = wb * val[pb];
+                        ++pb;
+                    } else {
+                        seg[k] = seg[pa];
+                        val[k] = wa * val[pa] + wb * val[pb];
+                        ++pa, ++pb;
+                    }
+                    ++k;
+                }
+            }
+        });
+    }
+    g->lut_val.resize(val.size());
+    for (size_t i = 0; i < val.size(); ++i) g->lut_val[i] = float(val[i]);
+    g->lut_seg = std::move(seg);
+    g->lut_ptr = std::move(ptr);
+    return MG_OK;
+}
+
 }  // namespace mg

@@ -402,9 +402,12 @@ __device__ inline uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstla
 
 // Streams one slab of node IDs: a wave covers a block of UNROLL lane tiles;
 // lane (lx, ly) = (lane mod 2^ltx, lane / 2^ltx) reads element
-// (t0 * 2^ltx + lx, rb + u * 64/2^ltx + ly) of slow slice k2, u = 0 .. UNROLL-1,
-// so the UNROLL loads of a lane are independent and all in flight together
-// (lanes outside the slab read a clamped address and see kEmpty). Blocks
+// (t0 * 2^ltx + lx, rb * rows + u * 64/2^ltx + ly) of slow slice k2, u < UNROLL,
+// so the UNROLL loads of a lane are independent and all in flight together.
+// Row tiles that start past the slab's last row are not consumed (a wave-
+// uniform bound n_u) and load from the last tile that starts inside it; lanes
+// outside the slab read their tile's first element, inside the slab, and see
+// kEmpty, so every load stays inside the slab. Blocks
 // (k2, rb, t0) are dealt to waves round-robin starting at wave `first`;
 // `use(v)` consumes each of the UNROLL values of a block (every lane calls it).
 // The row base of every u is a wave-uniform pointer (scalar registers) and a
@@ -434,19 +437,27 @@ __device__ inline bool stream_slab(const uint32_t *__restrict__ p, uint32_t e0, 
         if ((++iter & 7u) == 0 && stop()) return false;
         const uint32_t i0 = (t0 << ltx) + lx;
         const uint32_t row0 = rb * rows + ly;
-        // rows of this lane inside the slab: u < n_ok
+        // row tiles of this block that start inside the slab (wave-uniform, >= 1): later
+        // tiles are skipped; their row bases lie outside the slab
+        const uint32_t n_u = min(uint32_t(UNROLL), (e1 - rb * rows + ty - 1) >> lty);
+        __builtin_assume(n_u >= 1);  // rb < n_rb: the block's first tile starts inside the slab
+        // row tiles in which this lane's element is inside the slab: u < n_ok (<= n_u)
         const uint32_t n_ok = (i0 < e0 && row0 < e1) ? ((e1 - row0 + ty - 1) >> lty) : 0u;
         const char *blk = reinterpret_cast<const char *>(p) +
                           (uint64_t(rb) * rows * s1 + uint64_t(k2) * s2 + (t0 << ltx)) * 4u;
         const uint32_t lane_bytes = ly_bytes + lx * 4u;
         uint32_t v[UNROLL];
+        // every load is issued (all in flight together); a lane outside the slab reads the
+        // first element of tile min(u, n_u - 1), which is inside the slab, and sees kEmpty;
+        // tiles u >= n_u are not consumed
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            const char *row = blk + u * row_step;
+            const char *row = blk + min(uint32_t(u), n_u - 1) * row_step;
             v[u] = *reinterpret_cast<const uint32_t *>(row + (uint32_t(u) < n_ok ? lane_bytes : 0u));
         }
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) use(uint32_t(u) < n_ok ? v[u] : kEmpty);
+        for (int u = 0; u < UNROLL; ++u)
+            if (uint32_t(u) < n_u) use(uint32_t(u) < n_ok ? v[u] : kEmpty);
         // advance to this wave's next block
         t0 += WAVES;
         while (t0 >= n_t0) {
@@ -558,12 +569,40 @@ struct QueryArgs {
     uint32_t ovf_out_idx;         // counters[] entry that counts them
     uint32_t stats_tag;           // OR-ed into stats[q][1]: which launch answered the box
     uint32_t *stats;              // optional [n][2]: cubes, table entries (graph nodes) touched
+    const uint64_t *lut_ptr;      // mixture lookup table rows: expand instead of push (nullptr: push)
+    const uint32_t *lut_seg;
+    const float *lut_val;
     // fallback global regions (per worker)
     uint32_t *g_keys, *g_cnt, *g_used;
     float *g_hi, *g_lo;
     uint32_t *g_seg_cnt;
     float *g_seg_hi, *g_seg_lo;
 };
+
+// Mixture lookup expansion (the paper's query through per-node mixtures):
+// every graph node in the table adds its mass times its mixture row to the
+// sources. Groups of 8 lanes take one node each, lanes over the row's entries.
+// Replaces the rank-by-rank push; all threads of the block must call.
+template <int BLOCK, bool SPARSE>
+__device__ inline void expand_lut(const QueryArgs &A, const QueryState &st)
+{
+    constexpr uint32_t kGroup = 8;
+    const uint32_t nu = ld(st.n_used);
+    if (nu == 0 || (ld(st.flags) & 1u)) return;  // uniform
+    const uint32_t g = threadIdx.x & (kGroup - 1);
+    for (uint32_t i = threadIdx.x / kGroup; i < nu; i += BLOCK / kGroup) {
+        const uint32_t slot = ld(&st.used[i]);
+        const uint32_t key = ld(&st.keys[slot]);
+        if (key < A.gv.r1_end) continue;  // a source (sparse mode); rank-1 nodes never enter the table
+        const float mh = ld(&st.hi[slot]), ml = ld(&st.lo[slot]);
+        const uint64_t e = A.lut_ptr[key + 1];
+        for (uint64_t j = A.lut_ptr[key] + g; j < e; j += kGroup) {
+            float ph, pl;
+            scale_pair(A.lut_val[j], mh, ml, &ph, &pl);
+            add_source_mass<SPARSE>(st, A.lut_seg[j], ph, pl);
+        }
+    }
+}
 
 // LDS bytes of the query kernels' dynamic shared memory.
 __host__ __device__ inline uint32_t lds_bytes(uint32_t nseg, uint32_t cap, bool sparse)
@@ -669,7 +708,10 @@ __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const Quer
     __syncthreads();
     scatter_slabs<BLOCK, UNROLL, SPARSE>(sh.slabs, sh.n_slabs, A.maps, st, A.gv, &sh.flags);
     __syncthreads();
-    push_mass<BLOCK, SPARSE>(st, A.gv, sh.rank_ptr, A.depth);
+    if (A.lut_ptr)
+        expand_lut<BLOCK, SPARSE>(A, st);
+    else
+        push_mass<BLOCK, SPARSE>(st, A.gv, sh.rank_ptr, A.depth);
     __syncthreads();
     const bool overflow = (sh.flags & 1u) != 0;
     if (A.stats && threadIdx.x == 0 && (!overflow || !report_overflow)) {
@@ -1035,6 +1077,20 @@ __global__ void tf_step_kernel(const SchedNode *__restrict__ sched, uint32_t lo_
 
 // ---------------------------------------------------------------- upload helpers
 
+// Palette fetch: the node of each voxel at one level indexes the palette.
+__global__ void palette_fetch_kernel(const float4 *__restrict__ palette, uint32_t T, uint32_t n_nodes,
+                                     const uint32_t *__restrict__ map, uint32_t X, uint32_t Y, uint32_t Z,
+                                     const uint32_t *__restrict__ xyz, uint32_t n, float4 *__restrict__ out)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t x = xyz[3 * uint64_t(i)], y = xyz[3 * uint64_t(i) + 1], z = xyz[3 * uint64_t(i) + 2];
+    const bool in = x < X && y < Y && z < Z;
+    const uint32_t node = in ? map[x + uint64_t(X) * (y + uint64_t(Y) * z)] : 0u;
+    for (uint32_t t = 0; t < T; ++t)
+        out[uint64_t(t) * n + i] = in ? palette[uint64_t(t) * n_nodes + node] : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
 __global__ void transpose_level_kernel(const uint32_t *src, uint32_t *dst, uint32_t X, uint32_t Y, uint32_t Z)
 {
     // dst[y + Y (z + Z x)] = src[x + X (y + Y z)]
@@ -1264,6 +1320,51 @@ int dev_upload(Graph *g, int device, std::string *err)
         HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipDeviceSynchronize());
+    if (!g->lut_ptr.empty()) return dev_upload_lut(g, err);
+    return MG_OK;
+}
+
+int dev_upload_lut(Graph *g, std::string *err)
+{
+    DeviceGuard guard;
+    DeviceState &d = g->dev;
+    if (d.device < 0) {
+        *err = "graph not on a device";
+        return MG_ESTATE;
+    }
+    HIP_TRY(hipSetDevice(d.device));
+    if (d.lut_ptr) (void)hipFree(d.lut_ptr);
+    if (d.lut_seg) (void)hipFree(d.lut_seg);
+    if (d.lut_val) (void)hipFree(d.lut_val);
+    d.lut_ptr = nullptr, d.lut_seg = nullptr, d.lut_val = nullptr;
+    const uint64_t bp = g->lut_ptr.size() * sizeof(uint64_t), nnz = g->lut_seg.size();
+    if (hipMalloc(&d.lut_ptr, bp) != hipSuccess || hipMalloc(&d.lut_seg, nnz * 4) != hipSuccess ||
+        hipMalloc(&d.lut_val, nnz * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        if (d.lut_ptr) (void)hipFree(d.lut_ptr);
+        if (d.lut_seg) (void)hipFree(d.lut_seg);
+        d.lut_ptr = nullptr, d.lut_seg = nullptr, d.lut_val = nullptr;
+        *err = "mixture lookup table: device allocation failed";
+        return MG_ENOMEM;
+    }
+    HIP_TRY(hipMemcpy(d.lut_ptr, g->lut_ptr.data(), bp, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d.lut_seg, g->lut_seg.data(), nnz * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d.lut_val, g->lut_val.data(), nnz * 4, hipMemcpyHostToDevice));
+    d.bytes += bp + 8 * nnz;
+    return MG_OK;
+}
+
+int dev_palette_fetch(Graph *g, const float *palette, uint32_t T, uint32_t level, const uint32_t *xyz, uint32_t n,
+                      float *out, void *stream, std::string *err)
+{
+    DeviceGuard guard;
+    int rc = check_device(g, err);
+    if (rc) return rc;
+    const uint32_t X = g->lev_dims[3 * level], Y = g->lev_dims[3 * level + 1], Z = g->lev_dims[3 * level + 2];
+    hipLaunchKernelGGL(palette_fetch_kernel, dim3((n + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       reinterpret_cast<const float4 *>(palette), T, g->n_nodes, g->dev.maps + g->lev_off[level], X,
+                       Y, Z, xyz, n, reinterpret_cast<float4 *>(out));
+    HIP_TRY(hipGetLastError());
     return MG_OK;
 }
 
@@ -1277,6 +1378,9 @@ void dev_free(Graph *g)
     if (d.sched) (void)hipFree(d.sched);
     if (d.rank_ptr) (void)hipFree(d.rank_ptr);
     if (d.maps) (void)hipFree(d.maps);
+    if (d.lut_ptr) (void)hipFree(d.lut_ptr);
+    if (d.lut_seg) (void)hipFree(d.lut_seg);
+    if (d.lut_val) (void)hipFree(d.lut_val);
     for (void *e : d.ev_start) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
     for (void *e : d.ev_stop) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
     d = DeviceState();
@@ -1331,7 +1435,7 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
         return rc;
     hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, w.counters, 64u);
     if (A.sp_total) hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, A.sp_total, 1u);
-    if (variant == kQueryBatched) {
+    if (variant == kQueryBatched || variant == kQueryLut) {
         hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, w.buckets, 64u);
         const uint32_t blocks = (n + 255) / 256;
         hipLaunchKernelGGL(query_size_kernel, dim3(blocks), dim3(256), 0, s, lt, A.boxes, n, w.bucket_of, w.buckets);
@@ -1462,6 +1566,15 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const Spa
     A.stats = stats;
     A.g_keys = w.g_keys, A.g_cnt = w.g_cnt, A.g_used = w.g_used, A.g_hi = w.g_hi, A.g_lo = w.g_lo;
     A.g_seg_cnt = w.g_seg_cnt, A.g_seg_hi = w.g_seg_hi, A.g_seg_lo = w.g_seg_lo;
+    if (variant == kQueryLut) {
+        if (!g->dev.lut_ptr) {
+            *err = "the mixture lookup table is not on the device (mg_lut_build)";
+            return MG_ESTATE;
+        }
+        A.lut_ptr = g->dev.lut_ptr;
+        A.lut_seg = g->dev.lut_seg;
+        A.lut_val = g->dev.lut_val;
+    }
     // sources in LDS arrays while they fit, else as table entries (sparse mode)
     const bool sparse = sp != nullptr || g->nseg > kSegLdsMax;
     return sparse ? launch_query<true>(g, A, w, lt, n, s, variant, err)

@@ -34,6 +34,9 @@ struct DeviceState {
     SchedNode *sched = nullptr;    // [n_nodes] in step order
     uint32_t *maps = nullptr;      // all levels, x fastest
     uint32_t *maps_t = nullptr;    // all levels, y fastest then z then x
+    uint64_t *lut_ptr = nullptr;   // [n_nodes + 1] mixture lookup table rows (optional)
+    uint32_t *lut_seg = nullptr;   // [lut nnz]
+    float *lut_val = nullptr;      // [lut nnz]
     uint64_t bytes = 0;
     // launch parameters, queried once per device and graph
     bool launch_ready = false;
@@ -67,11 +70,18 @@ struct Graph {
     std::vector<uint32_t> rank_ptr;                      // [depth + 2] IDs of each rank
     std::vector<uint32_t> step_ptr;                      // [depth + 2] into sched
     std::vector<uint32_t> sched;                         // [n_nodes] IDs in step order
+    // mixture lookup table (optional, built by build_lut): row n = the sources of
+    // node n's mixture, increasing, with their fractions
+    std::vector<uint64_t> lut_ptr;                       // [n_nodes + 1], empty if not built
+    std::vector<uint32_t> lut_seg;
+    std::vector<float> lut_val;
     DeviceState dev;
 };
 
 // Host builder (builder.cpp). Returns MG_OK or an MG_E* code with *err set.
 int build_graph(const uint32_t *ids, const mg_build_opts *opts, Graph *g, std::string *err);
+// Mixture lookup table of every node, in fp64 through the DAG, stored fp32.
+int build_lut(Graph *g, uint32_t threads, std::string *err);
 // Structural validation of a graph's host arrays (used by mg_load).
 int validate_graph(const Graph &g, std::string *err);
 // Level dimensions: halve with rounding up until 1^3.
@@ -79,6 +89,7 @@ void level_dims(const uint32_t dims[3], std::vector<uint32_t> *out);
 
 // Device side (kernels.hip). All return MG_OK or an MG_E* code with *err set.
 int dev_upload(Graph *g, int device, std::string *err);
+int dev_upload_lut(Graph *g, std::string *err);
 void dev_free(Graph *g);
 uint64_t dev_workspace_bytes(const Graph &g, uint32_t max_boxes);
 int dev_workspace_init(Graph *g, void *work, uint64_t bytes, void *stream, std::string *err);
@@ -94,12 +105,14 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const Spa
 int dev_footprint(Graph *g, const uint32_t *boxes, uint32_t n, uint32_t *level_counts, uint32_t *cubes,
                   uint32_t cap, uint32_t *count, void *stream, std::string *err);
 int dev_propagate_tf(Graph *g, const uint8_t *tf, uint32_t T, float *out, void *stream, std::string *err);
+int dev_palette_fetch(Graph *g, const float *palette, uint32_t T, uint32_t level, const uint32_t *xyz, uint32_t n,
+                      float *out, void *stream, std::string *err);
 int dev_timing_enable(Graph *g, int enable, std::string *err);
 int dev_set_launch(Graph *g, const mg_launch_cfg *cfg, std::string *err);
 int dev_autotune(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *work, uint64_t bytes, uint32_t reps,
                  void *stream, mg_launch_cfg *chosen, std::string *err);
 int dev_timing_read(Graph *g, double *ms, uint32_t *launches, std::string *err);
 
-enum QueryVariant { kQueryBatched = 0, kQueryPlain = 1, kQueryNaive = 2 };
+enum QueryVariant { kQueryBatched = 0, kQueryPlain = 1, kQueryNaive = 2, kQueryLut = 3 };
 
 }  // namespace mg

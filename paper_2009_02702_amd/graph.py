@@ -150,7 +150,7 @@ class Graph:
             raise ValueError("out must be fp32 [n, S]")
         ws = workspace if workspace is not None else self.workspace(n, stream)
         fn = {"batched": self._lib.mg_query_boxes, "plain": self._lib.mg_query_boxes_plain,
-              "naive": self._lib.mg_naive_boxes}[variant]
+              "naive": self._lib.mg_naive_boxes, "lut": self._lib.mg_query_boxes_lut}[variant]
         check(fn(self._h, _dptr(boxes), n, _dptr(out), _dptr(ws), ws.numel(), _stream_ptr(stream)))
         return out
 
@@ -216,6 +216,40 @@ class Graph:
             out = torch.empty((T, inf["n_nodes"], 4), dtype=torch.float32, device=tf.device)
         check(self._lib.mg_propagate_tf(self._h, _dptr(tf), T, _dptr(out), _stream_ptr(stream)))
         return out
+
+    def palette_fetch(self, palette, level: int, xyz, out=None, stream=None):
+        """Palette [T, n_nodes, 4] fp32 (from propagate_tf) at voxels xyz (uint32 [n, 3], level coords)
+        -> fp32 [T, n, 4]; voxels outside the level give zeros."""
+        torch = _torch()
+        T = palette.shape[0]
+        inf = self.info()
+        if tuple(palette.shape) != (T, inf["n_nodes"], 4) or palette.dtype != torch.float32:
+            raise ValueError("palette must be fp32 [T, n_nodes, 4]")
+        if xyz.dim() != 2 or xyz.shape[1] != 3 or xyz.element_size() != 4:
+            raise ValueError("xyz must be a 32-bit [n, 3] tensor")
+        n = xyz.shape[0]
+        if out is None:
+            out = torch.empty((T, n, 4), dtype=torch.float32, device=palette.device)
+        check(self._lib.mg_palette_fetch(self._h, _dptr(palette), T, level, _dptr(xyz), n, _dptr(out),
+                                         _stream_ptr(stream)))
+        return out
+
+    def lut_build(self, threads: int = 0) -> int:
+        """Build (and upload, if on a device) the mixture lookup table; returns its entry count."""
+        nnz = ctypes.c_uint64(0)
+        check(self._lib.mg_lut_build(self._h, threads, ctypes.byref(nnz)))
+        return int(nnz.value)
+
+    def export_lut(self):
+        """(ptr uint64 [n_nodes + 1], seg uint32 [nnz], val float32 [nnz]) of the mixture lookup table."""
+        N = self.info()["n_nodes"]
+        ptr = np.zeros(N + 1, dtype=np.uint64)
+        check(self._lib.mg_export_lut(self._h, ptr.ctypes.data, None, None))
+        nnz = int(ptr[-1])
+        seg = np.zeros(nnz, dtype=np.uint32)
+        val = np.zeros(nnz, dtype=np.float32)
+        check(self._lib.mg_export_lut(self._h, ptr.ctypes.data, seg.ctypes.data, val.ctypes.data))
+        return ptr, seg, val
 
     def launch_config(self) -> dict:
         c = LaunchCfg()

@@ -226,3 +226,37 @@ def test_gpu_calls_before_upload_are_state_errors():
     assert b"mg_upload" in lib.mg_last_error()
     # n = 0 is a no-op even without a device
     assert lib.mg_query_boxes(g._h, None, 0, None, None, 0, None) == 0
+
+
+def test_mixture_lut_rows_are_the_exact_mixtures():
+    """mg_lut_build (Sec. 'Decoder', mixture lookup): row n lists exactly the segments of node n's
+    mixture, each fraction within one fp32 unit of the exact rational value (oracle.dag.expand_exact),
+    sources in increasing order."""
+    for w in (synth.workload(2, dims=(19, 17, 13), segments=9), synth.workload(4, dims=(21, 15, 11), segments=12)):
+        g = Graph.build(synth.make_volume(w))
+        S, N = g.info()["nseg"], g.info()["n_nodes"]
+        nnz = g.lut_build(threads=3)
+        ptr, seg, val = g.export_lut()
+        assert ptr[0] == 0 and int(ptr[-1]) == nnz == len(seg) and np.all(np.diff(ptr.astype(np.int64)) >= 1)
+        d = g.export_dag()
+        mix = dag.expand_exact(S, d["child_a"][S:], d["child_b"][S:], d["wnum"][S:], d["wden"][S:])
+        for n in range(N):
+            row = slice(int(ptr[n]), int(ptr[n + 1]))
+            s_row, v_row = seg[row].tolist(), val[row]
+            assert s_row == sorted(mix[n]), n
+            want = np.array([float(mix[n][s]) for s in s_row], dtype=np.float64)
+            ulp = np.spacing(want.astype(np.float32)).astype(np.float64)
+            assert np.all(np.abs(v_row.astype(np.float64) - want) <= ulp), n
+
+
+def test_mixture_lut_threads_deterministic_and_state_errors():
+    g = Graph.build(_rand((9, 8, 7), 6, 21))
+    with pytest.raises(MGError) as e:
+        g.export_lut()
+    assert e.value.code == -4
+    g.lut_build(threads=1)
+    a = g.export_lut()
+    g.lut_build(threads=8)
+    b = g.export_lut()
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)

@@ -58,10 +58,23 @@ def _graph(key, vol):
     return _GRAPHS[key]
 
 
+_LUT = set()
+
+
+def _lut(g):
+    """Build the mixture lookup table of a cached graph once."""
+    if id(g) not in _LUT:
+        g.lut_build()
+        _LUT.add(id(g))
+    return g
+
+
 def _check_workload(w, n=None, variants=("batched", "plain", "naive"), key=None):
     vol = synth.make_volume(w)
     boxes = synth.make_boxes(w, n)
     g = _graph(key or (w.config, w.dims, w.segments), vol)
+    if "lut" in variants:
+        _lut(g)
     ids, vol_c = scan.compact(vol)
     _, ref = scan.box_counts(vol_c, len(ids), boxes)
     db = _dev(boxes)
@@ -415,3 +428,84 @@ def test_serving_small_budget_queues_instead_of_failing():
     _compare(res, ref, None, "small budget")
     with pytest.raises(ValueError):
         Server(g, budget_bytes=16)
+
+
+# ------------------------------------------------------------------ mixture lookup table query and palette fetch
+
+def test_lut_query_config1_full():
+    _, errs = _check_workload(synth.workload(1), variants=("lut",))
+    print(errs)
+
+
+@pytest.mark.parametrize("config,dims,segments,n", [
+    (2, (96, 80, 72), 353, 3000),
+    (3, (256, 256, 40), 1182, 2000),
+    (4, (123, 96, 100), 1500, 3000),
+    (5, (118, 113, 79), 353, 3000),
+])
+def test_lut_query_reduced_recipes(config, dims, segments, n):
+    _, errs = _check_workload(synth.workload(config, dims=dims, segments=segments, n_boxes=n), variants=("lut",))
+    print(errs)
+
+
+def test_lut_query_many_segments_and_tiny_tables():
+    """Sources as table entries (> 2048 segments), and tables small enough to force the retry and
+    global-memory launches: the lookup-table expansion gives the oracle's histograms on every path."""
+    w = synth.workload(4, dims=(160, 200, 150), segments=4000, n_boxes=1500)
+    vol = synth.make_volume(w)
+    g = _lut(_graph("many", vol))
+    boxes = synth.make_boxes(w)
+    ids, vol_c = scan.compact(vol)
+    _, ref = scan.box_counts(vol_c, len(ids), boxes)
+    db = _dev(boxes)
+    _compare(g.query(db, variant="lut").cpu().numpy(), ref, _level0_only(g, db), "many segments lut")
+    w = synth.workload(2, dims=(160, 150, 140), segments=300, n_boxes=800)
+    vol = synth.make_volume(w)
+    g = _lut(_graph("ovf", vol))
+    boxes = synth.make_boxes(w)
+    boxes[:10] = [0, 0, 0, 160, 150, 140]
+    ids, vol_c = scan.compact(vol)
+    _, ref = scan.box_counts(vol_c, len(ids), boxes)
+    db = _dev(boxes)
+    for tb, ts, tr in ((64, 64, 8192), (64, 64, 64)):
+        g.set_launch_config(table_big=tb, table_small=ts, table_retry=tr)
+        _compare(g.query(db, variant="lut").cpu().numpy(), ref, None, "lut tables %d/%d/%d" % (tb, ts, tr))
+    g.set_launch_config(table_big=0, table_small=0, table_retry=0)
+
+
+def test_lut_query_needs_the_table():
+    g = Graph.build(synth.make_volume(synth.workload(2, dims=(20, 20, 20), segments=10))).upload(0)
+    with pytest.raises(MGError) as e:
+        g.query(_dev(np.array([[0, 0, 0, 5, 5, 5]], dtype=np.uint32)), variant="lut")
+    assert e.value.code == -4
+
+
+def test_palette_fetch_is_the_palette_at_the_voxel_node():
+    """Paletted fetch (Sec. 'Rendering'): colour of a mip voxel = palette[node of the voxel], bit for bit;
+    coordinates outside the level give zeros; the fetched colour is the mean TF over the voxel's support."""
+    vol = synth.make_volume(synth.workload(3, dims=(40, 36, 12), segments=30))
+    g = _graph("tf", vol)
+    inf = g.info()
+    S = inf["nseg"]
+    tfs = synth.make_tfs(synth.workload(3), S, 2)
+    pal = g.propagate_tf(torch.from_numpy(tfs).cuda())
+    pal_h = pal.cpu().numpy()
+    ids, vol_c = scan.compact(vol)
+    rng = np.random.default_rng(5)
+    atol = 4 * max(inf["depth"], 1) * 2.0 ** -24
+    for l in (0, 1, 3, inf["n_levels"] - 1):
+        m = g.export_map(l)                       # [Z, Y, X]
+        Z, Y, X = m.shape
+        xyz = np.stack([rng.integers(0, X + 2, 500), rng.integers(0, Y + 2, 500), rng.integers(0, Z + 2, 500)],
+                       axis=1).astype(np.uint32)
+        got = g.palette_fetch(pal, l, _dev(xyz)).cpu().numpy()
+        inside = (xyz[:, 0] < X) & (xyz[:, 1] < Y) & (xyz[:, 2] < Z)
+        assert (got[:, ~inside] == 0).all()
+        xi = xyz[inside].astype(np.int64)
+        node = m[xi[:, 2], xi[:, 1], xi[:, 0]]
+        assert np.array_equal(got[:, inside], pal_h[:, node])
+        for t in range(2):
+            want = otf.level_colours(vol_c, S, tfs[t], l)[xi[:, 2], xi[:, 1], xi[:, 0]]
+            assert np.abs(got[t, inside] - want).max() <= atol
+    with pytest.raises(MGError):
+        g.palette_fetch(pal, inf["n_levels"], _dev(np.zeros((1, 3), dtype=np.uint32)))
