@@ -238,10 +238,19 @@ def main():
     res_main = out.cpu().numpy()
 
     comp = {}
-    for v in ("plain", "naive"):
+    t0 = time.perf_counter()
+    lut_nnz = g.lut_build()
+    t_lut = time.perf_counter() - t0
+    print("[bench] mixture lookup table: %d entries, built in %.2f s" % (lut_nnz, t_lut), file=sys.stderr,
+          flush=True)
+    for v in ("plain", "naive", "lut"):
         e2, l2, k2 = run(v, args.competitor_steps, 1, True)
         comp[v] = {"value": args.competitor_steps * n / e2, "ms_per_step": 1e3 * e2 / args.competitor_steps,
                    "kernel_ms": k2}
+        if v == "lut":
+            comp[v]["max_abs_diff_vs_push"] = float((out - torch.from_numpy(res_main).to(out.device)).abs().max())
+            comp[v]["lut_entries"] = lut_nnz
+            comp[v]["lut_build_s"] = t_lut
         print("[bench] %s: %.3f ms/step" % (v, comp[v]["ms_per_step"]), file=sys.stderr, flush=True)
 
     tf_meas = measure_tf(g, w, args.tf_count, max(3, args.steps // 2), 1)

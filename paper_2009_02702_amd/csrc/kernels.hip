@@ -428,42 +428,53 @@ __device__ inline bool stream_slab(const uint32_t *__restrict__ p, uint32_t e0, 
     const uint32_t lx = lane & ((1u << ltx) - 1), ly = lane >> ltx;
     const uint32_t ly_bytes = ly * s1 * 4u;                // < 64 * s1 * 4 < 2^32 (s1 < 2^24)
     const uint64_t row_step = uint64_t(ty) * s1 * 4u;      // bytes between the rows of u and u + 1
+    const uint32_t lane_bytes = ly_bytes + lx * 4u;
     uint32_t fb = (wave + WAVES - first) % WAVES;
     if (fb >= n_blk) return true;
     uint32_t t0 = fb % n_t0, rest = fb / n_t0;
     uint32_t rb = rest % n_rb, k2 = rest / n_rb;
-    uint32_t iter = 0;
-    for (; fb < n_blk; fb += WAVES) {
-        if ((++iter & 7u) == 0 && stop()) return false;
-        const uint32_t i0 = (t0 << ltx) + lx;
-        const uint32_t row0 = rb * rows + ly;
-        // row tiles of this block that start inside the slab (wave-uniform, >= 1): later
-        // tiles are skipped; their row bases lie outside the slab
-        const uint32_t n_u = min(uint32_t(UNROLL), (e1 - rb * rows + ty - 1) >> lty);
-        __builtin_assume(n_u >= 1);  // rb < n_rb: the block's first tile starts inside the slab
-        // row tiles in which this lane's element is inside the slab: u < n_ok (<= n_u)
-        const uint32_t n_ok = (i0 < e0 && row0 < e1) ? ((e1 - row0 + ty - 1) >> lty) : 0u;
+    // Loads of block (t0, rb, k2) into v. n_u: row tiles of the block that start inside
+    // the slab (wave-uniform, >= 1); n_ok: tiles in which this lane's element is inside
+    // (<= n_u). Every load is issued; a lane outside the slab reads the first element of
+    // tile min(u, n_u - 1), which is inside the slab; tiles u >= n_u are not consumed.
+    auto load = [&](uint32_t (&v)[UNROLL], uint32_t &n_u, uint32_t &n_ok, uint32_t bt0, uint32_t brb,
+                    uint32_t bk2) {
+        const uint32_t i0 = (bt0 << ltx) + lx;
+        const uint32_t row0 = brb * rows + ly;
+        n_u = min(uint32_t(UNROLL), (e1 - brb * rows + ty - 1) >> lty);
+        __builtin_assume(n_u >= 1);  // brb < n_rb: the block's first tile starts inside the slab
+        n_ok = (i0 < e0 && row0 < e1) ? ((e1 - row0 + ty - 1) >> lty) : 0u;
         const char *blk = reinterpret_cast<const char *>(p) +
-                          (uint64_t(rb) * rows * s1 + uint64_t(k2) * s2 + (t0 << ltx)) * 4u;
-        const uint32_t lane_bytes = ly_bytes + lx * 4u;
-        uint32_t v[UNROLL];
-        // every load is issued (all in flight together); a lane outside the slab reads the
-        // first element of tile min(u, n_u - 1), which is inside the slab, and sees kEmpty;
-        // tiles u >= n_u are not consumed
+                          (uint64_t(brb) * rows * s1 + uint64_t(bk2) * s2 + (bt0 << ltx)) * 4u;
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
             const char *row = blk + min(uint32_t(u), n_u - 1) * row_step;
             v[u] = *reinterpret_cast<const uint32_t *>(row + (uint32_t(u) < n_ok ? lane_bytes : 0u));
         }
+    };
+    // software pipeline: the next block's loads are in flight while this block is consumed
+    uint32_t v[UNROLL], n_u, n_ok;
+    load(v, n_u, n_ok, t0, rb, k2);
+    uint32_t iter = 0;
+    for (; fb < n_blk; fb += WAVES) {
+        if ((++iter & 7u) == 0 && stop()) return false;
+        // this wave's next block; after its last one, the current block again (loaded, unused)
+        uint32_t nt0 = t0 + WAVES, nrb = rb, nk2 = k2;
+        while (nt0 >= n_t0) {
+            nt0 -= n_t0;
+            if (++nrb == n_rb) nrb = 0, ++nk2;
+        }
+        const bool more = fb + WAVES < n_blk;
+        if (!more) nt0 = t0, nrb = rb, nk2 = k2;
+        uint32_t w[UNROLL], w_n_u, w_n_ok;
+        load(w, w_n_u, w_n_ok, nt0, nrb, nk2);
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
             if (uint32_t(u) < n_u) use(uint32_t(u) < n_ok ? v[u] : kEmpty);
-        // advance to this wave's next block
-        t0 += WAVES;
-        while (t0 >= n_t0) {
-            t0 -= n_t0;
-            if (++rb == n_rb) rb = 0, ++k2;
-        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) v[u] = w[u];
+        n_u = w_n_u, n_ok = w_n_ok;
+        t0 = nt0, rb = nrb, k2 = nk2;
     }
     return true;
 }
