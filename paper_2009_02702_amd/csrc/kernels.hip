@@ -431,8 +431,12 @@ __device__ inline bool stream_slab(const uint32_t *__restrict__ p, uint32_t e0, 
     const uint32_t lane_bytes = ly_bytes + lx * 4u;
     uint32_t fb = (wave + WAVES - first) % WAVES;
     if (fb >= n_blk) return true;
-    uint32_t t0 = fb % n_t0, rest = fb / n_t0;
-    uint32_t rb = rest % n_rb, k2 = rest / n_rb;
+    // block fb < WAVES as (t0, rb, k2), by subtraction (no division)
+    uint32_t t0 = fb, rb = 0, k2 = 0;
+    while (t0 >= n_t0) {
+        t0 -= n_t0;
+        if (++rb == n_rb) rb = 0, ++k2;
+    }
     // Loads of block (t0, rb, k2) into v. n_u: row tiles of the block that start inside
     // the slab (wave-uniform, >= 1); n_ok: tiles in which this lane's element is inside
     // (<= n_u). Every load is issued; a lane outside the slab reads the first element of
@@ -446,9 +450,10 @@ __device__ inline bool stream_slab(const uint32_t *__restrict__ p, uint32_t e0, 
         n_ok = (i0 < e0 && row0 < e1) ? ((e1 - row0 + ty - 1) >> lty) : 0u;
         const char *blk = reinterpret_cast<const char *>(p) +
                           (uint64_t(brb) * rows * s1 + uint64_t(bk2) * s2 + (bt0 << ltx)) * 4u;
+        const char *row = blk;
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            const char *row = blk + min(uint32_t(u), n_u - 1) * row_step;
+            if (u > 0 && uint32_t(u) < n_u) row += row_step;  // stays on tile n_u - 1 after it
             v[u] = *reinterpret_cast<const uint32_t *>(row + (uint32_t(u) < n_ok ? lane_bytes : 0u));
         }
     };
