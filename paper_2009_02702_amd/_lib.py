@@ -63,6 +63,12 @@ def load() -> ctypes.CDLL:
     global _lib
     if _lib is not None:
         return _lib
+    # torch first: libmg then binds to the HIP runtime torch loaded; a HIP runtime loaded
+    # before torch's leaves torch without devices in the same process
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError("libmg.so is not built (%s); run `python -m paper_2009_02702_amd.build_ext` "
                           "or __graft_entry__.build()" % LIB_PATH)
