@@ -485,10 +485,12 @@ __device__ inline bool stream_slab(const uint32_t *__restrict__ p, uint32_t e0, 
 }
 
 // Scatter: every cube of every slab adds 8^level to its node. Neighbouring
-// lanes usually hold the same node (mixtures are spatially coherent), so each
-// run of equal nodes in a wave adds once: run length * 8^level. Runs on
-// sources add to an integer counter; runs on internal nodes (rare) take a
-// branch that the whole wave skips when no lane needs it.
+// lanes usually hold the same node (mixtures are spatially coherent), so a run
+// of equal nodes in a wave adds its total once. Runs on sources add to an
+// integer counter through their two end lanes (start: -a 8^l, end: (b+1) 8^l
+// for lanes a..b), which needs no run length; runs on internal nodes (rare)
+// take a branch that the whole wave skips when no lane needs it, and add
+// run length * 8^level at their start lane.
 template <int BLOCK, int UNROLL, bool SPARSE>
 __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint32_t *__restrict__ maps,
                                      const QueryState &st, const GraphView &gv, const uint32_t *flags_lds)
@@ -501,7 +503,9 @@ __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint3
         const Slab &sp = slabs[si];
         if (uni(*flags_lds) & 1u) return;  // overflowed: the box goes to the retry launch
         const uint32_t lw8 = 3 * uni(sp.level);
-        const uint32_t w8 = 1u << lw8;
+        // a run of lanes [a, b] on one source adds (b + 1 - a) 8^l as -a 8^l at its start lane
+        // and (b + 1) 8^l at its end lane (uint32 wrap-around; the counts stay below 2^32)
+        const uint32_t w_start = 0u - (lane << lw8), w_end = (lane + 1) << lw8;
         const uint64_t base = (uint64_t(uni(uint32_t(sp.base >> 32))) << 32) | uni(uint32_t(sp.base));
         const bool go = stream_slab<UNROLL, kWaves>(
             maps + base, uni(sp.e0), uni(sp.e1), uni(sp.e2), uni(sp.s1), uni(sp.s2), uni(sp.ltx),
@@ -512,16 +516,22 @@ __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint3
                     if (run_head(v, above, &len)) scatter_count<SPARSE>(st, gv, v, len << lw8);
                     return;
                 }
-                uint32_t prev;
-                const uint64_t starts = run_starts(v, &prev);
+                // neighbours by DPP wave shifts (lane 0 / lane 63 read 0 and are a start / an end)
+                const uint32_t prev = uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x138, 0xF, 0xF, true));
+                const uint32_t next = uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x130, 0xF, 0xF, true));
                 const bool start = v != prev || lane == 0;
-                const uint32_t len = run_len(starts, above, lane);
-                if (start && v < nseg) atomicAdd(&st.seg_cnt[v], len << lw8);
+                const bool end = v != next || lane == 63;
+                if (v < nseg) {  // a source (kEmpty is not)
+                    if (start) atomicAdd(&st.seg_cnt[v], w_start);
+                    if (end) atomicAdd(&st.seg_cnt[v], w_end);
+                }
                 // runs on internal nodes: a branch the wave skips unless a lane needs it
-                const uint64_t internal = starts & ~__builtin_amdgcn_uicmp(v, nseg, 36 /* ult */) &
-                                          __builtin_amdgcn_uicmp(v, kEmpty, 33 /* ne */);
-                if (__builtin_expect(internal != 0, 0))
+                const uint64_t internal = __builtin_amdgcn_uicmp(v - nseg, kEmpty - nseg, 36 /* ult */);
+                if (__builtin_expect(internal != 0, 0)) {
+                    const uint64_t starts = __builtin_amdgcn_uicmp(v, prev, 33 /* ne */) | 1u;
+                    const uint32_t len = run_len(starts, above, lane);
                     if (start && v >= nseg && v != kEmpty) scatter_count<SPARSE>(st, gv, v, len << lw8);
+                }
             },
             [&]() { return (uni(*flags_lds) & 1u) != 0; });
         if (!go) return;
@@ -1009,12 +1019,17 @@ __global__ __launch_bounds__(kBlock) void naive_kernel(NaiveArgs A)
         uint32_t ltx = 0;
         while (ltx < 6 && (1u << ltx) < ex) ++ltx;
         if (X >= (1u << 24)) ltx = 6;  // one row per tile: lane byte offsets stay below 2^32
-        const uint64_t above = lane_above_mask();
+        // runs of equal IDs: -start lane at the start, end lane + 1 at the end (see scatter_slabs)
+        const uint32_t lane = threadIdx.x & 63, w_start = 0u - lane, w_end = lane + 1;
         stream_slab<UNROLL, kBlock / 64>(
             p, ex, ey, ez, X, XY, ltx, 0u,
             [&](uint32_t v) {
-                uint32_t len;
-                if (run_head(v, above, &len)) atomicAdd(&cnt[v], len);
+                const uint32_t prev = uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x138, 0xF, 0xF, true));
+                const uint32_t next = uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x130, 0xF, 0xF, true));
+                if (v != kEmpty) {
+                    if (v != prev || lane == 0) atomicAdd(&cnt[v], w_start);
+                    if (v != next || lane == 63) atomicAdd(&cnt[v], w_end);
+                }
             },
             []() { return false; });
     }
