@@ -207,7 +207,11 @@ def main():
     touched = (st[:, 1] & 0x3FFFFFFF).astype(np.float64)
     fallback = (st[:, 1] >> 31).astype(bool)
     retried = ((st[:, 1] >> 30) & 1).astype(bool)
-    alg_bytes = float(np.sum(24.0 + 4.0 * cubes + 12.0 * touched + 4.0 * S))
+    # node IDs: 2 bytes per level-0 cube (16-bit copy, used when S < 65535), 4 bytes above
+    lvl_counts, _ = g.footprint(dboxes)
+    cubes0 = lvl_counts.cpu().numpy()[:, 0].astype(np.float64)
+    id0 = 2.0 if S < 65535 else 4.0
+    alg_bytes = float(np.sum(24.0 + id0 * cubes0 + 4.0 * (cubes - cubes0) + 12.0 * touched + 4.0 * S))
 
     def run(variant, steps, warmup, timing):
         for _ in range(warmup):
@@ -270,7 +274,8 @@ def main():
                 "kernel": "query_tier_kernel big + small tiers, with query_retry_kernel and query_fallback_kernel (timed together)",
                 "kernel_ms": kern_ms,
                 "alg_bytes_per_launch": alg_bytes,
-                "alg_bytes_formula": "sum over boxes of 24 + 4*cubes + 12*graph nodes touched + 4*S (dense output)"}
+                "alg_bytes_formula": "sum over boxes of 24 + 2*level-0 cubes + 4*higher-level cubes + "
+                                     "12*graph nodes touched + 4*S (dense output)"}
 
     cpu = None
     max_rel = None
@@ -316,7 +321,8 @@ def main():
         "launch": tuned,
         "graph": {"nodes": inf["n_nodes"], "depth": inf["depth"], "levels": inf["n_levels"],
                   "build_s": t_build, "volume_gen_s": t_gen, "device_bytes": inf["device_bytes"]},
-        "work": {"cubes_mean": float(cubes.mean()), "nodes_touched_mean": float(touched.mean()),
+        "work": {"cubes_mean": float(cubes.mean()), "level0_cubes_mean": float(cubes0.mean()),
+                 "nodes_touched_mean": float(touched.mean()),
                  "nodes_touched_max": int(touched.max()), "boxes_via_fallback": int(fallback.sum()),
                  "boxes_via_retry": int(retried.sum()),
                  "cubes_share_via_fallback": float(cubes[fallback].sum() / max(cubes.sum(), 1.0)),

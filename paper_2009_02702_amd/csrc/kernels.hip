@@ -67,6 +67,12 @@ struct LevelTable {
     uint32_t dims[MG_MAX_LEVELS][3];
     uint64_t off[MG_MAX_LEVELS];     // element offset of each level in maps
     uint64_t total;                  // elements of one full copy (maps_t starts here)
+    // 16-bit copy of level 0 (both orientations), rows padded to an even length:
+    // x-fastest index x + pitch_x (y + Y z), then at total16 the y-fastest index
+    // y + pitch_y (z + Z x); used when `use16` (dense mode, sources < 65535)
+    uint32_t use16;
+    uint32_t pitch_x, pitch_y;
+    uint64_t total16;
 };
 
 // A slab of cubes at one level, as read from memory: the fast axis is the
@@ -484,6 +490,101 @@ __device__ inline bool stream_slab(const uint32_t *__restrict__ p, uint32_t e0, 
     return true;
 }
 
+// Streams one level-0 slab of the 16-bit copy: lane (lx, ly) reads one aligned
+// 32-bit word, the pair of elements (2 pp - odd, 2 pp + 1 - odd) of row
+// rb * rows + u * 64/2^ltx + ly of slow slice k2, pp = t0 * 2^ltx + lx, where
+// `odd` is the parity of the slab's first element along the fast axis (rows are
+// padded to an even length, so every pair lies inside its row). Elements outside
+// the slab are handed to `use(lo, hi)` as kEmpty. Block walk, row-tile bounds
+// and software pipeline as in stream_slab.
+template <int UNROLL, int WAVES, class Use>
+__device__ inline void stream_pairs(const uint16_t *__restrict__ p, uint32_t e0, uint32_t e1, uint32_t e2,
+                                    uint32_t s1, uint32_t s2, uint32_t odd, uint32_t ltx, uint32_t first, Use use)
+{
+    const uint32_t lane = threadIdx.x & 63, wave = uni(threadIdx.x >> 6);
+    const uint32_t np = (e0 + odd + 1) >> 1;               // pairs along the fast axis
+    const uint32_t lty = 6u - ltx;
+    const uint32_t ty = 1u << lty;
+    const uint32_t n_t0 = (np + (1u << ltx) - 1) >> ltx;
+    const uint32_t rows = ty * UNROLL;
+    const uint32_t n_rb = (e1 + rows - 1) / rows;
+    const uint32_t n_blk = n_t0 * n_rb * e2;
+    const uint32_t lx = lane & ((1u << ltx) - 1), ly = lane >> ltx;
+    const uint32_t lane_bytes = ly * s1 * 2u + lx * 4u;   // s1 < 2^24
+    const uint64_t row_step = uint64_t(ty) * s1 * 2u;
+    const char *p0 = reinterpret_cast<const char *>(p - odd);  // aligned start of the slab's first row
+    uint32_t fb = (wave + WAVES - first) % WAVES;
+    if (fb >= n_blk) return;
+    uint32_t t0 = fb, rb = 0, k2 = 0;
+    while (t0 >= n_t0) {
+        t0 -= n_t0;
+        if (++rb == n_rb) rb = 0, ++k2;
+    }
+    // n_lo / n_hi: row tiles in which this lane's low / high element is inside the slab
+    auto load = [&](uint32_t (&v)[UNROLL], uint32_t &n_u, uint32_t &n_lo, uint32_t &n_hi, uint32_t bt0,
+                    uint32_t brb, uint32_t bk2) {
+        const uint32_t pp = (bt0 << ltx) + lx;
+        const uint32_t row0 = brb * rows + ly;
+        n_u = min(uint32_t(UNROLL), (e1 - brb * rows + ty - 1) >> lty);
+        __builtin_assume(n_u >= 1);
+        const uint32_t n_ok = (pp < np && row0 < e1) ? ((e1 - row0 + ty - 1) >> lty) : 0u;
+        n_lo = (pp > 0 || odd == 0) ? n_ok : 0u;
+        n_hi = (2 * pp + 1 < e0 + odd) ? n_ok : 0u;
+        const char *blk = p0 + (uint64_t(brb) * rows * s1 + uint64_t(bk2) * s2) * 2u + (bt0 << ltx) * 4u;
+        const char *row = blk;
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            if (u > 0 && uint32_t(u) < n_u) row += row_step;
+            v[u] = *reinterpret_cast<const uint32_t *>(row + (uint32_t(u) < n_ok ? lane_bytes : 0u));
+        }
+    };
+    uint32_t v[UNROLL], n_u, n_lo, n_hi;
+    load(v, n_u, n_lo, n_hi, t0, rb, k2);
+    for (; fb < n_blk; fb += WAVES) {
+        uint32_t nt0 = t0 + WAVES, nrb = rb, nk2 = k2;
+        while (nt0 >= n_t0) {
+            nt0 -= n_t0;
+            if (++nrb == n_rb) nrb = 0, ++nk2;
+        }
+        if (fb + WAVES >= n_blk) nt0 = t0, nrb = rb, nk2 = k2;
+        uint32_t w[UNROLL], w_n_u, w_n_lo, w_n_hi;
+        load(w, w_n_u, w_n_lo, w_n_hi, nt0, nrb, nk2);
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+            if (uint32_t(u) < n_u)
+                use(uint32_t(u) < n_lo ? (v[u] & 0xFFFFu) : kEmpty, uint32_t(u) < n_hi ? (v[u] >> 16) : kEmpty);
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) v[u] = w[u];
+        n_u = w_n_u, n_lo = w_n_lo, n_hi = w_n_hi;
+        t0 = nt0, rb = nrb, k2 = nk2;
+    }
+}
+
+// Counts a wave's 128 level-0 elements (lane l holds elements 2l and 2l+1) into
+// integer per-source counters: a run of equal sources over elements a..b adds
+// -a at its start element and b+1 at its end element (uint32 wrap-around).
+__device__ inline void count_pairs(uint32_t *cnt, uint32_t lo, uint32_t hi, uint32_t lane)
+{
+    const uint32_t prev_hi = uint32_t(__builtin_amdgcn_update_dpp(0, int(hi), 0x138, 0xF, 0xF, true));
+    const uint32_t next_lo = uint32_t(__builtin_amdgcn_update_dpp(0, int(lo), 0x130, 0xF, 0xF, true));
+    const bool s_lo = lo != prev_hi || lane == 0;   // element 2l starts a run
+    const bool e_lo = lo != hi;                     // element 2l ends one, 2l+1 starts one
+    const bool e_hi = hi != next_lo || lane == 63;  // element 2l+1 ends one
+    if (lo != kEmpty && (s_lo || e_lo)) atomicAdd(&cnt[lo], (s_lo ? 0u - 2 * lane : 0u) + (e_lo ? 2 * lane + 1 : 0u));
+    if (hi != kEmpty && (e_lo || e_hi))
+        atomicAdd(&cnt[hi], (e_lo ? 0u - (2 * lane + 1) : 0u) + (e_hi ? 2 * lane + 2 : 0u));
+}
+
+// Tile width for a pair-streamed slab: smallest 2^ltx pairs covering the row, at most 64;
+// one row per tile when the mid stride is 2^24 elements or more (lane offsets < 2^32).
+__device__ inline uint32_t pair_ltx(uint32_t e0, uint32_t odd, uint32_t s1)
+{
+    const uint32_t np = (e0 + odd + 1) >> 1;
+    uint32_t ltx = 0;
+    while (ltx < 6 && (1u << ltx) < np) ++ltx;
+    return s1 >= (1u << 24) ? 6u : ltx;
+}
+
 // Scatter: every cube of every slab adds 8^level to its node. Neighbouring
 // lanes usually hold the same node (mixtures are spatially coherent), so a run
 // of equal nodes in a wave adds its total once. Runs on sources add to an
@@ -493,6 +594,7 @@ __device__ inline bool stream_slab(const uint32_t *__restrict__ p, uint32_t e0, 
 // run length * 8^level at their start lane.
 template <int BLOCK, int UNROLL, bool SPARSE>
 __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint32_t *__restrict__ maps,
+                                     const uint16_t *__restrict__ maps16, const LevelTable &lt,
                                      const QueryState &st, const GraphView &gv, const uint32_t *flags_lds)
 {
     constexpr uint32_t kWaves = BLOCK / 64;
@@ -502,6 +604,24 @@ __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint3
     for (int si = 0; si < n_slabs; ++si) {
         const Slab &sp = slabs[si];
         if (uni(*flags_lds) & 1u) return;  // overflowed: the box goes to the retry launch
+        if (!SPARSE && lt.use16 && uni(sp.level) == 0) {
+            // level 0: every node is a source; read the 16-bit copy, two cubes per lane
+            const uint32_t axes = uni(sp.axes), f = axes & 3, m = (axes >> 2) & 3, w = (axes >> 4) & 3;
+            const uint32_t X = lt.dims[0][0], Y = lt.dims[0][1], Z = lt.dims[0][2];
+            const bool tr = f == 1;  // rows along y: the y-fastest copy
+            uint64_t str[3];
+            if (tr) str[0] = uint64_t(lt.pitch_y) * Z, str[1] = 1, str[2] = lt.pitch_y;
+            else str[0] = 1, str[1] = lt.pitch_x, str[2] = uint64_t(lt.pitch_x) * Y;
+            const uint32_t bx = uni(sp.bx), by = uni(sp.by), bz = uni(sp.bz);
+            const uint64_t base16 = (tr ? lt.total16 : 0) + bx * str[0] + by * str[1] + bz * str[2];
+            const uint32_t odd = (tr ? by : bx) & 1u;
+            const uint32_t s1 = uint32_t(str[m]), s2 = uint32_t(str[w]);
+            const uint32_t e0 = uni(sp.e0);
+            stream_pairs<UNROLL, kWaves>(maps16 + base16, e0, uni(sp.e1), uni(sp.e2), s1, s2, odd,
+                                         pair_ltx(e0, odd, s1), uint32_t(si) % kWaves,
+                                         [&](uint32_t lo, uint32_t hi) { count_pairs(st.seg_cnt, lo, hi, lane); });
+            continue;
+        }
         const uint32_t lw8 = 3 * uni(sp.level);
         // a run of lanes [a, b] on one source adds (b + 1 - a) 8^l as -a 8^l at its start lane
         // and (b + 1) 8^l at its end lane (uint32 wrap-around; the counts stay below 2^32)
@@ -580,6 +700,7 @@ struct QueryArgs {
     uint32_t sp_cap;              // entries sp_seg / sp_val hold
     uint32_t *sp_total;           // entries produced (may exceed sp_cap: then the rest are dropped)
     const uint32_t *maps;         // maps then maps_t
+    const uint16_t *maps16;       // level 0 as 16-bit IDs (both orientations), if lt.use16
     GraphView gv;
     const uint32_t *rank_ptr;     // [depth + 2]
     uint32_t depth;
@@ -732,7 +853,7 @@ __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const Quer
     __syncthreads();
     if (nonempty) build_slabs(A.lt, lo, hi, sh.slabs, &sh.n_slabs);
     __syncthreads();
-    scatter_slabs<BLOCK, UNROLL, SPARSE>(sh.slabs, sh.n_slabs, A.maps, st, A.gv, &sh.flags);
+    scatter_slabs<BLOCK, UNROLL, SPARSE>(sh.slabs, sh.n_slabs, A.maps, A.maps16, A.lt, st, A.gv, &sh.flags);
     __syncthreads();
     if (A.lut_ptr)
         expand_lut<BLOCK, SPARSE>(A, st);
@@ -996,6 +1117,7 @@ struct NaiveArgs {
     const uint32_t *boxes;
     float *out;
     const uint32_t *map0;
+    const uint16_t *map16;        // 16-bit level 0 (x-fastest, row pitch lt.pitch_x), if lt.use16
     uint32_t nseg;
     uint32_t n;
 };
@@ -1012,7 +1134,14 @@ __global__ __launch_bounds__(kBlock) void naive_kernel(NaiveArgs A)
     uint32_t lo[3], hi[3];
     const bool nonempty = clip_box(A.boxes + 6 * uint64_t(q), A.lt, lo, hi);
     __syncthreads();
-    if (nonempty) {
+    if (nonempty && A.lt.use16) {
+        const uint32_t ex = hi[0] - lo[0], ey = hi[1] - lo[1], ez = hi[2] - lo[2];
+        const uint32_t px = A.lt.pitch_x, pxy = A.lt.pitch_x * A.lt.vol[1];
+        const uint32_t odd = lo[0] & 1u, lane = threadIdx.x & 63;
+        stream_pairs<UNROLL, kBlock / 64>(A.map16 + (lo[0] + uint64_t(px) * lo[1] + uint64_t(pxy) * lo[2]), ex, ey, ez,
+                                          px, pxy, odd, pair_ltx(ex, odd, px), 0u,
+                                          [&](uint32_t a, uint32_t b) { count_pairs(cnt, a, b, lane); });
+    } else if (nonempty) {
         const uint32_t ex = hi[0] - lo[0], ey = hi[1] - lo[1], ez = hi[2] - lo[2];
         const uint32_t X = A.lt.vol[0], XY = A.lt.vol[0] * A.lt.vol[1];
         const uint32_t *__restrict__ p = A.map0 + (lo[0] + uint64_t(X) * lo[1] + uint64_t(XY) * lo[2]);
@@ -1122,6 +1251,25 @@ __global__ void palette_fetch_kernel(const float4 *__restrict__ palette, uint32_
         out[uint64_t(t) * n + i] = in ? palette[uint64_t(t) * n_nodes + node] : make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
+// 16-bit copies of level 0: x-fastest with row pitch px, and y-fastest (y + py (z + Z x))
+// with row pitch py; padding elements hold 0xFFFF.
+__global__ void pack16_kernel(const uint32_t *__restrict__ map0, uint16_t *__restrict__ out, uint32_t X, uint32_t Y,
+                              uint32_t Z, uint32_t px, uint32_t py, uint64_t total16, uint64_t total16t)
+{
+    const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < total16) {  // x-fastest copy: element i = x + px (y + Y z)
+        const uint32_t x = uint32_t(i % px);
+        const uint64_t yz = i / px;
+        out[i] = x < X ? uint16_t(map0[x + uint64_t(X) * yz]) : uint16_t(0xFFFF);
+    }
+    if (i < total16t) {  // y-fastest copy: element i = y + py (z + Z x)
+        const uint32_t y = uint32_t(i % py);
+        const uint64_t zx = i / py;
+        const uint32_t z = uint32_t(zx % Z), x = uint32_t(zx / Z);
+        out[total16 + i] = y < Y ? uint16_t(map0[x + uint64_t(X) * (y + uint64_t(Y) * z)]) : uint16_t(0xFFFF);
+    }
+}
+
 __global__ void transpose_level_kernel(const uint32_t *src, uint32_t *dst, uint32_t X, uint32_t Y, uint32_t Z)
 {
     // dst[y + Y (z + Z x)] = src[x + X (y + Y z)]
@@ -1151,6 +1299,10 @@ LevelTable level_table(const Graph &g)
         lt.off[l] = g.lev_off[l];
     }
     lt.total = g.lev_off[g.n_levels];
+    lt.pitch_x = g.dims[0] + (g.dims[0] & 1u);
+    lt.pitch_y = g.dims[1] + (g.dims[1] & 1u);
+    lt.total16 = uint64_t(lt.pitch_x) * g.dims[1] * g.dims[2];
+    lt.use16 = 0;  // set per launch where the 16-bit copy is used
     return lt;
 }
 
@@ -1350,7 +1502,24 @@ int dev_upload(Graph *g, int device, std::string *err)
                            d.maps_t + g->lev_off[l], X, Y, Z);
         HIP_TRY(hipGetLastError());
     }
-    HIP_TRY(hipDeviceSynchronize());
+    // 16-bit level 0 for the hot path, when every source ID fits below 0xFFFF
+    if (g->nseg < 0xFFFFu) {
+        const LevelTable lt = level_table(*g);
+        const uint64_t n16 = lt.total16;
+        const uint64_t n16t = uint64_t(lt.pitch_y) * g->dims[2] * g->dims[0];
+        if (hipMalloc(&d.maps16, (n16 + n16t) * sizeof(uint16_t)) != hipSuccess) {
+            (void)hipGetLastError();
+            dev_free(g);
+            *err = "mg_upload: device allocation failed (16-bit level-0 maps)";
+            return MG_ENOMEM;
+        }
+        d.bytes += (n16 + n16t) * sizeof(uint16_t);
+        const uint64_t n = std::max(n16, n16t);
+        hipLaunchKernelGGL(pack16_kernel, dim3(uint32_t((n + 255) / 256)), dim3(256), 0, 0, d.maps, d.maps16,
+                           g->dims[0], g->dims[1], g->dims[2], lt.pitch_x, lt.pitch_y, n16, n16t);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipDeviceSynchronize());
+    }
     if (!g->lut_ptr.empty()) return dev_upload_lut(g, err);
     return MG_OK;
 }
@@ -1409,6 +1578,7 @@ void dev_free(Graph *g)
     if (d.sched) (void)hipFree(d.sched);
     if (d.rank_ptr) (void)hipFree(d.rank_ptr);
     if (d.maps) (void)hipFree(d.maps);
+    if (d.maps16) (void)hipFree(d.maps16);
     if (d.lut_ptr) (void)hipFree(d.lut_ptr);
     if (d.lut_seg) (void)hipFree(d.lut_seg);
     if (d.lut_val) (void)hipFree(d.lut_val);
@@ -1561,6 +1731,8 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const Spa
         A.boxes = boxes;
         A.out = out;
         A.map0 = g->dev.maps;
+        A.map16 = g->dev.maps16;
+        A.lt.use16 = g->dev.maps16 ? 1u : 0u;
         A.nseg = g->nseg;
         A.n = n;
         rc = timing_begin(g, s, err);
@@ -1583,6 +1755,7 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const Spa
         A.sp_total = sp->total;
     }
     A.maps = g->dev.maps;
+    A.maps16 = g->dev.maps16;
     A.gv.nodes = g->dev.nodes;
     A.gv.nseg = g->nseg;
     A.gv.r1_end = g->depth >= 1 ? g->rank_ptr[2] : g->nseg;
@@ -1608,6 +1781,7 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const Spa
     }
     // sources in LDS arrays while they fit, else as table entries (sparse mode)
     const bool sparse = sp != nullptr || g->nseg > kSegLdsMax;
+    A.lt.use16 = (!sparse && g->dev.maps16) ? 1u : 0u;
     return sparse ? launch_query<true>(g, A, w, lt, n, s, variant, err)
                   : launch_query<false>(g, A, w, lt, n, s, variant, err);
 }

@@ -34,6 +34,7 @@ struct DeviceState {
     SchedNode *sched = nullptr;    // [n_nodes] in step order
     uint32_t *maps = nullptr;      // all levels, x fastest
     uint32_t *maps_t = nullptr;    // all levels, y fastest then z then x
+    uint16_t *maps16 = nullptr;    // level 0 as 16-bit IDs, both orientations (rows padded to even)
     uint64_t *lut_ptr = nullptr;   // [n_nodes + 1] mixture lookup table rows (optional)
     uint32_t *lut_seg = nullptr;   // [lut nnz]
     float *lut_val = nullptr;      // [lut nnz]
