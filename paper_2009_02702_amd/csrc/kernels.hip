@@ -706,16 +706,12 @@ struct QueryArgs {
     uint32_t depth;
     uint32_t n;
     const uint32_t *order;        // query order (batched) or nullptr (identity)
-    uint32_t *counters;           // [0] next big-tier box, [1] boxes in list 1a (big tier or plain
-                                  // overflow), [2] next box of the global fallback, [3] next
-                                  // small-tier box, [4] next box of list 1a, [5] boxes in list 2,
-                                  // [6] boxes in list 1b (small-tier overflow), [7] next box of
-                                  // list 1b, [8] number of big-tier boxes
+    uint32_t *counters;           // [0] next big-tier box, [1] boxes in list 1, [2] next box of the
+                                  // global fallback, [3] next small-tier box, [4] next retry box,
+                                  // [5] boxes in list 2, [8] number of big-tier boxes
     uint32_t table_cap;           // LDS hash slots of this launch
+    uint32_t *overflow;           // list 1: boxes whose tier table overflowed
     uint32_t *overflow2;          // list 2: boxes whose retry table overflowed too
-    const uint32_t *retry_list;   // the overflow list a retry launch works on
-    uint32_t retry_count;         // counters[] entry holding its length
-    uint32_t retry_claim;         // counters[] entry through which its boxes are claimed
     uint32_t *ovf_out;            // where this launch reports overflowed boxes (nullptr: mark NaN)
     uint32_t ovf_out_idx;         // counters[] entry that counts them
     uint32_t stats_tag;           // OR-ed into stats[q][1]: which launch answered the box
@@ -988,8 +984,7 @@ __global__ __launch_bounds__(BLOCK) void query_tier_kernel(QueryArgs A)
     }
 }
 
-// Retry of the boxes of one overflow list (A.retry_list, A.counters[A.retry_count]
-// entries, claimed through A.counters[A.retry_claim]) with a larger LDS table;
+// Retry of boxes whose tier table overflowed (list 1), with a larger LDS table;
 // what overflows again goes to list 2.
 template <int BLOCK, int UNROLL, bool SPARSE>
 __global__ __launch_bounds__(BLOCK) void query_retry_kernel(QueryArgs A)
@@ -999,13 +994,13 @@ __global__ __launch_bounds__(BLOCK) void query_retry_kernel(QueryArgs A)
     const QueryState st = lds_state<SPARSE>(dyn, sh, A.gv.nseg, A.table_cap);
     load_rank_ptr<BLOCK>(A, sh);
     clear_lds_state<BLOCK, SPARSE>(st, A.gv.nseg);
-    const uint32_t n_list = ld(&A.counters[A.retry_count]);
+    const uint32_t n_list = ld(&A.counters[1]);
     for (;;) {
-        if (threadIdx.x == 0) sh.q = atomicAdd(&A.counters[A.retry_claim], 1u);
+        if (threadIdx.x == 0) sh.q = atomicAdd(&A.counters[4], 1u);
         __syncthreads();
         const uint32_t k = sh.q;
         if (k >= n_list) break;  // uniform
-        run_query<BLOCK, UNROLL, SPARSE>(A, sh, st, A.retry_list[k], true);
+        run_query<BLOCK, UNROLL, SPARSE>(A, sh, st, A.overflow[k], true);
     }
 }
 
@@ -1318,9 +1313,8 @@ struct Workspace {
     uint32_t *buckets;    // 64 u32
     uint32_t *bucket_of;  // [max_boxes]
     uint32_t *order;      // [max_boxes]
-    uint32_t *overflow;   // [max_boxes] list 1a
-    uint32_t *overflow_b; // [max_boxes] list 1b
-    uint32_t *overflow2;  // [max_boxes] list 2
+    uint32_t *overflow;   // [max_boxes]
+    uint32_t *overflow2;  // [max_boxes]
     uint32_t *g_keys, *g_cnt, *g_used;
     float *g_hi, *g_lo;
     uint32_t *g_seg_cnt;
@@ -1357,7 +1351,6 @@ Workspace carve(const Graph &g, char *base, uint32_t max_boxes)
     w.bucket_of = reinterpret_cast<uint32_t *>(take(uint64_t(max_boxes) * 4));
     w.order = reinterpret_cast<uint32_t *>(take(uint64_t(max_boxes) * 4));
     w.overflow = reinterpret_cast<uint32_t *>(take(uint64_t(max_boxes) * 4));
-    w.overflow_b = reinterpret_cast<uint32_t *>(take(uint64_t(max_boxes) * 4));
     w.overflow2 = reinterpret_cast<uint32_t *>(take(uint64_t(max_boxes) * 4));
     w.bytes = off;
     w.max_boxes = max_boxes;
@@ -1463,8 +1456,6 @@ int occupancy(DeviceState &d, const void *k, int block, uint32_t dyn, int *out, 
 
 // ---------------------------------------------------------------- entry points
 
-int aux_stream(Graph *g, std::string *err);
-
 int dev_upload(Graph *g, int device, std::string *err)
 {
     DeviceGuard guard;
@@ -1529,8 +1520,6 @@ int dev_upload(Graph *g, int device, std::string *err)
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipDeviceSynchronize());
     }
-    // the second stream now, so that a first query under stream capture creates nothing
-    if (const int rc = aux_stream(g, err)) return rc;
     if (!g->lut_ptr.empty()) return dev_upload_lut(g, err);
     return MG_OK;
 }
@@ -1593,9 +1582,6 @@ void dev_free(Graph *g)
     if (d.lut_ptr) (void)hipFree(d.lut_ptr);
     if (d.lut_seg) (void)hipFree(d.lut_seg);
     if (d.lut_val) (void)hipFree(d.lut_val);
-    if (d.aux) (void)hipStreamDestroy(static_cast<hipStream_t>(d.aux));
-    if (d.ev_fork) (void)hipEventDestroy(static_cast<hipEvent_t>(d.ev_fork));
-    if (d.ev_join) (void)hipEventDestroy(static_cast<hipEvent_t>(d.ev_join));
     for (void *e : d.ev_start) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
     for (void *e : d.ev_stop) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
     d = DeviceState();
@@ -1630,24 +1616,6 @@ int dev_workspace_init(Graph *g, void *work, uint64_t bytes, void *stream, std::
     return MG_OK;
 }
 
-// The library's second stream (default priority) and its fork / join events,
-// created on first use. A call records the fork event on the caller's stream,
-// the second stream waits for it, and the caller's stream waits for the join
-// event before the call's last kernels: the caller sees one stream, and a
-// capture of the caller's stream captures both.
-int aux_stream(Graph *g, std::string *err)
-{
-    DeviceState &d = g->dev;
-    if (d.aux) return MG_OK;
-    hipStream_t st;
-    hipEvent_t a, b;
-    HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    HIP_TRY(hipEventCreateWithFlags(&a, hipEventDisableTiming));
-    HIP_TRY(hipEventCreateWithFlags(&b, hipEventDisableTiming));
-    d.aux = st, d.ev_fork = a, d.ev_join = b;
-    return MG_OK;
-}
-
 template <bool SPARSE>
 int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &lt, uint32_t n, hipStream_t s,
                  int variant, std::string *err)
@@ -1666,8 +1634,6 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
         (rc = occupancy(d, reinterpret_cast<const void *>(ksmall), kBlock, dyn_small, &occ_small, err)) ||
         (rc = occupancy(d, reinterpret_cast<const void *>(kplain), kBlock, dyn_plain, &occ_plain, err)))
         return rc;
-    const uint32_t wbig = std::max(1u, std::min<uint32_t>(n, uint32_t(d.ncu) * uint32_t(occ_big)));
-    const uint32_t wsmall = std::max(1u, std::min<uint32_t>(n, uint32_t(d.ncu) * uint32_t(occ_small)));
     hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, w.counters, 64u);
     if (A.sp_total) hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, A.sp_total, 1u);
     if (variant == kQueryBatched || variant == kQueryLut) {
@@ -1677,8 +1643,22 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
         hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(64), 0, s, w.buckets, w.counters);
         hipLaunchKernelGGL(query_order_kernel, dim3(blocks), dim3(256), 0, s, w.bucket_of, n, w.buckets, w.order);
         A.order = w.order;
+        const uint32_t wbig = std::max(1u, std::min<uint32_t>(n, uint32_t(d.ncu) * uint32_t(occ_big)));
+        const uint32_t wsmall = std::max(1u, std::min<uint32_t>(n, uint32_t(d.ncu) * uint32_t(occ_small)));
         rc = timing_begin(g, s, err);
         if (rc) return rc;
+        A.table_cap = cap_big;
+        hipLaunchKernelGGL(kbig, dim3(wbig), dim3(kBlockBig), dyn_big, s, A);
+        HIP_TRY(hipGetLastError());
+        A.table_cap = cap_small;
+        hipLaunchKernelGGL(ksmall, dim3(wsmall), dim3(kBlock), dyn_small, s, A);
+        HIP_TRY(hipGetLastError());
+    } else {
+        A.table_cap = kHashPlain;
+        rc = timing_begin(g, s, err);
+        if (rc) return rc;
+        hipLaunchKernelGGL(kplain, dim3(n), dim3(kBlock), dyn_plain, s, A);
+        HIP_TRY(hipGetLastError());
     }
     // boxes whose table overflowed: once more with a larger LDS table, then in global memory
     const QueryKernel kretry = query_retry_kernel<kBlockBig, 8, SPARSE>;
@@ -1693,45 +1673,12 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
     int occ_retry = 1;
     if ((rc = occupancy(d, reinterpret_cast<const void *>(kretry), kBlockBig, dyn_retry, &occ_retry, err)))
         return rc;
-    QueryArgs R = A;  // the retry launches
-    R.table_cap = cap_retry;
-    R.stats_tag = 0x40000000u;
-    R.ovf_out = w.overflow2;
-    R.ovf_out_idx = 5;
-    const uint32_t g_retry = uint32_t(d.ncu) * uint32_t(occ_retry);
-    if (variant == kQueryBatched || variant == kQueryLut) {
-        if ((rc = aux_stream(g, err))) return rc;
-        hipStream_t aux = static_cast<hipStream_t>(d.aux);
-        A.table_cap = cap_big;
-        hipLaunchKernelGGL(kbig, dim3(wbig), dim3(kBlockBig), dyn_big, s, A);
-        HIP_TRY(hipGetLastError());
-        // big-tier overflows (list 1a) are retried on the second stream while the small
-        // tier runs; small-tier overflows (list 1b) after it; both join before the fallback
-        HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(d.ev_fork), s));
-        HIP_TRY(hipStreamWaitEvent(aux, static_cast<hipEvent_t>(d.ev_fork), 0));
-        R.retry_list = w.overflow, R.retry_count = 1, R.retry_claim = 4;
-        hipLaunchKernelGGL(kretry, dim3(std::max(1u, g_retry / 4)), dim3(kBlockBig), dyn_retry, aux, R);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(d.ev_join), aux));
-        A.table_cap = cap_small;
-        A.ovf_out = w.overflow_b;
-        A.ovf_out_idx = 6;
-        hipLaunchKernelGGL(ksmall, dim3(wsmall), dim3(kBlock), dyn_small, s, A);
-        HIP_TRY(hipGetLastError());
-        R.retry_list = w.overflow_b, R.retry_count = 6, R.retry_claim = 7;
-        hipLaunchKernelGGL(kretry, dim3(g_retry), dim3(kBlockBig), dyn_retry, s, R);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipStreamWaitEvent(s, static_cast<hipEvent_t>(d.ev_join), 0));
-    } else {
-        A.table_cap = kHashPlain;
-        rc = timing_begin(g, s, err);
-        if (rc) return rc;
-        hipLaunchKernelGGL(kplain, dim3(n), dim3(kBlock), dyn_plain, s, A);
-        HIP_TRY(hipGetLastError());
-        R.retry_list = w.overflow, R.retry_count = 1, R.retry_claim = 4;
-        hipLaunchKernelGGL(kretry, dim3(g_retry), dim3(kBlockBig), dyn_retry, s, R);
-        HIP_TRY(hipGetLastError());
-    }
+    A.table_cap = cap_retry;
+    A.stats_tag = 0x40000000u;
+    A.ovf_out = w.overflow2;
+    A.ovf_out_idx = 5;
+    hipLaunchKernelGGL(kretry, dim3(uint32_t(d.ncu) * uint32_t(occ_retry)), dim3(kBlockBig), dyn_retry, s, A);
+    HIP_TRY(hipGetLastError());
     A.ovf_out = nullptr;
     A.stats_tag = 0x80000000u;
     hipLaunchKernelGGL(query_fallback_kernel<SPARSE>, dim3(kFallbackWorkers), dim3(kBlock), 0, s, A);
@@ -1816,6 +1763,7 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const Spa
     A.depth = g->depth;
     A.n = n;
     A.counters = w.counters;
+    A.overflow = w.overflow;
     A.overflow2 = w.overflow2;
     A.ovf_out = w.overflow;
     A.ovf_out_idx = 1;

@@ -49,8 +49,6 @@ struct DeviceState {
     };
     std::vector<Occ> occupancy;  // per kernel variant and LDS size
     mg_launch_cfg cfg = {8, 8, 8, 256, 0, 0, 0, 0};
-    void *aux = nullptr;                    // second stream (hipStream_t), created on first use
-    void *ev_fork = nullptr, *ev_join = nullptr;  // its fork / join events (hipEvent_t)
     bool timing = false;
     std::vector<void *> ev_start, ev_stop;  // hipEvent_t pairs recorded around the dominant kernel
     uint32_t ev_used = 0;
