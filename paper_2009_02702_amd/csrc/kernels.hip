@@ -212,10 +212,10 @@ __device__ inline void build_slabs(const LevelTable &lt, const uint32_t lo[3], c
 
 // ---------------------------------------------------------------- per-query state
 
-// Per-query accumulators. Internal nodes of rank >= 2 live in an
-// open-addressing table (key, mass, compensation); rank-1 nodes (both
-// predecessors are sources) never enter it: their mass goes straight to their
-// two sources. Sources keep an exact integer count (cubes whose node is a
+// Per-query accumulators. Internal nodes of rank >= 3 live in an
+// open-addressing table (key, mass, compensation); nodes of rank 1 (both
+// predecessors are sources) and rank 2 (predecessors of rank <= 1) never enter
+// it: their mass goes straight to the sources, in at most two hops. Sources keep an exact integer count (cubes whose node is a
 // source) plus pushed fp32 mass with its compensation term: in dense mode in
 // per-source arrays [S], in sparse mode (many sources) as entries of the same
 // table. Pointers are into LDS or into a global per-worker region; the same
@@ -238,6 +238,7 @@ struct GraphView {
     const NodeTriple *__restrict__ nodes;
     uint32_t nseg;     // sources are IDs [0, nseg)
     uint32_t r1_end;   // rank-1 nodes are IDs [nseg, r1_end)
+    uint32_t r2_end;   // rank-2 nodes are IDs [r1_end, r2_end)
 };
 
 // Loads of per-query state written by other threads of the block: relaxed
@@ -337,7 +338,22 @@ __device__ inline void push_pair(const QueryState &st, const NodeTriple &t, floa
     add_source_mass<SPARSE>(st, t.b, bh, bl);
 }
 
-// Mass pushed into `node` during the reverse push.
+// Mass (h, l) on a rank-2 node: each predecessor is a source or a rank-1 node,
+// so it is pushed to the sources at once (at most two hops), without a table entry.
+template <bool SPARSE>
+__device__ inline void push_rank2(const QueryState &st, const GraphView &gv, const NodeTriple &t, float h, float l)
+{
+    float ah, al, bh, bl;
+    scale_pair(1.0f - t.w, h, l, &ah, &al);
+    scale_pair(t.w, h, l, &bh, &bl);
+    if (t.a < gv.nseg) add_source_mass<SPARSE>(st, t.a, ah, al);
+    else push_pair<SPARSE>(st, gv.nodes[t.a], ah, al);
+    if (t.b < gv.nseg) add_source_mass<SPARSE>(st, t.b, bh, bl);
+    else push_pair<SPARSE>(st, gv.nodes[t.b], bh, bl);
+}
+
+// Mass pushed into `node` during the reverse push. Nodes of rank <= 2 go straight
+// to the sources; only nodes of rank >= 3 accumulate in the table.
 template <bool SPARSE>
 __device__ inline void route_mass(const QueryState &st, const GraphView &gv, uint32_t node, float h, float l)
 {
@@ -345,6 +361,8 @@ __device__ inline void route_mass(const QueryState &st, const GraphView &gv, uin
         add_source_mass<SPARSE>(st, node, h, l);
     } else if (node < gv.r1_end) {
         push_pair<SPARSE>(st, gv.nodes[node], h, l);
+    } else if (node < gv.r2_end) {
+        push_rank2<SPARSE>(st, gv, gv.nodes[node], h, l);
     } else {
         const uint32_t slot = table_slot(st, node);
         if (slot != kEmpty) add_mass_at(&st.hi[slot], &st.lo[slot], h, l);
@@ -362,6 +380,8 @@ __device__ inline void scatter_count(const QueryState &st, const GraphView &gv, 
     const float h = float(c & 0xFFFFFF00u), l = float(c & 0xFFu);  // both exact in fp32
     if (node < gv.r1_end) {
         push_pair<SPARSE>(st, gv.nodes[node], h, l);
+    } else if (node < gv.r2_end) {
+        push_rank2<SPARSE>(st, gv, gv.nodes[node], h, l);
     } else {
         const uint32_t slot = table_slot(st, node);
         if (slot != kEmpty) add_mass_at(&st.hi[slot], &st.lo[slot], h, l);
@@ -658,7 +678,7 @@ __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint3
     }
 }
 
-// Reverse push through the nodes of rank >= 2 in the table, rank by rank from
+// Reverse push through the nodes of rank >= 3 in the table, rank by rank from
 // the highest present. All threads of the block must call.
 template <int BLOCK, bool SPARSE>
 __device__ inline void push_mass(const QueryState &st, const GraphView &gv, const uint32_t *rank_ptr_lds,
@@ -667,10 +687,10 @@ __device__ inline void push_mass(const QueryState &st, const GraphView &gv, cons
     const uint32_t nu = ld(st.n_used);
     if (nu == 0 || (ld(st.flags) & 1u)) return;  // uniform
     const uint32_t top_key = ld(st.max_key);
-    if (top_key < gv.r1_end) return;  // only sources in the table: nothing to push
+    if (top_key < gv.r2_end) return;  // only sources in the table: nothing to push
     uint32_t r = depth;
-    while (r > 2 && rank_ptr_lds[r] > top_key) --r;
-    for (; r >= 2; --r) {
+    while (r > 3 && rank_ptr_lds[r] > top_key) --r;
+    for (; r >= 3; --r) {  // ranks <= 2 never enter the table
         const uint32_t lo_id = rank_ptr_lds[r], hi_id = rank_ptr_lds[r + 1];
         const uint32_t n_now = ld(st.n_used);
         __syncthreads();  // every thread has read n_now before any insert of this rank
@@ -1759,6 +1779,7 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const Spa
     A.gv.nodes = g->dev.nodes;
     A.gv.nseg = g->nseg;
     A.gv.r1_end = g->depth >= 1 ? g->rank_ptr[2] : g->nseg;
+    A.gv.r2_end = g->depth >= 2 ? g->rank_ptr[3] : A.gv.r1_end;
     A.rank_ptr = g->dev.rank_ptr;
     A.depth = g->depth;
     A.n = n;
