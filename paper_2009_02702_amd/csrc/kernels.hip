@@ -1905,6 +1905,24 @@ int dev_autotune(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *
             if ((rc = time_variant(kQueryBatched, &ms))) break;
             if (ms < best) best = ms, best_cfg.unroll_big = ub, best_cfg.unroll_small = usm;
         }
+    // table sizes (LDS per workgroup, hence occupancy), one tier at a time
+    const uint32_t tb[3] = {1024, 2048, 4096}, ts[3] = {256, 512, 1024};
+    for (uint32_t t : tb) {
+        if (rc) break;
+        g->dev.cfg = best_cfg;
+        g->dev.cfg.table_big = t;
+        float ms = 0;
+        if ((rc = time_variant(kQueryBatched, &ms))) break;
+        if (ms < best) best = ms, best_cfg.table_big = t;
+    }
+    for (uint32_t t : ts) {
+        if (rc) break;
+        g->dev.cfg = best_cfg;
+        g->dev.cfg.table_small = t;
+        float ms = 0;
+        if ((rc = time_variant(kQueryBatched, &ms))) break;
+        if (ms < best) best = ms, best_cfg.table_small = t;
+    }
     float best_naive = 1e30f;
     for (uint32_t u : us) {
         if (rc) break;
