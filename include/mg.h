@@ -225,9 +225,10 @@ typedef struct {
     uint32_t table_big;     /* per-box LDS hash slots, big-box tier (0: 4096)                  */
     uint32_t table_small;   /* small-box tier (0: 1024)                                         */
     uint32_t table_retry;   /* retry of overflowed boxes (0: the largest of 8192 that fits)     */
-    uint32_t reserved;      /* must be 0. Table sizes are 0 or powers of two in [64, 8192];
-                               boxes that overflow every LDS table are answered from global
-                               memory, so smaller tables change speed, never results          */
+    uint32_t block_small;   /* threads per box in the small-box tier: 0 (256), 128 or 256.
+                               Table sizes are 0 or powers of two in [64, 8192]; boxes that
+                               overflow every LDS table are answered from global memory, so
+                               smaller tables change speed, never results                     */
 } mg_launch_cfg;
 
 int mg_get_launch(const mg_graph *g, mg_launch_cfg *out);

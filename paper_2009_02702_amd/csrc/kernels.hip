@@ -1643,7 +1643,9 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
     int rc = MG_OK;
     DeviceState &d = g->dev;
     const QueryKernel kbig = tier_kernel<kBlockBig, true, SPARSE>(d.cfg.unroll_big);
-    const QueryKernel ksmall = tier_kernel<kBlock, false, SPARSE>(d.cfg.unroll_small);
+    const int bsmall = d.cfg.block_small == 128 ? 128 : kBlock;  // threads per small-tier box
+    const QueryKernel ksmall = bsmall == 128 ? tier_kernel<128, false, SPARSE>(d.cfg.unroll_small)
+                                             : tier_kernel<kBlock, false, SPARSE>(d.cfg.unroll_small);
     const QueryKernel kplain = query_plain_kernel<SPARSE>;
     const uint32_t cap_big = d.cfg.table_big ? d.cfg.table_big : kHashBig;
     const uint32_t cap_small = d.cfg.table_small ? d.cfg.table_small : (SPARSE ? kHashPlain : kHashSmall);
@@ -1651,7 +1653,7 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
                    dyn_plain = lds_bytes(g->nseg, kHashPlain, SPARSE);
     int occ_big = 1, occ_small = 1, occ_plain = 1;
     if ((rc = occupancy(d, reinterpret_cast<const void *>(kbig), kBlockBig, dyn_big, &occ_big, err)) ||
-        (rc = occupancy(d, reinterpret_cast<const void *>(ksmall), kBlock, dyn_small, &occ_small, err)) ||
+        (rc = occupancy(d, reinterpret_cast<const void *>(ksmall), bsmall, dyn_small, &occ_small, err)) ||
         (rc = occupancy(d, reinterpret_cast<const void *>(kplain), kBlock, dyn_plain, &occ_plain, err)))
         return rc;
     hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, w.counters, 64u);
@@ -1671,7 +1673,7 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
         hipLaunchKernelGGL(kbig, dim3(wbig), dim3(kBlockBig), dyn_big, s, A);
         HIP_TRY(hipGetLastError());
         A.table_cap = cap_small;
-        hipLaunchKernelGGL(ksmall, dim3(wsmall), dim3(kBlock), dyn_small, s, A);
+        hipLaunchKernelGGL(ksmall, dim3(wsmall), dim3(bsmall), dyn_small, s, A);
         HIP_TRY(hipGetLastError());
     } else {
         A.table_cap = kHashPlain;
@@ -1847,8 +1849,8 @@ int dev_propagate_tf(Graph *g, const uint8_t *tf, uint32_t T, float *out, void *
 
 int dev_set_launch(Graph *g, const mg_launch_cfg *cfg, std::string *err)
 {
-    if (cfg->reserved) {
-        *err = "mg_set_launch: reserved field must be 0";
+    if (!(cfg->block_small == 0 || cfg->block_small == 128 || cfg->block_small == 256)) {
+        *err = "mg_set_launch: block_small must be 0, 128 or 256";
         return MG_EINVAL;
     }
     for (uint32_t t : {cfg->table_big, cfg->table_small, cfg->table_retry})
@@ -1915,14 +1917,16 @@ int dev_autotune(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *
         if ((rc = time_variant(kQueryBatched, &ms))) break;
         if (ms < best) best = ms, best_cfg.table_big = t;
     }
-    for (uint32_t t : ts) {
-        if (rc) break;
-        g->dev.cfg = best_cfg;
-        g->dev.cfg.table_small = t;
-        float ms = 0;
-        if ((rc = time_variant(kQueryBatched, &ms))) break;
-        if (ms < best) best = ms, best_cfg.table_small = t;
-    }
+    for (uint32_t bsm : {256u, 128u})
+        for (uint32_t t : ts) {
+            if (rc) break;
+            g->dev.cfg = best_cfg;
+            g->dev.cfg.table_small = t;
+            g->dev.cfg.block_small = bsm;
+            float ms = 0;
+            if ((rc = time_variant(kQueryBatched, &ms))) break;
+            if (ms < best) best = ms, best_cfg.table_small = t, best_cfg.block_small = bsm;
+        }
     float best_naive = 1e30f;
     for (uint32_t u : us) {
         if (rc) break;
