@@ -216,7 +216,7 @@ int mg_query_boxes_lut(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *
                        void *d_work, uint64_t work_bytes, void *stream);
 
 /* Launch configuration of the GPU kernels (per graph, after mg_upload).
- * Defaults: 8, 8, 8, 256. */
+ * Defaults: 16, 8, 16, 256, then zeros (sizes chosen per mode). */
 typedef struct {
     uint32_t unroll_big;    /* node-ID loads in flight per lane, boxes of >= 2^16 cubes: 4, 8 or 16 */
     uint32_t unroll_small;  /* the same for smaller boxes: 4, 8 or 16 */
@@ -225,10 +225,13 @@ typedef struct {
     uint32_t table_big;     /* per-box LDS hash slots, big-box tier (0: 4096)                  */
     uint32_t table_small;   /* small-box tier (0: 1024)                                         */
     uint32_t table_retry;   /* retry of overflowed boxes (0: the largest of 8192 that fits)     */
-    uint32_t block_small;   /* threads per box in the small-box tier: 0 (256), 128 or 256.
-                               Table sizes are 0 or powers of two in [64, 8192]; boxes that
-                               overflow every LDS table are answered from global memory, so
-                               smaller tables change speed, never results                     */
+    uint32_t block_small;   /* threads per box in the small-box tier: 0 (128), 128 or 256       */
+    uint32_t block_big;     /* threads per box in the big-box tier: 0 (512), 256 or 512.
+                               Table sizes are 0 or powers of two in [64, 8192] (0: 2048 big,
+                               256 small with per-source arrays; 4096 and 2048 when sources are
+                               table entries); boxes that overflow every LDS table are answered
+                               from global memory, so smaller tables change speed, never
+                               results                                                        */
 } mg_launch_cfg;
 
 int mg_get_launch(const mg_graph *g, mg_launch_cfg *out);

@@ -40,8 +40,10 @@ constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kMaxLevelsDev = 16;          // dims up to 32768 per axis
 constexpr int kMaxSlabs = 6 * kMaxLevelsDev;
 constexpr uint32_t kHashPlain = 2048;         // per-box hash slots in LDS, plain kernel
-constexpr uint32_t kHashSmall = 1024;         // small-box tier
-constexpr uint32_t kHashBig = 4096;           // big-box tier
+constexpr uint32_t kHashSmall = 256;          // small-box tier (per-source arrays in LDS)
+constexpr uint32_t kHashBig = 2048;           // big-box tier (per-source arrays in LDS)
+constexpr uint32_t kHashSmallSparse = 2048;   // small-box tier, sources as table entries
+constexpr uint32_t kHashBigSparse = 4096;     // big-box tier, sources as table entries
 constexpr uint32_t kHashRetry = 8192;         // boxes that overflowed a tier table
 constexpr uint32_t kBigLog2 = 16;             // boxes of >= 2^16 cubes go to the big tier
 constexpr uint32_t kHashGlobal = 1u << 16;    // per-worker hash slots in the fallback tables
@@ -1642,17 +1644,19 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
 {
     int rc = MG_OK;
     DeviceState &d = g->dev;
-    const QueryKernel kbig = tier_kernel<kBlockBig, true, SPARSE>(d.cfg.unroll_big);
-    const int bsmall = d.cfg.block_small == 128 ? 128 : kBlock;  // threads per small-tier box
+    const int bbig = d.cfg.block_big == 256 ? 256 : kBlockBig;    // threads per big-tier box
+    const QueryKernel kbig = bbig == 256 ? tier_kernel<256, true, SPARSE>(d.cfg.unroll_big)
+                                         : tier_kernel<kBlockBig, true, SPARSE>(d.cfg.unroll_big);
+    const int bsmall = d.cfg.block_small == 256 ? kBlock : 128;  // threads per small-tier box
     const QueryKernel ksmall = bsmall == 128 ? tier_kernel<128, false, SPARSE>(d.cfg.unroll_small)
                                              : tier_kernel<kBlock, false, SPARSE>(d.cfg.unroll_small);
     const QueryKernel kplain = query_plain_kernel<SPARSE>;
-    const uint32_t cap_big = d.cfg.table_big ? d.cfg.table_big : kHashBig;
-    const uint32_t cap_small = d.cfg.table_small ? d.cfg.table_small : (SPARSE ? kHashPlain : kHashSmall);
+    const uint32_t cap_big = d.cfg.table_big ? d.cfg.table_big : (SPARSE ? kHashBigSparse : kHashBig);
+    const uint32_t cap_small = d.cfg.table_small ? d.cfg.table_small : (SPARSE ? kHashSmallSparse : kHashSmall);
     const uint32_t dyn_big = lds_bytes(g->nseg, cap_big, SPARSE), dyn_small = lds_bytes(g->nseg, cap_small, SPARSE),
                    dyn_plain = lds_bytes(g->nseg, kHashPlain, SPARSE);
     int occ_big = 1, occ_small = 1, occ_plain = 1;
-    if ((rc = occupancy(d, reinterpret_cast<const void *>(kbig), kBlockBig, dyn_big, &occ_big, err)) ||
+    if ((rc = occupancy(d, reinterpret_cast<const void *>(kbig), bbig, dyn_big, &occ_big, err)) ||
         (rc = occupancy(d, reinterpret_cast<const void *>(ksmall), bsmall, dyn_small, &occ_small, err)) ||
         (rc = occupancy(d, reinterpret_cast<const void *>(kplain), kBlock, dyn_plain, &occ_plain, err)))
         return rc;
@@ -1670,7 +1674,7 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
         rc = timing_begin(g, s, err);
         if (rc) return rc;
         A.table_cap = cap_big;
-        hipLaunchKernelGGL(kbig, dim3(wbig), dim3(kBlockBig), dyn_big, s, A);
+        hipLaunchKernelGGL(kbig, dim3(wbig), dim3(bbig), dyn_big, s, A);
         HIP_TRY(hipGetLastError());
         A.table_cap = cap_small;
         hipLaunchKernelGGL(ksmall, dim3(wsmall), dim3(bsmall), dyn_small, s, A);
@@ -1687,7 +1691,7 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
     uint32_t cap_retry = d.cfg.table_retry;
     if (!cap_retry) {  // the largest table up to kHashRetry that fits the LDS of a workgroup
         cap_retry = kHashRetry;
-        while (cap_retry > kHashBig &&
+        while (cap_retry > kHashBigSparse &&
                lds_bytes(g->nseg, cap_retry, SPARSE) + sizeof(QueryShared) > uint64_t(d.lds_max))
             cap_retry /= 2;
     }
@@ -1849,8 +1853,9 @@ int dev_propagate_tf(Graph *g, const uint8_t *tf, uint32_t T, float *out, void *
 
 int dev_set_launch(Graph *g, const mg_launch_cfg *cfg, std::string *err)
 {
-    if (!(cfg->block_small == 0 || cfg->block_small == 128 || cfg->block_small == 256)) {
-        *err = "mg_set_launch: block_small must be 0, 128 or 256";
+    if (!(cfg->block_small == 0 || cfg->block_small == 128 || cfg->block_small == 256) ||
+        !(cfg->block_big == 0 || cfg->block_big == 256 || cfg->block_big == 512)) {
+        *err = "mg_set_launch: block_small must be 0, 128 or 256 and block_big 0, 256 or 512";
         return MG_EINVAL;
     }
     for (uint32_t t : {cfg->table_big, cfg->table_small, cfg->table_retry})
@@ -1909,15 +1914,17 @@ int dev_autotune(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *
         }
     // table sizes (LDS per workgroup, hence occupancy), one tier at a time
     const uint32_t tb[3] = {1024, 2048, 4096}, ts[3] = {256, 512, 1024};
-    for (uint32_t t : tb) {
-        if (rc) break;
-        g->dev.cfg = best_cfg;
-        g->dev.cfg.table_big = t;
-        float ms = 0;
-        if ((rc = time_variant(kQueryBatched, &ms))) break;
-        if (ms < best) best = ms, best_cfg.table_big = t;
-    }
-    for (uint32_t bsm : {256u, 128u})
+    for (uint32_t bbg : {512u, 256u})
+        for (uint32_t t : tb) {
+            if (rc) break;
+            g->dev.cfg = best_cfg;
+            g->dev.cfg.table_big = t;
+            g->dev.cfg.block_big = bbg;
+            float ms = 0;
+            if ((rc = time_variant(kQueryBatched, &ms))) break;
+            if (ms < best) best = ms, best_cfg.table_big = t, best_cfg.block_big = bbg;
+        }
+    for (uint32_t bsm : {128u, 256u})
         for (uint32_t t : ts) {
             if (rc) break;
             g->dev.cfg = best_cfg;

@@ -48,7 +48,7 @@ struct DeviceState {
         int blocks;     // blocks per CU
     };
     std::vector<Occ> occupancy;  // per kernel variant and LDS size
-    mg_launch_cfg cfg = {8, 8, 8, 256, 0, 0, 0, 0};
+    mg_launch_cfg cfg = {16, 8, 16, 256, 0, 0, 0, 0, 0};
     bool timing = false;
     std::vector<void *> ev_start, ev_stop;  // hipEvent_t pairs recorded around the dominant kernel
     uint32_t ev_used = 0;

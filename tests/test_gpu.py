@@ -257,19 +257,21 @@ def test_adjoint_box_colour():
 
 # ------------------------------------------------------------------ launch configurations (autotuner)
 
-@pytest.mark.parametrize("ub,us,un,bs", [(4, 16, 4, 256), (16, 4, 16, 128), (8, 8, 8, 128), (8, 16, 8, 0)])
-def test_query_every_unroll_variant(ub, us, un, bs):
+@pytest.mark.parametrize("ub,us,un,bs,bb", [(4, 16, 4, 256, 512), (16, 4, 16, 128, 256), (8, 8, 8, 128, 512),
+                                            (8, 16, 8, 0, 256), (16, 8, 16, 256, 0)])
+def test_query_every_unroll_variant(ub, us, un, bs, bb):
     w = synth.workload(2, dims=(150, 140, 130), segments=200, n_boxes=1500)
     vol = synth.make_volume(w)
     g = _graph(("unroll", ub, us, un), vol)
-    g.set_launch_config(unroll_big=ub, unroll_small=us, unroll_naive=un, block_small=bs)
+    g.set_launch_config(unroll_big=ub, unroll_small=us, unroll_naive=un, block_small=bs, block_big=bb)
     boxes = synth.make_boxes(w)
     boxes[:5] = [0, 0, 0, 150, 140, 130]          # big-tier boxes
     ids, vol_c = scan.compact(vol)
     _, ref = scan.box_counts(vol_c, len(ids), boxes)
     db = _dev(boxes)
     for v in ("batched", "naive"):
-        _compare(g.query(db, variant=v).cpu().numpy(), ref, None, "%s u=%d/%d/%d b=%d" % (v, ub, us, un, bs))
+        _compare(g.query(db, variant=v).cpu().numpy(), ref, None,
+                 "%s u=%d/%d/%d b=%d/%d" % (v, ub, us, un, bs, bb))
 
 
 def test_autotune_and_launch_validation():
@@ -290,6 +292,8 @@ def test_autotune_and_launch_validation():
         g.set_launch_config(tf_block=100)
     with pytest.raises(MGError):
         g.set_launch_config(block_small=192)
+    with pytest.raises(MGError):
+        g.set_launch_config(block_big=128)
     assert g.launch_config() == cfg
 
 
