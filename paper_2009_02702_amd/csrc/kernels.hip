@@ -82,16 +82,18 @@ struct LevelTable {
 // ordered so that the slow axis is the thinner one. Lanes cover tiles of
 // 2^ltx cubes along the fast axis times 64 / 2^ltx rows along the mid axis.
 struct Slab {
-    uint32_t count;      // cubes
-    uint32_t level;
+    uint64_t base;       // element index of the first cube in the combined map buffer
     uint32_t e0, e1, e2; // extents along the fast, mid and slow axes
     uint32_t s1, s2;     // element strides of the mid and slow axes (fast axis: 1)
-    uint32_t ltx;        // log2 of the tile width along the fast axis
-    uint32_t axes;       // fast | mid << 2 | slow << 4 (0 = x, 1 = y, 2 = z)
     uint32_t bx, by, bz; // first cube, level coordinates
-    uint32_t pad;
-    uint64_t base;       // element index of the first cube in the combined map buffer
+    uint8_t level;
+    uint8_t ltx;         // log2 of the tile width along the fast axis
+    uint8_t axes;        // fast | mid << 2 | slow << 4 (0 = x, 1 = y, 2 = z)
+    uint8_t pad;
 };
+static_assert(sizeof(Slab) == 48, "Slab layout");
+
+__host__ __device__ inline uint32_t slab_count(const Slab &sl) { return sl.e0 * sl.e1 * sl.e2; }
 
 // Level coordinates of the cube at (fast, mid, slow) offsets (i0, i1, i2).
 __device__ inline void slab_coords(const Slab &sl, uint32_t i0, uint32_t i1, uint32_t i2, uint32_t *x,
@@ -129,8 +131,7 @@ __device__ inline void put_slab(Slab *out, int *n, const LevelTable &lt, uint32_
     const uint32_t ex = x1 - x0, ey = y1 - y0, ez = z1 - z0;
     const uint32_t X = lt.dims[lev][0], Y = lt.dims[lev][1], Z = lt.dims[lev][2];
     Slab s;
-    s.count = ex * ey * ez;
-    s.level = lev;
+    s.level = uint8_t(lev);
     s.bx = x0, s.by = y0, s.bz = z0;
     s.pad = 0;
     uint32_t f, m, w, ef, em, ew, sm, sw;
@@ -150,11 +151,11 @@ __device__ inline void put_slab(Slab *out, int *n, const LevelTable &lt, uint32_
     }
     s.e0 = ef, s.e1 = em, s.e2 = ew;
     s.s1 = sm, s.s2 = sw;
-    s.axes = f | (m << 2) | (w << 4);
+    s.axes = uint8_t(f | (m << 2) | (w << 4));
     uint32_t ltx = 0;
     while (ltx < 6 && (1u << ltx) < ef) ++ltx;  // tile width: smallest power of two >= e0, at most 64
     if (sm >= (1u << 24)) ltx = 6;  // one row per tile: lane byte offsets stay below 2^32
-    s.ltx = ltx;
+    s.ltx = uint8_t(ltx);
     out[(*n)++] = s;
 }
 
@@ -234,6 +235,7 @@ struct QueryState {
     uint32_t limit;     // load-factor cap on n_used
     uint32_t *seg_cnt;  // [S] exact integer counts (dense mode)
     float *seg_hi, *seg_lo;  // [S] pushed mass and its compensation (dense mode)
+    Slab *slabs;        // [6 * levels] the box's slabs (LDS)
 };
 
 struct GraphView {
@@ -774,13 +776,18 @@ __device__ inline void expand_lut(const QueryArgs &A, const QueryState &st)
 }
 
 // LDS bytes of the query kernels' dynamic shared memory.
-__host__ __device__ inline uint32_t lds_bytes(uint32_t nseg, uint32_t cap, bool sparse)
+// Dynamic LDS of the query kernels: per-source arrays (dense mode) and the table,
+// then the slab list (6 per level) at a 16-byte aligned offset.
+__host__ __device__ inline uint32_t lds_state_bytes(uint32_t nseg, uint32_t cap, bool sparse)
 {
-    return sparse ? cap * 20u : nseg * 12u + cap * 16u;
+    return ((sparse ? cap * 20u : nseg * 12u + cap * 16u) + 15u) & ~15u;
+}
+__host__ __device__ inline uint32_t lds_bytes(uint32_t nseg, uint32_t cap, bool sparse, uint32_t n_levels)
+{
+    return lds_state_bytes(nseg, cap, sparse) + 6u * n_levels * uint32_t(sizeof(Slab));
 }
 
 struct QueryShared {
-    Slab slabs[kMaxSlabs];
     uint32_t rank_ptr[kMaxSteps + 2];
     int n_slabs;
     uint32_t n_used;
@@ -873,9 +880,9 @@ __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const Quer
         sh.n_slabs = 0;
     }
     __syncthreads();
-    if (nonempty) build_slabs(A.lt, lo, hi, sh.slabs, &sh.n_slabs);
+    if (nonempty) build_slabs(A.lt, lo, hi, st.slabs, &sh.n_slabs);
     __syncthreads();
-    scatter_slabs<BLOCK, UNROLL, SPARSE>(sh.slabs, sh.n_slabs, A.maps, A.maps16, A.lt, st, A.gv, &sh.flags);
+    scatter_slabs<BLOCK, UNROLL, SPARSE>(st.slabs, sh.n_slabs, A.maps, A.maps16, A.lt, st, A.gv, &sh.flags);
     __syncthreads();
     if (A.lut_ptr)
         expand_lut<BLOCK, SPARSE>(A, st);
@@ -885,7 +892,7 @@ __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const Quer
     const bool overflow = (sh.flags & 1u) != 0;
     if (A.stats && threadIdx.x == 0 && (!overflow || !report_overflow)) {
         uint32_t cubes = 0;
-        for (int i = 0; i < sh.n_slabs; ++i) cubes += sh.slabs[i].count;
+        for (int i = 0; i < sh.n_slabs; ++i) cubes += slab_count(st.slabs[i]);
         A.stats[2 * uint64_t(q)] = cubes;
         // bit 30: answered by the retry launch, bit 31: by the global-table fallback
         A.stats[2 * uint64_t(q) + 1] = sh.n_used | A.stats_tag;
@@ -931,6 +938,7 @@ template <bool SPARSE>
 __device__ inline QueryState lds_state(char *dyn, QueryShared &sh, uint32_t nseg, uint32_t cap)
 {
     QueryState st;
+    st.slabs = reinterpret_cast<Slab *>(dyn + lds_state_bytes(nseg, cap, SPARSE));
     uint32_t *t = reinterpret_cast<uint32_t *>(dyn);
     if (SPARSE) {
         st.seg_cnt = nullptr;
@@ -1031,6 +1039,7 @@ __global__ __launch_bounds__(BLOCK) void query_retry_kernel(QueryArgs A)
 template <bool SPARSE>
 __global__ __launch_bounds__(kBlock) void query_fallback_kernel(QueryArgs A)
 {
+    extern __shared__ __align__(16) char dyn[];
     __shared__ QueryShared sh;
     QueryState st;
     const uint64_t w = blockIdx.x;
@@ -1047,6 +1056,7 @@ __global__ __launch_bounds__(kBlock) void query_fallback_kernel(QueryArgs A)
     st.seg_cnt = SPARSE ? nullptr : A.g_seg_cnt + w * A.gv.nseg;
     st.seg_hi = SPARSE ? nullptr : A.g_seg_hi + w * A.gv.nseg;
     st.seg_lo = SPARSE ? nullptr : A.g_seg_lo + w * A.gv.nseg;
+    st.slabs = reinterpret_cast<Slab *>(dyn);  // the only dynamic LDS of this kernel
     load_rank_ptr<kBlock>(A, sh);
     __syncthreads();
     const uint32_t n_over = ld(&A.counters[5]);
@@ -1209,9 +1219,9 @@ __global__ __launch_bounds__(kBlock) void footprint_kernel(LevelTable lt, const 
     __syncthreads();
     for (int si = 0; si < n_slabs; ++si) {
         const Slab sl = slabs[si];
-        if (threadIdx.x == 0) atomicAdd(&per_level[sl.level], sl.count);
+        if (threadIdx.x == 0) atomicAdd(&per_level[sl.level], slab_count(sl));
         if (!cubes) continue;
-        for (uint32_t r = threadIdx.x; r < sl.count; r += kBlock) {
+        for (uint32_t r = threadIdx.x; r < slab_count(sl); r += kBlock) {
             const uint32_t i0 = r % sl.e0, i1 = (r / sl.e0) % sl.e1, i2 = r / (sl.e0 * sl.e1);
             uint32_t x, y, z;
             slab_coords(sl, i0, i1, i2, &x, &y, &z);
@@ -1653,8 +1663,10 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
     const QueryKernel kplain = query_plain_kernel<SPARSE>;
     const uint32_t cap_big = d.cfg.table_big ? d.cfg.table_big : (SPARSE ? kHashBigSparse : kHashBig);
     const uint32_t cap_small = d.cfg.table_small ? d.cfg.table_small : (SPARSE ? kHashSmallSparse : kHashSmall);
-    const uint32_t dyn_big = lds_bytes(g->nseg, cap_big, SPARSE), dyn_small = lds_bytes(g->nseg, cap_small, SPARSE),
-                   dyn_plain = lds_bytes(g->nseg, kHashPlain, SPARSE);
+    const uint32_t L = g->n_levels;
+    const uint32_t dyn_big = lds_bytes(g->nseg, cap_big, SPARSE, L),
+                   dyn_small = lds_bytes(g->nseg, cap_small, SPARSE, L),
+                   dyn_plain = lds_bytes(g->nseg, kHashPlain, SPARSE, L);
     int occ_big = 1, occ_small = 1, occ_plain = 1;
     if ((rc = occupancy(d, reinterpret_cast<const void *>(kbig), bbig, dyn_big, &occ_big, err)) ||
         (rc = occupancy(d, reinterpret_cast<const void *>(ksmall), bsmall, dyn_small, &occ_small, err)) ||
@@ -1692,10 +1704,10 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
     if (!cap_retry) {  // the largest table up to kHashRetry that fits the LDS of a workgroup
         cap_retry = kHashRetry;
         while (cap_retry > kHashBigSparse &&
-               lds_bytes(g->nseg, cap_retry, SPARSE) + sizeof(QueryShared) > uint64_t(d.lds_max))
+               lds_bytes(g->nseg, cap_retry, SPARSE, L) + sizeof(QueryShared) > uint64_t(d.lds_max))
             cap_retry /= 2;
     }
-    const uint32_t dyn_retry = lds_bytes(g->nseg, cap_retry, SPARSE);
+    const uint32_t dyn_retry = lds_bytes(g->nseg, cap_retry, SPARSE, L);
     int occ_retry = 1;
     if ((rc = occupancy(d, reinterpret_cast<const void *>(kretry), kBlockBig, dyn_retry, &occ_retry, err)))
         return rc;
@@ -1707,7 +1719,8 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
     HIP_TRY(hipGetLastError());
     A.ovf_out = nullptr;
     A.stats_tag = 0x80000000u;
-    hipLaunchKernelGGL(query_fallback_kernel<SPARSE>, dim3(kFallbackWorkers), dim3(kBlock), 0, s, A);
+    hipLaunchKernelGGL(query_fallback_kernel<SPARSE>, dim3(kFallbackWorkers), dim3(kBlock),
+                       6u * L * uint32_t(sizeof(Slab)), s, A);
     HIP_TRY(hipGetLastError());
     // the timed region: every kernel that answers boxes (tiers or plain, retry, fallback)
     return timing_end(g, s, err);
