@@ -17,6 +17,11 @@ arrival time.
 Admission is bounded by a device-memory budget: the number of slots (and, if
 one full slot does not fit, the batch size) is reduced until the slots fit the
 budget, so a small budget makes requests wait longer instead of failing.
+
+Admission is also size-aware: the host counts each box's footprint cubes in
+closed form, and boxes of at least `huge_cubes` cubes wait in a queue of their
+own and are batched only with each other, on at most half of the slots, so a
+batch of small requests is never held up by one huge box.
 """
 from __future__ import annotations
 
@@ -49,6 +54,29 @@ class ServeStats:
         }
 
 
+def cube_counts(boxes: np.ndarray, dims) -> np.ndarray:
+    """Footprint cubes of each box (uint32 [n, 6] rows x0, y0, z0, dx, dy, dz, clipped to dims),
+    in closed form per level: the aligned cells of the level inside the box minus those covered
+    by cells of the next level."""
+    b = np.asarray(boxes, dtype=np.int64)
+    d = np.asarray(dims, dtype=np.int64)
+    lo = np.minimum(b[:, :3], d)
+    hi = np.minimum(b[:, :3] + b[:, 3:], d)
+    out = np.zeros(len(b), dtype=np.int64)
+    l = 0
+    while True:
+        one = 1 << l
+        a, c = (lo + one - 1) >> l, hi >> l
+        outer = np.prod(np.maximum(c - a, 0), axis=1)
+        if not outer.any():
+            break
+        pa, pc = (lo + 2 * one - 1) >> (l + 1), hi >> (l + 1)
+        inner = np.prod(np.maximum(2 * (pc - pa), 0), axis=1)
+        out += outer - inner
+        l += 1
+    return out
+
+
 class _Slot:
     def __init__(self, g: Graph, max_batch: int, max_tf: int, device, use_graphs: bool, classes):
         torch = _torch()
@@ -70,6 +98,7 @@ class _Slot:
         check(g._lib.mg_workspace_init(g._h, self.ws.data_ptr(), nbytes, self.stream.cuda_stream))
         self.event = torch.cuda.Event()
         self.busy = False
+        self.huge = False
         self.reqs = None
         self.graphs = {}
         self.classes = [c for c in classes if c <= max_batch] or [max_batch]
@@ -125,11 +154,13 @@ class Server:
 
     def __init__(self, g: Graph, slots: int = 4, max_batch: int = 4096, max_tf: int = 64,
                  budget_bytes: Optional[int] = None, use_graphs: bool = True,
-                 classes=(64, 256, 1024, 4096, 16384)):
+                 classes=(64, 256, 1024, 4096, 16384), huge_cubes: int = 1 << 20):
         torch = _torch()
         self.g = g
         inf = g.info()
         S, N = inf["nseg"], inf["n_nodes"]
+        self.dims = inf["dims"][0]
+        self.huge_cubes = huge_cubes
 
         def slot_bytes(b, t):
             return g.workspace_bytes(b) + b * (24 + 4 * S) + t * (4 * S + 16 * N)
@@ -162,7 +193,8 @@ class Server:
         arrivals = np.asarray(arrivals, dtype=np.float64)
         assert n == len(arrivals) and np.all(np.diff(arrivals) >= 0), "arrivals must be sorted"
         done = np.full(n, np.nan)
-        pending = deque()
+        huge = cube_counts(boxes, self.dims) >= self.huge_cubes
+        pending, pending_huge = deque(), deque()
         nxt = 0
         batches, sizes = 0, []
         finished = 0
@@ -170,7 +202,7 @@ class Server:
         while finished < n:
             now = time.perf_counter() - t0
             while nxt < n and arrivals[nxt] <= now:
-                pending.append(nxt)
+                (pending_huge if huge[nxt] else pending).append(nxt)
                 nxt += 1
             progressed = False
             for sl in self.slots:
@@ -182,21 +214,29 @@ class Server:
                         results[r] = sl.h_out[:len(r)].numpy()
                     finished += len(r)
                     sl.busy = False
+                    sl.huge = False
                     progressed = True
             for sl in self.slots:
-                if not pending:
+                if not pending and not pending_huge:
                     break
                 if sl.busy:
                     continue
+                # huge boxes batch only with each other, on at most half of the slots
+                n_huge_busy = sum(1 for x in self.slots if x.busy and x.huge)
+                use_huge = bool(pending_huge) and (not pending or n_huge_busy < max(1, len(self.slots) // 2))
+                if not use_huge and not pending:
+                    continue
+                queue = pending_huge if use_huge else pending
                 # up to max_batch requests, of which at most max_tf carry a transfer function
                 take, n_tf = [], 0
-                while pending and len(take) < self.max_batch:
-                    i = pending[0]
+                while queue and len(take) < self.max_batch:
+                    i = queue[0]
                     if tf_index is not None and tf_index[i] >= 0:
                         if n_tf == self.max_tf:
                             break
                         n_tf += 1
-                    take.append(pending.popleft())
+                    take.append(queue.popleft())
+                sl.huge = use_huge
                 r = np.array(take, dtype=np.int64)
                 k = len(r)
                 tf_batch = None
@@ -208,7 +248,7 @@ class Server:
                 batches += 1
                 sizes.append(k)
                 progressed = True
-            if not progressed and not pending and nxt < n:
+            if not progressed and not pending and not pending_huge and nxt < n:
                 wait = arrivals[nxt] - (time.perf_counter() - t0)
                 if wait > 200e-6:
                     time.sleep(wait - 100e-6)

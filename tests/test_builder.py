@@ -260,3 +260,17 @@ def test_mixture_lut_threads_deterministic_and_state_errors():
     b = g.export_lut()
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+def test_server_cube_counts_match_the_oracle():
+    """The server's closed-form cube count per box (size-aware admission) equals the footprint's cube
+    count of the oracle (Alg. footprint assembly), clipped boxes and empty boxes included."""
+    from oracle import footprint as ofp
+    from paper_2009_02702_amd.serve import cube_counts
+    rng = np.random.default_rng(3)
+    dims = (37, 23, 50)
+    b = np.concatenate([rng.integers(0, 45, (300, 3)), rng.integers(0, 40, (300, 3))], axis=1).astype(np.uint32)
+    b[:5, 3:] = 0
+    got = cube_counts(b, dims)
+    for i, row in enumerate(b.astype(int)):
+        assert got[i] == ofp.cube_count(row[:3], row[3:], dims), i
