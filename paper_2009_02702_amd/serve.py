@@ -19,9 +19,11 @@ one full slot does not fit, the batch size) is reduced until the slots fit the
 budget, so a small budget makes requests wait longer instead of failing.
 
 Admission is also size-aware: the host counts each box's footprint cubes in
-closed form, and boxes of at least `huge_cubes` cubes wait in a queue of their
-own and are batched only with each other, on at most half of the slots, so a
-batch of small requests is never held up by one huge box.
+closed form, and a box of at least `split_cubes` cubes is cut into sub-boxes
+along its longest axis at aligned positions (multiples of a power of two, so
+few cubes are cut) that are answered as separate rows of the same batch, in
+parallel on different workgroups. Histograms of disjoint parts add up, so the
+request's row is the volume-weighted sum of its rows' fractions (in fp64).
 """
 from __future__ import annotations
 
@@ -77,6 +79,26 @@ def cube_counts(boxes: np.ndarray, dims) -> np.ndarray:
     return out
 
 
+def split_box(box, dims, pieces: int):
+    """Sub-boxes (uint32 [m, 6]) covering the clipped box, cut along its longest axis into about
+    `pieces` parts at multiples of a power of two."""
+    lo = [min(int(box[a]), int(dims[a])) for a in range(3)]
+    hi = [min(int(box[a]) + int(box[3 + a]), int(dims[a])) for a in range(3)]
+    ext = [h - l for l, h in zip(lo, hi)]
+    ax = int(np.argmax(ext))
+    if pieces < 2 or ext[ax] < 2 or min(ext) == 0:
+        return np.array([list(lo) + ext], dtype=np.uint32)
+    align = 1 << max(0, int(np.floor(np.log2(ext[ax] / pieces))))
+    cuts = list(range((lo[ax] // align + 1) * align, hi[ax], align))
+    edges = [lo[ax]] + cuts + [hi[ax]]
+    out = []
+    for a, b in zip(edges[:-1], edges[1:]):
+        r = list(lo) + ext
+        r[ax], r[3 + ax] = a, b - a
+        out.append(r)
+    return np.array(out, dtype=np.uint32)
+
+
 class _Slot:
     def __init__(self, g: Graph, max_batch: int, max_tf: int, device, use_graphs: bool, classes):
         torch = _torch()
@@ -98,8 +120,8 @@ class _Slot:
         check(g._lib.mg_workspace_init(g._h, self.ws.data_ptr(), nbytes, self.stream.cuda_stream))
         self.event = torch.cuda.Event()
         self.busy = False
-        self.huge = False
         self.reqs = None
+        self.n_rows = 0
         self.graphs = {}
         self.classes = [c for c in classes if c <= max_batch] or [max_batch]
         if use_graphs:
@@ -154,13 +176,14 @@ class Server:
 
     def __init__(self, g: Graph, slots: int = 4, max_batch: int = 4096, max_tf: int = 64,
                  budget_bytes: Optional[int] = None, use_graphs: bool = True,
-                 classes=(64, 256, 1024, 4096, 16384), huge_cubes: int = 1 << 20):
+                 classes=(64, 256, 1024, 4096, 16384), split_cubes: int = 1 << 18,
+                 piece_cubes: int = 1 << 16):
         torch = _torch()
         self.g = g
         inf = g.info()
         S, N = inf["nseg"], inf["n_nodes"]
         self.dims = inf["dims"][0]
-        self.huge_cubes = huge_cubes
+        self.split_cubes, self.piece_cubes = split_cubes, piece_cubes
 
         def slot_bytes(b, t):
             return g.workspace_bytes(b) + b * (24 + 4 * S) + t * (4 * S + 16 * N)
@@ -193,8 +216,14 @@ class Server:
         arrivals = np.asarray(arrivals, dtype=np.float64)
         assert n == len(arrivals) and np.all(np.diff(arrivals) >= 0), "arrivals must be sorted"
         done = np.full(n, np.nan)
-        huge = cube_counts(boxes, self.dims) >= self.huge_cubes
-        pending, pending_huge = deque(), deque()
+        # rows of each request: the box itself, or its sub-boxes
+        cubes = cube_counts(boxes, self.dims)
+        rows = {}
+        for i in np.nonzero(cubes >= self.split_cubes)[0]:
+            sub = split_box(boxes[i], self.dims, int(min(64, -(-cubes[i] // self.piece_cubes))))
+            if len(sub) > 1 and len(sub) <= self.max_batch:
+                rows[int(i)] = sub
+        pending = deque()
         nxt = 0
         batches, sizes = 0, []
         finished = 0
@@ -202,41 +231,48 @@ class Server:
         while finished < n:
             now = time.perf_counter() - t0
             while nxt < n and arrivals[nxt] <= now:
-                (pending_huge if huge[nxt] else pending).append(nxt)
+                pending.append(nxt)
                 nxt += 1
             progressed = False
             for sl in self.slots:
                 if sl.busy and sl.event.query():
-                    t_done = time.perf_counter() - t0
                     r = sl.reqs
-                    done[r] = t_done
-                    if results is not None:
-                        results[r] = sl.h_out[:len(r)].numpy()
+                    h = sl.h_out[:sl.n_rows].numpy()
+                    row = 0
+                    for i in r.tolist():
+                        sub = rows.get(i)
+                        if sub is None:
+                            if results is not None:
+                                results[i] = h[row]
+                            row += 1
+                        else:  # volume-weighted sum of the sub-boxes' fractions
+                            v = np.prod(sub[:, 3:].astype(np.float64), axis=1)
+                            comb = (h[row:row + len(sub)].astype(np.float64).T @ v) / v.sum()
+                            if results is not None:
+                                results[i] = comb
+                            row += len(sub)
+                    done[r] = time.perf_counter() - t0
                     finished += len(r)
                     sl.busy = False
-                    sl.huge = False
                     progressed = True
             for sl in self.slots:
-                if not pending and not pending_huge:
+                if not pending:
                     break
                 if sl.busy:
                     continue
-                # huge boxes batch only with each other, on at most half of the slots
-                n_huge_busy = sum(1 for x in self.slots if x.busy and x.huge)
-                use_huge = bool(pending_huge) and (not pending or n_huge_busy < max(1, len(self.slots) // 2))
-                if not use_huge and not pending:
-                    continue
-                queue = pending_huge if use_huge else pending
-                # up to max_batch requests, of which at most max_tf carry a transfer function
-                take, n_tf = [], 0
-                while queue and len(take) < self.max_batch:
-                    i = queue[0]
+                # requests whose rows fit max_batch, of which at most max_tf carry a transfer function
+                take, n_tf, n_rows = [], 0, 0
+                while pending:
+                    i = pending[0]
+                    k_i = len(rows[i]) if i in rows else 1
+                    if n_rows + k_i > self.max_batch:
+                        break
                     if tf_index is not None and tf_index[i] >= 0:
                         if n_tf == self.max_tf:
                             break
                         n_tf += 1
-                    take.append(queue.popleft())
-                sl.huge = use_huge
+                    take.append(pending.popleft())
+                    n_rows += k_i
                 r = np.array(take, dtype=np.int64)
                 k = len(r)
                 tf_batch = None
@@ -244,11 +280,14 @@ class Server:
                     sel = tf_index[r]
                     tf_batch = tfs[sel[sel >= 0]]
                 sl.reqs = r
-                sl.launch(self.g, boxes[r], tf_batch)
+                sl.n_rows = n_rows
+                bx = boxes[r] if not any(i in rows for i in take) else np.concatenate(
+                    [rows[i] if i in rows else boxes[i:i + 1] for i in take])
+                sl.launch(self.g, bx, tf_batch)
                 batches += 1
                 sizes.append(k)
                 progressed = True
-            if not progressed and not pending and not pending_huge and nxt < n:
+            if not progressed and not pending and nxt < n:
                 wait = arrivals[nxt] - (time.perf_counter() - t0)
                 if wait > 200e-6:
                     time.sleep(wait - 100e-6)

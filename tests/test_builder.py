@@ -274,3 +274,23 @@ def test_server_cube_counts_match_the_oracle():
     got = cube_counts(b, dims)
     for i, row in enumerate(b.astype(int)):
         assert got[i] == ofp.cube_count(row[:3], row[3:], dims), i
+
+
+def test_server_split_box_tiles_the_box_at_aligned_cuts():
+    from paper_2009_02702_amd.serve import split_box
+    rng = np.random.default_rng(4)
+    dims = (300, 200, 250)
+    for _ in range(200):
+        box = np.concatenate([rng.integers(0, 290, 3), rng.integers(1, 300, 3)]).astype(np.uint32)
+        p = int(rng.integers(1, 40))
+        sub = split_box(box, dims, p).astype(np.int64)
+        lo = np.minimum(box[:3].astype(np.int64), dims)
+        hi = np.minimum(box[:3].astype(np.int64) + box[3:], dims)
+        assert np.prod(sub[:, 3:], axis=1).sum() == np.prod(np.maximum(hi - lo, 0))
+        assert (sub[:, 3:] > 0).all() or len(sub) == 1
+        ax = int(np.argmax(hi - lo))
+        inner = sub[1:, ax]                                  # cut positions share one power of two
+        if len(inner):
+            step = inner[1] - inner[0] if len(inner) > 1 else None
+            assert step is None or (step & (step - 1)) == 0
+            assert (inner % (step or 1) == 0).all()

@@ -421,6 +421,24 @@ def test_serving_results_equal_alone_and_in_the_mix():
     print(stats.summary())
 
 
+def test_serving_splits_big_boxes_into_sub_boxes():
+    """Boxes above the split threshold are answered as aligned sub-boxes in the same batch and
+    recombined by volume: the result still matches the oracle (tiny thresholds force splits)."""
+    from paper_2009_02702_amd.serve import cube_counts, split_box
+    w = synth.workload(2, dims=(120, 110, 90), segments=70)
+    g, boxes, res, stats = _served(w, 600, 5000.0, slots=2, max_batch=512, max_tf=8, split_cubes=2000,
+                                   piece_cubes=700)
+    cubes = cube_counts(boxes, w.dims)
+    assert (cubes >= 2000).sum() > 50          # many requests were split
+    big = boxes[np.argmax(cubes)].astype(np.int64)
+    sub = split_box(big, w.dims, 8)
+    clipped = np.prod(np.minimum(big[:3] + big[3:], w.dims) - big[:3])
+    assert len(sub) > 1 and np.prod(sub[:, 3:].astype(np.int64), axis=1).sum() == clipped
+    ids, vol_c = scan.compact(synth.make_volume(w))
+    _, ref = scan.box_counts(vol_c, len(ids), boxes)
+    _compare(res, ref, None, "served with splits")
+
+
 def test_serving_small_budget_queues_instead_of_failing():
     from paper_2009_02702_amd.serve import Server
     w = synth.workload(5, dims=(100, 90, 80), segments=40)
