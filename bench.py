@@ -123,8 +123,9 @@ def main():
                          "serve: Poisson-arrival stream through the continuous-batching server on --config")
     ap.add_argument("--tf-count", type=int, default=8)
     ap.add_argument("--qps", type=str, default="5000,20000,50000,100000,200000")
-    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--autotune", action="store_true", help="serve mode: autotune the launch on the workload's boxes first")
     ap.add_argument("--serve-qps", type=float, default=100000.0,
                     help="full mode: offered rate of the short serving leg (per-request p50/p99); 0 skips it")
     args = ap.parse_args()
@@ -173,6 +174,9 @@ def main():
         print(json.dumps(r), flush=True)
         return
     if args.mode == "serve":
+        if args.autotune:
+            print("[bench] autotuned %s" % (g.autotune(dboxes, out=out, reps=3, workspace=ws),), file=sys.stderr,
+                  flush=True)
         qps = [float(x) for x in args.qps.split(",") if x]
         r = {"mode": "serve", "workload": w.name, "levels": measure_serve(g, w, qps, args.serve_seconds)}
         print(json.dumps(r), flush=True)

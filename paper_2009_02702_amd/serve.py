@@ -27,6 +27,7 @@ request's row is the volume-weighted sum of its rows' fractions (in fp64).
 """
 from __future__ import annotations
 
+import gc
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -210,7 +211,17 @@ class Server:
         """Serve requests i = 0..n-1 arriving at arrivals[i] seconds after the start.
 
         tf_index[i] >= 0 makes request i also propagate tfs[tf_index[i]] ([S, 4] uint8).
-        Results (fp32 [n, S]) are written into `results` if given."""
+        Results (fp32 [n, S]) are written into `results` if given. Python's cyclic garbage
+        collector is paused while serving (a full collection can stall the loop for milliseconds)."""
+        was_enabled = gc.isenabled()
+        gc.disable()
+        try:
+            return self._serve(boxes, arrivals, tf_index, tfs, results)
+        finally:
+            if was_enabled:
+                gc.enable()
+
+    def _serve(self, boxes, arrivals, tf_index, tfs, results) -> ServeStats:
         n = len(boxes)
         boxes = np.ascontiguousarray(boxes, dtype=np.uint32)
         arrivals = np.asarray(arrivals, dtype=np.float64)
