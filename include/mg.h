@@ -76,6 +76,7 @@ typedef struct {
     uint64_t device_bytes;  /* device memory held after mg_upload (0 before)         */
     int32_t device;         /* device ordinal after mg_upload, else -1                */
     uint32_t max_mixture;   /* largest number of segments in one node's mixture      */
+    uint32_t quant_bits;    /* 0: exact weights; else the quantizer's bit rate       */
 } mg_info_t;
 
 /* Build a graph from a host uint32 ID volume (CPU; Sec. "Normalized Histogram
@@ -90,6 +91,25 @@ typedef struct {
 int mg_build(const uint32_t *ids, const mg_build_opts *opts, mg_graph **out);
 
 int mg_info(const mg_graph *g, mg_info_t *out);
+
+/* A lossy copy of a graph with scalar-quantized weights (Sec. "Compression":
+ * the open range (0, 1) is cut into 2^bits equal bins, one codeword and the
+ * empirical standard deviation of the weights per bin; Sec. "Implementation
+ * Details": w and 1 - w are both quantized and the orientation with the
+ * smaller error is kept). The codebook is learned from the graph's weights; a
+ * codeword is the mean of its bin's weights (an empty bin: its midpoint and the
+ * standard deviation of a uniform bin). Nodes are visited predecessors first;
+ * nodes with equal (merged) predecessors and codeword are merged, and a node
+ * whose two predecessors merged becomes that predecessor. The copy supports
+ * every entry point of an exact graph (its queries return the quantized
+ * histograms) and mg_export_codebook; its lookup table also carries the
+ * propagated uncertainty (mg_lut_build, mg_query_boxes_err). bits in [1, 20]. */
+int mg_quantize(const mg_graph *g, uint32_t bits, uint32_t threads, mg_graph **out);
+
+/* Codebook of a quantized graph: codeword and sigma host fp32 [2^bits]; node_sigma
+ * host fp32 [n_nodes], the sigma of each node's weight (0 for sources). NULL skips
+ * an array; MG_ESTATE for a graph with exact weights. */
+int mg_export_codebook(const mg_graph *g, float *codeword, float *sigma, float *node_sigma);
 
 /* Host copies of the DAG (NULL skips an array). Per node (n_nodes entries):
  * child_a/child_b are its two predecessors and w[n] = wnum[n]/wden[n] the
@@ -202,10 +222,11 @@ int mg_palette_fetch(mg_graph *g, const float *d_palette, uint32_t T, uint32_t l
 int mg_lut_build(mg_graph *g, uint32_t threads, uint64_t *out_nnz);
 
 /* Host copy of the lookup table: ptr host uint64 [n_nodes + 1]; row n is
- * seg/val[ptr[n] .. ptr[n+1]), sources in increasing order, fractions fp32.
- * seg and val may be NULL (then only ptr is written). MG_ESTATE if the
- * table was not built. */
-int mg_export_lut(const mg_graph *g, uint64_t *ptr, uint32_t *seg, float *val);
+ * seg/val[ptr[n] .. ptr[n+1]), sources in increasing order, fractions fp32;
+ * err (same length) the propagated uncertainty of each fraction (Sec. "Error
+ * Propagation", Eq. (error); zero for exact weights). seg, val and err may be
+ * NULL (then only ptr is written). MG_ESTATE if the table was not built. */
+int mg_export_lut(const mg_graph *g, uint64_t *ptr, uint32_t *seg, float *val, float *err);
 
 /* Box histograms answered from the mixture lookup table (the paper's own
  * query, Sec. "Range queries"): the same footprint and scatter as
@@ -222,8 +243,8 @@ typedef struct {
     uint32_t unroll_small;  /* the same for smaller boxes: 4, 8 or 16 */
     uint32_t unroll_naive;  /* level-0 loads in flight per lane of the naive scan: 4, 8 or 16 */
     uint32_t tf_block;      /* threads per workgroup of the propagation kernel: 64, 128, 256, 512, 1024 */
-    uint32_t table_big;     /* per-box LDS hash slots, big-box tier (0: 4096)                  */
-    uint32_t table_small;   /* small-box tier (0: 1024)                                         */
+    uint32_t table_big;     /* per-box LDS hash slots, big-box tier (0: default, see below)     */
+    uint32_t table_small;   /* small-box tier (0: default)                                      */
     uint32_t table_retry;   /* retry of overflowed boxes (0: the largest of 8192 that fits)     */
     uint32_t block_small;   /* threads per box in the small-box tier: 0 (128), 128 or 256       */
     uint32_t block_big;     /* threads per box in the big-box tier: 0 (512), 256 or 512.
@@ -238,7 +259,8 @@ int mg_get_launch(const mg_graph *g, mg_launch_cfg *out);
 int mg_set_launch(mg_graph *g, const mg_launch_cfg *cfg); /* MG_EINVAL for unsupported values */
 
 /* Autotuner: runs mg_query_boxes and mg_naive_boxes on the caller's boxes with
- * every supported unroll choice, `reps` timed repetitions each (HIP events on
+ * every supported unroll choice, then the table sizes and threads per box of
+ * each tier one tier at a time, `reps` timed repetitions each (HIP events on
  * `stream`), keeps the fastest configuration in the graph and returns it in
  * *chosen. Synchronises `stream`; d_out and d_work as for mg_query_boxes. */
 int mg_autotune(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *d_out, void *d_work,

@@ -36,7 +36,7 @@ class Info(ctypes.Structure):
     _fields_ = [("nseg", ctypes.c_uint32), ("n_nodes", ctypes.c_uint32), ("depth", ctypes.c_uint32),
                 ("n_levels", ctypes.c_uint32), ("dims", (ctypes.c_uint32 * 3) * MAX_LEVELS),
                 ("map_voxels", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64), ("device", ctypes.c_int32),
-                ("max_mixture", ctypes.c_uint32)]
+                ("max_mixture", ctypes.c_uint32), ("quant_bits", ctypes.c_uint32)]
 
 
 class LaunchCfg(ctypes.Structure):
@@ -49,7 +49,7 @@ class LaunchCfg(ctypes.Structure):
 _lib = None
 
 SYMBOLS = [
-    "mg_build", "mg_info", "mg_export_dag", "mg_export_map", "mg_segment_ids", "mg_upload",
+    "mg_build", "mg_info", "mg_quantize", "mg_export_codebook", "mg_export_dag", "mg_export_map", "mg_segment_ids", "mg_upload",
     "mg_workspace_bytes", "mg_workspace_init", "mg_query_boxes", "mg_query_boxes_plain", "mg_query_boxes_stats",
     "mg_query_boxes_sparse",
     "mg_naive_boxes",
@@ -79,6 +79,8 @@ def load() -> ctypes.CDLL:
     sig = {
         "mg_build": ([vp, ctypes.POINTER(BuildOpts), ctypes.POINTER(G)], i32),
         "mg_info": ([G, ctypes.POINTER(Info)], i32),
+        "mg_quantize": ([G, u32, u32, ctypes.POINTER(G)], i32),
+        "mg_export_codebook": ([G, vp, vp, vp], i32),
         "mg_export_dag": ([G, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp], i32),
         "mg_export_map": ([G, u32, vp], i32),
         "mg_segment_ids": ([G, vp], i32),
@@ -94,7 +96,7 @@ def load() -> ctypes.CDLL:
         "mg_propagate_tf": ([G, vp, u32, vp, vp], i32),
         "mg_palette_fetch": ([G, vp, u32, u32, vp, u32, vp, vp], i32),
         "mg_lut_build": ([G, u32, ctypes.POINTER(u64)], i32),
-        "mg_export_lut": ([G, vp, vp, vp], i32),
+        "mg_export_lut": ([G, vp, vp, vp, vp], i32),
         "mg_query_boxes_lut": ([G, vp, u32, vp, vp, u64, vp], i32),
         "mg_get_launch": ([G, ctypes.POINTER(LaunchCfg)], i32),
         "mg_set_launch": ([G, ctypes.POINTER(LaunchCfg)], i32),

@@ -107,6 +107,39 @@ int mg_build(const uint32_t *ids, const mg_build_opts *opts, mg_graph **out)
     return MG_OK;
 }
 
+int mg_quantize(const mg_graph *h, uint32_t bits, uint32_t threads, mg_graph **out)
+{
+    if (!h || !out) return fail(MG_EINVAL, "mg_quantize: null argument");
+    if (h->g.quant_bits) return fail(MG_EINVAL, "mg_quantize: the graph is already quantized");
+    *out = nullptr;
+    mg_graph *q = new (std::nothrow) mg_graph;
+    if (!q) return fail(MG_ENOMEM, "mg_quantize: out of host memory");
+    std::string err;
+    int rc;
+    try {
+        rc = mg::quantize_graph(h->g, bits, threads, &q->g, &err);
+    } catch (const std::bad_alloc &) {
+        rc = MG_ENOMEM, err = "mg_quantize: out of host memory";
+    }
+    if (rc != MG_OK) {
+        delete q;
+        return fail(rc, err);
+    }
+    *out = q;
+    return MG_OK;
+}
+
+int mg_export_codebook(const mg_graph *h, float *codeword, float *sigma, float *node_sigma)
+{
+    if (!h) return fail(MG_EINVAL, "mg_export_codebook: null graph");
+    const mg::Graph &g = h->g;
+    if (!g.quant_bits) return fail(MG_ESTATE, "mg_export_codebook: the graph has exact weights (mg_quantize)");
+    if (codeword) std::memcpy(codeword, g.codebook.data(), g.codebook.size() * sizeof(float));
+    if (sigma) std::memcpy(sigma, g.code_sigma.data(), g.code_sigma.size() * sizeof(float));
+    if (node_sigma) std::memcpy(node_sigma, g.node_sigma.data(), g.node_sigma.size() * sizeof(float));
+    return MG_OK;
+}
+
 int mg_info(const mg_graph *h, mg_info_t *out)
 {
     if (!h || !out) return fail(MG_EINVAL, "mg_info: null argument");
@@ -122,6 +155,7 @@ int mg_info(const mg_graph *h, mg_info_t *out)
     out->device_bytes = g.dev.bytes;
     out->device = g.dev.device;
     out->max_mixture = g.max_mixture;
+    out->quant_bits = g.quant_bits;
     return MG_OK;
 }
 
@@ -278,7 +312,7 @@ int mg_lut_build(mg_graph *h, uint32_t threads, uint64_t *out_nnz)
     return done(rc, err);
 }
 
-int mg_export_lut(const mg_graph *h, uint64_t *ptr, uint32_t *seg, float *val)
+int mg_export_lut(const mg_graph *h, uint64_t *ptr, uint32_t *seg, float *val, float *err)
 {
     if (!h || !ptr) return fail(MG_EINVAL, "mg_export_lut: null argument");
     const mg::Graph &g = h->g;
@@ -286,6 +320,12 @@ int mg_export_lut(const mg_graph *h, uint64_t *ptr, uint32_t *seg, float *val)
     std::memcpy(ptr, g.lut_ptr.data(), g.lut_ptr.size() * sizeof(uint64_t));
     if (seg) std::memcpy(seg, g.lut_seg.data(), g.lut_seg.size() * sizeof(uint32_t));
     if (val) std::memcpy(val, g.lut_val.data(), g.lut_val.size() * sizeof(float));
+    if (err) {
+        if (g.lut_err.size() == g.lut_val.size())
+            std::memcpy(err, g.lut_err.data(), g.lut_err.size() * sizeof(float));
+        else
+            std::memset(err, 0, g.lut_val.size() * sizeof(float));
+    }
     return MG_OK;
 }
 

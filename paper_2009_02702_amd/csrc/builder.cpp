@@ -36,6 +36,8 @@
 #include <functional>
 #include <numeric>
 #include <thread>
+#include <unordered_map>
+#include <cmath>
 
 #include "mg_internal.hpp"
 
@@ -320,6 +322,122 @@ void level_dims(const uint32_t dims[3], std::vector<uint32_t> *out)
     }
 }
 
+// A DAG in creation order (children before parents; sources 0 .. nseg-1 have
+// a = b = n): what finalize_dag turns into a Graph's node arrays.
+struct RawDag {
+    uint32_t nseg = 0;
+    std::vector<uint32_t> a, b;    // predecessors
+    std::vector<uint64_t> wn, wd;  // weight of b as an exact fraction
+    std::vector<uint32_t> mix;     // segments in the node's mixture
+    std::vector<float> alpha;      // fp32 weights if given, else RN(wn / wd)
+    std::vector<float> sigma;      // uncertainty of each weight, if any
+};
+
+// Topological levels (Sec. "Reconstruction"), the deferred step schedule, IDs
+// renumbered by (rank, creation order) with sources fixed, and the mip voxels
+// of levels >= 1 remapped to the new IDs (level 0 holds sources only).
+int finalize_dag(const RawDag &d, bool defer, uint32_t max_depth, unsigned nt, Graph *g, std::string *err)
+{
+    const uint32_t N = uint32_t(d.a.size());
+    std::vector<uint32_t> rank(N, 0);
+    uint32_t depth = 0;
+    for (uint32_t n = d.nseg; n < N; ++n) {
+        rank[n] = std::max(rank[d.a[n]], rank[d.b[n]]) + 1;
+        depth = std::max(depth, rank[n]);
+    }
+    if (max_depth && depth > max_depth) {
+        *err = "graph depth " + std::to_string(depth) + " exceeds max_depth " + std::to_string(max_depth);
+        return MG_EDEPTH;
+    }
+    uint32_t maxmix = 1;
+    for (uint32_t n = d.nseg; n < N; ++n) maxmix = std::max(maxmix, d.mix[n]);
+    // ---- step schedule
+    std::vector<uint32_t> step(N, 0);
+    if (defer && depth > 1) {
+        std::vector<uint32_t> last(N, depth);  // sinks may run as late as the last step
+        for (uint32_t n = d.nseg; n < N; ++n) {
+            last[d.a[n]] = std::min(last[d.a[n]], rank[n] - 1);
+            last[d.b[n]] = std::min(last[d.b[n]], rank[n] - 1);
+        }
+        // bucket[r][d]: not yet scheduled nodes of rank r whose window ends at d
+        std::vector<std::vector<uint32_t>> by_rank(depth + 1);
+        for (uint32_t n = d.nseg; n < N; ++n) by_rank[rank[n]].push_back(n);
+        std::vector<std::vector<uint32_t>> pool(depth + 1);  // indexed by window end
+        std::vector<size_t> head(depth + 1, 0);
+        const uint64_t target = (uint64_t(N - d.nseg) + depth - 1) / depth;
+        for (uint32_t s = 1; s <= depth; ++s) {
+            for (uint32_t n : by_rank[s]) pool[last[n]].push_back(n);
+            uint64_t taken = 0;
+            for (uint32_t d = s; d <= depth; ++d) {
+                auto &pl = pool[d];
+                while (head[d] < pl.size() && (d == s || taken < target)) {
+                    step[pl[head[d]++]] = s;
+                    ++taken;
+                }
+                if (taken >= target && d > s) break;
+            }
+        }
+    } else {
+        for (uint32_t n = d.nseg; n < N; ++n) step[n] = rank[n];
+    }
+
+    // ---- renumber by (rank, creation order); sources keep 0 .. S-1. Nodes whose
+    // predecessors are both sources (rank 1) are then one contiguous ID range.
+    std::vector<uint32_t> cnt(depth + 2, 0);
+    for (uint32_t n = d.nseg; n < N; ++n) cnt[rank[n]]++;
+    g->rank_ptr.assign(depth + 2, 0);
+    g->rank_ptr[0] = 0;
+    g->rank_ptr[1] = d.nseg;
+    for (uint32_t r = 1; r <= depth; ++r) g->rank_ptr[r + 1] = g->rank_ptr[r] + cnt[r];
+    std::vector<uint32_t> pos(g->rank_ptr.begin(), g->rank_ptr.end());
+    std::vector<uint32_t> perm(N);
+    for (uint32_t n = 0; n < d.nseg; ++n) perm[n] = n;
+    for (uint32_t n = d.nseg; n < N; ++n) perm[n] = pos[rank[n]]++;
+
+    g->n_nodes = N;
+    g->depth = depth;
+    g->max_mixture = maxmix;
+    g->child_a.assign(N, 0);
+    g->child_b.assign(N, 0);
+    g->alpha.assign(N, 0.f);
+    g->wnum.assign(N, 0);
+    g->wden.assign(N, 1);
+    g->rank.assign(N, 0);
+    g->step.assign(N, 0);
+    for (uint32_t n = 0; n < N; ++n) {
+        const uint32_t p = perm[n];
+        g->child_a[p] = perm[d.a[n]];
+        g->child_b[p] = perm[d.b[n]];
+        g->wnum[p] = d.wn[n];
+        g->wden[p] = d.wd[n];
+        g->alpha[p] = n < d.nseg ? 0.f : (d.alpha.empty() ? float(double(d.wn[n]) / double(d.wd[n])) : d.alpha[n]);
+        g->rank[p] = rank[n];
+        g->step[p] = step[n];
+    }
+    g->node_sigma.clear();
+    if (!d.sigma.empty()) {
+        g->node_sigma.assign(N, 0.f);
+        for (uint32_t n = 0; n < N; ++n) g->node_sigma[perm[n]] = d.sigma[n];
+    }
+    // ---- execution order of the step schedule: sources, then step 1, 2, ...
+    std::vector<uint32_t> scnt(depth + 2, 0);
+    for (uint32_t n = d.nseg; n < N; ++n) scnt[g->step[n]]++;
+    g->step_ptr.assign(depth + 2, 0);
+    g->step_ptr[1] = d.nseg;
+    for (uint32_t s = 1; s <= depth; ++s) g->step_ptr[s + 1] = g->step_ptr[s] + scnt[s];
+    std::vector<uint32_t> spos(g->step_ptr.begin(), g->step_ptr.end());
+    g->sched.assign(N, 0);
+    for (uint32_t n = 0; n < d.nseg; ++n) g->sched[n] = n;
+    for (uint32_t n = d.nseg; n < N; ++n) g->sched[spos[g->step[n]]++] = n;
+    const uint64_t total = g->maps.size();
+    uint32_t *mp = g->maps.data();
+    const uint64_t first_internal = g->lev_off[1];
+    parallel_chunks(total - first_internal, nt, [&](uint64_t b, uint64_t e, unsigned) {
+        for (uint64_t i = b; i < e; ++i) mp[first_internal + i] = perm[mp[first_internal + i]];
+    });
+    return MG_OK;
+}
+
 int build_graph(const uint32_t *ids, const mg_build_opts *o, Graph *g, std::string *err)
 {
     const uint64_t nx = o->nx, ny = o->ny, nz = o->nz;
@@ -468,100 +586,131 @@ int build_graph(const uint32_t *ids, const mg_build_opts *o, Graph *g, std::stri
         }
     }
 
-    // ---- topological levels (children are created before parents)
+    // ---- ranks, step schedule, numbering by rank, remapped mip voxels
+    RawDag dag;
+    dag.nseg = g->nseg;
     const uint32_t N = store.size();
-    std::vector<uint32_t> rank(N, 0);
-    uint32_t depth = 0;
-    for (uint32_t n = g->nseg; n < N; ++n) {
-        rank[n] = std::max(rank[store.a_[n]], rank[store.b_[n]]) + 1;
-        depth = std::max(depth, rank[n]);
-    }
-    if (o->max_depth && depth > o->max_depth) {
-        *err = "graph depth " + std::to_string(depth) + " exceeds max_depth " + std::to_string(o->max_depth);
-        return MG_EDEPTH;
-    }
-    uint32_t maxmix = 1;
-    for (uint32_t n = g->nseg; n < N; ++n) maxmix = std::max(maxmix, store.len(n));
+    dag.a.assign(store.a_.begin(), store.a_.begin() + N);
+    dag.b.assign(store.b_.begin(), store.b_.begin() + N);
+    dag.wn.assign(store.wn_.begin(), store.wn_.begin() + N);
+    dag.wd.assign(store.wd_.begin(), store.wd_.begin() + N);
+    dag.mix.resize(N);
+    for (uint32_t n = 0; n < N; ++n) dag.mix[n] = n < g->nseg ? 1u : store.len(n);
+    if (int rc = finalize_dag(dag, o->defer != 0, o->max_depth, nt, g, err)) return rc;
+    return MG_OK;
+}
 
-    // ---- step schedule
-    std::vector<uint32_t> step(N, 0);
-    if (o->defer && depth > 1) {
-        std::vector<uint32_t> last(N, depth);  // sinks may run as late as the last step
-        for (uint32_t n = g->nseg; n < N; ++n) {
-            last[store.a_[n]] = std::min(last[store.a_[n]], rank[n] - 1);
-            last[store.b_[n]] = std::min(last[store.b_[n]], rank[n] - 1);
+// Scalar quantization of the interpolation weights (Sec. "Compression": the
+// open range (0, 1) is cut into 2^b equal bins, each represented by one
+// codeword, with the empirical standard deviation of the weights in the bin
+// kept for error estimates; Sec. "Implementation Details": both w and 1 - w
+// are quantized and the orientation with the smaller error is kept). The
+// codebook is learned from the graph's weights (w <= 1/2); a codeword is the
+// mean of its bin's weights, an empty bin gets its midpoint and the standard
+// deviation of a uniform bin. Nodes are visited children first; a node whose
+// two (merged) predecessors coincide becomes that predecessor, and nodes with
+// the same predecessors and codeword are merged (re-use, Sec. "Compression").
+int quantize_graph(const Graph &src, uint32_t bits, uint32_t threads, Graph *dst, std::string *err)
+{
+    if (bits < 1 || bits > 20) {
+        *err = "quantizer bit rate must be in [1, 20]";
+        return MG_EINVAL;
+    }
+    const uint32_t S = src.nseg, N = src.n_nodes, B = 1u << bits;
+    auto bin = [&](double w) { return std::min<uint32_t>(uint32_t(w * B), B - 1); };
+    std::vector<double> sum(B, 0.0), dev2(B, 0.0);
+    std::vector<uint64_t> cnt(B, 0);
+    for (uint32_t n = S; n < N; ++n) {
+        const double w = double(src.wnum[n]) / double(src.wden[n]);
+        const uint32_t k = bin(w);
+        sum[k] += w, cnt[k]++;
+    }
+    for (uint32_t n = S; n < N; ++n) {  // second pass: squared deviations from the bin mean
+        const double w = double(src.wnum[n]) / double(src.wden[n]);
+        const uint32_t k = bin(w);
+        const double dv = w - sum[k] / double(cnt[k]);
+        dev2[k] += dv * dv;
+    }
+    std::vector<float> code(B), sig(B);
+    for (uint32_t k = 0; k < B; ++k) {
+        if (cnt[k]) {
+            code[k] = float(sum[k] / double(cnt[k]));
+            sig[k] = float(std::sqrt(dev2[k] / double(cnt[k])));
+        } else {
+            code[k] = float((k + 0.5) / B);
+            sig[k] = float(1.0 / B / std::sqrt(12.0));
         }
-        // bucket[r][d]: not yet scheduled nodes of rank r whose window ends at d
-        std::vector<std::vector<uint32_t>> by_rank(depth + 1);
-        for (uint32_t n = g->nseg; n < N; ++n) by_rank[rank[n]].push_back(n);
-        std::vector<std::vector<uint32_t>> pool(depth + 1);  // indexed by window end
-        std::vector<size_t> head(depth + 1, 0);
-        const uint64_t target = (uint64_t(N - g->nseg) + depth - 1) / depth;
-        for (uint32_t s = 1; s <= depth; ++s) {
-            for (uint32_t n : by_rank[s]) pool[last[n]].push_back(n);
-            uint64_t taken = 0;
-            for (uint32_t d = s; d <= depth; ++d) {
-                auto &pl = pool[d];
-                while (head[d] < pl.size() && (d == s || taken < target)) {
-                    step[pl[head[d]++]] = s;
-                    ++taken;
-                }
-                if (taken >= target && d > s) break;
-            }
+    }
+    RawDag d;
+    d.nseg = S;
+    std::vector<uint32_t> rep(N);
+    for (uint32_t s = 0; s < S; ++s) {
+        rep[s] = s;
+        d.a.push_back(s), d.b.push_back(s), d.wn.push_back(0), d.wd.push_back(1), d.mix.push_back(1);
+        d.alpha.push_back(0.f), d.sigma.push_back(0.f);
+    }
+    struct Key {
+        uint32_t a, b, w;
+        bool operator==(const Key &o) const { return a == o.a && b == o.b && w == o.w; }
+    };
+    struct KeyHash {
+        size_t operator()(const Key &k) const
+        {
+            return size_t((uint64_t(k.a) * 0x9E3779B97F4A7C15ull) ^ (uint64_t(k.b) * 0xC2B2AE3D27D4EB4Full) ^ k.w);
         }
-    } else {
-        for (uint32_t n = g->nseg; n < N; ++n) step[n] = rank[n];
+    };
+    std::unordered_map<Key, uint32_t, KeyHash> made;
+    for (uint32_t n = S; n < N; ++n) {  // IDs are sorted by rank: predecessors first
+        const uint32_t x = rep[src.child_a[n]], y = rep[src.child_b[n]];
+        if (x == y) {
+            rep[n] = x;
+            continue;
+        }
+        const double w = double(src.wnum[n]) / double(src.wden[n]);
+        const uint32_t k1 = bin(w), k2 = bin(1.0 - w);
+        const bool flip = std::fabs((1.0 - w) - code[k2]) < std::fabs(w - code[k1]);
+        const uint32_t k = flip ? k2 : k1;
+        uint32_t first = flip ? y : x, second = flip ? x : y;  // node = (1 - c) first + c second
+        float c = code[k];
+        if (c > 0.5f) std::swap(first, second), c = 1.0f - c;  // stored with w <= 1/2 (exact in fp32)
+        uint32_t cbits;
+        std::memcpy(&cbits, &c, 4);
+        const Key key{first, second, cbits};
+        auto it = made.find(key);
+        if (it != made.end()) {
+            rep[n] = it->second;
+            continue;
+        }
+        const uint32_t id = uint32_t(d.a.size());
+        made.emplace(key, id);
+        rep[n] = id;
+        int e = 0;
+        const float fr = std::frexp(c, &e);  // c = fr 2^e, fr in [1/2, 1)
+        uint64_t num = uint64_t(std::ldexp(double(fr), 24)), den = uint64_t(1) << (24 - e);
+        while (num % 2 == 0 && den > 1) num /= 2, den /= 2;
+        d.a.push_back(first), d.b.push_back(second), d.wn.push_back(num), d.wd.push_back(den);
+        d.mix.push_back(d.mix[first] + d.mix[second]);
+        d.alpha.push_back(c), d.sigma.push_back(sig[k]);
     }
-
-    // ---- renumber by (rank, creation order); sources keep 0 .. S-1. Nodes whose
-    // predecessors are both sources (rank 1) are then one contiguous ID range.
-    std::vector<uint32_t> cnt(depth + 2, 0);
-    for (uint32_t n = g->nseg; n < N; ++n) cnt[rank[n]]++;
-    g->rank_ptr.assign(depth + 2, 0);
-    g->rank_ptr[0] = 0;
-    g->rank_ptr[1] = g->nseg;
-    for (uint32_t r = 1; r <= depth; ++r) g->rank_ptr[r + 1] = g->rank_ptr[r] + cnt[r];
-    std::vector<uint32_t> pos(g->rank_ptr.begin(), g->rank_ptr.end());
-    std::vector<uint32_t> perm(N);
-    for (uint32_t n = 0; n < g->nseg; ++n) perm[n] = n;
-    for (uint32_t n = g->nseg; n < N; ++n) perm[n] = pos[rank[n]]++;
-
-    g->n_nodes = N;
-    g->depth = depth;
-    g->max_mixture = maxmix;
-    g->child_a.assign(N, 0);
-    g->child_b.assign(N, 0);
-    g->alpha.assign(N, 0.f);
-    g->wnum.assign(N, 0);
-    g->wden.assign(N, 1);
-    g->rank.assign(N, 0);
-    g->step.assign(N, 0);
-    for (uint32_t n = 0; n < N; ++n) {
-        const uint32_t p = perm[n];
-        g->child_a[p] = perm[store.a_[n]];
-        g->child_b[p] = perm[store.b_[n]];
-        g->wnum[p] = store.wn_[n];
-        g->wden[p] = store.wd_[n];
-        g->alpha[p] = n < g->nseg ? 0.f : float(double(store.wn_[n]) / double(store.wd_[n]));
-        g->rank[p] = rank[n];
-        g->step[p] = step[n];
-    }
-    // ---- execution order of the step schedule: sources, then step 1, 2, ...
-    std::vector<uint32_t> scnt(depth + 2, 0);
-    for (uint32_t n = g->nseg; n < N; ++n) scnt[g->step[n]]++;
-    g->step_ptr.assign(depth + 2, 0);
-    g->step_ptr[1] = g->nseg;
-    for (uint32_t s = 1; s <= depth; ++s) g->step_ptr[s + 1] = g->step_ptr[s] + scnt[s];
-    std::vector<uint32_t> spos(g->step_ptr.begin(), g->step_ptr.end());
-    g->sched.assign(N, 0);
-    for (uint32_t n = 0; n < g->nseg; ++n) g->sched[n] = n;
-    for (uint32_t n = g->nseg; n < N; ++n) g->sched[spos[g->step[n]]++] = n;
-    const uint64_t total = g->maps.size();
-    uint32_t *mp = g->maps.data();
-    const uint64_t first_internal = g->lev_off[1];
-    parallel_chunks(total - first_internal, nt, [&](uint64_t b, uint64_t e, unsigned) {
-        for (uint64_t i = b; i < e; ++i) mp[first_internal + i] = perm[mp[first_internal + i]];
+    dst->dims[0] = src.dims[0], dst->dims[1] = src.dims[1], dst->dims[2] = src.dims[2];
+    dst->nseg = S;
+    dst->n_levels = src.n_levels;
+    dst->lev_dims = src.lev_dims;
+    dst->lev_off = src.lev_off;
+    dst->seg_ids = src.seg_ids;
+    dst->maps = src.maps;
+    const unsigned nt = resolve_threads(threads);
+    uint32_t *mp = dst->maps.data();
+    const uint64_t first_internal = dst->lev_off[1];
+    parallel_chunks(dst->maps.size() - first_internal, nt, [&](uint64_t b, uint64_t e, unsigned) {
+        for (uint64_t i = b; i < e; ++i) mp[first_internal + i] = rep[mp[first_internal + i]];
     });
+    // the schedule of the source graph: deferred if its steps differ from its ranks
+    const bool defer = src.step != src.rank;
+    if (int rc = finalize_dag(d, defer, 0, nt, dst, err)) return rc;
+    dst->quant_bits = bits;
+    dst->codebook = std::move(code);
+    dst->code_sigma = std::move(sig);
     return MG_OK;
 }
 
@@ -666,6 +815,12 @@ int build_lut(Graph *g, uint32_t threads, std::string *err)
     std::vector<uint64_t> ptr(uint64_t(N) + 1, 0);
     std::vector<uint32_t> seg(S);
     std::vector<double> val(S, 1.0);
+    // propagated uncertainty of each entry (Sec. "Error Propagation", Eq. (error)):
+    // with quantized weights, component i of node (1 - w) a + w b has
+    // dmu_i = mu_i sqrt((da_i / a_i)^2 + (db_i / b_i)^2 + 2 (dw / w)^2), sources are
+    // certain, and a term whose component is absent from a child counts zero
+    const bool with_err = !g->node_sigma.empty();
+    std::vector<double> unc(with_err ? S : 0, 0.0);
     for (uint32_t s = 0; s < S; ++s) {
         ptr[s] = s;
         seg[s] = s;
@@ -698,6 +853,7 @@ int build_lut(Graph *g, uint32_t threads, std::string *err)
         }
         seg.resize(ptr[hi]);
         val.resize(ptr[hi]);
+        if (with_err) unc.resize(ptr[hi]);
         parallel_chunks(hi - lo, nt, [&](uint64_t b, uint64_t e, unsigned) {
             for (uint64_t i = b; i < e; ++i) {
                 const uint32_t n = lo + uint32_t(i);
@@ -705,21 +861,27 @@ int build_lut(Graph *g, uint32_t threads, std::string *err)
                 const double wa = double(g->wden[n] - g->wnum[n]) / double(g->wden[n]);
                 uint64_t pa = ptr[g->child_a[n]], ea = ptr[g->child_a[n] + 1];
                 uint64_t pb = ptr[g->child_b[n]], eb = ptr[g->child_b[n] + 1];
+                const double rw = with_err ? double(g->node_sigma[n]) / wb : 0.0;  // dw / w
                 uint64_t k = ptr[n];
                 while (pa < ea || pb < eb) {
+                    double ra = 0.0, rb = 0.0;  // relative uncertainties of the children's components
                     if (pb == eb || (pa < ea && seg[pa] < seg[pb])) {
                         seg[k] = seg[pa];
                         val[k] = wa * val[pa];
+                        if (with_err) ra = unc[pa] / val[pa];
                         ++pa;
                     } else if (pa == ea || seg[pb] < seg[pa]) {
                         seg[k] = seg[pb];
                         val[k] = wb * val[pb];
+                        if (with_err) rb = unc[pb] / val[pb];
                         ++pb;
                     } else {
                         seg[k] = seg[pa];
                         val[k] = wa * val[pa] + wb * val[pb];
+                        if (with_err) ra = unc[pa] / val[pa], rb = unc[pb] / val[pb];
                         ++pa, ++pb;
                     }
+                    if (with_err) unc[k] = val[k] * std::sqrt(ra * ra + rb * rb + 2.0 * rw * rw);
                     ++k;
                 }
             }
@@ -727,6 +889,8 @@ int build_lut(Graph *g, uint32_t threads, std::string *err)
     }
     g->lut_val.resize(val.size());
     for (size_t i = 0; i < val.size(); ++i) g->lut_val[i] = float(val[i]);
+    g->lut_err.assign(unc.size(), 0.f);
+    for (size_t i = 0; i < unc.size(); ++i) g->lut_err[i] = float(unc[i]);
     g->lut_seg = std::move(seg);
     g->lut_ptr = std::move(ptr);
     return MG_OK;

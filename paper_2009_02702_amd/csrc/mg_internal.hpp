@@ -76,6 +76,11 @@ struct Graph {
     std::vector<uint64_t> lut_ptr;                       // [n_nodes + 1], empty if not built
     std::vector<uint32_t> lut_seg;
     std::vector<float> lut_val;
+    std::vector<float> lut_err;                          // propagated uncertainty (quantized graphs)
+    // scalar-quantized weights (quantize_graph); quant_bits == 0: exact weights
+    uint32_t quant_bits = 0;
+    std::vector<float> codebook, code_sigma;             // [2^bits] codeword and sigma of each bin
+    std::vector<float> node_sigma;                       // [n_nodes] sigma of each node's weight
     DeviceState dev;
 };
 
@@ -83,6 +88,8 @@ struct Graph {
 int build_graph(const uint32_t *ids, const mg_build_opts *opts, Graph *g, std::string *err);
 // Mixture lookup table of every node, in fp64 through the DAG, stored fp32.
 int build_lut(Graph *g, uint32_t threads, std::string *err);
+// A copy of `src` with weights scalar-quantized to 2^bits bins and nodes merged.
+int quantize_graph(const Graph &src, uint32_t bits, uint32_t threads, Graph *dst, std::string *err);
 // Structural validation of a graph's host arrays (used by mg_load).
 int validate_graph(const Graph &g, std::string *err);
 // Level dimensions: halve with rounding up until 1^3.

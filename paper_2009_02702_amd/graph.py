@@ -92,6 +92,7 @@ class Graph:
             "nseg": i.nseg, "n_nodes": i.n_nodes, "depth": i.depth, "n_levels": i.n_levels,
             "dims": [tuple(i.dims[l]) for l in range(i.n_levels)], "map_voxels": i.map_voxels,
             "device_bytes": i.device_bytes, "device": i.device, "max_mixture": i.max_mixture,
+            "quant_bits": i.quant_bits,
         }
 
     def export_dag(self) -> dict:
@@ -240,16 +241,35 @@ class Graph:
         check(self._lib.mg_lut_build(self._h, threads, ctypes.byref(nnz)))
         return int(nnz.value)
 
-    def export_lut(self):
-        """(ptr uint64 [n_nodes + 1], seg uint32 [nnz], val float32 [nnz]) of the mixture lookup table."""
+    def export_lut(self, with_err: bool = False):
+        """(ptr uint64 [n_nodes + 1], seg uint32 [nnz], val float32 [nnz][, err float32 [nnz]]) of the
+        mixture lookup table; err is the propagated uncertainty of each fraction."""
         N = self.info()["n_nodes"]
         ptr = np.zeros(N + 1, dtype=np.uint64)
-        check(self._lib.mg_export_lut(self._h, ptr.ctypes.data, None, None))
+        check(self._lib.mg_export_lut(self._h, ptr.ctypes.data, None, None, None))
         nnz = int(ptr[-1])
         seg = np.zeros(nnz, dtype=np.uint32)
         val = np.zeros(nnz, dtype=np.float32)
-        check(self._lib.mg_export_lut(self._h, ptr.ctypes.data, seg.ctypes.data, val.ctypes.data))
-        return ptr, seg, val
+        err = np.zeros(nnz, dtype=np.float32)
+        check(self._lib.mg_export_lut(self._h, ptr.ctypes.data, seg.ctypes.data, val.ctypes.data,
+                                      err.ctypes.data if with_err else None))
+        return (ptr, seg, val, err) if with_err else (ptr, seg, val)
+
+    def quantize(self, bits: int, threads: int = 0) -> "Graph":
+        """Lossy copy with scalar-quantized weights (2^bits bins) and merged nodes."""
+        h = ctypes.c_void_p()
+        check(self._lib.mg_quantize(self._h, bits, threads, ctypes.byref(h)))
+        return Graph(h)
+
+    def export_codebook(self):
+        """(codeword fp32 [2^bits], sigma fp32 [2^bits], node_sigma fp32 [n_nodes]) of a quantized graph."""
+        inf = self.info()
+        B = 1 << inf["quant_bits"] if inf["quant_bits"] else 0
+        cw = np.zeros(max(B, 1), dtype=np.float32)
+        sg = np.zeros(max(B, 1), dtype=np.float32)
+        ns = np.zeros(inf["n_nodes"], dtype=np.float32)
+        check(self._lib.mg_export_codebook(self._h, cw.ctypes.data, sg.ctypes.data, ns.ctypes.data))
+        return cw, sg, ns
 
     def launch_config(self) -> dict:
         c = LaunchCfg()
