@@ -236,6 +236,18 @@ int mg_export_lut(const mg_graph *g, uint64_t *ptr, uint32_t *seg, float *val, f
 int mg_query_boxes_lut(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *d_out,
                        void *d_work, uint64_t work_bytes, void *stream);
 
+/* Box histograms with uncertainties, for graphs with quantized weights (Sec.
+ * "Error Propagation": the uncertainty of range queries; Sec. "Range
+ * queries"): the lookup-table query, with every scattered graph node's count
+ * c_n applied to its row once, and per segment d_err = sqrt(sum_n (c_n
+ * dmu_n)^2) / |box| (the sum rule of error propagation over the nodes' terms).
+ *   d_out  device fp32 [n][S] fractions (as mg_query_boxes_lut)
+ *   d_err  device fp32 [n][S] their uncertainties
+ * Needs mg_quantize'd graph and mg_lut_build (else MG_ESTATE) and S <= 2048
+ * (MG_ELIMIT). */
+int mg_query_boxes_err(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *d_out, float *d_err,
+                       void *d_work, uint64_t work_bytes, void *stream);
+
 /* Launch configuration of the GPU kernels (per graph, after mg_upload).
  * Defaults: 16, 8, 16, 256, then zeros (sizes chosen per mode). */
 typedef struct {

@@ -53,7 +53,7 @@ SYMBOLS = [
     "mg_workspace_bytes", "mg_workspace_init", "mg_query_boxes", "mg_query_boxes_plain", "mg_query_boxes_stats",
     "mg_query_boxes_sparse",
     "mg_naive_boxes",
-    "mg_footprint", "mg_propagate_tf", "mg_palette_fetch", "mg_lut_build", "mg_export_lut", "mg_query_boxes_lut",
+    "mg_footprint", "mg_propagate_tf", "mg_palette_fetch", "mg_lut_build", "mg_export_lut", "mg_query_boxes_lut", "mg_query_boxes_err",
     "mg_get_launch", "mg_set_launch", "mg_autotune",
     "mg_save", "mg_load", "mg_timing_enable", "mg_timing_read",
     "mg_last_error", "mg_free",
@@ -98,6 +98,7 @@ def load() -> ctypes.CDLL:
         "mg_lut_build": ([G, u32, ctypes.POINTER(u64)], i32),
         "mg_export_lut": ([G, vp, vp, vp, vp], i32),
         "mg_query_boxes_lut": ([G, vp, u32, vp, vp, u64, vp], i32),
+        "mg_query_boxes_err": ([G, vp, u32, vp, vp, vp, u64, vp], i32),
         "mg_get_launch": ([G, ctypes.POINTER(LaunchCfg)], i32),
         "mg_set_launch": ([G, ctypes.POINTER(LaunchCfg)], i32),
         "mg_autotune": ([G, vp, u32, vp, vp, u64, u32, vp, ctypes.POINTER(LaunchCfg)], i32),

@@ -335,6 +335,18 @@ int mg_query_boxes_lut(mg_graph *h, const uint32_t *d_boxes, uint32_t n, float *
     return query_common(h, d_boxes, n, d_out, d_work, work_bytes, stream, mg::kQueryLut, "mg_query_boxes_lut");
 }
 
+int mg_query_boxes_err(mg_graph *h, const uint32_t *d_boxes, uint32_t n, float *d_out, float *d_err, void *d_work,
+                       uint64_t work_bytes, void *stream)
+{
+    if (!h) return fail(MG_EINVAL, "mg_query_boxes_err: null graph");
+    if (n == 0) return MG_OK;
+    if (!d_boxes || !d_out || !d_err || !d_work) return fail(MG_EINVAL, "mg_query_boxes_err: null buffer");
+    std::string err;
+    return done(mg::dev_query(&h->g, d_boxes, n, d_out, nullptr, d_work, work_bytes, stream, mg::kQueryLutErr,
+                              nullptr, &err, d_err),
+                err);
+}
+
 int mg_get_launch(const mg_graph *h, mg_launch_cfg *out)
 {
     if (!h || !out) return fail(MG_EINVAL, "mg_get_launch: null argument");

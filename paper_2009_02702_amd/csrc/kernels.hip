@@ -236,6 +236,7 @@ struct QueryState {
     uint32_t *seg_cnt;  // [S] exact integer counts (dense mode)
     float *seg_hi, *seg_lo;  // [S] pushed mass and its compensation (dense mode)
     Slab *slabs;        // [6 * levels] the box's slabs (LDS)
+    float *seg_var;     // [S] accumulated variance per source (uncertainty queries), or null
 };
 
 struct GraphView {
@@ -743,11 +744,13 @@ struct QueryArgs {
     const uint64_t *lut_ptr;      // mixture lookup table rows: expand instead of push (nullptr: push)
     const uint32_t *lut_seg;
     const float *lut_val;
+    const float *lut_err;         // propagated uncertainty of each row entry (uncertainty queries)
+    float *out_err;               // [n][S] uncertainty of each fraction, or null (dense output only)
     // fallback global regions (per worker)
     uint32_t *g_keys, *g_cnt, *g_used;
     float *g_hi, *g_lo;
     uint32_t *g_seg_cnt;
-    float *g_seg_hi, *g_seg_lo;
+    float *g_seg_hi, *g_seg_lo, *g_seg_var;
 };
 
 // Mixture lookup expansion (the paper's query through per-node mixtures):
@@ -771,6 +774,10 @@ __device__ inline void expand_lut(const QueryArgs &A, const QueryState &st)
             float ph, pl;
             scale_pair(A.lut_val[j], mh, ml, &ph, &pl);
             add_source_mass<SPARSE>(st, A.lut_seg[j], ph, pl);
+            if (st.seg_var) {  // uncertainty: the node's count times its row's, added in quadrature
+                const float d = (mh + ml) * A.lut_err[j];
+                atomicAdd(&st.seg_var[A.lut_seg[j]], d * d);
+            }
         }
     }
 }
@@ -782,9 +789,10 @@ __host__ __device__ inline uint32_t lds_state_bytes(uint32_t nseg, uint32_t cap,
 {
     return ((sparse ? cap * 20u : nseg * 12u + cap * 16u) + 15u) & ~15u;
 }
-__host__ __device__ inline uint32_t lds_bytes(uint32_t nseg, uint32_t cap, bool sparse, uint32_t n_levels)
+__host__ __device__ inline uint32_t lds_bytes(uint32_t nseg, uint32_t cap, bool sparse, uint32_t n_levels,
+                                              bool err = false)
 {
-    return lds_state_bytes(nseg, cap, sparse) + 6u * n_levels * uint32_t(sizeof(Slab));
+    return lds_state_bytes(nseg, cap, sparse) + 6u * n_levels * uint32_t(sizeof(Slab)) + (err ? 4u * nseg : 0u);
 }
 
 struct QueryShared {
@@ -810,6 +818,11 @@ __device__ inline void write_result(const QueryArgs &A, QueryShared &sh, const Q
         for (uint32_t s = threadIdx.x; s < nseg; s += BLOCK) {
             const double c = double(ld(&st.seg_cnt[s])) + double(ld(&st.seg_hi[s])) + double(ld(&st.seg_lo[s]));
             o[s] = nonempty ? float(c / vol) : 0.0f;
+        }
+        if (A.out_err) {
+            float *e = A.out_err + uint64_t(q) * nseg;
+            for (uint32_t s = threadIdx.x; s < nseg; s += BLOCK)
+                e[s] = nonempty ? float(sqrt(double(ld(&st.seg_var[s]))) / vol) : 0.0f;
         }
         return;
     }
@@ -924,6 +937,7 @@ __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const Quer
             st.seg_cnt[s] = 0;
             st.seg_hi[s] = 0.f;
             st.seg_lo[s] = 0.f;
+            if (st.seg_var) st.seg_var[s] = 0.f;
         }
     __syncthreads();
 }
@@ -935,10 +949,14 @@ __device__ inline void load_rank_ptr(const QueryArgs &A, QueryShared &sh)
 }
 
 template <bool SPARSE>
-__device__ inline QueryState lds_state(char *dyn, QueryShared &sh, uint32_t nseg, uint32_t cap)
+__device__ inline QueryState lds_state(char *dyn, QueryShared &sh, uint32_t nseg, uint32_t cap, uint32_t n_levels,
+                                      bool err)
 {
     QueryState st;
     st.slabs = reinterpret_cast<Slab *>(dyn + lds_state_bytes(nseg, cap, SPARSE));
+    st.seg_var = err ? reinterpret_cast<float *>(dyn + lds_state_bytes(nseg, cap, SPARSE) +
+                                                 6u * n_levels * uint32_t(sizeof(Slab)))
+                     : nullptr;
     uint32_t *t = reinterpret_cast<uint32_t *>(dyn);
     if (SPARSE) {
         st.seg_cnt = nullptr;
@@ -977,6 +995,7 @@ __device__ inline void clear_lds_state(const QueryState &st, uint32_t nseg)
             st.seg_cnt[s] = 0;
             st.seg_hi[s] = 0.f;
             st.seg_lo[s] = 0.f;
+            if (st.seg_var) st.seg_var[s] = 0.f;
         }
 }
 
@@ -986,7 +1005,7 @@ __global__ __launch_bounds__(kBlock) void query_plain_kernel(QueryArgs A)
 {
     extern __shared__ __align__(16) char dyn[];
     __shared__ QueryShared sh;
-    const QueryState st = lds_state<SPARSE>(dyn, sh, A.gv.nseg, A.table_cap);
+    const QueryState st = lds_state<SPARSE>(dyn, sh, A.gv.nseg, A.table_cap, A.lt.n_levels, A.out_err != nullptr);
     load_rank_ptr<kBlock>(A, sh);
     clear_lds_state<kBlock, SPARSE>(st, A.gv.nseg);
     __syncthreads();
@@ -1000,7 +1019,7 @@ __global__ __launch_bounds__(BLOCK) void query_tier_kernel(QueryArgs A)
 {
     extern __shared__ __align__(16) char dyn[];
     __shared__ QueryShared sh;
-    const QueryState st = lds_state<SPARSE>(dyn, sh, A.gv.nseg, A.table_cap);
+    const QueryState st = lds_state<SPARSE>(dyn, sh, A.gv.nseg, A.table_cap, A.lt.n_levels, A.out_err != nullptr);
     load_rank_ptr<BLOCK>(A, sh);
     clear_lds_state<BLOCK, SPARSE>(st, A.gv.nseg);
     const uint32_t split = ld(&A.counters[8]);
@@ -1021,7 +1040,7 @@ __global__ __launch_bounds__(BLOCK) void query_retry_kernel(QueryArgs A)
 {
     extern __shared__ __align__(16) char dyn[];
     __shared__ QueryShared sh;
-    const QueryState st = lds_state<SPARSE>(dyn, sh, A.gv.nseg, A.table_cap);
+    const QueryState st = lds_state<SPARSE>(dyn, sh, A.gv.nseg, A.table_cap, A.lt.n_levels, A.out_err != nullptr);
     load_rank_ptr<BLOCK>(A, sh);
     clear_lds_state<BLOCK, SPARSE>(st, A.gv.nseg);
     const uint32_t n_list = ld(&A.counters[1]);
@@ -1057,6 +1076,7 @@ __global__ __launch_bounds__(kBlock) void query_fallback_kernel(QueryArgs A)
     st.seg_hi = SPARSE ? nullptr : A.g_seg_hi + w * A.gv.nseg;
     st.seg_lo = SPARSE ? nullptr : A.g_seg_lo + w * A.gv.nseg;
     st.slabs = reinterpret_cast<Slab *>(dyn);  // the only dynamic LDS of this kernel
+    st.seg_var = (!SPARSE && A.out_err) ? A.g_seg_var + w * A.gv.nseg : nullptr;
     load_rank_ptr<kBlock>(A, sh);
     __syncthreads();
     const uint32_t n_over = ld(&A.counters[5]);
@@ -1350,7 +1370,7 @@ struct Workspace {
     uint32_t *g_keys, *g_cnt, *g_used;
     float *g_hi, *g_lo;
     uint32_t *g_seg_cnt;
-    float *g_seg_hi, *g_seg_lo;
+    float *g_seg_hi, *g_seg_lo, *g_seg_var;
     uint64_t bytes;
     uint32_t max_boxes;
 };
@@ -1380,6 +1400,7 @@ Workspace carve(const Graph &g, char *base, uint32_t max_boxes)
     w.g_seg_cnt = reinterpret_cast<uint32_t *>(take(ss * 4));
     w.g_seg_hi = reinterpret_cast<float *>(take(ss * 4));
     w.g_seg_lo = reinterpret_cast<float *>(take(ss * 4));
+    w.g_seg_var = reinterpret_cast<float *>(take(ss * 4));
     w.bucket_of = reinterpret_cast<uint32_t *>(take(uint64_t(max_boxes) * 4));
     w.order = reinterpret_cast<uint32_t *>(take(uint64_t(max_boxes) * 4));
     w.overflow = reinterpret_cast<uint32_t *>(take(uint64_t(max_boxes) * 4));
@@ -1568,7 +1589,8 @@ int dev_upload_lut(Graph *g, std::string *err)
     if (d.lut_ptr) (void)hipFree(d.lut_ptr);
     if (d.lut_seg) (void)hipFree(d.lut_seg);
     if (d.lut_val) (void)hipFree(d.lut_val);
-    d.lut_ptr = nullptr, d.lut_seg = nullptr, d.lut_val = nullptr;
+    if (d.lut_err) (void)hipFree(d.lut_err);
+    d.lut_ptr = nullptr, d.lut_seg = nullptr, d.lut_val = nullptr, d.lut_err = nullptr;
     const uint64_t bp = g->lut_ptr.size() * sizeof(uint64_t), nnz = g->lut_seg.size();
     if (hipMalloc(&d.lut_ptr, bp) != hipSuccess || hipMalloc(&d.lut_seg, nnz * 4) != hipSuccess ||
         hipMalloc(&d.lut_val, nnz * 4) != hipSuccess) {
@@ -1583,6 +1605,16 @@ int dev_upload_lut(Graph *g, std::string *err)
     HIP_TRY(hipMemcpy(d.lut_seg, g->lut_seg.data(), nnz * 4, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(d.lut_val, g->lut_val.data(), nnz * 4, hipMemcpyHostToDevice));
     d.bytes += bp + 8 * nnz;
+    if (g->lut_err.size() == nnz && nnz) {
+        if (hipMalloc(&d.lut_err, nnz * 4) != hipSuccess) {
+            (void)hipGetLastError();
+            d.lut_err = nullptr;
+            *err = "mixture lookup table: device allocation failed (uncertainties)";
+            return MG_ENOMEM;
+        }
+        HIP_TRY(hipMemcpy(d.lut_err, g->lut_err.data(), nnz * 4, hipMemcpyHostToDevice));
+        d.bytes += 4 * nnz;
+    }
     return MG_OK;
 }
 
@@ -1614,6 +1646,7 @@ void dev_free(Graph *g)
     if (d.lut_ptr) (void)hipFree(d.lut_ptr);
     if (d.lut_seg) (void)hipFree(d.lut_seg);
     if (d.lut_val) (void)hipFree(d.lut_val);
+    if (d.lut_err) (void)hipFree(d.lut_err);
     for (void *e : d.ev_start) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
     for (void *e : d.ev_stop) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
     d = DeviceState();
@@ -1644,6 +1677,7 @@ int dev_workspace_init(Graph *g, void *work, uint64_t bytes, void *stream, std::
     hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, w.g_seg_cnt, ss, 0u);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_seg_hi), ss, 0u);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_seg_lo), ss, 0u);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_seg_var), ss, 0u);
     HIP_TRY(hipGetLastError());
     return MG_OK;
 }
@@ -1664,9 +1698,10 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
     const uint32_t cap_big = d.cfg.table_big ? d.cfg.table_big : (SPARSE ? kHashBigSparse : kHashBig);
     const uint32_t cap_small = d.cfg.table_small ? d.cfg.table_small : (SPARSE ? kHashSmallSparse : kHashSmall);
     const uint32_t L = g->n_levels;
-    const uint32_t dyn_big = lds_bytes(g->nseg, cap_big, SPARSE, L),
-                   dyn_small = lds_bytes(g->nseg, cap_small, SPARSE, L),
-                   dyn_plain = lds_bytes(g->nseg, kHashPlain, SPARSE, L);
+    const bool E = A.out_err != nullptr;
+    const uint32_t dyn_big = lds_bytes(g->nseg, cap_big, SPARSE, L, E),
+                   dyn_small = lds_bytes(g->nseg, cap_small, SPARSE, L, E),
+                   dyn_plain = lds_bytes(g->nseg, kHashPlain, SPARSE, L, E);
     int occ_big = 1, occ_small = 1, occ_plain = 1;
     if ((rc = occupancy(d, reinterpret_cast<const void *>(kbig), bbig, dyn_big, &occ_big, err)) ||
         (rc = occupancy(d, reinterpret_cast<const void *>(ksmall), bsmall, dyn_small, &occ_small, err)) ||
@@ -1704,10 +1739,10 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
     if (!cap_retry) {  // the largest table up to kHashRetry that fits the LDS of a workgroup
         cap_retry = kHashRetry;
         while (cap_retry > kHashBigSparse &&
-               lds_bytes(g->nseg, cap_retry, SPARSE, L) + sizeof(QueryShared) > uint64_t(d.lds_max))
+               lds_bytes(g->nseg, cap_retry, SPARSE, L, E) + sizeof(QueryShared) > uint64_t(d.lds_max))
             cap_retry /= 2;
     }
-    const uint32_t dyn_retry = lds_bytes(g->nseg, cap_retry, SPARSE, L);
+    const uint32_t dyn_retry = lds_bytes(g->nseg, cap_retry, SPARSE, L, E);
     int occ_retry = 1;
     if ((rc = occupancy(d, reinterpret_cast<const void *>(kretry), kBlockBig, dyn_retry, &occ_retry, err)))
         return rc;
@@ -1727,7 +1762,7 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
 }
 
 int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const SparseOut *sp, void *work,
-              uint64_t bytes, void *stream, int variant, uint32_t *stats, std::string *err)
+              uint64_t bytes, void *stream, int variant, uint32_t *stats, std::string *err, float *out_err)
 {
     DeviceGuard guard;
     int rc = check_device(g, err);
@@ -1809,8 +1844,8 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const Spa
     A.ovf_out_idx = 1;
     A.stats = stats;
     A.g_keys = w.g_keys, A.g_cnt = w.g_cnt, A.g_used = w.g_used, A.g_hi = w.g_hi, A.g_lo = w.g_lo;
-    A.g_seg_cnt = w.g_seg_cnt, A.g_seg_hi = w.g_seg_hi, A.g_seg_lo = w.g_seg_lo;
-    if (variant == kQueryLut) {
+    A.g_seg_cnt = w.g_seg_cnt, A.g_seg_hi = w.g_seg_hi, A.g_seg_lo = w.g_seg_lo, A.g_seg_var = w.g_seg_var;
+    if (variant == kQueryLut || variant == kQueryLutErr) {
         if (!g->dev.lut_ptr) {
             *err = "the mixture lookup table is not on the device (mg_lut_build)";
             return MG_ESTATE;
@@ -1818,6 +1853,22 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const Spa
         A.lut_ptr = g->dev.lut_ptr;
         A.lut_seg = g->dev.lut_seg;
         A.lut_val = g->dev.lut_val;
+    }
+    if (variant == kQueryLutErr) {
+        if (!g->dev.lut_err) {
+            *err = "uncertainties need a graph with quantized weights (mg_quantize) and its lookup table";
+            return MG_ESTATE;
+        }
+        if (sp || g->nseg > kSegLdsMax) {
+            *err = "uncertainty queries keep per-source arrays in LDS: at most " + std::to_string(kSegLdsMax) +
+                   " sources, dense output";
+            return MG_ELIMIT;
+        }
+        A.lut_err = g->dev.lut_err;
+        A.out_err = out_err;
+        // every internal node is a table entry, so each node's count meets its row's uncertainty once
+        A.gv.r1_end = A.gv.r2_end = g->nseg;
+        variant = kQueryLut;
     }
     // sources in LDS arrays while they fit, else as table entries (sparse mode)
     const bool sparse = sp != nullptr || g->nseg > kSegLdsMax;

@@ -38,6 +38,7 @@ struct DeviceState {
     uint64_t *lut_ptr = nullptr;   // [n_nodes + 1] mixture lookup table rows (optional)
     uint32_t *lut_seg = nullptr;   // [lut nnz]
     float *lut_val = nullptr;      // [lut nnz]
+    float *lut_err = nullptr;      // [lut nnz] propagated uncertainty (quantized graphs)
     uint64_t bytes = 0;
     // launch parameters, queried once per device and graph
     bool launch_ready = false;
@@ -109,7 +110,8 @@ struct SparseOut {
     uint32_t *total;   // device counter
 };
 int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const SparseOut *sp, void *work,
-              uint64_t bytes, void *stream, int variant, uint32_t *stats, std::string *err);
+              uint64_t bytes, void *stream, int variant, uint32_t *stats, std::string *err,
+              float *out_err = nullptr);
 int dev_footprint(Graph *g, const uint32_t *boxes, uint32_t n, uint32_t *level_counts, uint32_t *cubes,
                   uint32_t cap, uint32_t *count, void *stream, std::string *err);
 int dev_propagate_tf(Graph *g, const uint8_t *tf, uint32_t T, float *out, void *stream, std::string *err);
@@ -121,6 +123,6 @@ int dev_autotune(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *
                  void *stream, mg_launch_cfg *chosen, std::string *err);
 int dev_timing_read(Graph *g, double *ms, uint32_t *launches, std::string *err);
 
-enum QueryVariant { kQueryBatched = 0, kQueryPlain = 1, kQueryNaive = 2, kQueryLut = 3 };
+enum QueryVariant { kQueryBatched = 0, kQueryPlain = 1, kQueryNaive = 2, kQueryLut = 3, kQueryLutErr = 4 };
 
 }  // namespace mg

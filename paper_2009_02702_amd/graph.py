@@ -155,6 +155,20 @@ class Graph:
         check(fn(self._h, _dptr(boxes), n, _dptr(out), _dptr(ws), ws.numel(), _stream_ptr(stream)))
         return out
 
+    def query_err(self, boxes, out=None, err=None, workspace=None, stream=None):
+        """Quantized graphs: (fractions fp32 [n, S], uncertainties fp32 [n, S]) from the lookup table."""
+        torch = _torch()
+        n = boxes.shape[0]
+        S = self.info()["nseg"]
+        if out is None:
+            out = torch.empty((n, S), dtype=torch.float32, device=boxes.device)
+        if err is None:
+            err = torch.empty((n, S), dtype=torch.float32, device=boxes.device)
+        ws = workspace if workspace is not None else self.workspace(n, stream)
+        check(self._lib.mg_query_boxes_err(self._h, _dptr(boxes), n, _dptr(out), _dptr(err), _dptr(ws), ws.numel(),
+                                           _stream_ptr(stream)))
+        return out, err
+
     def query_stats(self, boxes, out=None, workspace=None, stream=None):
         """Batched query that also returns int32 [n, 2] (cubes, graph nodes touched) per box."""
         torch = _torch()
