@@ -757,7 +757,7 @@ struct QueryArgs {
 // every graph node in the table adds its mass times its mixture row to the
 // sources. Groups of 8 lanes take one node each, lanes over the row's entries.
 // Replaces the rank-by-rank push; all threads of the block must call.
-template <int BLOCK, bool SPARSE>
+template <int BLOCK, bool SPARSE, bool ERR>
 __device__ inline void expand_lut(const QueryArgs &A, const QueryState &st)
 {
     constexpr uint32_t kGroup = 8;
@@ -774,7 +774,7 @@ __device__ inline void expand_lut(const QueryArgs &A, const QueryState &st)
             float ph, pl;
             scale_pair(A.lut_val[j], mh, ml, &ph, &pl);
             add_source_mass<SPARSE>(st, A.lut_seg[j], ph, pl);
-            if (st.seg_var) {  // uncertainty: the node's count times its row's, added in quadrature
+            if (ERR) {  // uncertainty: the node's count times its row's, added in quadrature
                 const float d = (mh + ml) * A.lut_err[j];
                 atomicAdd(&st.seg_var[A.lut_seg[j]], d * d);
             }
@@ -808,7 +808,7 @@ struct QueryShared {
 
 // Fraction of voxels of each source of one box, written to the dense row or
 // appended to the sparse output. All threads of the block must call.
-template <int BLOCK, bool SPARSE>
+template <int BLOCK, bool SPARSE, bool ERR>
 __device__ inline void write_result(const QueryArgs &A, QueryShared &sh, const QueryState &st, uint32_t q,
                                     bool nonempty, double vol)
 {
@@ -819,7 +819,7 @@ __device__ inline void write_result(const QueryArgs &A, QueryShared &sh, const Q
             const double c = double(ld(&st.seg_cnt[s])) + double(ld(&st.seg_hi[s])) + double(ld(&st.seg_lo[s]));
             o[s] = nonempty ? float(c / vol) : 0.0f;
         }
-        if (A.out_err) {
+        if (ERR) {
             float *e = A.out_err + uint64_t(q) * nseg;
             for (uint32_t s = threadIdx.x; s < nseg; s += BLOCK)
                 e[s] = nonempty ? float(sqrt(double(ld(&st.seg_var[s]))) / vol) : 0.0f;
@@ -880,7 +880,8 @@ __device__ inline void write_failure(const QueryArgs &A, uint32_t q)
 }
 
 // One query, by the whole block. `st` must be clean (keys empty, values 0).
-template <int BLOCK, int UNROLL, bool SPARSE>
+// ERR: lookup-table expansion that also accumulates uncertainties (dense output).
+template <int BLOCK, int UNROLL, bool SPARSE, bool ERR>
 __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const QueryState &st, uint32_t q,
                                  bool report_overflow)
 {
@@ -897,8 +898,8 @@ __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const Quer
     __syncthreads();
     scatter_slabs<BLOCK, UNROLL, SPARSE>(st.slabs, sh.n_slabs, A.maps, A.maps16, A.lt, st, A.gv, &sh.flags);
     __syncthreads();
-    if (A.lut_ptr)
-        expand_lut<BLOCK, SPARSE>(A, st);
+    if (ERR || A.lut_ptr)
+        expand_lut<BLOCK, SPARSE, ERR>(A, st);
     else
         push_mass<BLOCK, SPARSE>(st, A.gv, sh.rank_ptr, A.depth);
     __syncthreads();
@@ -913,7 +914,7 @@ __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const Quer
     const uint32_t nseg = A.gv.nseg;
     if (!overflow) {
         const double vol = nonempty ? double(hi[0] - lo[0]) * double(hi[1] - lo[1]) * double(hi[2] - lo[2]) : 0.0;
-        write_result<BLOCK, SPARSE>(A, sh, st, q, nonempty, vol);
+        write_result<BLOCK, SPARSE, ERR>(A, sh, st, q, nonempty, vol);
     } else if (report_overflow) {
         if (threadIdx.x == 0) {
             const uint32_t k = atomicAdd(&A.counters[A.ovf_out_idx], 1u);
@@ -937,7 +938,7 @@ __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const Quer
             st.seg_cnt[s] = 0;
             st.seg_hi[s] = 0.f;
             st.seg_lo[s] = 0.f;
-            if (st.seg_var) st.seg_var[s] = 0.f;
+            if (ERR) st.seg_var[s] = 0.f;
         }
     __syncthreads();
 }
@@ -981,7 +982,7 @@ __device__ inline QueryState lds_state(char *dyn, QueryShared &sh, uint32_t nseg
     return st;
 }
 
-template <int BLOCK, bool SPARSE>
+template <int BLOCK, bool SPARSE, bool ERR>
 __device__ inline void clear_lds_state(const QueryState &st, uint32_t nseg)
 {
     for (uint32_t i = threadIdx.x; i < st.cap; i += BLOCK) {
@@ -995,7 +996,7 @@ __device__ inline void clear_lds_state(const QueryState &st, uint32_t nseg)
             st.seg_cnt[s] = 0;
             st.seg_hi[s] = 0.f;
             st.seg_lo[s] = 0.f;
-            if (st.seg_var) st.seg_var[s] = 0.f;
+            if (ERR) st.seg_var[s] = 0.f;
         }
 }
 
@@ -1005,23 +1006,23 @@ __global__ __launch_bounds__(kBlock) void query_plain_kernel(QueryArgs A)
 {
     extern __shared__ __align__(16) char dyn[];
     __shared__ QueryShared sh;
-    const QueryState st = lds_state<SPARSE>(dyn, sh, A.gv.nseg, A.table_cap, A.lt.n_levels, A.out_err != nullptr);
+    const QueryState st = lds_state<SPARSE>(dyn, sh, A.gv.nseg, A.table_cap, A.lt.n_levels, false);
     load_rank_ptr<kBlock>(A, sh);
-    clear_lds_state<kBlock, SPARSE>(st, A.gv.nseg);
+    clear_lds_state<kBlock, SPARSE, false>(st, A.gv.nseg);
     __syncthreads();
-    run_query<kBlock, kUnroll, SPARSE>(A, sh, st, blockIdx.x, A.ovf_out != nullptr);
+    run_query<kBlock, kUnroll, SPARSE, false>(A, sh, st, blockIdx.x, A.ovf_out != nullptr);
 }
 
 // Batched tiers: persistent blocks take queries from the largest-first order.
 // BIG: positions [0, counters[8]); otherwise [counters[8], n).
-template <int BLOCK, bool BIG, int UNROLL, bool SPARSE>
+template <int BLOCK, bool BIG, int UNROLL, bool SPARSE, bool ERR>
 __global__ __launch_bounds__(BLOCK) void query_tier_kernel(QueryArgs A)
 {
     extern __shared__ __align__(16) char dyn[];
     __shared__ QueryShared sh;
-    const QueryState st = lds_state<SPARSE>(dyn, sh, A.gv.nseg, A.table_cap, A.lt.n_levels, A.out_err != nullptr);
+    const QueryState st = lds_state<SPARSE>(dyn, sh, A.gv.nseg, A.table_cap, A.lt.n_levels, ERR);
     load_rank_ptr<BLOCK>(A, sh);
-    clear_lds_state<BLOCK, SPARSE>(st, A.gv.nseg);
+    clear_lds_state<BLOCK, SPARSE, ERR>(st, A.gv.nseg);
     const uint32_t split = ld(&A.counters[8]);
     const uint32_t begin = BIG ? 0u : split, end = BIG ? split : A.n;
     for (;;) {
@@ -1029,33 +1030,33 @@ __global__ __launch_bounds__(BLOCK) void query_tier_kernel(QueryArgs A)
         __syncthreads();
         const uint32_t k = sh.q;
         if (k >= end) break;  // uniform
-        run_query<BLOCK, UNROLL, SPARSE>(A, sh, st, A.order[k], A.ovf_out != nullptr);
+        run_query<BLOCK, UNROLL, SPARSE, ERR>(A, sh, st, A.order[k], A.ovf_out != nullptr);
     }
 }
 
 // Retry of boxes whose tier table overflowed (list 1), with a larger LDS table;
 // what overflows again goes to list 2.
-template <int BLOCK, int UNROLL, bool SPARSE>
+template <int BLOCK, int UNROLL, bool SPARSE, bool ERR>
 __global__ __launch_bounds__(BLOCK) void query_retry_kernel(QueryArgs A)
 {
     extern __shared__ __align__(16) char dyn[];
     __shared__ QueryShared sh;
-    const QueryState st = lds_state<SPARSE>(dyn, sh, A.gv.nseg, A.table_cap, A.lt.n_levels, A.out_err != nullptr);
+    const QueryState st = lds_state<SPARSE>(dyn, sh, A.gv.nseg, A.table_cap, A.lt.n_levels, ERR);
     load_rank_ptr<BLOCK>(A, sh);
-    clear_lds_state<BLOCK, SPARSE>(st, A.gv.nseg);
+    clear_lds_state<BLOCK, SPARSE, ERR>(st, A.gv.nseg);
     const uint32_t n_list = ld(&A.counters[1]);
     for (;;) {
         if (threadIdx.x == 0) sh.q = atomicAdd(&A.counters[4], 1u);
         __syncthreads();
         const uint32_t k = sh.q;
         if (k >= n_list) break;  // uniform
-        run_query<BLOCK, UNROLL, SPARSE>(A, sh, st, A.overflow[k], true);
+        run_query<BLOCK, UNROLL, SPARSE, ERR>(A, sh, st, A.overflow[k], true);
     }
 }
 
 // Fallback for boxes that overflowed the retry table too (list 2): per-worker
 // tables and source arrays in the workspace (global memory).
-template <bool SPARSE>
+template <bool SPARSE, bool ERR>
 __global__ __launch_bounds__(kBlock) void query_fallback_kernel(QueryArgs A)
 {
     extern __shared__ __align__(16) char dyn[];
@@ -1076,7 +1077,7 @@ __global__ __launch_bounds__(kBlock) void query_fallback_kernel(QueryArgs A)
     st.seg_hi = SPARSE ? nullptr : A.g_seg_hi + w * A.gv.nseg;
     st.seg_lo = SPARSE ? nullptr : A.g_seg_lo + w * A.gv.nseg;
     st.slabs = reinterpret_cast<Slab *>(dyn);  // the only dynamic LDS of this kernel
-    st.seg_var = (!SPARSE && A.out_err) ? A.g_seg_var + w * A.gv.nseg : nullptr;
+    st.seg_var = ERR ? A.g_seg_var + w * A.gv.nseg : nullptr;
     load_rank_ptr<kBlock>(A, sh);
     __syncthreads();
     const uint32_t n_over = ld(&A.counters[5]);
@@ -1085,7 +1086,7 @@ __global__ __launch_bounds__(kBlock) void query_fallback_kernel(QueryArgs A)
         __syncthreads();
         const uint32_t k = sh.q;
         if (k >= n_over) break;
-        run_query<kBlock, kUnroll, SPARSE>(A, sh, st, A.overflow2[k], false);
+        run_query<kBlock, kUnroll, SPARSE, ERR>(A, sh, st, A.overflow2[k], false);
     }
 }
 
@@ -1458,13 +1459,17 @@ int timing_end(Graph *g, hipStream_t s, std::string *err)
 using QueryKernel = void (*)(QueryArgs);
 using NaiveKernel = void (*)(NaiveArgs);
 
-template <int BLOCK, bool BIG, bool SPARSE>
+template <int BLOCK, bool BIG, bool SPARSE, bool ERR>
 QueryKernel tier_kernel(uint32_t unroll)
 {
-    switch (unroll) {
-    case 4: return query_tier_kernel<BLOCK, BIG, 4, SPARSE>;
-    case 8: return query_tier_kernel<BLOCK, BIG, 8, SPARSE>;
-    default: return query_tier_kernel<BLOCK, BIG, 16, SPARSE>;
+    if constexpr (ERR) {
+        return query_tier_kernel<BLOCK, BIG, 8, SPARSE, true>;  // one unroll for uncertainty queries
+    } else {
+        switch (unroll) {
+        case 4: return query_tier_kernel<BLOCK, BIG, 4, SPARSE, false>;
+        case 8: return query_tier_kernel<BLOCK, BIG, 8, SPARSE, false>;
+        default: return query_tier_kernel<BLOCK, BIG, 16, SPARSE, false>;
+        }
     }
 }
 
@@ -1682,23 +1687,23 @@ int dev_workspace_init(Graph *g, void *work, uint64_t bytes, void *stream, std::
     return MG_OK;
 }
 
-template <bool SPARSE>
+template <bool SPARSE, bool ERR>
 int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &lt, uint32_t n, hipStream_t s,
                  int variant, std::string *err)
 {
     int rc = MG_OK;
     DeviceState &d = g->dev;
     const int bbig = d.cfg.block_big == 256 ? 256 : kBlockBig;    // threads per big-tier box
-    const QueryKernel kbig = bbig == 256 ? tier_kernel<256, true, SPARSE>(d.cfg.unroll_big)
-                                         : tier_kernel<kBlockBig, true, SPARSE>(d.cfg.unroll_big);
+    const QueryKernel kbig = bbig == 256 ? tier_kernel<256, true, SPARSE, ERR>(d.cfg.unroll_big)
+                                         : tier_kernel<kBlockBig, true, SPARSE, ERR>(d.cfg.unroll_big);
     const int bsmall = d.cfg.block_small == 256 ? kBlock : 128;  // threads per small-tier box
-    const QueryKernel ksmall = bsmall == 128 ? tier_kernel<128, false, SPARSE>(d.cfg.unroll_small)
-                                             : tier_kernel<kBlock, false, SPARSE>(d.cfg.unroll_small);
+    const QueryKernel ksmall = bsmall == 128 ? tier_kernel<128, false, SPARSE, ERR>(d.cfg.unroll_small)
+                                             : tier_kernel<kBlock, false, SPARSE, ERR>(d.cfg.unroll_small);
     const QueryKernel kplain = query_plain_kernel<SPARSE>;
     const uint32_t cap_big = d.cfg.table_big ? d.cfg.table_big : (SPARSE ? kHashBigSparse : kHashBig);
     const uint32_t cap_small = d.cfg.table_small ? d.cfg.table_small : (SPARSE ? kHashSmallSparse : kHashSmall);
     const uint32_t L = g->n_levels;
-    const bool E = A.out_err != nullptr;
+    constexpr bool E = ERR;
     const uint32_t dyn_big = lds_bytes(g->nseg, cap_big, SPARSE, L, E),
                    dyn_small = lds_bytes(g->nseg, cap_small, SPARSE, L, E),
                    dyn_plain = lds_bytes(g->nseg, kHashPlain, SPARSE, L, E);
@@ -1734,7 +1739,7 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
         HIP_TRY(hipGetLastError());
     }
     // boxes whose table overflowed: once more with a larger LDS table, then in global memory
-    const QueryKernel kretry = query_retry_kernel<kBlockBig, 8, SPARSE>;
+    const QueryKernel kretry = query_retry_kernel<kBlockBig, 8, SPARSE, ERR>;
     uint32_t cap_retry = d.cfg.table_retry;
     if (!cap_retry) {  // the largest table up to kHashRetry that fits the LDS of a workgroup
         cap_retry = kHashRetry;
@@ -1754,7 +1759,8 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
     HIP_TRY(hipGetLastError());
     A.ovf_out = nullptr;
     A.stats_tag = 0x80000000u;
-    hipLaunchKernelGGL(query_fallback_kernel<SPARSE>, dim3(kFallbackWorkers), dim3(kBlock),
+    const QueryKernel kfallback = query_fallback_kernel<SPARSE, ERR>;
+    hipLaunchKernelGGL(kfallback, dim3(kFallbackWorkers), dim3(kBlock),
                        6u * L * uint32_t(sizeof(Slab)), s, A);
     HIP_TRY(hipGetLastError());
     // the timed region: every kernel that answers boxes (tiers or plain, retry, fallback)
@@ -1873,8 +1879,9 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const Spa
     // sources in LDS arrays while they fit, else as table entries (sparse mode)
     const bool sparse = sp != nullptr || g->nseg > kSegLdsMax;
     A.lt.use16 = (!sparse && g->dev.maps16) ? 1u : 0u;
-    return sparse ? launch_query<true>(g, A, w, lt, n, s, variant, err)
-                  : launch_query<false>(g, A, w, lt, n, s, variant, err);
+    if (A.out_err) return launch_query<false, true>(g, A, w, lt, n, s, variant, err);
+    return sparse ? launch_query<true, false>(g, A, w, lt, n, s, variant, err)
+                  : launch_query<false, false>(g, A, w, lt, n, s, variant, err);
 }
 
 int dev_footprint(Graph *g, const uint32_t *boxes, uint32_t n, uint32_t *level_counts, uint32_t *cubes, uint32_t cap,
