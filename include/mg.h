@@ -98,18 +98,25 @@ int mg_info(const mg_graph *g, mg_info_t *out);
  * Details": w and 1 - w are both quantized and the orientation with the
  * smaller error is kept). The codebook is learned from the graph's weights; a
  * codeword is the mean of its bin's weights (an empty bin: its midpoint and the
- * standard deviation of a uniform bin). Nodes are visited predecessors first;
+ * standard deviation of a uniform bin), rounded to the 20-bit field the graph
+ * stream stores it in (Table "bitstream", C): the nearest multiple of 2^-20 in
+ * (0, 1); sigmas to the nearest multiple of sigma_max / (2^20 - 1), sigma_max
+ * being the largest bin sigma in fp32. Nodes are visited predecessors first;
  * nodes with equal (merged) predecessors and codeword are merged, and a node
  * whose two predecessors merged becomes that predecessor. The copy supports
  * every entry point of an exact graph (its queries return the quantized
  * histograms) and mg_export_codebook; its lookup table also carries the
- * propagated uncertainty (mg_lut_build, mg_query_boxes_err). bits in [1, 20]. */
+ * propagated uncertainty (mg_lut_build, mg_query_boxes_err) and can be
+ * written as a bit-packed stream (mg_pack). bits in [1, 16] (the stream's
+ * 4-bit bit-rate field), else MG_EINVAL; MG_EINVAL for a quantized graph. */
 int mg_quantize(const mg_graph *g, uint32_t bits, uint32_t threads, mg_graph **out);
 
 /* Codebook of a quantized graph: codeword and sigma host fp32 [2^bits]; node_sigma
- * host fp32 [n_nodes], the sigma of each node's weight (0 for sources). NULL skips
- * an array; MG_ESTATE for a graph with exact weights. */
-int mg_export_codebook(const mg_graph *g, float *codeword, float *sigma, float *node_sigma);
+ * host fp32 [n_nodes], the sigma of each node's weight (0 for sources); node_code
+ * host u32 [n_nodes], the bin of each node's weight (the stored weight is the
+ * codeword or 1 - codeword; 0 for sources). NULL skips an array; MG_ESTATE for a
+ * graph with exact weights. */
+int mg_export_codebook(const mg_graph *g, float *codeword, float *sigma, float *node_sigma, uint32_t *node_code);
 
 /* Host copies of the DAG (NULL skips an array). Per node (n_nodes entries):
  * child_a/child_b are its two predecessors and w[n] = wnum[n]/wden[n] the
@@ -278,12 +285,33 @@ int mg_set_launch(mg_graph *g, const mg_launch_cfg *cfg); /* MG_EINVAL for unsup
 int mg_autotune(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *d_out, void *d_work,
                 uint64_t work_bytes, uint32_t reps, void *stream, mg_launch_cfg *chosen);
 
-/* Persist / restore the host graph (raw arrays with a header and checksums;
- * not the paper's bit-packed stream). mg_load validates the arrays (IDs in
+/* Persist / restore the host graph (raw arrays with a header and checksums,
+ * the quantizer's codebook included). mg_load validates the arrays (IDs in
  * range, children before parents, weights in (0, 1/2]) and returns
  * MG_EFORMAT on any mismatch. */
 int mg_save(const mg_graph *g, const char *path);
 int mg_load(const char *path, mg_graph **out);
+
+/* The bit-packed graph stream of Sec. "Compression" (Table "bitstream"), for a
+ * quantized graph (else MG_ESTATE). Header: sources (32 bits), fractional-input
+ * flag (1, always 0), bits per node minus 1 (6), sigma_max (32, fp32 bits),
+ * level-0 resolution (3 x 32), quantizer bit rate minus 1 (4), internal nodes
+ * (bits per node); per level r(l) and i_min(l) (bits per node each). Bulk: per
+ * level and voxel (x fastest) its node ID - i_min(l) at r(l) bits; per internal
+ * node (first, second, codebook index) at 2 x bits per node + bit rate bits,
+ * node = (1 - code) first + code second; per bin codeword x 2^20 and
+ * sigma / sigma_max x (2^20 - 1) at 20 bits each; then (an addition) the input
+ * label of each source at 32 bits. Bits per node = ceil(log2 #nodes), r(l) =
+ * ceil(log2(i_max(l) - i_min(l) + 1)). Fields are unsigned, least significant
+ * bit first; bit i of the stream is bit i mod 8 of byte i / 8; zero bits pad
+ * the last byte.
+ * mg_pack: *size = the stream's bytes; with buf == NULL only the size is
+ * returned; MG_ELIMIT if capacity < *size. Host memory, caller-owned.
+ * mg_unpack: a new host graph from a stream (nodes renumbered by rank as
+ * mg_build does, deferred step schedule); MG_EFORMAT on any malformed or
+ * truncated field. unpack(pack(g)) has g's maps, nodes, weights and codebook. */
+int mg_pack(const mg_graph *g, uint8_t *buf, uint64_t capacity, uint64_t *size);
+int mg_unpack(const uint8_t *buf, uint64_t size, uint32_t threads, mg_graph **out);
 
 /* Kernel timing: when enabled, the dominant kernel of each query /
  * propagation call is bracketed by HIP events on the call's stream;

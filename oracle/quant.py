@@ -10,6 +10,11 @@ Python / NumPy fp64:
   best in the least-squares sense), the standard deviation is the population
   one, and a bin no weight falls into gets its midpoint and the standard
   deviation of a uniform distribution over the bin.
+- Table "bitstream" (C): each codeword and each standard deviation is stored
+  with 20 bits. Reading: a codeword is the nearest multiple of 2^-20 inside
+  (0, 1), a standard deviation the nearest multiple of sigma_max / (2^20 - 1),
+  where sigma_max (header field 4, 32 bits) is the largest one in fp32; the
+  quantizer's codebook is the stored one.
 - Sec. "Implementation Details": a lerp (i, j, w) equals (j, i, 1 - w); both w
   and 1 - w are quantized and the orientation with the smaller quantization
   error is kept (ties: w).
@@ -31,21 +36,30 @@ import math
 import numpy as np
 
 
+CODE_BITS = 20
+
+
 def codebook(weights, bits: int):
-    """(codeword [2^bits], sigma [2^bits]) learned from weights in (0, 1)."""
+    """(codeword [2^bits], sigma [2^bits]) learned from weights in (0, 1), at the stored resolution."""
     B = 1 << bits
     w = np.asarray(weights, dtype=np.float64)
     k = np.minimum((w * B).astype(np.int64), B - 1)
-    code = np.empty(B)
-    sig = np.empty(B)
+    mean = np.empty(B)
+    sd = np.empty(B)
     for b in range(B):
         sel = w[k == b]
         if len(sel):
-            code[b] = sel.mean()
-            sig[b] = math.sqrt(float(((sel - sel.mean()) ** 2).mean()))
+            mean[b] = sel.mean()
+            sd[b] = math.sqrt(float(((sel - sel.mean()) ** 2).mean()))
         else:
-            code[b] = (b + 0.5) / B
-            sig[b] = 1.0 / B / math.sqrt(12.0)
+            mean[b] = (b + 0.5) / B
+            sd[b] = 1.0 / B / math.sqrt(12.0)
+    scale = float(1 << CODE_BITS)
+    code = np.array([min(max(math.floor(m * scale + 0.5), 1), scale - 1) / scale for m in mean])
+    smax = float(np.float32(sd.max()))
+    top = float((1 << CODE_BITS) - 1)
+    sig = np.array([float(np.float32(smax * min(math.floor(x / smax * top + 0.5), top) / top)) if smax > 0 else 0.0
+                    for x in sd])
     return code, sig
 
 

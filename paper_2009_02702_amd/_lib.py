@@ -55,7 +55,7 @@ SYMBOLS = [
     "mg_naive_boxes",
     "mg_footprint", "mg_propagate_tf", "mg_palette_fetch", "mg_lut_build", "mg_export_lut", "mg_query_boxes_lut", "mg_query_boxes_err",
     "mg_get_launch", "mg_set_launch", "mg_autotune",
-    "mg_save", "mg_load", "mg_timing_enable", "mg_timing_read",
+    "mg_save", "mg_load", "mg_pack", "mg_unpack", "mg_timing_enable", "mg_timing_read",
     "mg_last_error", "mg_free",
 ]
 
@@ -80,7 +80,7 @@ def load() -> ctypes.CDLL:
         "mg_build": ([vp, ctypes.POINTER(BuildOpts), ctypes.POINTER(G)], i32),
         "mg_info": ([G, ctypes.POINTER(Info)], i32),
         "mg_quantize": ([G, u32, u32, ctypes.POINTER(G)], i32),
-        "mg_export_codebook": ([G, vp, vp, vp], i32),
+        "mg_export_codebook": ([G, vp, vp, vp, vp], i32),
         "mg_export_dag": ([G, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp], i32),
         "mg_export_map": ([G, u32, vp], i32),
         "mg_segment_ids": ([G, vp], i32),
@@ -104,6 +104,8 @@ def load() -> ctypes.CDLL:
         "mg_autotune": ([G, vp, u32, vp, vp, u64, u32, vp, ctypes.POINTER(LaunchCfg)], i32),
         "mg_save": ([G, ctypes.c_char_p], i32),
         "mg_load": ([ctypes.c_char_p, ctypes.POINTER(G)], i32),
+        "mg_pack": ([G, vp, u64, ctypes.POINTER(u64)], i32),
+        "mg_unpack": ([vp, u64, u32, ctypes.POINTER(G)], i32),
         "mg_timing_enable": ([G, i32], i32),
         "mg_timing_read": ([G, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u32)], i32),
         "mg_last_error": ([], ctypes.c_char_p),

@@ -28,7 +28,7 @@ int done(int code, const std::string &msg)
 }
 
 // ---- save / load: "MGRAPH01" + header + arrays, each followed by FNV-1a 64
-constexpr char kMagic[8] = {'M', 'G', 'R', 'A', 'P', 'H', '0', '2'};
+constexpr char kMagic[8] = {'M', 'G', 'R', 'A', 'P', 'H', '0', '3'};
 
 uint64_t fnv(const void *p, size_t n, uint64_t h = 0xcbf29ce484222325ULL)
 {
@@ -129,7 +129,7 @@ int mg_quantize(const mg_graph *h, uint32_t bits, uint32_t threads, mg_graph **o
     return MG_OK;
 }
 
-int mg_export_codebook(const mg_graph *h, float *codeword, float *sigma, float *node_sigma)
+int mg_export_codebook(const mg_graph *h, float *codeword, float *sigma, float *node_sigma, uint32_t *node_code)
 {
     if (!h) return fail(MG_EINVAL, "mg_export_codebook: null graph");
     const mg::Graph &g = h->g;
@@ -137,6 +137,7 @@ int mg_export_codebook(const mg_graph *h, float *codeword, float *sigma, float *
     if (codeword) std::memcpy(codeword, g.codebook.data(), g.codebook.size() * sizeof(float));
     if (sigma) std::memcpy(sigma, g.code_sigma.data(), g.code_sigma.size() * sizeof(float));
     if (node_sigma) std::memcpy(node_sigma, g.node_sigma.data(), g.node_sigma.size() * sizeof(float));
+    if (node_code) std::memcpy(node_code, g.node_code.data(), g.node_code.size() * sizeof(uint32_t));
     return MG_OK;
 }
 
@@ -347,6 +348,36 @@ int mg_query_boxes_err(mg_graph *h, const uint32_t *d_boxes, uint32_t n, float *
                 err);
 }
 
+int mg_pack(const mg_graph *h, uint8_t *buf, uint64_t capacity, uint64_t *size)
+{
+    if (!h || !size) return fail(MG_EINVAL, "mg_pack: null argument");
+    std::vector<uint8_t> s;
+    std::string err;
+    if (int rc = mg::pack_graph(h->g, &s, &err)) return fail(rc, "mg_pack: " + err);
+    *size = s.size();
+    if (!buf) return MG_OK;
+    if (capacity < s.size())
+        return fail(MG_ELIMIT, "mg_pack: the stream needs " + std::to_string(s.size()) + " bytes, capacity is " +
+                                   std::to_string(capacity));
+    std::memcpy(buf, s.data(), s.size());
+    return MG_OK;
+}
+
+int mg_unpack(const uint8_t *buf, uint64_t size, uint32_t threads, mg_graph **out)
+{
+    if (!buf || !out) return fail(MG_EINVAL, "mg_unpack: null argument");
+    *out = nullptr;
+    mg_graph *h = new (std::nothrow) mg_graph;
+    if (!h) return fail(MG_ENOMEM, "mg_unpack: out of host memory");
+    std::string err;
+    if (int rc = mg::unpack_graph(buf, size, threads, &h->g, &err)) {
+        delete h;
+        return fail(rc, "mg_unpack: " + err);
+    }
+    *out = h;
+    return MG_OK;
+}
+
 int mg_get_launch(const mg_graph *h, mg_launch_cfg *out)
 {
     if (!h || !out) return fail(MG_EINVAL, "mg_get_launch: null argument");
@@ -391,12 +422,13 @@ int mg_save(const mg_graph *h, const char *path)
     const mg::Graph &g = h->g;
     FILE *f = std::fopen(path, "wb");
     if (!f) return fail(MG_EIO, std::string("mg_save: cannot open ") + path);
-    uint32_t hdr[8] = {g.dims[0], g.dims[1], g.dims[2], g.nseg, g.n_nodes, g.depth, g.n_levels, g.max_mixture};
+    uint32_t hdr[9] = {g.dims[0], g.dims[1], g.dims[2], g.nseg, g.n_nodes, g.depth, g.n_levels, g.max_mixture,
+                       g.quant_bits};
     bool ok = wr(f, kMagic, 8) && wr(f, hdr, sizeof(hdr)) && wr_vec(f, g.seg_ids) && wr_vec(f, g.child_a) &&
               wr_vec(f, g.child_b) && wr_vec(f, g.alpha) && wr_vec(f, g.wnum) && wr_vec(f, g.wden) &&
               wr_vec(f, g.rank) && wr_vec(f, g.step) && wr_vec(f, g.rank_ptr) && wr_vec(f, g.sched) &&
-              wr_vec(f, g.step_ptr) && wr_vec(f, g.lev_off) &&
-              wr_vec(f, g.maps);
+              wr_vec(f, g.step_ptr) && wr_vec(f, g.lev_off) && wr_vec(f, g.maps) && wr_vec(f, g.codebook) &&
+              wr_vec(f, g.code_sigma) && wr_vec(f, g.node_sigma) && wr_vec(f, g.node_code);
     ok = (std::fclose(f) == 0) && ok;
     return ok ? MG_OK : fail(MG_EIO, std::string("mg_save: write failed for ") + path);
 }
@@ -414,17 +446,18 @@ int mg_load(const char *path, mg_graph **out)
     }
     mg::Graph &g = h->g;
     char magic[8];
-    uint32_t hdr[8];
+    uint32_t hdr[9];
     int rc = MG_OK;
     if (!rd(f, magic, 8) || !rd(f, hdr, sizeof(hdr))) rc = MG_EIO;
     else if (std::memcmp(magic, kMagic, 8) != 0) rc = MG_EFORMAT;
     if (rc == MG_OK) {
         g.dims[0] = hdr[0], g.dims[1] = hdr[1], g.dims[2] = hdr[2];
         g.nseg = hdr[3], g.n_nodes = hdr[4], g.depth = hdr[5], g.n_levels = hdr[6], g.max_mixture = hdr[7];
+        g.quant_bits = hdr[8];
         const uint64_t nvox = uint64_t(g.dims[0]) * g.dims[1] * g.dims[2];
         const uint64_t N = g.n_nodes, lim_maps = 2 * nvox + 64;
         if (g.dims[0] == 0 || g.dims[1] == 0 || g.dims[2] == 0 || nvox >= (1ull << 31) ||
-            g.n_levels > MG_MAX_LEVELS)
+            g.n_levels > MG_MAX_LEVELS || g.quant_bits > mg::kMaxQuantBits)
             rc = MG_EFORMAT;
         if (rc == MG_OK) rc = rd_vec(f, &g.seg_ids, N);
         if (rc == MG_OK) rc = rd_vec(f, &g.child_a, N);
@@ -439,6 +472,17 @@ int mg_load(const char *path, mg_graph **out)
         if (rc == MG_OK) rc = rd_vec(f, &g.step_ptr, uint64_t(g.depth) + 2);
         if (rc == MG_OK) rc = rd_vec(f, &g.lev_off, uint64_t(MG_MAX_LEVELS) + 1);
         if (rc == MG_OK) rc = rd_vec(f, &g.maps, lim_maps);
+        const uint64_t nb = g.quant_bits ? (uint64_t(1) << g.quant_bits) : 0, nn = g.quant_bits ? N : 0;
+        if (rc == MG_OK) rc = rd_vec(f, &g.codebook, nb);
+        if (rc == MG_OK) rc = rd_vec(f, &g.code_sigma, nb);
+        if (rc == MG_OK) rc = rd_vec(f, &g.node_sigma, nn);
+        if (rc == MG_OK) rc = rd_vec(f, &g.node_code, nn);
+        if (rc == MG_OK && (g.codebook.size() != nb || g.code_sigma.size() != nb || g.node_sigma.size() != nn ||
+                            g.node_code.size() != nn))
+            rc = MG_EFORMAT;
+        if (rc == MG_OK)
+            for (uint32_t k : g.node_code)
+                if (k >= nb && nb) rc = MG_EFORMAT;
         if (rc == MG_OK) mg::level_dims(g.dims, &g.lev_dims);
     }
     std::fclose(f);

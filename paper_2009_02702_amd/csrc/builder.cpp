@@ -42,9 +42,6 @@
 #include "mg_internal.hpp"
 
 namespace mg {
-namespace {
-
-constexpr uint32_t kMixed = 0xFFFFFFFFu;
 
 unsigned resolve_threads(uint32_t t)
 {
@@ -52,6 +49,10 @@ unsigned resolve_threads(uint32_t t)
     if (hw == 0) hw = 1;
     return t == 0 ? hw : std::min<unsigned>(t, 4 * hw);
 }
+
+namespace {
+
+constexpr uint32_t kMixed = 0xFFFFFFFFu;
 
 // Run fn(begin, end, worker) over [0, n) in `nt` contiguous chunks, in order.
 void parallel_chunks(uint64_t n, unsigned nt, const std::function<void(uint64_t, uint64_t, unsigned)> &fn)
@@ -322,17 +323,6 @@ void level_dims(const uint32_t dims[3], std::vector<uint32_t> *out)
     }
 }
 
-// A DAG in creation order (children before parents; sources 0 .. nseg-1 have
-// a = b = n): what finalize_dag turns into a Graph's node arrays.
-struct RawDag {
-    uint32_t nseg = 0;
-    std::vector<uint32_t> a, b;    // predecessors
-    std::vector<uint64_t> wn, wd;  // weight of b as an exact fraction
-    std::vector<uint32_t> mix;     // segments in the node's mixture
-    std::vector<float> alpha;      // fp32 weights if given, else RN(wn / wd)
-    std::vector<float> sigma;      // uncertainty of each weight, if any
-};
-
 // Topological levels (Sec. "Reconstruction"), the deferred step schedule, IDs
 // renumbered by (rank, creation order) with sources fixed, and the mip voxels
 // of levels >= 1 remapped to the new IDs (level 0 holds sources only).
@@ -418,6 +408,11 @@ int finalize_dag(const RawDag &d, bool defer, uint32_t max_depth, unsigned nt, G
     if (!d.sigma.empty()) {
         g->node_sigma.assign(N, 0.f);
         for (uint32_t n = 0; n < N; ++n) g->node_sigma[perm[n]] = d.sigma[n];
+    }
+    g->node_code.clear();
+    if (!d.code.empty()) {
+        g->node_code.assign(N, 0);
+        for (uint32_t n = 0; n < N; ++n) g->node_code[perm[n]] = d.code[n];
     }
     // ---- execution order of the step schedule: sources, then step 1, 2, ...
     std::vector<uint32_t> scnt(depth + 2, 0);
@@ -600,6 +595,16 @@ int build_graph(const uint32_t *ids, const mg_build_opts *o, Graph *g, std::stri
     return MG_OK;
 }
 
+// The exact fraction of an fp32 weight: c = fr 2^e with a 24-bit fr.
+void weight_fraction(float c, uint64_t *num, uint64_t *den)
+{
+    int e = 0;
+    const float fr = std::frexp(c, &e);  // c = fr 2^e, fr in [1/2, 1)
+    uint64_t n = uint64_t(std::ldexp(double(fr), 24)), d = uint64_t(1) << (24 - e);
+    while (n % 2 == 0 && d > 1) n /= 2, d /= 2;
+    *num = n, *den = d;
+}
+
 // Scalar quantization of the interpolation weights (Sec. "Compression": the
 // open range (0, 1) is cut into 2^b equal bins, each represented by one
 // codeword, with the empirical standard deviation of the weights in the bin
@@ -607,13 +612,15 @@ int build_graph(const uint32_t *ids, const mg_build_opts *o, Graph *g, std::stri
 // are quantized and the orientation with the smaller error is kept). The
 // codebook is learned from the graph's weights (w <= 1/2); a codeword is the
 // mean of its bin's weights, an empty bin gets its midpoint and the standard
-// deviation of a uniform bin. Nodes are visited children first; a node whose
-// two (merged) predecessors coincide becomes that predecessor, and nodes with
-// the same predecessors and codeword are merged (re-use, Sec. "Compression").
+// deviation of a uniform bin; codewords and sigmas are then rounded to the
+// 20-bit fields the graph stream stores them in (Table "bitstream", C). Nodes
+// are visited children first; a node whose two (merged) predecessors coincide
+// becomes that predecessor, and nodes with the same predecessors and codeword
+// are merged (re-use, Sec. "Compression").
 int quantize_graph(const Graph &src, uint32_t bits, uint32_t threads, Graph *dst, std::string *err)
 {
-    if (bits < 1 || bits > 20) {
-        *err = "quantizer bit rate must be in [1, 20]";
+    if (bits < 1 || bits > kMaxQuantBits) {
+        *err = "quantizer bit rate must be in [1, " + std::to_string(kMaxQuantBits) + "]";
         return MG_EINVAL;
     }
     const uint32_t S = src.nseg, N = src.n_nodes, B = 1u << bits;
@@ -631,15 +638,28 @@ int quantize_graph(const Graph &src, uint32_t bits, uint32_t threads, Graph *dst
         const double dv = w - sum[k] / double(cnt[k]);
         dev2[k] += dv * dv;
     }
+    // codewords and sigmas at the stream's 20-bit resolution: a codeword is the
+    // nearest multiple of 2^-20 inside (0, 1); a sigma the nearest multiple of
+    // sigma_max / (2^20 - 1), sigma_max being the largest sigma rounded to fp32
+    const double scale = double(1u << kCodeBits), smax_q = double((1u << kCodeBits) - 1);
     std::vector<float> code(B), sig(B);
+    std::vector<double> sd(B);
     for (uint32_t k = 0; k < B; ++k) {
+        double mean;
         if (cnt[k]) {
-            code[k] = float(sum[k] / double(cnt[k]));
-            sig[k] = float(std::sqrt(dev2[k] / double(cnt[k])));
+            mean = sum[k] / double(cnt[k]);
+            sd[k] = std::sqrt(dev2[k] / double(cnt[k]));
         } else {
-            code[k] = float((k + 0.5) / B);
-            sig[k] = float(1.0 / B / std::sqrt(12.0));
+            mean = (k + 0.5) / B;
+            sd[k] = 1.0 / B / std::sqrt(12.0);
         }
+        const double m = std::min(std::max(std::floor(mean * scale + 0.5), 1.0), scale - 1.0);
+        code[k] = float(m / scale);
+    }
+    const float sigma_max = float(*std::max_element(sd.begin(), sd.end()));
+    for (uint32_t k = 0; k < B; ++k) {
+        const double m = sigma_max > 0.f ? std::min(std::floor(sd[k] / double(sigma_max) * smax_q + 0.5), smax_q) : 0.0;
+        sig[k] = code_sigma_value(sigma_max, uint32_t(m));
     }
     RawDag d;
     d.nseg = S;
@@ -647,7 +667,7 @@ int quantize_graph(const Graph &src, uint32_t bits, uint32_t threads, Graph *dst
     for (uint32_t s = 0; s < S; ++s) {
         rep[s] = s;
         d.a.push_back(s), d.b.push_back(s), d.wn.push_back(0), d.wd.push_back(1), d.mix.push_back(1);
-        d.alpha.push_back(0.f), d.sigma.push_back(0.f);
+        d.alpha.push_back(0.f), d.sigma.push_back(0.f), d.code.push_back(0);
     }
     struct Key {
         uint32_t a, b, w;
@@ -684,13 +704,11 @@ int quantize_graph(const Graph &src, uint32_t bits, uint32_t threads, Graph *dst
         const uint32_t id = uint32_t(d.a.size());
         made.emplace(key, id);
         rep[n] = id;
-        int e = 0;
-        const float fr = std::frexp(c, &e);  // c = fr 2^e, fr in [1/2, 1)
-        uint64_t num = uint64_t(std::ldexp(double(fr), 24)), den = uint64_t(1) << (24 - e);
-        while (num % 2 == 0 && den > 1) num /= 2, den /= 2;
+        uint64_t num = 0, den = 1;
+        weight_fraction(c, &num, &den);
         d.a.push_back(first), d.b.push_back(second), d.wn.push_back(num), d.wd.push_back(den);
         d.mix.push_back(d.mix[first] + d.mix[second]);
-        d.alpha.push_back(c), d.sigma.push_back(sig[k]);
+        d.alpha.push_back(c), d.sigma.push_back(sig[k]), d.code.push_back(k);
     }
     dst->dims[0] = src.dims[0], dst->dims[1] = src.dims[1], dst->dims[2] = src.dims[2];
     dst->nseg = S;

@@ -82,8 +82,34 @@ struct Graph {
     uint32_t quant_bits = 0;
     std::vector<float> codebook, code_sigma;             // [2^bits] codeword and sigma of each bin
     std::vector<float> node_sigma;                       // [n_nodes] sigma of each node's weight
+    std::vector<uint32_t> node_code;                     // [n_nodes] codebook index of each node's weight
     DeviceState dev;
 };
+
+// A DAG in creation order (children before parents; sources 0 .. nseg-1 have
+// a = b = n): what finalize_dag turns into a Graph's node arrays.
+struct RawDag {
+    uint32_t nseg = 0;
+    std::vector<uint32_t> a, b;    // predecessors
+    std::vector<uint64_t> wn, wd;  // weight of b as an exact fraction
+    std::vector<uint32_t> mix;     // segments in the node's mixture
+    std::vector<float> alpha;      // fp32 weights if given, else RN(wn / wd)
+    std::vector<float> sigma;      // uncertainty of each weight, if any
+    std::vector<uint32_t> code;    // codebook index of each weight (quantized graphs), if any
+};
+
+// Codewords and their standard deviations are 20-bit fields of the graph
+// stream (Table "bitstream", C): codewords are multiples of 2^-20 in (0, 1),
+// sigmas multiples of sigma_max / (2^20 - 1).
+constexpr uint32_t kCodeBits = 20;
+constexpr uint32_t kMaxQuantBits = 16;  // the stream's 4-bit bit-rate field
+// sigma of a bin as stored: sigma_max * m / (2^20 - 1), rounded to fp32
+inline float code_sigma_value(float sigma_max, uint32_t m)
+{
+    return float(double(sigma_max) * double(m) / double((1u << kCodeBits) - 1));
+}
+// The exact fraction num / den of an fp32 weight in (0, 1).
+void weight_fraction(float c, uint64_t *num, uint64_t *den);
 
 // Host builder (builder.cpp). Returns MG_OK or an MG_E* code with *err set.
 int build_graph(const uint32_t *ids, const mg_build_opts *opts, Graph *g, std::string *err);
@@ -91,6 +117,14 @@ int build_graph(const uint32_t *ids, const mg_build_opts *opts, Graph *g, std::s
 int build_lut(Graph *g, uint32_t threads, std::string *err);
 // A copy of `src` with weights scalar-quantized to 2^bits bins and nodes merged.
 int quantize_graph(const Graph &src, uint32_t bits, uint32_t threads, Graph *dst, std::string *err);
+// Ranks, step schedule and rank-sorted IDs of a DAG in creation order; the maps
+// already in g (levels >= 1) are renumbered with the nodes.
+int finalize_dag(const RawDag &d, bool defer, uint32_t max_depth, unsigned nt, Graph *g, std::string *err);
+// Worker threads for a request (0: all hardware threads).
+unsigned resolve_threads(uint32_t t);
+// Bit-packed graph stream (Table "bitstream"); quantized graphs only.
+int pack_graph(const Graph &g, std::vector<uint8_t> *out, std::string *err);
+int unpack_graph(const uint8_t *buf, uint64_t size, uint32_t threads, Graph *g, std::string *err);
 // Structural validation of a graph's host arrays (used by mg_load).
 int validate_graph(const Graph &g, std::string *err);
 // Level dimensions: halve with rounding up until 1^3.

@@ -72,6 +72,22 @@ class Graph:
     def save(self, path: str) -> None:
         check(self._lib.mg_save(self._h, path.encode()))
 
+    def pack(self) -> bytes:
+        """The bit-packed graph stream (mg_pack) of a quantized graph."""
+        size = ctypes.c_uint64()
+        check(self._lib.mg_pack(self._h, None, 0, ctypes.byref(size)))
+        buf = (ctypes.c_uint8 * max(size.value, 1))()
+        check(self._lib.mg_pack(self._h, buf, size.value, ctypes.byref(size)))
+        return bytes(buf)[:size.value]
+
+    @classmethod
+    def unpack(cls, stream: bytes, threads: int = 0) -> "Graph":
+        """A host graph from a bit-packed stream (mg_unpack)."""
+        h = ctypes.c_void_p()
+        data = bytes(stream)
+        check(_lib.load().mg_unpack(data, len(data), threads, ctypes.byref(h)))
+        return cls(h)
+
     def close(self) -> None:
         if self._h:
             self._ws = None
@@ -275,15 +291,17 @@ class Graph:
         check(self._lib.mg_quantize(self._h, bits, threads, ctypes.byref(h)))
         return Graph(h)
 
-    def export_codebook(self):
-        """(codeword fp32 [2^bits], sigma fp32 [2^bits], node_sigma fp32 [n_nodes]) of a quantized graph."""
+    def export_codebook(self, with_code: bool = False):
+        """(codeword fp32 [2^bits], sigma fp32 [2^bits], node_sigma fp32 [n_nodes][, node_code u32 [n_nodes]])
+        of a quantized graph."""
         inf = self.info()
         B = 1 << inf["quant_bits"] if inf["quant_bits"] else 0
         cw = np.zeros(max(B, 1), dtype=np.float32)
         sg = np.zeros(max(B, 1), dtype=np.float32)
         ns = np.zeros(inf["n_nodes"], dtype=np.float32)
-        check(self._lib.mg_export_codebook(self._h, cw.ctypes.data, sg.ctypes.data, ns.ctypes.data))
-        return cw, sg, ns
+        nc = np.zeros(inf["n_nodes"], dtype=np.uint32)
+        check(self._lib.mg_export_codebook(self._h, cw.ctypes.data, sg.ctypes.data, ns.ctypes.data, nc.ctypes.data))
+        return (cw, sg, ns, nc) if with_code else (cw, sg, ns)
 
     def launch_config(self) -> dict:
         c = LaunchCfg()

@@ -136,3 +136,21 @@ def test_uncertainty_query_preconditions():
     empty = _dev(np.array([[3, 3, 3, 0, 4, 4], [30, 0, 0, 5, 5, 5]], dtype=np.uint32))
     out, err = q.query_err(empty)
     assert (out == 0).all() and (err == 0).all()
+
+
+def test_graph_from_the_bit_packed_stream_answers_like_its_source():
+    """A quantized graph written as the bit-packed stream (Table "bitstream") and read back answers
+    every box like the graph it was written from (up to the order of the kernels' atomic adds), and
+    like the oracle."""
+    g, q, boxes, f, u, l0, S = _setup(2, (64, 60, 56), 120, 300, 9)
+    r = Graph.unpack(q.pack()).upload(0)
+    r.lut_build()
+    db = _dev(boxes)
+    a = q.query(db).cpu().numpy().astype(np.float64)
+    b = r.query(db).cpu().numpy().astype(np.float64)
+    assert np.array_equal(a == 0, b == 0) and np.allclose(a, b, rtol=2e-6, atol=0)
+    _compare(b, f, l0, "unpacked")
+    oa, ea = q.query_err(db)
+    ob, eb = r.query_err(db)
+    _compare(ob.cpu().numpy(), f, l0, "unpacked err/fractions")
+    _compare_err(eb.cpu().numpy(), u, "unpacked err")

@@ -12,10 +12,13 @@ from paper_2009_02702_amd import Graph, MGError, synth
 def test_codebook_is_the_mean_and_spread_of_each_bin():
     w = np.array([0.1, 0.12, 0.3, 0.31, 0.33])
     code, sig = quant.codebook(w, 2)                      # bins [0, .25) [.25, .5) [.5, .75) [.75, 1)
-    assert np.allclose(code[:2], [0.11, (0.3 + 0.31 + 0.33) / 3])
     m = (0.3 + 0.31 + 0.33) / 3
-    assert np.allclose(sig[:2], [0.01, math.sqrt(((0.3 - m) ** 2 + (0.31 - m) ** 2 + (0.33 - m) ** 2) / 3)])
-    assert np.allclose(code[2:], [0.625, 0.875]) and np.allclose(sig[2:], 0.25 / math.sqrt(12))
+    q = 2.0 ** -20                                        # stored resolution of codewords
+    assert np.abs(code[:2] - [0.11, m]).max() <= q / 2 and (code * 2 ** 20 == np.round(code * 2 ** 20)).all()
+    s1 = math.sqrt(((0.3 - m) ** 2 + (0.31 - m) ** 2 + (0.33 - m) ** 2) / 3)
+    smax = 0.25 / math.sqrt(12)                           # the empty bins' spread is the largest
+    assert np.allclose(sig, [0.01, s1, smax, smax], rtol=0, atol=smax / (2 ** 20 - 1))
+    assert np.allclose(code[2:], [0.625, 0.875])
 
 
 def test_symmetric_orientation_keeps_the_smaller_error():
@@ -23,13 +26,13 @@ def test_symmetric_orientation_keeps_the_smaller_error():
     rep, nodes, code, _ = quant.quantize_dag(2, [0, 0], [1, 1], [0.26, 0.49], 2)
     assert len(nodes) == 1 and rep[2] == rep[3] == 2
     assert nodes[0][:2] == (0, 1) and nodes[0][2] == float(np.float32(code[1]))
-    # a codebook learned from {0.2, 0.3, 0.7} with 2 bins: codewords 0.25 and 0.7. For w = 0.3,
-    # |0.3 - 0.25| = 0.05 > |(1 - 0.3) - 0.7| = 0: the flipped orientation (1, 0, 0.7) is kept and
-    # stored with the weight <= 1/2 as (0, 1, 1 - 0.7); for w = 0.2 (error 0.05 vs 0.1) w is kept.
+    # a codebook learned from {0.2, 0.3, 0.7} with 2 bins: codewords 0.25 and 0.7 (to 2^-20). For
+    # w = 0.3, |0.3 - 0.25| = 0.05 > |(1 - 0.3) - 0.7| ~ 0: the flipped orientation (1, 0, 0.7) is kept
+    # and stored with the weight <= 1/2 as (0, 1, 1 - 0.7); for w = 0.2 (error 0.05 vs 0.1) w is kept.
     code, _ = quant.codebook([0.2, 0.3, 0.7], 1)
-    assert np.allclose(code, [0.25, 0.7])
+    assert np.allclose(code, [0.25, 0.7], rtol=0, atol=2.0 ** -21)
     rep, nodes, code32, _ = quant.quantize_dag(2, [0, 0, 0], [1, 1, 1], [0.2, 0.3, 0.7], 1)
-    c07 = float(np.float32(1) - np.float32(0.7))
+    c07 = float(np.float32(1) - np.float32(code[1]))
     tri = {n: nodes[rep[n] - 2][:3] for n in (2, 3, 4)}
     assert tri[2] == (0, 1, float(np.float32(0.25)))   # w = 0.2: kept
     assert tri[3] == (0, 1, c07)                         # w = 0.3: flipped, 0.7 e0 + 0.3 e1 as before
@@ -97,7 +100,7 @@ def test_library_quantizer_matches_the_oracle():
 
 def test_quantized_rows_stay_convex_and_fine_bits_are_near_exact():
     vol, g, S, d, w = _exact((16, 14, 12), 12, 7)
-    q = g.quantize(20)
+    q = g.quantize(16)
     q.lut_build()
     g.lut_build()
     p, s_, v = q.export_lut()
@@ -114,6 +117,8 @@ def test_quantized_rows_stay_convex_and_fine_bits_are_near_exact():
         q3.quantize(4)
     with np.testing.assert_raises(MGError):
         g.quantize(0)
+    with np.testing.assert_raises(MGError):
+        g.quantize(17)
     with np.testing.assert_raises(MGError):
         g.export_codebook()
 
