@@ -217,7 +217,7 @@ def main():
     id0 = 2.0 if S < 65535 else 4.0
     alg_bytes = float(np.sum(24.0 + id0 * cubes0 + 4.0 * (cubes - cubes0) + 12.0 * touched + 4.0 * S))
 
-    def run(variant, steps, warmup, timing):
+    def run(variant, steps, warmup, timing, g=g, ws=ws):
         for _ in range(warmup):
             g.query(dboxes, out=out, variant=variant, workspace=ws)
         torch.cuda.synchronize()
@@ -260,6 +260,22 @@ def main():
             comp[v]["lut_entries"] = lut_nnz
             comp[v]["lut_build_s"] = t_lut
         print("[bench] %s: %.3f ms/step" % (v, comp[v]["ms_per_step"]), file=sys.stderr, flush=True)
+
+    # the same boxes on a graph from the paper's greedy factorizer (max-reduction, tau = 3)
+    t0 = time.perf_counter()
+    gg = Graph.build(vol, factorizer="reduction", tau=3)
+    t_gb = time.perf_counter() - t0
+    gg.upload(0)
+    gg.set_launch_config(**{k: v for k, v in tuned.items()})
+    wsg = gg.workspace(n)
+    e2, l2, k2 = run("batched", args.competitor_steps, 1, True, g=gg, ws=wsg)
+    gi = gg.info()
+    comp["greedy_push"] = {"value": args.competitor_steps * n / e2, "ms_per_step": 1e3 * e2 / args.competitor_steps,
+                           "kernel_ms": k2, "nodes": gi["n_nodes"], "depth": gi["depth"], "build_s": t_gb,
+                           "max_abs_diff_vs_push": float((out - torch.from_numpy(res_main).to(out.device)).abs().max())}
+    print("[bench] greedy_push: %.3f ms/step (graph %d nodes, depth %d, built in %.2f s)"
+          % (comp["greedy_push"]["ms_per_step"], gi["n_nodes"], gi["depth"], t_gb), file=sys.stderr, flush=True)
+    del gg, wsg
 
     tf_meas = measure_tf(g, w, args.tf_count, max(3, args.steps // 2), 1)
     print("[bench] tf: %.3f ms per frame of %d TFs" % (tf_meas["ms_per_frame"], args.tf_count), file=sys.stderr,

@@ -61,8 +61,24 @@ typedef struct {
                               "Reconstruction"); 0: one step per topological level */
     uint32_t max_depth;    /* 0: no cap; else fail with MG_EDEPTH beyond it         */
     uint32_t threads;      /* CPU threads for the build; 0 = all hardware threads   */
-    uint32_t reserved[4];  /* must be 0                                             */
+    uint32_t factorizer;   /* MG_FACTOR_*: how mixtures become interpolations       */
+    uint32_t tau;          /* greedy factorizers: mixtures with more than tau
+                              components go through the global maximum search,
+                              the rest are factorized in scanline order (Sec.
+                              "Implementation Details"); 0 or 1: all global      */
+    uint32_t reserved[2];  /* must be 0                                             */
 } mg_build_opts;
+
+/* Factorizers (mg_build_opts.factorizer). HALVING: each distinct mip-voxel
+ * mixture is split into its first and second half of segments, recursively,
+ * and equal sub-mixtures are shared (exact counts). GREEDY_REDUCTION /
+ * GREEDY_OCCURRENCE: the paper's greedy pair picks (Sec. "Compression", Eq.
+ * greedy2 max-reduction phi2, Eq. greedy1 max-occurrence phi1) over the
+ * distinct mip-voxel mixtures, in exact integer ratios, with the two-stage
+ * cutoff tau; ties between pairs go to the smallest (i, j). */
+#define MG_FACTOR_HALVING 0
+#define MG_FACTOR_GREEDY_REDUCTION 1
+#define MG_FACTOR_GREEDY_OCCURRENCE 2
 
 #define MG_MAX_LEVELS 24
 

@@ -29,7 +29,7 @@ class MGError(RuntimeError):
 class BuildOpts(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_uint32), ("ny", ctypes.c_uint32), ("nz", ctypes.c_uint32),
                 ("defer", ctypes.c_uint32), ("max_depth", ctypes.c_uint32), ("threads", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 4)]
+                ("factorizer", ctypes.c_uint32), ("tau", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 2)]
 
 
 class Info(ctypes.Structure):

@@ -88,6 +88,7 @@ int mg_build(const uint32_t *ids, const mg_build_opts *opts, mg_graph **out)
     for (uint32_t r : opts->reserved)
         if (r) return fail(MG_EINVAL, "mg_build: reserved fields must be 0");
     if (opts->defer > 1) return fail(MG_EINVAL, "mg_build: defer must be 0 or 1");
+    if (opts->factorizer > MG_FACTOR_GREEDY_OCCURRENCE) return fail(MG_EINVAL, "mg_build: unknown factorizer");
     mg_graph *h = new (std::nothrow) mg_graph;
     if (!h) return fail(MG_ENOMEM, "mg_build: out of host memory");
     std::string err;

@@ -581,6 +581,32 @@ int build_graph(const uint32_t *ids, const mg_build_opts *o, Graph *g, std::stri
         }
     }
 
+    if (o->factorizer != MG_FACTOR_HALVING) {
+        // the distinct mixtures the maps hold, in scanline order of first
+        // appearance (level by level, x fastest), refactored greedily
+        const uint32_t S = g->nseg;
+        std::vector<uint32_t> slot(store.size(), kMixed);
+        std::vector<std::vector<std::pair<uint32_t, uint64_t>>> mix;
+        uint32_t *mp = g->maps.data();
+        const uint64_t first_internal = g->lev_off[1], total = g->maps.size();
+        for (uint64_t i = first_internal; i < total; ++i) {
+            const uint32_t n = mp[i];
+            if (n < S || slot[n] != kMixed) continue;
+            slot[n] = uint32_t(mix.size());
+            std::vector<std::pair<uint32_t, uint64_t>> h(store.len(n));
+            for (uint32_t q = 0; q < store.len(n); ++q) h[q] = {store.seg(n)[q], store.cnt(n)[q]};
+            mix.push_back(std::move(h));
+        }
+        RawDag dag;
+        std::vector<uint32_t> root;
+        if (int rc = greedy_factorize(S, mix, o->factorizer, o->tau, &dag, &root, err)) return rc;
+        parallel_chunks(total - first_internal, nt, [&](uint64_t b, uint64_t e, unsigned) {
+            for (uint64_t i = first_internal + b; i < first_internal + e; ++i)
+                if (mp[i] >= S) mp[i] = root[slot[mp[i]]];
+        });
+        return finalize_dag(dag, o->defer != 0, o->max_depth, nt, g, err);
+    }
+
     // ---- ranks, step schedule, numbering by rank, remapped mip voxels
     RawDag dag;
     dag.nseg = g->nseg;

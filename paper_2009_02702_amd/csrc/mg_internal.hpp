@@ -120,6 +120,11 @@ int quantize_graph(const Graph &src, uint32_t bits, uint32_t threads, Graph *dst
 // Ranks, step schedule and rank-sorted IDs of a DAG in creation order; the maps
 // already in g (levels >= 1) are renumbered with the nodes.
 int finalize_dag(const RawDag &d, bool defer, uint32_t max_depth, unsigned nt, Graph *g, std::string *err);
+// Greedy factorization (Sec. "Compression") of mixtures given as sorted
+// (source, count) vectors, in scanline order; appends the sources and the
+// interpolation nodes to d and returns each mixture's node in root. Consumes mix.
+int greedy_factorize(uint32_t nseg, std::vector<std::vector<std::pair<uint32_t, uint64_t>>> &mix, uint32_t strategy,
+                     uint32_t tau, RawDag *d, std::vector<uint32_t> *root, std::string *err);
 // Worker threads for a request (0: all hardware threads).
 unsigned resolve_threads(uint32_t t);
 // Bit-packed graph stream (Table "bitstream"); quantized graphs only.

@@ -15,6 +15,7 @@ from . import _lib
 from ._lib import BuildOpts, Info, LaunchCfg, check
 
 VARIANTS = ("batched", "plain", "naive")
+FACTORIZERS = {"halving": 0, "reduction": 1, "occurrence": 2}
 
 
 def _torch():
@@ -47,8 +48,10 @@ class Graph:
 
     # -------------------------------------------------------------- construction
     @classmethod
-    def build(cls, volume: np.ndarray, defer: bool = True, max_depth: int = 0, threads: int = 0) -> "Graph":
-        """mg_build on a (nz, ny, nx) ID volume; uint8/uint16 volumes are widened to uint32."""
+    def build(cls, volume: np.ndarray, defer: bool = True, max_depth: int = 0, threads: int = 0,
+              factorizer: str = "halving", tau: int = 3) -> "Graph":
+        """mg_build on a (nz, ny, nx) ID volume; uint8/uint16 volumes are widened to uint32.
+        factorizer: "halving", or the paper's greedy "reduction" (phi2) / "occurrence" (phi1) with cutoff tau."""
         vol = np.asarray(volume)
         if vol.ndim != 3:
             raise ValueError("volume must be 3-D (nz, ny, nx)")
@@ -58,7 +61,8 @@ class Graph:
             vol = vol.astype(np.uint32)
         vol = np.ascontiguousarray(vol)
         nz, ny, nx = vol.shape
-        o = BuildOpts(nx=nx, ny=ny, nz=nz, defer=1 if defer else 0, max_depth=max_depth, threads=threads)
+        o = BuildOpts(nx=nx, ny=ny, nz=nz, defer=1 if defer else 0, max_depth=max_depth, threads=threads,
+                      factorizer=FACTORIZERS[factorizer], tau=tau)
         h = ctypes.c_void_p()
         check(_lib.load().mg_build(vol.ctypes.data_as(ctypes.c_void_p), ctypes.byref(o), ctypes.byref(h)))
         return cls(h)

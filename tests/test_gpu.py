@@ -504,6 +504,24 @@ def test_lut_query_needs_the_table():
     assert e.value.code == -4
 
 
+@pytest.mark.parametrize("factorizer,tau", [("reduction", 3), ("occurrence", 3), ("reduction", 0)])
+def test_query_on_greedy_factorized_graphs(factorizer, tau):
+    """Graphs from the paper's greedy factorizer (deeper, different shape) answer every box like O1,
+    through the batched push, the plain kernel and the lookup table."""
+    w = synth.workload(2, dims=(96, 90, 80), segments=120, n_boxes=600)
+    vol = synth.make_volume(w)
+    boxes = synth.make_boxes(w)
+    boxes[0] = [0, 0, 0, 96, 90, 80]
+    g = Graph.build(vol, factorizer=factorizer, tau=tau).upload(0)
+    g.lut_build()
+    ids, vol_c = scan.compact(vol)
+    _, ref = scan.box_counts(vol_c, len(ids), boxes)
+    db = _dev(boxes)
+    l0 = _level0_only(g, db)
+    for v in ("batched", "plain", "lut"):
+        _compare(g.query(db, variant=v).cpu().numpy(), ref, l0, "greedy %s/%s" % (factorizer, v))
+
+
 def test_palette_fetch_is_the_palette_at_the_voxel_node():
     """Paletted fetch (Sec. 'Rendering'): colour of a mip voxel = palette[node of the voxel], bit for bit;
     coordinates outside the level give zeros; the fetched colour is the mean TF over the voxel's support."""
