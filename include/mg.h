@@ -288,6 +288,8 @@ typedef struct {
                                table entries); boxes that overflow every LDS table are answered
                                from global memory, so smaller tables change speed, never
                                results                                                        */
+    uint32_t chunk_small;   /* boxes a small-tier workgroup takes per dequeue from its work
+                               queue: 0 (one) or 1..64                                          */
 } mg_launch_cfg;
 
 int mg_get_launch(const mg_graph *g, mg_launch_cfg *out);

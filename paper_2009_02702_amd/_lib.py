@@ -43,7 +43,7 @@ class LaunchCfg(ctypes.Structure):
     _fields_ = [("unroll_big", ctypes.c_uint32), ("unroll_small", ctypes.c_uint32),
                 ("unroll_naive", ctypes.c_uint32), ("tf_block", ctypes.c_uint32), ("table_big", ctypes.c_uint32),
                 ("table_small", ctypes.c_uint32), ("table_retry", ctypes.c_uint32), ("block_small", ctypes.c_uint32),
-                ("block_big", ctypes.c_uint32)]
+                ("block_big", ctypes.c_uint32), ("chunk_small", ctypes.c_uint32)]
 
 
 _lib = None

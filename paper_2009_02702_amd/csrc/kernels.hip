@@ -49,6 +49,8 @@ constexpr uint32_t kBigLog2 = 16;             // boxes of >= 2^16 cubes go to th
 constexpr uint32_t kHashGlobal = 1u << 16;    // per-worker hash slots in the fallback tables
 constexpr uint32_t kSegLdsMax = 2048;         // sources kept in LDS
 constexpr uint32_t kFallbackWorkers = 128;    // workers of the global-table kernel
+constexpr uint32_t kQueues = 8;                // work queues per tier
+constexpr uint32_t kQueueStride = 64;          // u32 between queue counters (256 bytes)
 constexpr int kUnroll = 4;                     // node-ID loads in flight per lane (plain, fallback)
 constexpr uint32_t kMaxSteps = 64;              // graph depth the step table holds
 
@@ -735,6 +737,8 @@ struct QueryArgs {
                                   // global fallback, [3] next small-tier box, [4] next retry box,
                                   // [5] boxes in list 2, [8] number of big-tier boxes
     uint32_t table_cap;           // LDS hash slots of this launch
+    uint32_t chunk;               // small tier: boxes per dequeue (0: automatic)
+    uint32_t *queues;             // tier work queues: counter of queue j at [j * kQueueStride]
     uint32_t *overflow;           // list 1: boxes whose tier table overflowed
     uint32_t *overflow2;          // list 2: boxes whose retry table overflowed too
     uint32_t *ovf_out;            // where this launch reports overflowed boxes (nullptr: mark NaN)
@@ -1025,12 +1029,31 @@ __global__ __launch_bounds__(BLOCK) void query_tier_kernel(QueryArgs A)
     clear_lds_state<BLOCK, SPARSE, ERR>(st, A.gv.nseg);
     const uint32_t split = ld(&A.counters[8]);
     const uint32_t begin = BIG ? 0u : split, end = BIG ? split : A.n;
+    // Work queues: a single counter that every workgroup increments serialises
+    // at one L2 atomic unit (about 12 ns per box), so the tier's positions of
+    // the largest-first order are dealt to kQueues interleaved queues (queue j:
+    // positions begin + j, begin + j + kQueues, ...), each with its own counter
+    // on its own 256-byte line; workgroup b serves queue b mod kQueues. Each
+    // queue is still largest-first. A dequeue takes `chunk` positions (small
+    // tier only; 1 by default).
+    // (fewer queues when the grid is smaller, so that every queue has a workgroup)
+    const uint32_t nq = min(kQueues, gridDim.x);
+    const uint32_t qn = blockIdx.x % nq;
+    uint32_t *const qc = A.queues + qn * kQueueStride + (BIG ? 0u : 16u);
+    const uint32_t chunk = BIG ? 1u : (A.chunk ? A.chunk : 1u);
     for (;;) {
-        if (threadIdx.x == 0) sh.q = begin + atomicAdd(&A.counters[BIG ? 0 : 3], 1u);
+        if (threadIdx.x == 0) sh.q = atomicAdd(qc, chunk);
         __syncthreads();
-        const uint32_t k = sh.q;
-        if (k >= end) break;  // uniform
-        run_query<BLOCK, UNROLL, SPARSE, ERR>(A, sh, st, A.order[k], A.ovf_out != nullptr);
+        const uint32_t i0 = sh.q;
+        if (i0 >= end) break;  // uniform; keeps begin + qn + i0 * nq below 2^32
+        const uint32_t k0 = begin + qn + i0 * nq;
+        if (k0 >= end) break;  // uniform
+        // run_query ends with a barrier, so thread 0 rewrites sh.q only after every thread read it
+        for (uint32_t i = 0; i < chunk; ++i) {
+            const uint32_t k = k0 + i * nq;
+            if (k >= end) break;
+            run_query<BLOCK, UNROLL, SPARSE, ERR>(A, sh, st, A.order[k], A.ovf_out != nullptr);
+        }
     }
 }
 
@@ -1362,7 +1385,8 @@ LevelTable level_table(const Graph &g)
 // ---------------------------------------------------------------- workspace layout
 
 struct Workspace {
-    uint32_t *counters;   // 64 u32: [0] next, [1] overflow count, [2] next fallback
+    uint32_t *counters;   // 64 u32
+    uint32_t *queues;     // kQueues * kQueueStride u32: [0] next, [1] overflow count, [2] next fallback
     uint32_t *buckets;    // 64 u32
     uint32_t *bucket_of;  // [max_boxes]
     uint32_t *order;      // [max_boxes]
@@ -1391,6 +1415,7 @@ Workspace carve(const Graph &g, char *base, uint32_t max_boxes)
     // fixed-size part first, so that its layout does not depend on max_boxes
     w.counters = reinterpret_cast<uint32_t *>(take(64 * 4));
     w.buckets = reinterpret_cast<uint32_t *>(take(64 * 4));
+    w.queues = reinterpret_cast<uint32_t *>(take(uint64_t(kQueues) * kQueueStride * 4));
     const uint64_t hs = uint64_t(kFallbackWorkers) * kHashGlobal;
     w.g_keys = reinterpret_cast<uint32_t *>(take(hs * 4));
     w.g_cnt = reinterpret_cast<uint32_t *>(take(hs * 4));
@@ -1713,6 +1738,8 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
         (rc = occupancy(d, reinterpret_cast<const void *>(kplain), kBlock, dyn_plain, &occ_plain, err)))
         return rc;
     hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, w.counters, 64u);
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(256), 0, s, w.queues, kQueues * kQueueStride);
+    A.queues = w.queues;
     if (A.sp_total) hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, A.sp_total, 1u);
     if (variant == kQueryBatched || variant == kQueryLut) {
         hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, w.buckets, 64u);
@@ -1729,6 +1756,7 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
         hipLaunchKernelGGL(kbig, dim3(wbig), dim3(bbig), dyn_big, s, A);
         HIP_TRY(hipGetLastError());
         A.table_cap = cap_small;
+        A.chunk = d.cfg.chunk_small;
         hipLaunchKernelGGL(ksmall, dim3(wsmall), dim3(bsmall), dyn_small, s, A);
         HIP_TRY(hipGetLastError());
     } else {
@@ -1924,6 +1952,10 @@ int dev_propagate_tf(Graph *g, const uint8_t *tf, uint32_t T, float *out, void *
 
 int dev_set_launch(Graph *g, const mg_launch_cfg *cfg, std::string *err)
 {
+    if (cfg->chunk_small > 64) {
+        *err = "mg_set_launch: chunk_small must be in [0, 64]";
+        return MG_EINVAL;
+    }
     if (!(cfg->block_small == 0 || cfg->block_small == 128 || cfg->block_small == 256) ||
         !(cfg->block_big == 0 || cfg->block_big == 256 || cfg->block_big == 512)) {
         *err = "mg_set_launch: block_small must be 0, 128 or 256 and block_big 0, 256 or 512";
@@ -2005,6 +2037,14 @@ int dev_autotune(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *
             if ((rc = time_variant(kQueryBatched, &ms))) break;
             if (ms < best) best = ms, best_cfg.table_small = t, best_cfg.block_small = bsm;
         }
+    for (uint32_t c : {0u, 2u, 4u}) {
+        if (rc) break;
+        g->dev.cfg = best_cfg;
+        g->dev.cfg.chunk_small = c;
+        float ms = 0;
+        if ((rc = time_variant(kQueryBatched, &ms))) break;
+        if (ms < best) best = ms, best_cfg.chunk_small = c;
+    }
     float best_naive = 1e30f;
     for (uint32_t u : us) {
         if (rc) break;

@@ -312,7 +312,8 @@ class Graph:
         check(self._lib.mg_get_launch(self._h, ctypes.byref(c)))
         return {"unroll_big": c.unroll_big, "unroll_small": c.unroll_small, "unroll_naive": c.unroll_naive,
                 "tf_block": c.tf_block, "table_big": c.table_big, "table_small": c.table_small,
-                "table_retry": c.table_retry, "block_small": c.block_small, "block_big": c.block_big}
+                "table_retry": c.table_retry, "block_small": c.block_small, "block_big": c.block_big,
+                "chunk_small": c.chunk_small}
 
     def set_launch_config(self, **kw) -> None:
         cur = self.launch_config()

@@ -139,6 +139,10 @@ class _Slot:
             with torch.cuda.graph(graph, stream=self.stream):
                 g.query(self.d_boxes[:c], out=self.d_out[:c], workspace=self.ws, stream=self.stream)
             self.graphs[c] = graph
+        # the first replay of a captured graph pays its one-time upload: do it here, not while serving
+        with torch.cuda.stream(self.stream):
+            for c in self.classes:
+                self.graphs[c].replay()
         self.stream.synchronize()
 
     def size_class(self, k: int) -> int:

@@ -294,7 +294,14 @@ def test_autotune_and_launch_validation():
         g.set_launch_config(block_small=192)
     with pytest.raises(MGError):
         g.set_launch_config(block_big=128)
+    with pytest.raises(MGError):
+        g.set_launch_config(chunk_small=65)
     assert g.launch_config() == cfg
+    # boxes per dequeue of the small tier: a scheduling knob, never a change of results
+    for c in (1, 3, 64, 0):
+        g.set_launch_config(chunk_small=c)
+        _compare(g.query(db).cpu().numpy(), ref, None, "chunk_small %d" % c)
+    g.set_launch_config(**cfg)
 
 
 def test_overflow_retry_and_global_fallback_paths():
