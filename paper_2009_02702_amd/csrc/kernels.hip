@@ -522,8 +522,9 @@ __device__ inline bool stream_slab(const uint32_t *__restrict__ p, uint32_t e0, 
 // rb * rows + u * 64/2^ltx + ly of slow slice k2, pp = t0 * 2^ltx + lx, where
 // `odd` is the parity of the slab's first element along the fast axis (rows are
 // padded to an even length, so every pair lies inside its row). Elements outside
-// the slab are handed to `use(lo, hi)` as kEmpty. Block walk, row-tile bounds
-// and software pipeline as in stream_slab.
+// the slab are handed to `use(lo, hi)` as kEmpty. Block walk and row-tile
+// bounds as in stream_slab; the software pipeline keeps three blocks in flight
+// (level 0 is most of the cubes, and its 32-bit words leave registers to spare).
 template <int UNROLL, int WAVES, class Use>
 __device__ inline void stream_pairs(const uint16_t *__restrict__ p, uint32_t e0, uint32_t e1, uint32_t e2,
                                     uint32_t s1, uint32_t s2, uint32_t odd, uint32_t ltx, uint32_t first, Use use)
@@ -565,25 +566,37 @@ __device__ inline void stream_pairs(const uint16_t *__restrict__ p, uint32_t e0,
             v[u] = *reinterpret_cast<const uint32_t *>(row + (uint32_t(u) < n_ok ? lane_bytes : 0u));
         }
     };
+    // three blocks in flight: this wave's current block v, its next block w and the one
+    // after, x, which is loaded before v is consumed (so v waits only for its own loads).
+    // A block past the wave's last one is replaced by the block before it (valid
+    // addresses, never consumed).
+    auto advance = [&](uint32_t &bt0, uint32_t &brb, uint32_t &bk2) {
+        bt0 += WAVES;
+        while (bt0 >= n_t0) {
+            bt0 -= n_t0;
+            if (++brb == n_rb) brb = 0, ++bk2;
+        }
+    };
     uint32_t v[UNROLL], n_u, n_lo, n_hi;
     load(v, n_u, n_lo, n_hi, t0, rb, k2);
+    uint32_t t1 = t0, rb1 = rb, k21 = k2;
+    if (fb + WAVES < n_blk) advance(t1, rb1, k21);
+    uint32_t w[UNROLL], w_n_u, w_n_lo, w_n_hi;
+    load(w, w_n_u, w_n_lo, w_n_hi, t1, rb1, k21);
     for (; fb < n_blk; fb += WAVES) {
-        uint32_t nt0 = t0 + WAVES, nrb = rb, nk2 = k2;
-        while (nt0 >= n_t0) {
-            nt0 -= n_t0;
-            if (++nrb == n_rb) nrb = 0, ++nk2;
-        }
-        if (fb + WAVES >= n_blk) nt0 = t0, nrb = rb, nk2 = k2;
-        uint32_t w[UNROLL], w_n_u, w_n_lo, w_n_hi;
-        load(w, w_n_u, w_n_lo, w_n_hi, nt0, nrb, nk2);
+        uint32_t t2 = t1, rb2 = rb1, k22 = k21;
+        if (fb + 2 * WAVES < n_blk) advance(t2, rb2, k22);
+        uint32_t x[UNROLL], x_n_u, x_n_lo, x_n_hi;
+        load(x, x_n_u, x_n_lo, x_n_hi, t2, rb2, k22);
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
             if (uint32_t(u) < n_u)
                 use(uint32_t(u) < n_lo ? (v[u] & 0xFFFFu) : kEmpty, uint32_t(u) < n_hi ? (v[u] >> 16) : kEmpty);
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) v[u] = w[u];
+        for (int u = 0; u < UNROLL; ++u) v[u] = w[u], w[u] = x[u];
         n_u = w_n_u, n_lo = w_n_lo, n_hi = w_n_hi;
-        t0 = nt0, rb = nrb, k2 = nk2;
+        w_n_u = x_n_u, w_n_lo = x_n_lo, w_n_hi = x_n_hi;
+        t1 = t2, rb1 = rb2, k21 = k22;
     }
 }
 
