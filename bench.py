@@ -183,7 +183,7 @@ def main():
         return
     if args.mode == "query":
         # same launch selection as the full run (untimed), so profilers see the same kernels
-        tuned = g.autotune(dboxes, out=out, reps=3, workspace=ws)
+        tuned = g.autotune(dboxes, out=out, reps=5, workspace=ws)
         print("[bench] autotuned %s" % (tuned,), file=sys.stderr, flush=True)
         for _ in range(args.warmup):
             g.query(dboxes, out=out, workspace=ws)
@@ -199,7 +199,7 @@ def main():
 
     # launch configuration picked by the autotuner on this batch (not timed)
     t0 = time.perf_counter()
-    tuned = g.autotune(dboxes, out=out, reps=3, workspace=ws)
+    tuned = g.autotune(dboxes, out=out, reps=5, workspace=ws)
     t_tune = time.perf_counter() - t0
     print("[bench] autotuned %s in %.2f s" % (tuned, t_tune), file=sys.stderr, flush=True)
 
