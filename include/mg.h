@@ -174,6 +174,10 @@ int mg_workspace_init(mg_graph *g, void *d_work, uint64_t work_bytes, void *stre
  *            node is a source are exact integers; mass pushed through the DAG
  *            is accumulated in fp32 with compensated (two-sum) updates.
  *   d_work   workspace of mg_workspace_bytes(g, n) bytes, initialised once.
+ * Boxes whose nodes overflow the per-box LDS tables are redone with a larger
+ * LDS table, then in global-memory tables that hold every node of graphs of
+ * up to 50,331,647 nodes; only on larger graphs can a box still overflow,
+ * and its row is then all NaN.
  */
 int mg_query_boxes(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *d_out,
                    void *d_work, uint64_t work_bytes, void *stream);
@@ -199,8 +203,8 @@ int mg_query_boxes_stats(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float
  *   d_total  device uint32: reset by the call, then the entries produced. If
  *            it exceeds `capacity` after the stream completes, entries at or
  *            beyond `capacity` were not written (call again with more room).
- * A box that no table could hold (never seen in the tested workloads) gets
- * 0xFFFFFFFF in both index fields. */
+ * A box that no table could hold (possible only on graphs of more than
+ * 50,331,647 nodes) gets 0xFFFFFFFF in both index fields. */
 int mg_query_boxes_sparse(mg_graph *g, const uint32_t *d_boxes, uint32_t n, uint32_t *d_index,
                           uint32_t *d_seg, float *d_val, uint32_t capacity, uint32_t *d_total,
                           void *d_work, uint64_t work_bytes, void *stream);

@@ -46,7 +46,7 @@ constexpr uint32_t kHashSmallSparse = 2048;   // small-box tier, sources as tabl
 constexpr uint32_t kHashBigSparse = 4096;     // big-box tier, sources as table entries
 constexpr uint32_t kHashRetry = 8192;         // boxes that overflowed a tier table
 constexpr uint32_t kBigLog2 = 16;             // boxes of >= 2^16 cubes go to the big tier
-constexpr uint32_t kHashGlobal = 1u << 16;    // per-worker hash slots in the fallback tables
+constexpr uint32_t kHashGlobal = 1u << 16;    // fewest per-worker hash slots in the fallback tables
 constexpr uint32_t kSegLdsMax = 2048;         // sources kept in LDS
 constexpr uint32_t kFallbackWorkers = 128;    // workers of the global-table kernel
 constexpr uint32_t kQueues = 8;                // work queues per tier
@@ -751,6 +751,7 @@ struct QueryArgs {
                                   // [5] boxes in list 2, [8] number of big-tier boxes
     uint32_t table_cap;           // LDS hash slots of this launch
     uint32_t chunk;               // small tier: boxes per dequeue (0: automatic)
+    uint32_t g_slots;             // hash slots of each fallback worker's global table
     uint32_t *queues;             // tier work queues: counter of queue j at [j * kQueueStride]
     uint32_t *overflow;           // list 1: boxes whose tier table overflowed
     uint32_t *overflow2;          // list 2: boxes whose retry table overflowed too
@@ -1099,13 +1100,14 @@ __global__ __launch_bounds__(kBlock) void query_fallback_kernel(QueryArgs A)
     __shared__ QueryShared sh;
     QueryState st;
     const uint64_t w = blockIdx.x;
-    st.keys = A.g_keys + w * kHashGlobal;
-    st.cnt = A.g_cnt + w * kHashGlobal;
-    st.hi = A.g_hi + w * kHashGlobal;
-    st.lo = A.g_lo + w * kHashGlobal;
-    st.used = A.g_used + w * kHashGlobal;
-    st.cap = kHashGlobal;
-    st.limit = kHashGlobal / 4 * 3;
+    const uint64_t gs = A.g_slots;
+    st.keys = A.g_keys + w * gs;
+    st.cnt = A.g_cnt + w * gs;
+    st.hi = A.g_hi + w * gs;
+    st.lo = A.g_lo + w * gs;
+    st.used = A.g_used + w * gs;
+    st.cap = A.g_slots;
+    st.limit = A.g_slots / 4 * 3;
     st.n_used = &sh.n_used;
     st.flags = &sh.flags;
     st.max_key = &sh.max_key;
@@ -1415,6 +1417,22 @@ struct Workspace {
 
 inline uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
 
+// Global fallback tables: each worker's table holds every node of the graph below
+// its 3/4 load limit (a box touches a node at most once), so no box can overflow
+// it, with at least 2^16 and at most 2^26 slots; the workers share a budget of
+// 128 x 2^16 slots (fewer workers for larger graphs, at least one).
+inline uint32_t fallback_slots(const Graph &g)
+{
+    const uint64_t need = uint64_t(g.n_nodes) * 4 / 3 + 2;
+    uint64_t cap = kHashGlobal;
+    while (cap < need && cap < (uint64_t(1) << 26)) cap <<= 1;
+    return uint32_t(cap);
+}
+inline uint32_t fallback_workers(const Graph &g)
+{
+    return std::max<uint32_t>(1u, uint32_t(uint64_t(kFallbackWorkers) * kHashGlobal / fallback_slots(g)));
+}
+
 // Carves the workspace; with base == nullptr only computes the size.
 Workspace carve(const Graph &g, char *base, uint32_t max_boxes)
 {
@@ -1429,13 +1447,13 @@ Workspace carve(const Graph &g, char *base, uint32_t max_boxes)
     w.counters = reinterpret_cast<uint32_t *>(take(64 * 4));
     w.buckets = reinterpret_cast<uint32_t *>(take(64 * 4));
     w.queues = reinterpret_cast<uint32_t *>(take(uint64_t(kQueues) * kQueueStride * 4));
-    const uint64_t hs = uint64_t(kFallbackWorkers) * kHashGlobal;
+    const uint64_t hs = uint64_t(fallback_workers(g)) * fallback_slots(g);
     w.g_keys = reinterpret_cast<uint32_t *>(take(hs * 4));
     w.g_cnt = reinterpret_cast<uint32_t *>(take(hs * 4));
     w.g_used = reinterpret_cast<uint32_t *>(take(hs * 4));
     w.g_hi = reinterpret_cast<float *>(take(hs * 4));
     w.g_lo = reinterpret_cast<float *>(take(hs * 4));
-    const uint64_t ss = uint64_t(kFallbackWorkers) * g.nseg;
+    const uint64_t ss = uint64_t(fallback_workers(g)) * g.nseg;
     w.g_seg_cnt = reinterpret_cast<uint32_t *>(take(ss * 4));
     w.g_seg_hi = reinterpret_cast<float *>(take(ss * 4));
     w.g_seg_lo = reinterpret_cast<float *>(take(ss * 4));
@@ -1711,12 +1729,12 @@ int dev_workspace_init(Graph *g, void *work, uint64_t bytes, void *stream, std::
         return MG_EINVAL;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const uint64_t hs = uint64_t(kFallbackWorkers) * kHashGlobal;
+    const uint64_t hs = uint64_t(fallback_workers(*g)) * fallback_slots(*g);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, w.g_keys, hs, kEmpty);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, w.g_cnt, hs, 0u);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_hi), hs, 0u);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_lo), hs, 0u);
-    const uint64_t ss = uint64_t(kFallbackWorkers) * g->nseg;
+    const uint64_t ss = uint64_t(fallback_workers(*g)) * g->nseg;
     hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, w.g_seg_cnt, ss, 0u);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_seg_hi), ss, 0u);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_seg_lo), ss, 0u);
@@ -1801,7 +1819,8 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
     A.ovf_out = nullptr;
     A.stats_tag = 0x80000000u;
     const QueryKernel kfallback = query_fallback_kernel<SPARSE, ERR>;
-    hipLaunchKernelGGL(kfallback, dim3(kFallbackWorkers), dim3(kBlock),
+    A.g_slots = fallback_slots(*g);
+    hipLaunchKernelGGL(kfallback, dim3(fallback_workers(*g)), dim3(kBlock),
                        6u * L * uint32_t(sizeof(Slab)), s, A);
     HIP_TRY(hipGetLastError());
     // the timed region: every kernel that answers boxes (tiers or plain, retry, fallback)

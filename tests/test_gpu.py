@@ -368,6 +368,37 @@ def test_query_many_segments_dense_and_sparse():
     _compare(dense, ref, l0, "sparse output")
 
 
+def test_query_more_sources_than_16_bit_ids():
+    """70,001 sources (more than a 16-bit ID holds): no 16-bit level-0 copy, sources are table
+    entries, depth 17; dense rows and sparse entries match the oracle, the naive scan (per-source
+    LDS counters) refuses with MG_ELIMIT."""
+    Z, Y, X = 48, 64, 64
+    blocks = np.arange(Z * Y * (X // 2)).reshape(Z, Y, X // 2)
+    vol = np.repeat((blocks * 7919) % 70001, 2, axis=2).astype(np.uint32)
+    g = Graph.build(vol).upload(0)
+    S = g.info()["nseg"]
+    assert S == 70001
+    rng = np.random.default_rng(11)
+    boxes = np.concatenate([rng.integers(0, 40, size=(300, 3)), rng.integers(1, 30, size=(300, 3))],
+                           axis=1).astype(np.uint32)
+    boxes[0] = [0, 0, 0, X, Y, Z]
+    boxes[1] = [5, 6, 7, 1, 1, 1]
+    ids, vol_c = scan.compact(vol)
+    _, ref = scan.box_counts(vol_c, S, boxes)
+    db = _dev(boxes)
+    l0 = _level0_only(g, db)
+    for v in ("batched", "plain"):
+        _compare(g.query(db, variant=v).cpu().numpy(), ref, l0, "70001 sources " + v)
+    nnz = int((ref > 0).sum())
+    index, seg, val, total = g.query_sparse(db, capacity=nnz)
+    assert int(total.item()) == nnz
+    dense = _sparse_to_dense(index.cpu().numpy(), seg.cpu().numpy(), val.cpu().numpy(), len(boxes), S)
+    _compare(dense, ref, l0, "70001 sources sparse")
+    with pytest.raises(MGError) as e:
+        g.query(db, variant="naive")
+    assert e.value.code == -8
+
+
 def test_query_sparse_output_small_segment_count_and_truncation():
     w = synth.workload(2, dims=(90, 80, 70), segments=120, n_boxes=700)
     vol = synth.make_volume(w)
