@@ -135,3 +135,20 @@ def test_greedy_build_options():
     assert a.info()["n_nodes"] == b.info()["n_nodes"]
     for k in ("child_a", "child_b", "wnum", "wden"):
         assert np.array_equal(a.export_dag()[k], b.export_dag()[k])
+
+
+@pytest.mark.parametrize("factorizer", ["halving", "reduction", "occurrence"])
+def test_degenerate_volumes_build_quantize_and_round_trip(factorizer):
+    """One voxel, one segment, two alternating segments, a thin random column: every factorizer
+    builds them; quantized copies survive the bit-packed stream."""
+    vols = [np.array([[[7]]], dtype=np.uint32), np.full((4, 4, 4), 5, dtype=np.uint32),
+            (np.arange(105).reshape(3, 5, 7) % 2).astype(np.uint32),
+            np.random.default_rng(1).integers(0, 5, size=(9, 1, 1)).astype(np.uint32)]
+    for vol in vols:
+        for tau in (0, 3, 100):
+            g = Graph.build(vol, factorizer=factorizer, tau=tau)
+            ids, vol_c = scan.compact(vol)
+            assert g.info()["nseg"] == len(ids)
+            q = g.quantize(4)
+            u = Graph.unpack(q.pack())
+            assert u.info()["n_nodes"] == q.info()["n_nodes"] and u.pack() == q.pack()
