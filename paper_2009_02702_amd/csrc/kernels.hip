@@ -1420,7 +1420,7 @@ inline uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
 // Global fallback tables: each worker's table holds every node of the graph below
 // its 3/4 load limit (a box touches a node at most once), so no box can overflow
 // it, with at least 2^16 and at most 2^26 slots; the workers share a budget of
-// 128 x 2^16 slots (fewer workers for larger graphs, at least one).
+// 128 x 2^16 slots (fewer workers for larger graphs, at least 16).
 inline uint32_t fallback_slots(const Graph &g)
 {
     const uint64_t need = uint64_t(g.n_nodes) * 4 / 3 + 2;
@@ -1430,7 +1430,7 @@ inline uint32_t fallback_slots(const Graph &g)
 }
 inline uint32_t fallback_workers(const Graph &g)
 {
-    return std::max<uint32_t>(1u, uint32_t(uint64_t(kFallbackWorkers) * kHashGlobal / fallback_slots(g)));
+    return std::max<uint32_t>(16u, uint32_t(uint64_t(kFallbackWorkers) * kHashGlobal / fallback_slots(g)));
 }
 
 // Carves the workspace; with base == nullptr only computes the size.

@@ -197,6 +197,45 @@ def test_query_full_config2_sampled():
         _compare(o, ref, None, "cfg2 sample " + v)
 
 
+def test_query_full_config4_million_boxes_sparse():
+    """The capsule volume at full size (614x961x600, 15,917 segments, 5.9M nodes) with its 10^6 boxes
+    (0.1% full-volume, 1% single-voxel) in one sparse-output launch: every box's entries sum to 1,
+    single-voxel boxes are one-hot and exact, and O1 on a sample (including full-volume boxes)."""
+    w = synth.workload(4)
+    vol = synth.make_volume(w)
+    boxes = synth.make_boxes(w)
+    assert len(boxes) == 1_000_000
+    g = Graph.build(vol).upload(0)
+    S = g.info()["nseg"]
+    db = _dev(boxes)
+    cap = 300_000_000   # about 215 non-zero segments per box on average
+    index, seg, val, total = g.query_sparse(db, capacity=cap)
+    torch.cuda.synchronize()
+    nnz = int(total.item())
+    assert 0 < nnz <= cap
+    idx = index.long()
+    assert bool((idx[:, 0] >= 0).all()) and bool((idx[:, 0] + idx[:, 1] <= nnz).all())
+    cs = torch.cat([torch.zeros(1, dtype=torch.float64, device=val.device), torch.cumsum(val[:nnz].double(), 0)])
+    sums = (cs[idx[:, 0] + idx[:, 1]] - cs[idx[:, 0]]).cpu().numpy()
+    cnt = idx[:, 1].cpu().numpy()
+    nonempty = (boxes[:, 3:] > 0).all(axis=1)
+    assert np.abs(sums[nonempty] - 1.0).max() < 1e-5
+    one = nonempty & (boxes[:, 3:] == 1).all(axis=1)
+    first = val[idx[:, 0].clamp(max=nnz - 1)].cpu().numpy()
+    assert one.sum() > 5000 and (cnt[one] == 1).all() and (first[one] == 1.0).all()
+    full = (boxes[:, 3:] == np.array(w.dims, dtype=np.uint32)).all(axis=1)
+    rng = np.random.default_rng(4)
+    sample = np.unique(np.concatenate([np.nonzero(full)[0][:2], rng.choice(len(boxes), 150, replace=False)]))
+    ids, vol_c = scan.compact(vol)
+    _, ref = scan.box_counts(vol_c, len(ids), boxes[sample])
+    ih = idx.cpu().numpy()
+    dense = np.zeros((len(sample), S))
+    for r, q in enumerate(sample):
+        a, k = int(ih[q, 0]), int(ih[q, 1])
+        dense[r, seg[a:a + k].cpu().numpy()] = val[a:a + k].cpu().numpy()
+    _compare(dense, ref, None, "cfg4 sample")
+
+
 # ------------------------------------------------------------------ TF propagation (a8)
 
 def test_tf_matches_oracle_every_mip_voxel():
