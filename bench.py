@@ -295,7 +295,10 @@ def main():
                 "kernel_ms": kern_ms,
                 "alg_bytes_per_launch": alg_bytes,
                 "alg_bytes_formula": "sum over boxes of 24 + 2*level-0 cubes + 4*higher-level cubes + "
-                                     "12*graph nodes touched + 4*S (dense output)"}
+                                     "12*graph nodes touched + 4*S (dense output)",
+                # the node triples (12 B x nodes touched) may be served from L2 / MALL rather than HBM
+                "frac_excl_node_triples": (alg_bytes - 12.0 * float(touched.sum())) / (kern_ms * 1e-3) / 1e9
+                / HBM_PEAK_GBS}
 
     cpu = None
     max_rel = None
