@@ -130,7 +130,7 @@ def main():
                     help="full mode: offered rate of the short serving leg (per-request p50/p99); 0 skips it")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: this library has no multi-GPU path "
               "(queries shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
         sys.exit(2)
 

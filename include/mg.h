@@ -51,7 +51,7 @@ extern "C" {
 #define MG_EDEPTH (-5)    /* graph deeper than mg_build_opts.max_depth             */
 #define MG_EIO (-6)       /* file error in mg_save / mg_load                        */
 #define MG_EFORMAT (-7)   /* corrupt or incompatible graph file or graph arrays    */
-#define MG_ELIMIT (-8)    /* a size beyond what this build supports (message says) */
+#define MG_ELIMIT (-8)    /* a size beyond what this library supports (message says) */
 
 typedef struct mg_graph mg_graph; /* opaque; owned by the library, freed by mg_free */
 
