@@ -340,6 +340,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "max_rel_err_vs_oracle": max_rel,
+        "oracle_checked_boxes": (m if not args.no_cpu_baseline else 0),
         "serving": serving,
         "competitors": comp,
         "tf_propagation": tf_meas,
