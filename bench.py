@@ -354,8 +354,8 @@ def main():
                  "nodes_touched_max": int(touched.max()), "boxes_via_fallback": int(fallback.sum()),
                  "boxes_via_retry": int(retried.sum()),
                  "cubes_share_via_fallback": float(cubes[fallback].sum() / max(cubes.sum(), 1.0)),
-                 "touched_max_big_tier": int(touched[cubes >= 65536].max(initial=0)),
-                 "touched_max_small_tier": int(touched[cubes < 65536].max(initial=0))},
+                 "touched_max_big_tier": int(touched[cubes >= 16384].max(initial=0)),
+                 "touched_max_small_tier": int(touched[cubes < 16384].max(initial=0))},
         "paper_context": "178.95x footprint assembly vs 10-core naive CPU range query (Polymer 256^3, "
                          "i9-9820X; Table 'query'); other hardware and data, not a target",
     }

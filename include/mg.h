@@ -278,7 +278,7 @@ int mg_query_boxes_err(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *
 /* Launch configuration of the GPU kernels (per graph, after mg_upload).
  * Defaults: 16, 8, 16, 256, then zeros (sizes chosen per mode). */
 typedef struct {
-    uint32_t unroll_big;    /* node-ID loads in flight per lane, boxes of >= 2^16 cubes: 4, 8 or 16 */
+    uint32_t unroll_big;    /* node-ID loads in flight per lane, boxes of >= 2^14 cubes: 4, 8 or 16 */
     uint32_t unroll_small;  /* the same for smaller boxes: 4, 8 or 16 */
     uint32_t unroll_naive;  /* level-0 loads in flight per lane of the naive scan: 4, 8 or 16 */
     uint32_t tf_block;      /* threads per workgroup of the propagation kernel: 64, 128, 256, 512, 1024 */

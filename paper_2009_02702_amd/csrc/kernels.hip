@@ -45,7 +45,7 @@ constexpr uint32_t kHashBig = 2048;           // big-box tier (per-source arrays
 constexpr uint32_t kHashSmallSparse = 2048;   // small-box tier, sources as table entries
 constexpr uint32_t kHashBigSparse = 4096;     // big-box tier, sources as table entries
 constexpr uint32_t kHashRetry = 8192;         // boxes that overflowed a tier table
-constexpr uint32_t kBigLog2 = 16;             // boxes of >= 2^16 cubes go to the big tier
+constexpr uint32_t kBigLog2 = 14;             // boxes of >= 2^14 cubes go to the big tier
 constexpr uint32_t kHashGlobal = 1u << 16;    // fewest per-worker hash slots in the fallback tables
 constexpr uint32_t kSegLdsMax = 2048;         // sources kept in LDS
 constexpr uint32_t kFallbackWorkers = 128;    // workers of the global-table kernel
