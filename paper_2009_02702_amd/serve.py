@@ -139,10 +139,13 @@ class _Slot:
             with torch.cuda.graph(graph, stream=self.stream):
                 g.query(self.d_boxes[:c], out=self.d_out[:c], workspace=self.ws, stream=self.stream)
             self.graphs[c] = graph
-        # the first replay of a captured graph pays its one-time upload: do it here, not while serving
+        # the first replay of a captured graph pays its one-time upload, and the first launch of the
+        # propagation kernels their loading: do both here, not while serving
         with torch.cuda.stream(self.stream):
             for c in self.classes:
                 self.graphs[c].replay()
+            if self.max_tf:
+                g.propagate_tf(self.d_tf[:1], out=self.d_pal[:1], stream=self.stream)
         self.stream.synchronize()
 
     def size_class(self, k: int) -> int:
