@@ -12,9 +12,21 @@ inputs already resident in HBM. Prints one JSON line.
 Also measured on the same inputs: the plain per-box kernel and the naive
 level-0 range scan (GPU competitors), the dominant kernel's HIP-event time for
 the roofline, and the CPU oracle (brute-force scan) on a bounded sample of the
-boxes, whose results also give the maximum relative error of the GPU output.
+boxes (all host cores and one thread), whose results also give the maximum
+relative error of the GPU output.
+
+Further legs, each on its own workload and graph (--legs):
+  aniso   2048x2048x300 Voronoi volume, 1,182 cells (z stretched by 7): its
+          50,000 boxes and frames of 8 random RGBA8 transfer functions
+  capsule 614x961x600 volume of 15,917 capsules: 10^6 boxes (0.1% the whole
+          volume, 1% single voxels) in one sparse-output launch
+  stream  1178x1125x789 Voronoi volume, 353 cells: Poisson arrivals at 5k,
+          20k, 50k, 100k and 200k requests/s through the continuous-batching
+          server, 10% of requests with one transfer function; per-request
+          p50/p99 latency (completion - arrival)
 """
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -72,22 +84,26 @@ def measure_tf(g, w, T, steps, warmup):
     g.timing(False)
     kern_ms = ms / max(k, 1)
     internal = N - S
-    # per internal node: its 16-B schedule entry, T pairs of 16-B gathers and one 16-B store
-    alg = internal * (16.0 + 48.0 * T)
+    # the method's bytes per frame: per internal node its (a, b, w) triple (12 B), its T colours
+    # written (16 B each) and read once by a successor (16 B each); per source its T RGBA8 colours
+    alg = internal * (12.0 + 32.0 * T) + S * 4.0 * T
     achieved = alg / (kern_ms * 1e-3) / 1e9
+    traffic = read_traffic("tf_step_kernel", w.name, alg)
     return {"frames_per_s": steps / el, "ms_per_frame": 1e3 * el / steps, "tfs_per_frame": T,
             "nodes": N, "depth": D, "steps_launched": D,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "tf_step_kernel x depth",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                         "kernel": "tf_sources_kernel + tf_step_kernel x steps (one frame, timed together)",
                          "kernel_ms": kern_ms, "alg_bytes_per_launch": alg,
-                         "alg_bytes_formula": "internal nodes x (16 + 48 T)"}}
+                         "alg_bytes_formula": "internal nodes x (12 + 32 T) + sources x 4 T"}}
 
 
-def measure_serve(g, w, qps_list, seconds):
-    """Poisson arrivals through the continuous-batching server; p50/p99 latency and achieved rate."""
+def measure_serve(g, w, qps_list, seconds, trace_dir=None):
+    """Poisson arrivals through the continuous-batching server; per-request p50/p99 latency and
+    achieved rate per offered rate. trace_dir: also write each rate's per-batch trace there."""
     import numpy as np
     from paper_2009_02702_amd import synth
-    from paper_2009_02702_amd.serve import Server
+    from paper_2009_02702_amd.serve import TRACE_FIELDS, Server
     S = g.info()["nseg"]
     srv = Server(g, slots=4, max_batch=4096, max_tf=64)
     out = []
@@ -103,8 +119,150 @@ def measure_serve(g, w, qps_list, seconds):
         r = st.summary()
         r["offered_qps"] = qps
         out.append(r)
+        if trace_dir:
+            os.makedirs(trace_dir, exist_ok=True)
+            np.savetxt(os.path.join(trace_dir, "serve_trace_%s_%d.txt" % (w.name, int(qps))), st.trace,
+                       header=" ".join(TRACE_FIELDS), fmt="%.6f")
         print("[bench] serve %s" % r, file=sys.stderr, flush=True)
     return out
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_rate(vol, boxes, seconds, threads, chunk):
+    """The CPU oracle (O1) on consecutive chunks of the box list until about `seconds` have
+    passed: (boxes/s, boxes done, elapsed, fractions of the boxes done)."""
+    import numpy as np
+    from oracle import scan
+    ids, vol_c = scan.compact(vol)
+    m, el, refs = 0, 0.0, []
+    while m < len(boxes) and el < seconds:
+        t0 = time.perf_counter()
+        _, r = scan.box_counts(vol_c, len(ids), boxes[m:m + chunk], threads=threads)
+        el += time.perf_counter() - t0
+        refs.append(r)
+        m += len(r)
+    return m / el, m, el, np.concatenate(refs)
+
+
+def _timed(fn, steps, warmup, g=None):
+    """Run fn() warmup + steps times; (wall seconds of the timed steps, library kernel ms per
+    step from the HIP events the library records around its launches, or None)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    if g is not None:
+        g.timing_read()
+        g.timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kern = None
+    if g is not None:
+        ms, k = g.timing_read()
+        g.timing(False)
+        kern = ms / max(k, 1)
+    return el, kern
+
+
+def leg_aniso(args):
+    """2048x2048x300 Voronoi volume: its 50,000 boxes (batched) and frames of 8 TFs."""
+    import numpy as np
+    import torch
+    from paper_2009_02702_amd import Graph, synth
+    w = synth.workload(3)
+    vol = synth.make_volume(w)
+    boxes = synth.make_boxes(w)
+    t0 = time.perf_counter()
+    g = Graph.build(vol)
+    t_build = time.perf_counter() - t0
+    g.upload(0)
+    del vol
+    inf = g.info()
+    S, n = inf["nseg"], len(boxes)
+    db = torch.from_numpy(boxes.view(np.int32)).cuda()
+    out = torch.empty((n, S), dtype=torch.float32, device="cuda")
+    ws = g.workspace(n)
+    el, kern = _timed(lambda: g.query(db, out=out, workspace=ws), max(3, args.steps // 2), 1, g)
+    steps = max(3, args.steps // 2)
+    r = {"workload": w.name, "boxes": n, "segments": S, "nodes": inf["n_nodes"], "depth": inf["depth"],
+         "levels": inf["n_levels"], "build_s": t_build, "device_bytes": inf["device_bytes"],
+         "query": {"value": steps * n / el, "unit": "queries/s", "ms_per_step": 1e3 * el / steps,
+                   "kernel_ms": kern}}
+    del out, ws
+    r["tf_propagation"] = measure_tf(g, w, 8, max(5, args.steps), 2)
+    print("[bench] aniso: %.3f ms per batch of %d boxes; %.3f ms per frame of 8 TFs (frac %.2f)"
+          % (r["query"]["ms_per_step"], n, r["tf_propagation"]["ms_per_frame"],
+             r["tf_propagation"]["roofline"]["frac"]), file=sys.stderr, flush=True)
+    g.close()
+    return r
+
+
+def leg_capsule(args):
+    """614x961x600 capsule volume: 10^6 boxes in one sparse-output launch."""
+    import numpy as np
+    import torch
+    from paper_2009_02702_amd import Graph, synth
+    w = synth.workload(4)
+    vol = synth.make_volume(w)
+    boxes = synth.make_boxes(w)
+    t0 = time.perf_counter()
+    g = Graph.build(vol)
+    t_build = time.perf_counter() - t0
+    g.upload(0)
+    del vol
+    inf = g.info()
+    n = len(boxes)
+    db = torch.from_numpy(boxes.view(np.int32)).cuda()
+    ws = g.workspace(n)
+    cap = 300_000_000
+    bufs = (torch.empty((n, 2), dtype=torch.int32, device="cuda"), torch.empty(cap, dtype=torch.int32, device="cuda"),
+            torch.empty(cap, dtype=torch.float32, device="cuda"), torch.empty(1, dtype=torch.int32, device="cuda"))
+    steps = 3
+    el, kern = _timed(lambda: g.query_sparse(db, capacity=cap, workspace=ws, bufs=bufs), steps, 1, g)
+    nnz = int(bufs[3].item())
+    r = {"workload": w.name, "boxes": n, "segments": inf["nseg"], "nodes": inf["n_nodes"], "depth": inf["depth"],
+         "build_s": t_build, "entries": nnz, "output": "sparse (segment, fraction) entries",
+         "value": steps * n / el, "unit": "queries/s", "ms_per_step": 1e3 * el / steps, "kernel_ms": kern}
+    print("[bench] capsule: %.2f ms per launch of %d boxes (%d entries)" % (r["ms_per_step"], n, nnz),
+          file=sys.stderr, flush=True)
+    del bufs, ws
+    g.close()
+    return r
+
+
+def leg_stream(args):
+    """1178x1125x789 Voronoi volume served at 5k-200k requests/s."""
+    from paper_2009_02702_amd import Graph, synth
+    w = synth.workload(5)
+    vol = synth.make_volume(w)
+    t0 = time.perf_counter()
+    g = Graph.build(vol)
+    t_build = time.perf_counter() - t0
+    g.upload(0)
+    del vol
+    inf = g.info()
+    qps = [float(x) for x in args.qps.split(",") if x]
+    levels = measure_serve(g, w, qps, args.serve_seconds, args.trace_dir)
+    g.close()
+    return {"workload": w.name, "segments": inf["nseg"], "nodes": inf["n_nodes"], "depth": inf["depth"],
+            "build_s": t_build,
+            "what": "per-request latency (completion seen by the server - arrival) of Poisson arrivals "
+                    "through the continuous-batching server (4 HIP-stream slots, captured graphs), 10% of "
+                    "requests with one TF (propagated, and the box coloured with it)",
+            "levels": levels}
 
 
 def main():
@@ -115,19 +273,22 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--competitor-steps", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu1-seconds", type=float, default=6.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=("full", "query", "copy", "tf", "serve"), default="full",
                     help="full: the JSON line; query: only the timed batched launches (for profilers); "
                          "copy: one device copy of --copy-mib MiB (calibrates HBM byte counters); "
                          "tf: transfer-function propagation frames (8 TFs) on --config; "
                          "serve: Poisson-arrival stream through the continuous-batching server on --config")
+    ap.add_argument("--variant", default="batched", help="query mode: batched, plain, naive or lut")
     ap.add_argument("--tf-count", type=int, default=8)
     ap.add_argument("--qps", type=str, default="5000,20000,50000,100000,200000")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--autotune", action="store_true", help="serve mode: autotune the launch on the workload's boxes first")
-    ap.add_argument("--serve-qps", type=float, default=100000.0,
-                    help="full mode: offered rate of the short serving leg (per-request p50/p99); 0 skips it")
+    ap.add_argument("--legs", type=str, default="aniso,capsule,stream",
+                    help="full mode: further workloads (aniso, capsule, stream; empty for none)")
+    ap.add_argument("--trace-dir", type=str, default=None, help="write the serving legs' per-batch traces here")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path "
@@ -164,8 +325,8 @@ def main():
           % (w.name, w.dims, S, n, inf["n_nodes"], inf["depth"], t_build), file=sys.stderr, flush=True)
 
     dboxes = torch.from_numpy(boxes.view(np.int32)).to(dev)
-    out = torch.empty((n, S), dtype=torch.float32, device=dev)
-    ws = g.workspace(n)
+    out = torch.empty((n, S), dtype=torch.float32, device=dev) if args.mode != "tf" else None
+    ws = g.workspace(n) if args.mode != "tf" else None
     torch.cuda.synchronize()
 
     if args.mode == "tf":
@@ -178,22 +339,19 @@ def main():
             print("[bench] autotuned %s" % (g.autotune(dboxes, out=out, reps=3, workspace=ws),), file=sys.stderr,
                   flush=True)
         qps = [float(x) for x in args.qps.split(",") if x]
-        r = {"mode": "serve", "workload": w.name, "levels": measure_serve(g, w, qps, args.serve_seconds)}
+        r = {"mode": "serve", "workload": w.name, "levels": measure_serve(g, w, qps, args.serve_seconds,
+                                                                         args.trace_dir)}
         print(json.dumps(r), flush=True)
         return
     if args.mode == "query":
         # same launch selection as the full run (untimed), so profilers see the same kernels
         tuned = g.autotune(dboxes, out=out, reps=5, workspace=ws)
         print("[bench] autotuned %s" % (tuned,), file=sys.stderr, flush=True)
-        for _ in range(args.warmup):
-            g.query(dboxes, out=out, workspace=ws)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            g.query(dboxes, out=out, workspace=ws)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        print(json.dumps({"mode": "query", "workload": w.name, "steps": args.steps,
+        if args.variant == "lut":
+            g.lut_build()
+        el, _ = _timed(lambda: g.query(dboxes, out=out, variant=args.variant, workspace=ws), args.steps,
+                       args.warmup)
+        print(json.dumps({"mode": "query", "variant": args.variant, "workload": w.name, "steps": args.steps,
                           "ms_per_step": 1e3 * el / args.steps}), flush=True)
         return
 
@@ -221,31 +379,20 @@ def main():
     alg_bytes_stored = float(np.sum(24.0 + id0 * cubes0 + 4.0 * (cubes - cubes0) + 12.0 * touched + 4.0 * S))
 
     def run(variant, steps, warmup, timing, g=g, ws=ws):
-        for _ in range(warmup):
-            g.query(dboxes, out=out, variant=variant, workspace=ws)
-        torch.cuda.synchronize()
-        if timing:
-            g.timing_read()
-            g.timing(True)
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for a, b in evs:
-            a.record()
-            g.query(dboxes, out=out, variant=variant, workspace=ws)
-            b.record()
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        kern = None
-        if timing:
-            ms, k = g.timing_read()
-            g.timing(False)
-            kern = ms / max(k, 1)
-        lat = np.array([a.elapsed_time(b) for a, b in evs])
-        return el, lat, kern
+        el, kern = _timed(lambda: g.query(dboxes, out=out, variant=variant, workspace=ws), steps, warmup,
+                          g if timing else None)
+        return el, kern
 
-    el, lat, kern_ms = run("batched", args.steps, args.warmup, True)
+    el, kern_ms = run("batched", args.steps, args.warmup, True)
     value = args.steps * n / el
+    # completion time of one whole batch, from events around each call (not a per-request latency)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+    for a, b in evs:
+        a.record()
+        g.query(dboxes, out=out, workspace=ws)
+        b.record()
+    torch.cuda.synchronize()
+    batch_ms = np.array([a.elapsed_time(b) for a, b in evs])
     res_main = out.cpu().numpy()
 
     comp = {}
@@ -255,7 +402,7 @@ def main():
     print("[bench] mixture lookup table: %d entries, built in %.2f s" % (lut_nnz, t_lut), file=sys.stderr,
           flush=True)
     for v in ("plain", "naive", "lut"):
-        e2, l2, k2 = run(v, args.competitor_steps, 1, True)
+        e2, k2 = run(v, args.competitor_steps, 1, True)
         comp[v] = {"value": args.competitor_steps * n / e2, "ms_per_step": 1e3 * e2 / args.competitor_steps,
                    "kernel_ms": k2}
         if v == "lut":
@@ -271,24 +418,19 @@ def main():
     gg.upload(0)
     gg.set_launch_config(**{k: v for k, v in tuned.items()})
     wsg = gg.workspace(n)
-    e2, l2, k2 = run("batched", args.competitor_steps, 1, True, g=gg, ws=wsg)
+    e2, k2 = run("batched", args.competitor_steps, 1, True, g=gg, ws=wsg)
     gi = gg.info()
     comp["greedy_push"] = {"value": args.competitor_steps * n / e2, "ms_per_step": 1e3 * e2 / args.competitor_steps,
                            "kernel_ms": k2, "nodes": gi["n_nodes"], "depth": gi["depth"], "build_s": t_gb,
                            "max_abs_diff_vs_push": float((out - torch.from_numpy(res_main).to(out.device)).abs().max())}
     print("[bench] greedy_push: %.3f ms/step (graph %d nodes, depth %d, built in %.2f s)"
           % (comp["greedy_push"]["ms_per_step"], gi["n_nodes"], gi["depth"], t_gb), file=sys.stderr, flush=True)
+    gg.close()
     del gg, wsg
 
     tf_meas = measure_tf(g, w, args.tf_count, max(3, args.steps // 2), 1)
     print("[bench] tf: %.3f ms per frame of %d TFs" % (tf_meas["ms_per_frame"], args.tf_count), file=sys.stderr,
           flush=True)
-
-    serving = None
-    if args.serve_qps > 0:
-        serving = measure_serve(g, w, [args.serve_qps], args.serve_seconds)[0]
-        serving["what"] = ("per-request latency (completion - arrival) of Poisson arrivals through the "
-                           "continuous-batching server, 10% of requests with one TF")
 
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     traffic = read_traffic("query_tier_kernel", w.name, alg_bytes)
@@ -306,27 +448,33 @@ def main():
 
     cpu = None
     max_rel = None
+    m = 0
     if not args.no_cpu_baseline:
         from oracle import scan
-        ids, vol_c = scan.compact(vol)
         threads = scan.max_threads()
-        # time consecutive chunks of the box list until about --cpu-seconds have passed
-        chunk, m, el_cpu, refs = 2000, 0, 0.0, []
-        while m < n and el_cpu < args.cpu_seconds:
-            t0 = time.perf_counter()
-            _, r = scan.box_counts(vol_c, len(ids), boxes[m:m + chunk], threads=threads)
-            el_cpu += time.perf_counter() - t0
-            refs.append(r)
-            m += len(r)
-        ref = np.concatenate(refs)
-        cpu = {"value": m / el_cpu, "unit": "queries/s", "cores": threads, "kind": "oracle",
-               "sample": "first %d of the %d boxes (%.1f s, %d OpenMP threads)" % (m, n, el_cpu, threads)}
+        rate, m, el_cpu, ref = oracle_rate(vol, boxes, args.cpu_seconds, threads, 2000)
+        rate1, m1, el1, _ = oracle_rate(vol, boxes, args.cpu1_seconds, 1, 200)
+        cpu = {"value": rate, "unit": "queries/s", "cores": threads, "kind": "oracle",
+               "sample": "first %d of the %d boxes (%.1f s, %d OpenMP threads)" % (m, n, el_cpu, threads),
+               "value_1_thread": rate1, "sample_1_thread": "first %d boxes (%.1f s, 1 thread)" % (m1, el1),
+               "cpu_model": cpu_model(), "host_cpus_visible": os.cpu_count()}
         got = res_main[:m].astype(np.float64)
         nz = ref > 0
         support_ok = bool(np.array_equal(got == 0, ref == 0))
         max_rel = float((np.abs(got[nz] - ref[nz]) / ref[nz]).max()) if nz.any() else 0.0
         if not support_ok:
             max_rel = float("inf")
+    g.close()
+    del vol, out, ws, dboxes
+    gc.collect()
+    torch.cuda.empty_cache()
+
+    legs = {}
+    for leg in [x for x in args.legs.split(",") if x]:
+        fn = {"aniso": leg_aniso, "capsule": leg_capsule, "stream": leg_stream}[leg]
+        legs[leg] = fn(args)
+        gc.collect()
+        torch.cuda.empty_cache()
 
     line = {
         "metric": METRIC, "value": value, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
@@ -335,15 +483,18 @@ def main():
         "config": {"workload": w.name, "dims": list(w.dims), "segments": S, "boxes": n,
                    "box_edges": "log-uniform per axis" if w.box_mode != "corners" else "two uniform corners",
                    "output": "dense fp32 [n, S]", "parallelism": "single GPU"},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "what": "completion latency of one batch of all boxes"},
+        "batch_completion_ms": {"median": float(np.median(batch_ms)), "max": float(batch_ms.max()),
+                                "what": "device time from before to after one call answering all boxes "
+                                        "(a batch figure, not a per-request latency: see serving)"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "max_rel_err_vs_oracle": max_rel,
-        "oracle_checked_boxes": (m if not args.no_cpu_baseline else 0),
-        "serving": serving,
+        "oracle_checked_boxes": m,
+        "serving": legs.get("stream"),
         "competitors": comp,
         "tf_propagation": tf_meas,
+        "aniso": legs.get("aniso"),
+        "capsule": legs.get("capsule"),
         "speedup_vs_naive": value / comp["naive"]["value"],
         "speedup_vs_plain": value / comp["plain"]["value"],
         "launch": tuned,

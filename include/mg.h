@@ -240,6 +240,19 @@ int mg_propagate_tf(mg_graph *g, const uint8_t *d_tf, uint32_t T, float *d_node_
 int mg_palette_fetch(mg_graph *g, const float *d_palette, uint32_t T, uint32_t level,
                      const uint32_t *d_xyz, uint32_t n, float *d_out, void *stream);
 
+/* Mean colour of each box under a propagated palette (Sec. "Rendering": the
+ * node of a mip voxel indexes the colour table; Sec. "Fast Sub-Volume
+ * Queries": a box is the disjoint union of its footprint cubes, each holding
+ * 8^l voxels of its node's mixture). d_palette device fp32 [T][n_nodes][4] as
+ * written by mg_propagate_tf; d_boxes device uint32 [n][6]; d_pal_of_box device
+ * uint32 [n], the palette (< T) each box is coloured with, or 0xFFFFFFFF for
+ * none; d_out device fp32 [n][4] = sum over the box's cubes of 8^l times the
+ * palette entry of the cube's node, divided by the box volume (fp64 sums), i.e.
+ * the TF colours averaged over the box's voxels. Empty boxes and boxes without
+ * a palette get zeros. */
+int mg_box_colour(mg_graph *g, const float *d_palette, uint32_t T, const uint32_t *d_boxes, uint32_t n,
+                  const uint32_t *d_pal_of_box, float *d_out, void *stream);
+
 /* Mixture lookup table (Sec. "Decoder": one mixture per node, found by
  * carrying each source's unit vector through the interpolations; Sec.
  * "Range queries" answers boxes from it). Built on the host in fp64 from the

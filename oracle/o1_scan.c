@@ -63,4 +63,34 @@ int o1_box_counts(const uint32_t *vol, int64_t nx, int64_t ny, int64_t nz, int64
     return bad ? -2 : 0;
 }
 
+/*
+ * Compaction of a label volume to segment indices (the distinct IDs in
+ * increasing order are numbered 0, 1, ...): lut[max_id + 1] must be zeroed by
+ * the caller; on return lut[id] is 1 + the index of every present ID (0 for
+ * absent ones) and out[i] the index of vol[i]. Returns the number of distinct
+ * IDs, or -1 if a voxel holds an ID above max_id.
+ */
+int64_t o1_compact(const uint32_t *vol, int64_t n, uint32_t max_id, uint32_t *lut, uint32_t *out, int threads)
+{
+    if (threads > 0) omp_set_num_threads(threads);
+    int bad = 0;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        if (vol[i] > max_id) {
+#pragma omp atomic write
+            bad = 1;
+            continue;
+        }
+#pragma omp atomic write
+        lut[vol[i]] = 1u;
+    }
+    if (bad) return -1;
+    int64_t k = 0;
+    for (int64_t v = 0; v <= (int64_t)max_id; ++v)
+        if (lut[v]) lut[v] = (uint32_t)(++k);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) out[i] = lut[vol[i]] - 1u;
+    return k;
+}
+
 int o1_max_threads(void) { return omp_get_max_threads(); }

@@ -41,6 +41,8 @@ def _load():
         lib.o1_box_counts.argtypes = [vp, i64, i64, i64, i64, vp, i64, vp, vp, ctypes.c_int]
         lib.o1_box_counts.restype = ctypes.c_int
         lib.o1_max_threads.restype = ctypes.c_int
+        lib.o1_compact.argtypes = [vp, i64, ctypes.c_uint32, vp, vp, ctypes.c_int]
+        lib.o1_compact.restype = i64
         _lib = lib
     return _lib
 
@@ -49,10 +51,26 @@ def max_threads() -> int:
     return int(_load().o1_max_threads())
 
 
-def compact(vol: np.ndarray):
-    """Segment IDs in increasing order and the volume as indices into them (uint32)."""
-    ids, inv = np.unique(np.asarray(vol).ravel(), return_inverse=True)
-    return ids.astype(np.uint64), inv.astype(np.uint32).reshape(np.asarray(vol).shape)
+def compact(vol: np.ndarray, threads: int = 0):
+    """Segment IDs in increasing order and the volume as indices into them (uint32).
+
+    Volumes whose largest ID is below 2^28 go through a table of all IDs up to the largest (C,
+    linear time); others through numpy.unique."""
+    vol = np.asarray(vol)
+    flat = np.ascontiguousarray(vol.ravel(), dtype=np.uint32) if vol.dtype != np.uint32 else \
+        np.ascontiguousarray(vol).ravel()
+    mx = int(flat.max()) if flat.size else 0
+    if mx >= (1 << 28):
+        ids, inv = np.unique(flat, return_inverse=True)
+        return ids.astype(np.uint64), inv.astype(np.uint32).reshape(vol.shape)
+    lut = np.zeros(mx + 1, dtype=np.uint32)
+    out = np.empty(flat.size, dtype=np.uint32)
+    k = _load().o1_compact(flat.ctypes.data, flat.size, mx, lut.ctypes.data, out.ctypes.data, int(threads))
+    if k < 0:
+        raise RuntimeError("o1_compact failed")
+    ids = np.nonzero(lut)[0].astype(np.uint64)
+    assert len(ids) == k
+    return ids, out.reshape(vol.shape)
 
 
 def clipped(box, dims):

@@ -53,7 +53,7 @@ SYMBOLS = [
     "mg_workspace_bytes", "mg_workspace_init", "mg_query_boxes", "mg_query_boxes_plain", "mg_query_boxes_stats",
     "mg_query_boxes_sparse",
     "mg_naive_boxes",
-    "mg_footprint", "mg_propagate_tf", "mg_palette_fetch", "mg_lut_build", "mg_export_lut", "mg_query_boxes_lut", "mg_query_boxes_err",
+    "mg_footprint", "mg_propagate_tf", "mg_palette_fetch", "mg_box_colour", "mg_lut_build", "mg_export_lut", "mg_query_boxes_lut", "mg_query_boxes_err",
     "mg_get_launch", "mg_set_launch", "mg_autotune",
     "mg_save", "mg_load", "mg_pack", "mg_unpack", "mg_timing_enable", "mg_timing_read",
     "mg_last_error", "mg_free",
@@ -95,6 +95,7 @@ def load() -> ctypes.CDLL:
         "mg_footprint": ([G, vp, u32, vp, vp, u32, vp, vp], i32),
         "mg_propagate_tf": ([G, vp, u32, vp, vp], i32),
         "mg_palette_fetch": ([G, vp, u32, u32, vp, u32, vp, vp], i32),
+        "mg_box_colour": ([G, vp, u32, vp, u32, vp, vp, vp], i32),
         "mg_lut_build": ([G, u32, ctypes.POINTER(u64)], i32),
         "mg_export_lut": ([G, vp, vp, vp, vp], i32),
         "mg_query_boxes_lut": ([G, vp, u32, vp, vp, u64, vp], i32),

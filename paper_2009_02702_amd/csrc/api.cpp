@@ -304,6 +304,16 @@ int mg_palette_fetch(mg_graph *h, const float *d_palette, uint32_t T, uint32_t l
     return done(mg::dev_palette_fetch(&h->g, d_palette, T, level, d_xyz, n, d_out, stream, &err), err);
 }
 
+int mg_box_colour(mg_graph *h, const float *d_palette, uint32_t T, const uint32_t *d_boxes, uint32_t n,
+                  const uint32_t *d_pal_of_box, float *d_out, void *stream)
+{
+    if (!h) return fail(MG_EINVAL, "mg_box_colour: null graph");
+    if (n == 0) return MG_OK;
+    if (!d_palette || !d_boxes || !d_pal_of_box || !d_out) return fail(MG_EINVAL, "mg_box_colour: null buffer");
+    std::string err;
+    return done(mg::dev_box_colour(&h->g, d_palette, T, d_boxes, n, d_pal_of_box, d_out, stream, &err), err);
+}
+
 int mg_lut_build(mg_graph *h, uint32_t threads, uint64_t *out_nnz)
 {
     if (!h) return fail(MG_EINVAL, "mg_lut_build: null graph");

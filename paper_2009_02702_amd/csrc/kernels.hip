@@ -1308,21 +1308,73 @@ __global__ void tf_sources_kernel(const uint8_t *tf, uint32_t T, uint32_t nseg, 
     out[uint64_t(t) * n_nodes + s] = make_float4(float(c.x) * k, float(c.y) * k, float(c.z) * k, float(c.w) * k);
 }
 
-__global__ void tf_step_kernel(const SchedNode *__restrict__ sched, uint32_t lo_i, uint32_t hi_i, uint32_t T,
-                               uint32_t n_nodes, float4 *out)
+// One step of the schedule: thread (x, y) computes node sched[lo_i + x] for transfer
+// function y (grid.y = T), so a step launches T threads per node and the gathers of
+// all T planes are in flight together. Lanes of a wave share the plane and take
+// consecutive schedule entries (coalesced schedule reads and, nodes being numbered
+// by rank, mostly contiguous stores).
+__global__ void tf_step_kernel(const SchedNode *__restrict__ sched, uint32_t lo_i, uint32_t hi_i, uint32_t n_nodes,
+                               float4 *out)
 {
     const uint32_t i = lo_i + blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= hi_i) return;
     const SchedNode t = sched[i];
-    for (uint32_t k = 0; k < T; ++k) {
-        float4 *o = out + uint64_t(k) * n_nodes;
-        const float4 va = o[t.a], vb = o[t.b];
-        float4 r;
-        r.x = fmaf(t.w, vb.x - va.x, va.x);
-        r.y = fmaf(t.w, vb.y - va.y, va.y);
-        r.z = fmaf(t.w, vb.z - va.z, va.z);
-        r.w = fmaf(t.w, vb.w - va.w, va.w);
-        o[t.id] = r;
+    float4 *o = out + uint64_t(blockIdx.y) * n_nodes;
+    const float4 va = o[t.a], vb = o[t.b];
+    float4 r;
+    r.x = fmaf(t.w, vb.x - va.x, va.x);
+    r.y = fmaf(t.w, vb.y - va.y, va.y);
+    r.z = fmaf(t.w, vb.z - va.z, va.z);
+    r.w = fmaf(t.w, vb.w - va.w, va.w);
+    o[t.id] = r;
+}
+
+// Mean colour of a box under one propagated palette: every footprint cube adds
+// its 8^l voxels times the palette entry of its node, divided by the box
+// volume. One workgroup per box; sums in fp64. Boxes whose palette index is
+// kEmpty get zeros.
+__global__ __launch_bounds__(kBlock) void box_colour_kernel(LevelTable lt, const uint32_t *boxes, uint32_t n,
+                                                            const uint32_t *__restrict__ maps,
+                                                            const float4 *__restrict__ palette, uint32_t T,
+                                                            uint32_t n_nodes, const uint32_t *pal_of_box,
+                                                            float4 *out)
+{
+    __shared__ Slab slabs[kMaxSlabs];
+    __shared__ int n_slabs;
+    __shared__ double part[kBlock / 64][4];
+    const uint32_t q = blockIdx.x;
+    const uint32_t t = pal_of_box[q];
+    uint32_t lo[3], hi[3];
+    const bool nonempty = clip_box(boxes + 6 * uint64_t(q), lt, lo, hi) && t < T;
+    if (threadIdx.x == 0) n_slabs = 0;
+    __syncthreads();
+    if (nonempty) build_slabs(lt, lo, hi, slabs, &n_slabs);
+    __syncthreads();
+    const float4 *pal = palette + uint64_t(t < T ? t : 0) * n_nodes;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int si = 0; si < n_slabs; ++si) {
+        const Slab sl = slabs[si];
+        const double w = double(uint64_t(1) << (3 * sl.level));
+        const uint32_t c = slab_count(sl);
+        for (uint32_t r = threadIdx.x; r < c; r += kBlock) {
+            const uint32_t i0 = r % sl.e0, i1 = (r / sl.e0) % sl.e1, i2 = r / (sl.e0 * sl.e1);
+            const uint32_t node = maps[sl.base + i0 + uint64_t(i1) * sl.s1 + uint64_t(i2) * sl.s2];
+            const float4 v = pal[node];
+            acc[0] += w * v.x, acc[1] += w * v.y, acc[2] += w * v.z, acc[3] += w * v.w;
+        }
+    }
+    for (int k = 0; k < 4; ++k)
+        for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_down(acc[k], off, 64);
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 4; ++k) part[threadIdx.x >> 6][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int wv = 0; wv < kBlock / 64; ++wv)
+            for (int k = 0; k < 4; ++k) s[k] += part[wv][k];
+        const double vol = nonempty ? double(hi[0] - lo[0]) * double(hi[1] - lo[1]) * double(hi[2] - lo[2]) : 1.0;
+        out[q] = nonempty ? make_float4(float(s[0] / vol), float(s[1] / vol), float(s[2] / vol), float(s[3] / vol))
+                          : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 }
 
@@ -1693,6 +1745,24 @@ int dev_palette_fetch(Graph *g, const float *palette, uint32_t T, uint32_t level
     return MG_OK;
 }
 
+int dev_box_colour(Graph *g, const float *palette, uint32_t T, const uint32_t *boxes, uint32_t n,
+                   const uint32_t *pal_of_box, float *out, void *stream, std::string *err)
+{
+    DeviceGuard guard;
+    int rc = check_device(g, err);
+    if (rc) return rc;
+    if (g->n_levels > kMaxLevelsDev) {
+        *err = "more than " + std::to_string(kMaxLevelsDev) + " mip levels";
+        return MG_ELIMIT;
+    }
+    const LevelTable lt = level_table(*g);
+    hipLaunchKernelGGL(box_colour_kernel, dim3(n), dim3(kBlock), 0, static_cast<hipStream_t>(stream), lt, boxes, n,
+                       g->dev.maps, reinterpret_cast<const float4 *>(palette), T, g->n_nodes, pal_of_box,
+                       reinterpret_cast<float4 *>(out));
+    HIP_TRY(hipGetLastError());
+    return MG_OK;
+}
+
 void dev_free(Graph *g)
 {
     DeviceState &d = g->dev;
@@ -1963,19 +2033,24 @@ int dev_propagate_tf(Graph *g, const uint8_t *tf, uint32_t T, float *out, void *
     DeviceGuard guard;
     int rc = check_device(g, err);
     if (rc) return rc;
+    if (T > 65535) {
+        *err = "at most 65535 transfer functions per call";
+        return MG_ELIMIT;
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     float4 *o = reinterpret_cast<float4 *>(out);
     const uint64_t src = uint64_t(T) * g->nseg;
+    // the timed region is the whole frame: sources, then every step
+    rc = timing_begin(g, s, err);
+    if (rc) return rc;
     hipLaunchKernelGGL(tf_sources_kernel, dim3(uint32_t((src + 255) / 256)), dim3(256), 0, s, tf, T, g->nseg,
                        g->n_nodes, o);
     HIP_TRY(hipGetLastError());
-    rc = timing_begin(g, s, err);
-    if (rc) return rc;
+    const uint32_t tb = g->dev.cfg.tf_block;
     for (uint32_t st = 1; st <= g->depth; ++st) {
         const uint32_t lo = g->step_ptr[st], hi = g->step_ptr[st + 1];
         if (hi <= lo) continue;
-        const uint32_t tb = g->dev.cfg.tf_block;
-        hipLaunchKernelGGL(tf_step_kernel, dim3((hi - lo + tb - 1) / tb), dim3(tb), 0, s, g->dev.sched, lo, hi, T,
+        hipLaunchKernelGGL(tf_step_kernel, dim3((hi - lo + tb - 1) / tb, T), dim3(tb), 0, s, g->dev.sched, lo, hi,
                            g->n_nodes, o);
         HIP_TRY(hipGetLastError());
     }

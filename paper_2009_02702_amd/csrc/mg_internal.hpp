@@ -156,6 +156,8 @@ int dev_footprint(Graph *g, const uint32_t *boxes, uint32_t n, uint32_t *level_c
 int dev_propagate_tf(Graph *g, const uint8_t *tf, uint32_t T, float *out, void *stream, std::string *err);
 int dev_palette_fetch(Graph *g, const float *palette, uint32_t T, uint32_t level, const uint32_t *xyz, uint32_t n,
                       float *out, void *stream, std::string *err);
+int dev_box_colour(Graph *g, const float *palette, uint32_t T, const uint32_t *boxes, uint32_t n,
+                   const uint32_t *pal_of_box, float *out, void *stream, std::string *err);
 int dev_timing_enable(Graph *g, int enable, std::string *err);
 int dev_set_launch(Graph *g, const mg_launch_cfg *cfg, std::string *err);
 int dev_autotune(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *work, uint64_t bytes, uint32_t reps,

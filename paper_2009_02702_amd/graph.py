@@ -202,18 +202,24 @@ class Graph:
                                              ws.numel(), _stream_ptr(stream)))
         return out, stats
 
-    def query_sparse(self, boxes, capacity: int, workspace=None, stream=None):
+    def query_sparse(self, boxes, capacity: int, workspace=None, stream=None, bufs=None):
         """Sparse histograms: (index int32 [n, 2], seg int32 [capacity], val fp32 [capacity], total int32 [1]).
 
         Box q's entries are seg/val[index[q,0] : index[q,0] + index[q,1]]; if total > capacity the
-        call must be repeated with more room."""
+        call must be repeated with more room. bufs: those four tensors, preallocated (reused)."""
         torch = _torch()
         n = boxes.shape[0]
         dev = boxes.device
-        index = torch.zeros((n, 2), dtype=torch.int32, device=dev)
-        seg = torch.zeros(max(capacity, 1), dtype=torch.int32, device=dev)
-        val = torch.zeros(max(capacity, 1), dtype=torch.float32, device=dev)
-        total = torch.zeros(1, dtype=torch.int32, device=dev)
+        if bufs is None:
+            index = torch.zeros((n, 2), dtype=torch.int32, device=dev)
+            seg = torch.zeros(max(capacity, 1), dtype=torch.int32, device=dev)
+            val = torch.zeros(max(capacity, 1), dtype=torch.float32, device=dev)
+            total = torch.zeros(1, dtype=torch.int32, device=dev)
+        else:
+            index, seg, val, total = bufs
+            if (tuple(index.shape) != (n, 2) or seg.numel() < capacity or val.numel() < capacity
+                    or total.numel() < 1):
+                raise ValueError("sparse output buffers too small")
         ws = workspace if workspace is not None else self.workspace(n, stream)
         check(self._lib.mg_query_boxes_sparse(self._h, _dptr(boxes), n, _dptr(index), _dptr(seg), _dptr(val),
                                               int(capacity), _dptr(total), _dptr(ws), ws.numel(),
@@ -267,6 +273,25 @@ class Graph:
             out = torch.empty((T, n, 4), dtype=torch.float32, device=palette.device)
         check(self._lib.mg_palette_fetch(self._h, _dptr(palette), T, level, _dptr(xyz), n, _dptr(out),
                                          _stream_ptr(stream)))
+        return out
+
+    def box_colour(self, palette, boxes, pal_of_box, out=None, stream=None):
+        """Mean colour fp32 [n, 4] of each box under palette[pal_of_box[q]] (0xFFFFFFFF: none, zeros);
+        palette fp32 [T, n_nodes, 4] from propagate_tf, boxes 32-bit [n, 6], pal_of_box 32-bit [n]."""
+        torch = _torch()
+        T = palette.shape[0]
+        inf = self.info()
+        if tuple(palette.shape) != (T, inf["n_nodes"], 4) or palette.dtype != torch.float32:
+            raise ValueError("palette must be fp32 [T, n_nodes, 4]")
+        n = boxes.shape[0]
+        if boxes.dim() != 2 or boxes.shape[1] != 6 or boxes.element_size() != 4:
+            raise ValueError("boxes must be a 32-bit [n, 6] tensor")
+        if pal_of_box.shape != (n,) or pal_of_box.element_size() != 4:
+            raise ValueError("pal_of_box must be a 32-bit [n] tensor")
+        if out is None:
+            out = torch.empty((n, 4), dtype=torch.float32, device=palette.device)
+        check(self._lib.mg_box_colour(self._h, _dptr(palette), T, _dptr(boxes), n, _dptr(pal_of_box), _dptr(out),
+                                      _stream_ptr(stream)))
         return out
 
     def lut_build(self, threads: int = 0) -> int:

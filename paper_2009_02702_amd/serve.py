@@ -8,7 +8,9 @@ and requests are waiting, the waiting requests (up to `max_batch`) are
 admitted as one batch on that slot: boxes are copied to the device, the
 batched query kernels run (replayed from a captured HIP graph when graphs are
 enabled), transfer-function requests of the batch are propagated together,
-and results are copied back into pinned host memory. Batches on different
+each transfer-function request's box is coloured with its propagated
+palette (mg_box_colour: the box's mean colour from its footprint cubes), and
+results are copied back into pinned host memory. Batches on different
 slots overlap on the device, so requests that arrive while others are in
 flight are admitted as soon as a slot frees up. A request completes when its
 batch's completion event has fired; its latency is completion time minus
@@ -39,6 +41,10 @@ from ._lib import check
 from .graph import Graph, _torch
 
 
+TRACE_FIELDS = ("t_admit", "t_launched", "t_seen", "device_ms", "oldest_arrival", "requests", "rows", "tfs",
+                "max_cubes", "slot")
+
+
 @dataclass
 class ServeStats:
     latency_s: np.ndarray            # per request, completion - arrival
@@ -46,15 +52,32 @@ class ServeStats:
     batches: int
     batch_sizes: List[int] = field(default_factory=list)
     wall_s: float = 0.0
+    # per batch (seconds from the start unless stated): admission, return of the launch calls,
+    # completion seen by the loop, device time between the batch's first and last stream event,
+    # arrival of its oldest request, requests, rows, transfer functions, largest box (cubes), slot
+    trace: Optional[np.ndarray] = None
 
     def summary(self) -> dict:
         lat = self.latency_s * 1e3
-        return {
+        out = {
             "requests": int(len(lat)), "batches": self.batches,
             "mean_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "max_ms": float(lat.max()), "qps": float(len(lat) / self.wall_s) if self.wall_s > 0 else 0.0,
         }
+        if self.trace is not None and len(self.trace):
+            tr = self.trace
+            wait = (tr[:, 0] - tr[:, 4]) * 1e3                 # oldest request's wait before admission
+            launch = (tr[:, 1] - tr[:, 0]) * 1e3               # host time in the launch calls
+            seen = (tr[:, 2] - tr[:, 1]) * 1e3                 # launch return -> completion seen
+            worst = int(np.argmax(tr[:, 2] - tr[:, 4]))
+            out["batch_ms"] = {
+                "admit_wait_p99": float(np.percentile(wait, 99)), "launch_p99": float(np.percentile(launch, 99)),
+                "launch_max": float(launch.max()), "device_p99": float(np.percentile(tr[:, 3], 99)),
+                "device_max": float(tr[:, 3].max()), "launch_to_seen_p99": float(np.percentile(seen, 99)),
+                "worst_batch": {k: float(tr[worst, i]) for i, k in enumerate(TRACE_FIELDS)},
+            }
+        return out
 
 
 def cube_counts(boxes: np.ndarray, dims) -> np.ndarray:
@@ -116,15 +139,24 @@ class _Slot:
             self.h_tf = torch.zeros((max_tf, self.S, 4), dtype=torch.uint8, pin_memory=True)
             self.d_tf = torch.zeros((max_tf, self.S, 4), dtype=torch.uint8, device=device)
             self.d_pal = torch.zeros((max_tf, self.N, 4), dtype=torch.float32, device=device)
+            # per row: the palette its box is coloured with (0xFFFFFFFF: none), and the colour
+            self.h_pal_of = torch.zeros(max_batch, dtype=torch.int32, pin_memory=True)
+            self.d_pal_of = torch.zeros(max_batch, dtype=torch.int32, device=device)
+            self.d_col = torch.zeros((max_batch, 4), dtype=torch.float32, device=device)
+            self.h_col = torch.zeros((max_batch, 4), dtype=torch.float32, pin_memory=True)
         nbytes = g.workspace_bytes(max_batch)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
         check(g._lib.mg_workspace_init(g._h, self.ws.data_ptr(), nbytes, self.stream.cuda_stream))
-        self.event = torch.cuda.Event()
+        self.event = torch.cuda.Event(enable_timing=True)
+        self.event0 = torch.cuda.Event(enable_timing=True)
         self.busy = False
+        self.n_tf = 0
+        self.trace = None
         self.reqs = None
         self.n_rows = 0
         self.graphs = {}
-        self.classes = [c for c in classes if c <= max_batch] or [max_batch]
+        # every batch size up to max_batch has a class: max_batch itself is always one
+        self.classes = sorted({int(c) for c in classes if c < max_batch} | {int(max_batch)})
         if use_graphs:
             self._capture(g)
 
@@ -146,24 +178,37 @@ class _Slot:
                 self.graphs[c].replay()
             if self.max_tf:
                 g.propagate_tf(self.d_tf[:1], out=self.d_pal[:1], stream=self.stream)
+                self.d_pal_of.fill_(-1)
+                g.box_colour(self.d_pal[:1], self.d_boxes[:1], self.d_pal_of[:1], out=self.d_col[:1],
+                             stream=self.stream)
         self.stream.synchronize()
 
     def size_class(self, k: int) -> int:
+        """The smallest captured batch size that holds k rows (k <= max_batch)."""
+        if not 0 < k <= self.max_batch:
+            raise ValueError("batch of %d rows for a slot of %d" % (k, self.max_batch))
         for c in self.classes:
             if k <= c:
                 return c
-        return self.classes[-1]
+        raise AssertionError("max_batch is always a class")
 
-    def launch(self, g: Graph, boxes: np.ndarray, tfs: Optional[np.ndarray]):
-        """Enqueue one batch: H2D boxes, query (graph replay or direct), TF propagation, D2H results."""
+    def launch(self, g: Graph, boxes: np.ndarray, tfs: Optional[np.ndarray],
+               pal_of_row: Optional[np.ndarray] = None):
+        """Enqueue one batch: H2D boxes, query (graph replay or direct), TF propagation and the
+        colour of each TF request's box, D2H results. pal_of_row[r] is the TF (index into tfs)
+        row r is coloured with, or -1."""
         torch = _torch()
         k = len(boxes)
         use = self.size_class(k) if self.graphs else k
+        if use < k:
+            raise AssertionError("size class below the batch")
         hb = self.h_boxes.numpy()
         hb[:k] = boxes.view(np.int32)
         if use > k:
             hb[k:use] = 0   # empty boxes pad the captured size
+        self.n_tf = 0
         with torch.cuda.stream(self.stream):
+            self.event0.record(self.stream)
             self.d_boxes[:use].copy_(self.h_boxes[:use], non_blocking=True)
             if self.graphs:
                 self.graphs[use].replay()
@@ -171,9 +216,17 @@ class _Slot:
                 g.query(self.d_boxes[:k], out=self.d_out[:k], workspace=self.ws, stream=self.stream)
             if tfs is not None and len(tfs):
                 t = len(tfs)
+                if t > self.max_tf:
+                    raise ValueError("%d transfer functions for a slot of %d" % (t, self.max_tf))
                 self.h_tf.numpy()[:t] = tfs
                 self.d_tf[:t].copy_(self.h_tf[:t], non_blocking=True)
                 g.propagate_tf(self.d_tf[:t], out=self.d_pal[:t], stream=self.stream)
+                self.h_pal_of.numpy()[:k] = pal_of_row
+                self.d_pal_of[:k].copy_(self.h_pal_of[:k], non_blocking=True)
+                g.box_colour(self.d_pal[:t], self.d_boxes[:k], self.d_pal_of[:k], out=self.d_col[:k],
+                             stream=self.stream)
+                self.h_col[:k].copy_(self.d_col[:k], non_blocking=True)
+                self.n_tf = t
             self.h_out[:k].copy_(self.d_out[:k], non_blocking=True)
             self.event.record(self.stream)
         self.busy = True
@@ -214,21 +267,46 @@ class Server:
         self.device_bytes = slots * slot_bytes(max_batch, max_tf)
 
     def serve(self, boxes: np.ndarray, arrivals: np.ndarray, tf_index: Optional[np.ndarray] = None,
-              tfs: Optional[np.ndarray] = None, results: Optional[np.ndarray] = None) -> ServeStats:
+              tfs: Optional[np.ndarray] = None, results: Optional[np.ndarray] = None,
+              colours: Optional[np.ndarray] = None) -> ServeStats:
         """Serve requests i = 0..n-1 arriving at arrivals[i] seconds after the start.
 
-        tf_index[i] >= 0 makes request i also propagate tfs[tf_index[i]] ([S, 4] uint8).
+        tf_index[i] >= 0 makes request i also propagate tfs[tf_index[i]] ([S, 4] uint8) and
+        colour its box with the result: colours[i] (fp32 [n, 4], if given) receives the box's
+        mean colour under that transfer function (rows of other requests are left alone).
         Results (fp32 [n, S]) are written into `results` if given. Python's cyclic garbage
         collector is paused while serving (a full collection can stall the loop for milliseconds)."""
+        if tf_index is not None and (np.asarray(tf_index) >= 0).any():
+            if self.max_tf == 0:
+                raise ValueError("transfer-function requests need a server with max_tf > 0")
+            if tfs is None:
+                raise ValueError("tf_index given without tfs")
         was_enabled = gc.isenabled()
         gc.disable()
         try:
-            return self._serve(boxes, arrivals, tf_index, tfs, results)
+            return self._serve(boxes, arrivals, tf_index, tfs, results, colours)
         finally:
             if was_enabled:
                 gc.enable()
 
-    def _serve(self, boxes, arrivals, tf_index, tfs, results) -> ServeStats:
+    def _admit(self, pending, rows, tf_index):
+        """Requests from the head of the queue for one batch: their rows fit max_batch and at most
+        max_tf of them carry a transfer function. Returns (requests, rows, TF requests)."""
+        take, n_tf, n_rows = [], 0, 0
+        while pending:
+            i = pending[0]
+            k_i = len(rows[i]) if i in rows else 1
+            if n_rows + k_i > self.max_batch:
+                break
+            if tf_index is not None and tf_index[i] >= 0:
+                if n_tf == self.max_tf:
+                    break
+                n_tf += 1
+            take.append(pending.popleft())
+            n_rows += k_i
+        return take, n_rows, n_tf
+
+    def _serve(self, boxes, arrivals, tf_index, tfs, results, colours) -> ServeStats:
         n = len(boxes)
         boxes = np.ascontiguousarray(boxes, dtype=np.uint32)
         arrivals = np.asarray(arrivals, dtype=np.float64)
@@ -244,6 +322,7 @@ class Server:
         pending = deque()
         nxt = 0
         batches, sizes = 0, []
+        trace = []
         finished = 0
         t0 = time.perf_counter()
         while finished < n:
@@ -254,22 +333,30 @@ class Server:
             progressed = False
             for sl in self.slots:
                 if sl.busy and sl.event.query():
+                    t_seen = time.perf_counter() - t0
                     r = sl.reqs
                     h = sl.h_out[:sl.n_rows].numpy()
+                    hc = sl.h_col[:sl.n_rows].numpy() if sl.n_tf else None
                     row = 0
                     for i in r.tolist():
                         sub = rows.get(i)
+                        k_i = 1 if sub is None else len(sub)
                         if sub is None:
                             if results is not None:
                                 results[i] = h[row]
-                            row += 1
-                        else:  # volume-weighted sum of the sub-boxes' fractions
+                            if hc is not None and colours is not None and tf_index[i] >= 0:
+                                colours[i] = hc[row]
+                        else:  # volume-weighted sums of the sub-boxes' fractions and colours
                             v = np.prod(sub[:, 3:].astype(np.float64), axis=1)
-                            comb = (h[row:row + len(sub)].astype(np.float64).T @ v) / v.sum()
                             if results is not None:
-                                results[i] = comb
-                            row += len(sub)
-                    done[r] = time.perf_counter() - t0
+                                results[i] = (h[row:row + k_i].astype(np.float64).T @ v) / v.sum()
+                            if hc is not None and colours is not None and tf_index[i] >= 0:
+                                colours[i] = (hc[row:row + k_i].astype(np.float64).T @ v) / v.sum()
+                        row += k_i
+                    done[r] = t_seen
+                    sl.trace[2] = t_seen
+                    sl.trace[3] = sl.event0.elapsed_time(sl.event)
+                    trace.append(sl.trace)
                     finished += len(r)
                     sl.busy = False
                     progressed = True
@@ -278,30 +365,30 @@ class Server:
                     break
                 if sl.busy:
                     continue
-                # requests whose rows fit max_batch, of which at most max_tf carry a transfer function
-                take, n_tf, n_rows = [], 0, 0
-                while pending:
-                    i = pending[0]
-                    k_i = len(rows[i]) if i in rows else 1
-                    if n_rows + k_i > self.max_batch:
-                        break
-                    if tf_index is not None and tf_index[i] >= 0:
-                        if n_tf == self.max_tf:
-                            break
-                        n_tf += 1
-                    take.append(pending.popleft())
-                    n_rows += k_i
+                t_admit = time.perf_counter() - t0
+                take, n_rows, n_tf = self._admit(pending, rows, tf_index)
+                if not take:
+                    break   # the head request fits no batch (cannot happen: max_batch, max_tf >= 1)
                 r = np.array(take, dtype=np.int64)
                 k = len(r)
-                tf_batch = None
+                tf_batch = pal_of_row = None
+                split = any(i in rows for i in take)
                 if n_tf:
                     sel = tf_index[r]
                     tf_batch = tfs[sel[sel >= 0]]
+                    # position of each TF request's transfer function in tf_batch, per row
+                    t_of_req = np.full(k, -1, dtype=np.int32)
+                    t_of_req[sel >= 0] = np.arange(n_tf, dtype=np.int32)
+                    pal_of_row = t_of_req if not split else np.repeat(
+                        t_of_req, [len(rows[i]) if i in rows else 1 for i in take])
                 sl.reqs = r
                 sl.n_rows = n_rows
-                bx = boxes[r] if not any(i in rows for i in take) else np.concatenate(
+                bx = boxes[r] if not split else np.concatenate(
                     [rows[i] if i in rows else boxes[i:i + 1] for i in take])
-                sl.launch(self.g, bx, tf_batch)
+                sl.launch(self.g, bx, tf_batch, pal_of_row)
+                t_launched = time.perf_counter() - t0
+                sl.trace = [t_admit, t_launched, 0.0, 0.0, float(arrivals[take[0]]), k, n_rows, n_tf,
+                            float(cubes[r].max()), float(self.slots.index(sl))]
                 batches += 1
                 sizes.append(k)
                 progressed = True
@@ -311,4 +398,4 @@ class Server:
                     time.sleep(wait - 100e-6)
         wall = time.perf_counter() - t0
         return ServeStats(latency_s=done - arrivals, completion_s=done, batches=batches, batch_sizes=sizes,
-                          wall_s=wall)
+                          wall_s=wall, trace=np.array(trace, dtype=np.float64).reshape(-1, len(TRACE_FIELDS)))

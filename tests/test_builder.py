@@ -294,3 +294,30 @@ def test_server_split_box_tiles_the_box_at_aligned_cuts():
             step = inner[1] - inner[0] if len(inner) > 1 else None
             assert step is None or (step & (step - 1)) == 0
             assert (inner % (step or 1) == 0).all()
+
+
+def test_server_admission_step():
+    """One admission step of the server (host logic, no GPU): requests are taken from the head of
+    the queue while their rows fit max_batch and at most max_tf carry a transfer function; the
+    head is never skipped, so the queue order is kept."""
+    from collections import deque
+
+    from paper_2009_02702_amd.serve import Server
+    srv = Server.__new__(Server)
+    srv.max_batch, srv.max_tf = 4, 1
+    rows = {2: [0, 1, 2]}                 # request 2 was split into three sub-boxes
+    ti = np.array([-1, 0, -1, 1, -1, -1])
+    q = deque(range(6))
+    take, n_rows, n_tf = srv._admit(q, rows, ti)
+    assert take == [0, 1] and n_rows == 2 and n_tf == 1     # request 2's 3 rows would exceed 4
+    take, n_rows, n_tf = srv._admit(q, rows, ti)
+    assert take == [2, 3] and n_rows == 4 and n_tf == 1     # full: 3 + 1 rows
+    srv.max_batch = 8
+    q = deque([3, 1, 4])
+    take, n_rows, n_tf = srv._admit(q, rows, ti)
+    assert take == [3] and n_tf == 1                        # a second TF request waits for the next batch
+    take, n_rows, n_tf = srv._admit(q, rows, ti)
+    assert take == [1, 4] and n_tf == 1
+    assert not q
+    take, n_rows, n_tf = srv._admit(q, rows, None)
+    assert take == [] and n_rows == 0

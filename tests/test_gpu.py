@@ -197,45 +197,6 @@ def test_query_full_config2_sampled():
         _compare(o, ref, None, "cfg2 sample " + v)
 
 
-def test_query_full_config4_million_boxes_sparse():
-    """The capsule volume at full size (614x961x600, 15,917 segments, 5.9M nodes) with its 10^6 boxes
-    (0.1% full-volume, 1% single-voxel) in one sparse-output launch: every box's entries sum to 1,
-    single-voxel boxes are one-hot and exact, and O1 on a sample (including full-volume boxes)."""
-    w = synth.workload(4)
-    vol = synth.make_volume(w)
-    boxes = synth.make_boxes(w)
-    assert len(boxes) == 1_000_000
-    g = Graph.build(vol).upload(0)
-    S = g.info()["nseg"]
-    db = _dev(boxes)
-    cap = 300_000_000   # about 215 non-zero segments per box on average
-    index, seg, val, total = g.query_sparse(db, capacity=cap)
-    torch.cuda.synchronize()
-    nnz = int(total.item())
-    assert 0 < nnz <= cap
-    idx = index.long()
-    assert bool((idx[:, 0] >= 0).all()) and bool((idx[:, 0] + idx[:, 1] <= nnz).all())
-    cs = torch.cat([torch.zeros(1, dtype=torch.float64, device=val.device), torch.cumsum(val[:nnz].double(), 0)])
-    sums = (cs[idx[:, 0] + idx[:, 1]] - cs[idx[:, 0]]).cpu().numpy()
-    cnt = idx[:, 1].cpu().numpy()
-    nonempty = (boxes[:, 3:] > 0).all(axis=1)
-    assert np.abs(sums[nonempty] - 1.0).max() < 1e-5
-    one = nonempty & (boxes[:, 3:] == 1).all(axis=1)
-    first = val[idx[:, 0].clamp(max=nnz - 1)].cpu().numpy()
-    assert one.sum() > 5000 and (cnt[one] == 1).all() and (first[one] == 1.0).all()
-    full = (boxes[:, 3:] == np.array(w.dims, dtype=np.uint32)).all(axis=1)
-    rng = np.random.default_rng(4)
-    sample = np.unique(np.concatenate([np.nonzero(full)[0][:2], rng.choice(len(boxes), 150, replace=False)]))
-    ids, vol_c = scan.compact(vol)
-    _, ref = scan.box_counts(vol_c, len(ids), boxes[sample])
-    ih = idx.cpu().numpy()
-    dense = np.zeros((len(sample), S))
-    for r, q in enumerate(sample):
-        a, k = int(ih[q, 0]), int(ih[q, 1])
-        dense[r, seg[a:a + k].cpu().numpy()] = val[a:a + k].cpu().numpy()
-    _compare(dense, ref, None, "cfg4 sample")
-
-
 # ------------------------------------------------------------------ TF propagation (a8)
 
 def test_tf_matches_oracle_every_mip_voxel():
@@ -466,26 +427,45 @@ def test_query_sparse_output_small_segment_count_and_truncation():
 
 # ------------------------------------------------------------------ serving loop (continuous batching)
 
-def _served(w, n, qps, **kw):
+def _served(w, n, qps, arrivals=None, **kw):
     from paper_2009_02702_amd.serve import Server
     vol = synth.make_volume(w)
     g = _graph(("serve", w.dims), vol)
     S = g.info()["nseg"]
     boxes = synth.make_boxes(w, n)
-    arrivals = synth.poisson_arrivals(w, n, qps)
+    if arrivals is None:
+        arrivals = synth.poisson_arrivals(w, n, qps)
     tf_index = np.full(n, -1, dtype=np.int64)
     tf_rows = np.arange(0, n, 10)
     tf_index[tf_rows] = np.arange(len(tf_rows))
     tfs = synth.make_tfs(w, S, len(tf_rows))
     srv = Server(g, **kw)
     res = np.zeros((n, S), dtype=np.float32)
-    stats = srv.serve(boxes, arrivals, tf_index, tfs, results=res)
+    col = np.full((n, 4), np.nan, dtype=np.float64)
+    stats = srv.serve(boxes, arrivals, tf_index, tfs, results=res, colours=col)
+    _served.last = {"tf_index": tf_index, "tfs": tfs, "colours": col}
     return g, boxes, res, stats
+
+
+def _check_served_colours(boxes, ref, tag):
+    """Each TF request's served box colour (from its propagated palette, over the box's footprint
+    cubes) equals the mean TF colour over the box's voxels: sum_s p_s TF_s / 255 from the oracle's
+    fractions (the adjoint of the push). Other requests get no colour."""
+    last = _served.last
+    ti, tfs, col = last["tf_index"], last["tfs"], last["colours"]
+    has = ti >= 0
+    assert np.isnan(col[~has]).all(), tag
+    want = np.einsum("qs,qsc->qc", ref[has], tfs[ti[has]].astype(np.float64) / 255.0)
+    empty = ref[has].sum(axis=1) == 0
+    want[empty] = 0.0
+    assert np.isfinite(col[has]).all(), tag
+    assert np.abs(col[has] - want).max() <= 1e-5, "%s: colour err %g" % (tag, np.abs(col[has] - want).max())
 
 
 def test_serving_results_equal_alone_and_in_the_mix():
     """Every served result (admitted in batches that overlap on several streams, replayed from
-    captured graphs) matches the same box queried alone, and the oracle."""
+    captured graphs) matches the same box queried alone, and the oracle; every TF request's box
+    colour matches the oracle's mean colour and the same colouring run alone."""
     w = synth.workload(5, dims=(140, 130, 100), segments=80)
     g, boxes, res, stats = _served(w, 3000, 20000.0, slots=3, max_batch=256, max_tf=8)
     assert np.isfinite(stats.latency_s).all() and (stats.latency_s >= 0).all()
@@ -495,7 +475,45 @@ def test_serving_results_equal_alone_and_in_the_mix():
     _compare(res, ref, None, "served")
     alone = np.stack([g.query(_dev(boxes[i:i + 1])).cpu().numpy()[0] for i in range(0, 3000, 97)])
     _compare(res[::97], alone.astype(np.float64), None, "served vs alone")
-    print(stats.summary())
+    _check_served_colours(boxes, ref, "served colours")
+    # the same colouring alone: propagate request 0's TF and colour its box on the default stream
+    last = _served.last
+    i0 = int(np.nonzero(last["tf_index"] >= 0)[0][0])
+    pal = g.propagate_tf(torch.from_numpy(last["tfs"][last["tf_index"][i0]][None].copy()).cuda())
+    one = g.box_colour(pal, _dev(boxes[i0:i0 + 1]), torch.zeros(1, dtype=torch.int32, device="cuda"))
+    assert np.abs(one.cpu().numpy()[0] - last["colours"][i0]).max() <= 1e-6
+    s = stats.summary()
+    assert s["batch_ms"]["device_max"] > 0
+    print(s)
+
+
+def test_serving_full_batches_above_every_default_class():
+    """max_batch outside the default size classes (512) with every request arriving at once, so
+    batches fill to max_batch: every row is answered (a regression test for batches larger than
+    the largest captured graph)."""
+    w = synth.workload(5, dims=(120, 100, 90), segments=60)
+    n = 2000
+    g, boxes, res, stats = _served(w, n, 1.0, arrivals=np.zeros(n), slots=2, max_batch=512, max_tf=64,
+                                   split_cubes=1 << 30)
+    assert max(stats.batch_sizes) == 512
+    ids, vol_c = scan.compact(synth.make_volume(w))
+    _, ref = scan.box_counts(vol_c, len(ids), boxes)
+    _compare(res, ref, None, "full batches")
+    _check_served_colours(boxes, ref, "full batches colours")
+
+
+def test_serving_rejects_tf_requests_without_tf_slots():
+    from paper_2009_02702_amd.serve import Server
+    w = synth.workload(5, dims=(60, 50, 40), segments=20)
+    g = _graph(("serve", w.dims), synth.make_volume(w))
+    srv = Server(g, slots=1, max_batch=64, max_tf=0, use_graphs=False)
+    boxes = synth.make_boxes(w, 10)
+    ti = np.full(10, -1)
+    ti[0] = 0
+    with pytest.raises(ValueError):
+        srv.serve(boxes, np.zeros(10), ti, synth.make_tfs(w, g.info()["nseg"], 1))
+    st = srv.serve(boxes, np.zeros(10))   # boxes alone still work
+    assert st.batches >= 1
 
 
 def test_serving_splits_big_boxes_into_sub_boxes():
@@ -514,6 +532,7 @@ def test_serving_splits_big_boxes_into_sub_boxes():
     ids, vol_c = scan.compact(synth.make_volume(w))
     _, ref = scan.box_counts(vol_c, len(ids), boxes)
     _compare(res, ref, None, "served with splits")
+    _check_served_colours(boxes, ref, "served with splits colours")
 
 
 def test_serving_small_budget_queues_instead_of_failing():

@@ -102,6 +102,20 @@ def test_o1_compaction_keeps_id_order():
     assert counts[0].tolist() == [2, 1, 1]
 
 
+def test_o1_compaction_table_path_equals_numpy_unique():
+    """The linear-time compaction (IDs below 2^28) gives what numpy.unique gives; IDs of 2^28 and
+    above take numpy.unique itself."""
+    rng = np.random.default_rng(3)
+    for hi in (5, 1000, (1 << 28) - 1, 1 << 31):
+        vol = rng.integers(0, hi, size=(7, 9, 11), dtype=np.uint64).astype(np.uint32)
+        vol[0, 0, 0] = hi - 1
+        ids, vc = scan.compact(vol)
+        u, inv = np.unique(vol.ravel(), return_inverse=True)
+        assert ids.tolist() == u.tolist()
+        assert np.array_equal(vc.ravel(), inv.astype(np.uint32))
+        assert vc.shape == vol.shape and vc.dtype == np.uint32
+
+
 # ------------------------------------------------------------------ footprint assembly
 
 def test_footprint_paper_figure_2d():
