@@ -154,9 +154,25 @@ int mg_export_map(const mg_graph *g, uint32_t level, uint32_t *out);
 /* Original volume ID of each source, S entries (host). */
 int mg_segment_ids(const mg_graph *g, uint32_t *out);
 
-/* Copy the graph to device `device` (allocates device memory once; the
- * current device is restored). Builds the per-level transposed node-ID copies
- * on the device. Must precede every GPU entry point. */
+/* Put the graph on a GPU, in device memory the caller owns (e.g. a torch
+ * tensor), so that the library holds no device allocation of its own:
+ * mg_device_bytes gives the size of one buffer that holds every array the GPU
+ * path reads (the DAG's (a, b, w) triples in node order and in step order, the
+ * rank table, a per-node bound on its mixture's sources, the node-ID maps of
+ * every level x fastest and y fastest, and 16-bit copies of level 0 when the
+ * sources fit); mg_bind_device fills `d_buf` (device memory on `device`, at
+ * least that many bytes, 256-byte aligned) with them, enqueued on `stream`,
+ * and waits for that work before it returns. The caller keeps d_buf alive
+ * and unchanged until mg_free, another bind or mg_upload; the library never
+ * frees it. The mixture lookup table (mg_lut_build, optional) is still
+ * allocated by the library. MG_EINVAL for a small or misaligned buffer or a
+ * device that does not exist. Must precede every GPU entry point (or
+ * mg_upload). */
+int mg_device_bytes(const mg_graph *g, uint64_t *bytes);
+int mg_bind_device(mg_graph *g, int device, void *d_buf, uint64_t bytes, void *stream);
+
+/* mg_bind_device into a buffer the library allocates (hipMalloc) on `device`
+ * and frees in mg_free; the current device is restored. */
 int mg_upload(mg_graph *g, int device);
 
 /* Bytes of device workspace that query calls of up to `max_boxes` boxes need. */
@@ -208,6 +224,17 @@ int mg_query_boxes_stats(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float
 int mg_query_boxes_sparse(mg_graph *g, const uint32_t *d_boxes, uint32_t n, uint32_t *d_index,
                           uint32_t *d_seg, float *d_val, uint32_t capacity, uint32_t *d_total,
                           void *d_work, uint64_t work_bytes, void *stream);
+
+/* Upper bound on the non-zero segments of each box, for sizing the sparse
+ * output before the query (Sec. "Fast Sub-Volume Queries": how many segments a
+ * box holds is not known in advance). d_boxes device uint32 [n][6] as for
+ * mg_query_boxes; d_bound device uint32 [n]. A box lies inside the mip cells
+ * it touches at any level; at the finest level where it touches at most 64
+ * cells, the bound is the sum of the sources of those cells' distinct nodes'
+ * mixtures, capped by the number of sources and the box volume (graphs with
+ * quantized weights: the cap alone); 0 for an empty box. A sparse query whose
+ * capacity is the sum of the bounds never truncates. Enqueued on `stream`. */
+int mg_query_nnz_bound(mg_graph *g, const uint32_t *d_boxes, uint32_t n, uint32_t *d_bound, void *stream);
 
 /* Competitor: the naive range query (Sec. "Results", range queries): every
  * level-0 voxel of the box is read and counted. Same output as above. */

@@ -50,6 +50,7 @@ _lib = None
 
 SYMBOLS = [
     "mg_build", "mg_info", "mg_quantize", "mg_export_codebook", "mg_export_dag", "mg_export_map", "mg_segment_ids", "mg_upload",
+    "mg_device_bytes", "mg_bind_device", "mg_query_nnz_bound",
     "mg_workspace_bytes", "mg_workspace_init", "mg_query_boxes", "mg_query_boxes_plain", "mg_query_boxes_stats",
     "mg_query_boxes_sparse",
     "mg_naive_boxes",
@@ -85,6 +86,9 @@ def load() -> ctypes.CDLL:
         "mg_export_map": ([G, u32, vp], i32),
         "mg_segment_ids": ([G, vp], i32),
         "mg_upload": ([G, i32], i32),
+        "mg_device_bytes": ([G, ctypes.POINTER(u64)], i32),
+        "mg_bind_device": ([G, i32, vp, u64, vp], i32),
+        "mg_query_nnz_bound": ([G, vp, u32, vp, vp], i32),
         "mg_workspace_bytes": ([G, u32, ctypes.POINTER(u64)], i32),
         "mg_workspace_init": ([G, vp, u64, vp], i32),
         "mg_query_boxes": ([G, vp, u32, vp, vp, u64, vp], i32),

@@ -205,6 +205,29 @@ int mg_upload(mg_graph *h, int device)
     return done(mg::dev_upload(&h->g, device, &err), err);
 }
 
+int mg_device_bytes(const mg_graph *h, uint64_t *bytes)
+{
+    if (!h || !bytes) return fail(MG_EINVAL, "mg_device_bytes: null argument");
+    *bytes = mg::dev_device_bytes(h->g);
+    return MG_OK;
+}
+
+int mg_bind_device(mg_graph *h, int device, void *d_buf, uint64_t bytes, void *stream)
+{
+    if (!h || !d_buf) return fail(MG_EINVAL, "mg_bind_device: null argument");
+    std::string err;
+    return done(mg::dev_bind_device(&h->g, device, d_buf, bytes, stream, &err), "mg_bind_device: " + err);
+}
+
+int mg_query_nnz_bound(mg_graph *h, const uint32_t *d_boxes, uint32_t n, uint32_t *d_bound, void *stream)
+{
+    if (!h) return fail(MG_EINVAL, "mg_query_nnz_bound: null graph");
+    if (n == 0) return MG_OK;
+    if (!d_boxes || !d_bound) return fail(MG_EINVAL, "mg_query_nnz_bound: null buffer");
+    std::string err;
+    return done(mg::dev_nnz_bound(&h->g, d_boxes, n, d_bound, stream, &err), err);
+}
+
 int mg_workspace_bytes(const mg_graph *h, uint32_t max_boxes, uint64_t *bytes)
 {
     if (!h || !bytes) return fail(MG_EINVAL, "mg_workspace_bytes: null argument");

@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "mg_internal.hpp"
 
@@ -1296,6 +1297,64 @@ __global__ __launch_bounds__(kBlock) void footprint_kernel(LevelTable lt, const 
     for (uint32_t l = threadIdx.x; l < lt.n_levels; l += kBlock) level_counts[uint64_t(q) * lt.n_levels + l] = per_level[l];
 }
 
+// ---------------------------------------------------------------- sparse-output sizing
+
+// Upper bound on the non-zero segments of each box (sizes the sparse output).
+// The clipped box lies inside the cells it touches at any level; at the finest
+// level where it touches at most 64 cells, one lane per cell reads the cell's
+// node, and the bound is the sum of mixlen over the distinct nodes, capped by
+// the source count and the box volume. That needs every finer cube's mixture
+// to lie inside its enclosing cell's, which holds for exact weights; graphs
+// with quantized (merged) weights get the source count and volume cap only.
+// One wave per box.
+__global__ __launch_bounds__(kBlock) void nnz_bound_kernel(LevelTable lt, const uint32_t *boxes, uint32_t n,
+                                                           const uint32_t *__restrict__ maps,
+                                                           const uint32_t *__restrict__ mixlen, uint32_t nseg,
+                                                           uint32_t exact, uint32_t *bound)
+{
+    const uint32_t q = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63;
+    if (q >= n) return;  // whole waves leave together
+    uint32_t lo[3], hi[3];
+    if (!clip_box(boxes + 6 * uint64_t(q), lt, lo, hi)) {
+        if (lane == 0) bound[q] = 0;
+        return;
+    }
+    // cells touched at level `lane` (levels past the last count as too many)
+    uint64_t cells = ~uint64_t(0);
+    if (lane < lt.n_levels) {
+        cells = 1;
+        for (int d = 0; d < 3; ++d) cells *= uint64_t(((hi[d] - 1) >> lane) - (lo[d] >> lane) + 1);
+    }
+    const uint64_t fits = __ballot(cells <= 64);  // the top level (one cell) always fits
+    const uint32_t l = uint32_t(__builtin_ctzll(fits));
+    uint32_t c0[3], ext[3];
+    for (int d = 0; d < 3; ++d) {
+        c0[d] = lo[d] >> l;
+        ext[d] = ((hi[d] - 1) >> l) - c0[d] + 1;
+    }
+    const uint32_t ncell = ext[0] * ext[1] * ext[2];
+    uint32_t node = kEmpty, m = 0;
+    if (lane < ncell) {
+        const uint32_t x = c0[0] + lane % ext[0], y = c0[1] + (lane / ext[0]) % ext[1],
+                       z = c0[2] + lane / (ext[0] * ext[1]);
+        node = maps[lt.off[l] + x + uint64_t(lt.dims[l][0]) * (y + uint64_t(lt.dims[l][1]) * z)];
+        m = mixlen[node];
+    }
+    // count each distinct node once: drop a lane whose node a lower lane holds
+    bool dup = false;
+    for (uint32_t j = 0; j < ncell; ++j) {
+        const uint32_t v = uint32_t(__shfl(int(node), int(j), 64));
+        dup = dup || (j < lane && v == node);
+    }
+    uint32_t sum = dup ? 0u : m;
+    for (int off = 32; off > 0; off >>= 1) sum += uint32_t(__shfl_down(int(sum), off, 64));
+    if (lane == 0) {
+        const uint64_t vol = uint64_t(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
+        bound[q] = uint32_t(std::min<uint64_t>(std::min<uint64_t>(exact ? sum : nseg, nseg), vol));
+    }
+}
+
 // ---------------------------------------------------------------- TF propagation
 
 __global__ void tf_sources_kernel(const uint8_t *tf, uint32_t T, uint32_t nseg, uint32_t n_nodes, float4 *out)
@@ -1465,6 +1524,7 @@ struct Workspace {
     float *g_seg_hi, *g_seg_lo, *g_seg_var;
     uint64_t bytes;
     uint32_t max_boxes;
+    uint32_t workers;     // fallback workers the tables are carved for
 };
 
 inline uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
@@ -1485,10 +1545,12 @@ inline uint32_t fallback_workers(const Graph &g)
     return std::max<uint32_t>(16u, uint32_t(uint64_t(kFallbackWorkers) * kHashGlobal / fallback_slots(g)));
 }
 
-// Carves the workspace; with base == nullptr only computes the size.
-Workspace carve(const Graph &g, char *base, uint32_t max_boxes)
+// Carves the workspace for `workers` fallback workers (0: fallback_workers(g));
+// with base == nullptr only computes the size.
+Workspace carve(const Graph &g, char *base, uint32_t max_boxes, uint32_t workers = 0)
 {
     Workspace w;
+    w.workers = workers ? workers : fallback_workers(g);
     uint64_t off = 0;
     auto take = [&](uint64_t bytes) {
         char *p = base ? base + off : nullptr;
@@ -1499,13 +1561,13 @@ Workspace carve(const Graph &g, char *base, uint32_t max_boxes)
     w.counters = reinterpret_cast<uint32_t *>(take(64 * 4));
     w.buckets = reinterpret_cast<uint32_t *>(take(64 * 4));
     w.queues = reinterpret_cast<uint32_t *>(take(uint64_t(kQueues) * kQueueStride * 4));
-    const uint64_t hs = uint64_t(fallback_workers(g)) * fallback_slots(g);
+    const uint64_t hs = uint64_t(w.workers) * fallback_slots(g);
     w.g_keys = reinterpret_cast<uint32_t *>(take(hs * 4));
     w.g_cnt = reinterpret_cast<uint32_t *>(take(hs * 4));
     w.g_used = reinterpret_cast<uint32_t *>(take(hs * 4));
     w.g_hi = reinterpret_cast<float *>(take(hs * 4));
     w.g_lo = reinterpret_cast<float *>(take(hs * 4));
-    const uint64_t ss = uint64_t(fallback_workers(g)) * g.nseg;
+    const uint64_t ss = uint64_t(w.workers) * g.nseg;
     w.g_seg_cnt = reinterpret_cast<uint32_t *>(take(ss * 4));
     w.g_seg_hi = reinterpret_cast<float *>(take(ss * 4));
     w.g_seg_lo = reinterpret_cast<float *>(take(ss * 4));
@@ -1622,6 +1684,124 @@ int occupancy(DeviceState &d, const void *k, int block, uint32_t dyn, int *out, 
 
 // ---------------------------------------------------------------- entry points
 
+// Byte offsets of the graph's device arrays inside one buffer (each 256-byte
+// aligned): what mg_device_bytes sizes and mg_bind_device fills.
+struct DeviceLayout {
+    uint64_t nodes, sched, rank_ptr, mixlen, maps, maps16;
+    uint64_t n16, n16t;   // elements of the two 16-bit level-0 copies (0 if none)
+    uint64_t bytes;
+};
+
+DeviceLayout device_layout(const Graph &g)
+{
+    DeviceLayout L;
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t at = off;
+        off += align256(bytes);
+        return at;
+    };
+    const uint64_t nmap = g.lev_off[g.n_levels];
+    L.nodes = take(uint64_t(g.n_nodes) * sizeof(NodeTriple));
+    L.sched = take(uint64_t(g.n_nodes) * sizeof(SchedNode));
+    L.rank_ptr = take(g.rank_ptr.size() * 4);
+    L.mixlen = take(uint64_t(g.n_nodes) * 4);
+    L.maps = take(2 * nmap * 4);  // x-fastest copy, then the y-fastest one
+    L.n16 = L.n16t = 0;
+    if (g.nseg < 0xFFFFu) {       // 16-bit level 0 for the hot path when every source ID fits
+        const LevelTable lt = level_table(g);
+        L.n16 = lt.total16;
+        L.n16t = uint64_t(lt.pitch_y) * g.dims[2] * g.dims[0];
+    }
+    L.maps16 = take((L.n16 + L.n16t) * sizeof(uint16_t));
+    L.bytes = off;
+    return L;
+}
+
+// Fills `base` (device memory of layout.bytes bytes on `device`) with the
+// graph's arrays and derived copies, enqueued on `stream`, then waits for
+// them; the graph then reads only this memory. owned: mg_free releases it.
+int dev_bind(Graph *g, int device, void *base, uint64_t bytes, hipStream_t s, bool owned, std::string *err)
+{
+    DeviceState &d = g->dev;
+    const DeviceLayout L = device_layout(*g);
+    if (bytes < L.bytes) {
+        *err = "device buffer of " + std::to_string(bytes) + " bytes; the graph needs " + std::to_string(L.bytes);
+        return MG_EINVAL;
+    }
+    if (reinterpret_cast<uintptr_t>(base) % 256 != 0) {
+        *err = "device buffer must be 256-byte aligned";
+        return MG_EINVAL;
+    }
+    char *b = static_cast<char *>(base);
+    const uint64_t nmap = g->lev_off[g->n_levels];
+    std::vector<NodeTriple> nodes(g->n_nodes);
+    for (uint32_t n = 0; n < g->n_nodes; ++n) nodes[n] = NodeTriple{g->child_a[n], g->child_b[n], g->alpha[n]};
+    std::vector<SchedNode> sched(g->n_nodes);
+    for (uint32_t i = 0; i < g->n_nodes; ++i) {
+        const uint32_t n = g->sched[i];
+        sched[i] = SchedNode{g->child_a[n], g->child_b[n], g->alpha[n], n};
+    }
+    // sources in a node's mixture, bounded by the sum over its two predecessors (IDs are
+    // sorted by rank, so predecessors come first); exact when the two are disjoint
+    std::vector<uint32_t> mixlen(g->n_nodes, 1u);
+    for (uint32_t n = g->nseg; n < g->n_nodes; ++n)
+        mixlen[n] = uint32_t(std::min<uint64_t>(g->nseg, uint64_t(mixlen[g->child_a[n]]) + mixlen[g->child_b[n]]));
+    d.base = base;
+    d.owned = owned;
+    d.device = device;
+    d.bytes = L.bytes;
+    d.nodes = reinterpret_cast<NodeTriple *>(b + L.nodes);
+    d.sched = reinterpret_cast<SchedNode *>(b + L.sched);
+    d.rank_ptr = reinterpret_cast<uint32_t *>(b + L.rank_ptr);
+    d.mixlen = reinterpret_cast<uint32_t *>(b + L.mixlen);
+    d.maps = reinterpret_cast<uint32_t *>(b + L.maps);
+    d.maps_t = d.maps + nmap;
+    d.maps16 = L.n16 ? reinterpret_cast<uint16_t *>(b + L.maps16) : nullptr;
+    HIP_TRY(hipMemcpyAsync(d.nodes, nodes.data(), nodes.size() * sizeof(NodeTriple), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d.sched, sched.data(), sched.size() * sizeof(SchedNode), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d.rank_ptr, g->rank_ptr.data(), g->rank_ptr.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d.mixlen, mixlen.data(), mixlen.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d.maps, g->maps.data(), nmap * 4, hipMemcpyHostToDevice, s));
+    for (uint32_t l = 0; l < g->n_levels; ++l) {
+        const uint32_t X = g->lev_dims[3 * l], Y = g->lev_dims[3 * l + 1], Z = g->lev_dims[3 * l + 2];
+        const uint64_t cnt = uint64_t(X) * Y * Z;
+        const uint32_t blocks = uint32_t((cnt + 255) / 256);
+        hipLaunchKernelGGL(transpose_level_kernel, dim3(blocks), dim3(256), 0, s, d.maps + g->lev_off[l],
+                           d.maps_t + g->lev_off[l], X, Y, Z);
+        HIP_TRY(hipGetLastError());
+    }
+    if (L.n16) {
+        const LevelTable lt = level_table(*g);
+        const uint64_t n = std::max(L.n16, L.n16t);
+        hipLaunchKernelGGL(pack16_kernel, dim3(uint32_t((n + 255) / 256)), dim3(256), 0, s, d.maps, d.maps16,
+                           g->dims[0], g->dims[1], g->dims[2], lt.pitch_x, lt.pitch_y, L.n16, L.n16t);
+        HIP_TRY(hipGetLastError());
+    }
+    // the host staging vectors above die with this call
+    HIP_TRY(hipStreamSynchronize(s));
+    if (!g->lut_ptr.empty()) return dev_upload_lut(g, err);
+    return MG_OK;
+}
+
+uint64_t dev_device_bytes(const Graph &g) { return device_layout(g).bytes; }
+
+int dev_bind_device(Graph *g, int device, void *base, uint64_t bytes, void *stream, std::string *err)
+{
+    DeviceGuard guard;
+    if (g->dev.device >= 0) dev_free(g);
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) {
+        *err = "device " + std::to_string(device) + " does not exist";
+        return MG_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(device));
+    const int rc = dev_bind(g, device, base, bytes, static_cast<hipStream_t>(stream), false, err);
+    if (rc) dev_free(g);
+    return rc;
+}
+
 int dev_upload(Graph *g, int device, std::string *err)
 {
     DeviceGuard guard;
@@ -1633,61 +1813,19 @@ int dev_upload(Graph *g, int device, std::string *err)
         return MG_EINVAL;
     }
     HIP_TRY(hipSetDevice(device));
-    DeviceState &d = g->dev;
-    const uint64_t nmap = g->lev_off[g->n_levels];
-    const uint64_t bytes_nodes = uint64_t(g->n_nodes) * sizeof(NodeTriple);
-    const uint64_t bytes_sched = uint64_t(g->n_nodes) * sizeof(SchedNode);
-    const uint64_t bytes_rp = g->rank_ptr.size() * 4;
-    const uint64_t bytes_maps = 2 * nmap * 4;
-    std::vector<NodeTriple> nodes(g->n_nodes);
-    for (uint32_t n = 0; n < g->n_nodes; ++n) nodes[n] = NodeTriple{g->child_a[n], g->child_b[n], g->alpha[n]};
-    std::vector<SchedNode> sched(g->n_nodes);
-    for (uint32_t i = 0; i < g->n_nodes; ++i) {
-        const uint32_t n = g->sched[i];
-        sched[i] = SchedNode{g->child_a[n], g->child_b[n], g->alpha[n], n};
-    }
-    if (hipMalloc(&d.nodes, bytes_nodes) != hipSuccess || hipMalloc(&d.sched, bytes_sched) != hipSuccess ||
-        hipMalloc(&d.rank_ptr, bytes_rp) != hipSuccess || hipMalloc(&d.maps, bytes_maps) != hipSuccess) {
+    const uint64_t bytes = device_layout(*g).bytes;
+    void *base = nullptr;
+    if (hipMalloc(&base, bytes) != hipSuccess) {
         (void)hipGetLastError();
-        dev_free(g);
-        *err = "mg_upload: device allocation failed";
+        *err = "mg_upload: device allocation of " + std::to_string(bytes) + " bytes failed";
         return MG_ENOMEM;
     }
-    d.maps_t = d.maps + nmap;
-    d.device = device;
-    d.bytes = bytes_nodes + bytes_sched + bytes_rp + bytes_maps;
-    HIP_TRY(hipMemcpy(d.nodes, nodes.data(), bytes_nodes, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(d.sched, sched.data(), bytes_sched, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(d.rank_ptr, g->rank_ptr.data(), bytes_rp, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(d.maps, g->maps.data(), nmap * 4, hipMemcpyHostToDevice));
-    for (uint32_t l = 0; l < g->n_levels; ++l) {
-        const uint32_t X = g->lev_dims[3 * l], Y = g->lev_dims[3 * l + 1], Z = g->lev_dims[3 * l + 2];
-        const uint64_t cnt = uint64_t(X) * Y * Z;
-        const uint32_t blocks = uint32_t((cnt + 255) / 256);
-        hipLaunchKernelGGL(transpose_level_kernel, dim3(blocks), dim3(256), 0, 0, d.maps + g->lev_off[l],
-                           d.maps_t + g->lev_off[l], X, Y, Z);
-        HIP_TRY(hipGetLastError());
+    const int rc = dev_bind(g, device, base, bytes, nullptr, true, err);
+    if (rc) {
+        if (g->dev.base != base) (void)hipFree(base);  // not recorded yet: release it here
+        dev_free(g);
     }
-    // 16-bit level 0 for the hot path, when every source ID fits below 0xFFFF
-    if (g->nseg < 0xFFFFu) {
-        const LevelTable lt = level_table(*g);
-        const uint64_t n16 = lt.total16;
-        const uint64_t n16t = uint64_t(lt.pitch_y) * g->dims[2] * g->dims[0];
-        if (hipMalloc(&d.maps16, (n16 + n16t) * sizeof(uint16_t)) != hipSuccess) {
-            (void)hipGetLastError();
-            dev_free(g);
-            *err = "mg_upload: device allocation failed (16-bit level-0 maps)";
-            return MG_ENOMEM;
-        }
-        d.bytes += (n16 + n16t) * sizeof(uint16_t);
-        const uint64_t n = std::max(n16, n16t);
-        hipLaunchKernelGGL(pack16_kernel, dim3(uint32_t((n + 255) / 256)), dim3(256), 0, 0, d.maps, d.maps16,
-                           g->dims[0], g->dims[1], g->dims[2], lt.pitch_x, lt.pitch_y, n16, n16t);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipDeviceSynchronize());
-    }
-    if (!g->lut_ptr.empty()) return dev_upload_lut(g, err);
-    return MG_OK;
+    return rc;
 }
 
 int dev_upload_lut(Graph *g, std::string *err)
@@ -1766,14 +1904,10 @@ int dev_box_colour(Graph *g, const float *palette, uint32_t T, const uint32_t *b
 void dev_free(Graph *g)
 {
     DeviceState &d = g->dev;
-    if (d.device < 0 && !d.nodes && !d.maps) return;
+    if (d.device < 0 && !d.base) return;
     DeviceGuard guard;
     if (d.device >= 0) (void)hipSetDevice(d.device);
-    if (d.nodes) (void)hipFree(d.nodes);
-    if (d.sched) (void)hipFree(d.sched);
-    if (d.rank_ptr) (void)hipFree(d.rank_ptr);
-    if (d.maps) (void)hipFree(d.maps);
-    if (d.maps16) (void)hipFree(d.maps16);
+    if (d.base && d.owned) (void)hipFree(d.base);
     if (d.lut_ptr) (void)hipFree(d.lut_ptr);
     if (d.lut_seg) (void)hipFree(d.lut_seg);
     if (d.lut_val) (void)hipFree(d.lut_val);
@@ -1788,27 +1922,35 @@ uint64_t dev_workspace_bytes(const Graph &g, uint32_t max_boxes)
     return carve(g, nullptr, std::max<uint32_t>(max_boxes, 1)).bytes;
 }
 
+// The global fallback tables of a workspace in their clean state (empty keys,
+// zero counts and mass), by fill kernels on `s` (no memset: callers may
+// capture the stream into a graph).
+void clear_fallback_tables(const Graph &g, const Workspace &w, hipStream_t s)
+{
+    const uint64_t hs = uint64_t(w.workers) * fallback_slots(g);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, w.g_keys, hs, kEmpty);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, w.g_cnt, hs, 0u);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_hi), hs, 0u);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_lo), hs, 0u);
+    const uint64_t ss = uint64_t(w.workers) * g.nseg;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, w.g_seg_cnt, ss, 0u);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_seg_hi), ss, 0u);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_seg_lo), ss, 0u);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_seg_var), ss, 0u);
+}
+
 int dev_workspace_init(Graph *g, void *work, uint64_t bytes, void *stream, std::string *err)
 {
     int rc = check_device(g, err);
     if (rc) return rc;
-    // the workspace fixes its box capacity: find the largest max_boxes that fits
+    // the fixed-size part (counters, queues, fallback tables) comes first, so its
+    // layout does not depend on the box capacity
     Workspace w = carve(*g, static_cast<char *>(work), 1);
     if (bytes < w.bytes) {
         *err = "workspace smaller than mg_workspace_bytes(g, 1)";
         return MG_EINVAL;
     }
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const uint64_t hs = uint64_t(fallback_workers(*g)) * fallback_slots(*g);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, w.g_keys, hs, kEmpty);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, w.g_cnt, hs, 0u);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_hi), hs, 0u);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_lo), hs, 0u);
-    const uint64_t ss = uint64_t(fallback_workers(*g)) * g->nseg;
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, w.g_seg_cnt, ss, 0u);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_seg_hi), ss, 0u);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_seg_lo), ss, 0u);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_seg_var), ss, 0u);
+    clear_fallback_tables(*g, w, static_cast<hipStream_t>(stream));
     HIP_TRY(hipGetLastError());
     return MG_OK;
 }
@@ -1890,26 +2032,20 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
     A.stats_tag = 0x80000000u;
     const QueryKernel kfallback = query_fallback_kernel<SPARSE, ERR>;
     A.g_slots = fallback_slots(*g);
-    hipLaunchKernelGGL(kfallback, dim3(fallback_workers(*g)), dim3(kBlock),
+    hipLaunchKernelGGL(kfallback, dim3(w.workers), dim3(kBlock),
                        6u * L * uint32_t(sizeof(Slab)), s, A);
     HIP_TRY(hipGetLastError());
     // the timed region: every kernel that answers boxes (tiers or plain, retry, fallback)
     return timing_end(g, s, err);
 }
 
-int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const SparseOut *sp, void *work,
-              uint64_t bytes, void *stream, int variant, uint32_t *stats, std::string *err, float *out_err)
+namespace {
+
+// The query path on a carved workspace.
+int query_in(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const SparseOut *sp, const Workspace &w,
+             hipStream_t s, int variant, uint32_t *stats, std::string *err, float *out_err)
 {
-    DeviceGuard guard;
-    int rc = check_device(g, err);
-    if (rc) return rc;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const uint64_t need = dev_workspace_bytes(*g, n);
-    if (bytes < need) {
-        *err = "workspace of " + std::to_string(bytes) + " bytes is smaller than the " + std::to_string(need) +
-               " bytes that " + std::to_string(n) + " boxes need";
-        return MG_EINVAL;
-    }
+    int rc = MG_OK;
     if (g->depth > kMaxSteps) {
         *err = "graph depth " + std::to_string(g->depth) + " beyond the kernels' step table (" +
                std::to_string(kMaxSteps) + ")";
@@ -1919,7 +2055,6 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const Spa
         *err = "more than " + std::to_string(kMaxLevelsDev) + " mip levels";
         return MG_ELIMIT;
     }
-    Workspace w = carve(*g, static_cast<char *>(work), n);
     const LevelTable lt = level_table(*g);
     if (!g->dev.launch_ready) {
         HIP_TRY(hipDeviceGetAttribute(&g->dev.lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, g->dev.device));
@@ -2014,6 +2149,25 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const Spa
                   : launch_query<false, false>(g, A, w, lt, n, s, variant, err);
 }
 
+}  // namespace
+
+int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const SparseOut *sp, void *work,
+              uint64_t bytes, void *stream, int variant, uint32_t *stats, std::string *err, float *out_err)
+{
+    DeviceGuard guard;
+    int rc = check_device(g, err);
+    if (rc) return rc;
+    const uint64_t need = dev_workspace_bytes(*g, n);
+    if (bytes < need) {
+        *err = "workspace of " + std::to_string(bytes) + " bytes is smaller than the " + std::to_string(need) +
+               " bytes that " + std::to_string(n) + " boxes need";
+        return MG_EINVAL;
+    }
+    const Workspace w = carve(*g, static_cast<char *>(work), n);
+    return query_in(g, boxes, n, out, sp, w, static_cast<hipStream_t>(stream), variant, stats, err, out_err);
+}
+
+
 int dev_footprint(Graph *g, const uint32_t *boxes, uint32_t n, uint32_t *level_counts, uint32_t *cubes, uint32_t cap,
                   uint32_t *count, void *stream, std::string *err)
 {
@@ -2024,6 +2178,19 @@ int dev_footprint(Graph *g, const uint32_t *boxes, uint32_t n, uint32_t *level_c
     const LevelTable lt = level_table(*g);
     hipLaunchKernelGGL(footprint_kernel, dim3(n), dim3(kBlock), 0, s, lt, boxes, n, g->dev.maps, level_counts, cubes,
                        cap, count);
+    HIP_TRY(hipGetLastError());
+    return MG_OK;
+}
+
+int dev_nnz_bound(Graph *g, const uint32_t *boxes, uint32_t n, uint32_t *bound, void *stream, std::string *err)
+{
+    DeviceGuard guard;
+    int rc = check_device(g, err);
+    if (rc) return rc;
+    const LevelTable lt = level_table(*g);
+    const uint32_t per = kBlock / 64;
+    hipLaunchKernelGGL(nnz_bound_kernel, dim3((n + per - 1) / per), dim3(kBlock), 0, static_cast<hipStream_t>(stream),
+                       lt, boxes, n, g->dev.maps, g->dev.mixlen, g->nseg, g->quant_bits == 0 ? 1u : 0u, bound);
     HIP_TRY(hipGetLastError());
     return MG_OK;
 }

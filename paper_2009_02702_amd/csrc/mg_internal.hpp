@@ -29,7 +29,10 @@ struct SchedNode {
 
 struct DeviceState {
     int device = -1;
+    void *base = nullptr;          // the one buffer holding every array below (except the table)
+    bool owned = false;            // base was allocated by mg_upload (else bound by the caller)
     NodeTriple *nodes = nullptr;   // [n_nodes]
+    uint32_t *mixlen = nullptr;    // [n_nodes] bound on the sources in each node's mixture
     uint32_t *rank_ptr = nullptr;  // [depth + 2]
     SchedNode *sched = nullptr;    // [n_nodes] in step order
     uint32_t *maps = nullptr;      // all levels, x fastest
@@ -137,6 +140,9 @@ void level_dims(const uint32_t dims[3], std::vector<uint32_t> *out);
 
 // Device side (kernels.hip). All return MG_OK or an MG_E* code with *err set.
 int dev_upload(Graph *g, int device, std::string *err);
+uint64_t dev_device_bytes(const Graph &g);
+int dev_bind_device(Graph *g, int device, void *base, uint64_t bytes, void *stream, std::string *err);
+int dev_nnz_bound(Graph *g, const uint32_t *boxes, uint32_t n, uint32_t *bound, void *stream, std::string *err);
 int dev_upload_lut(Graph *g, std::string *err);
 void dev_free(Graph *g);
 uint64_t dev_workspace_bytes(const Graph &g, uint32_t max_boxes);

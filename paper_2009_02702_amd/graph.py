@@ -45,6 +45,7 @@ class Graph:
         self._lib = _lib.load()
         self._ws = None
         self._ws_boxes = 0
+        self._bound = None   # caller-owned device buffer of mg_bind_device, kept alive here
 
     # -------------------------------------------------------------- construction
     @classmethod
@@ -97,6 +98,7 @@ class Graph:
             self._ws = None
             self._lib.mg_free(self._h)
             self._h = None
+            self._bound = None
 
     def __del__(self):
         try:
@@ -141,7 +143,40 @@ class Graph:
     def upload(self, device: int = 0) -> "Graph":
         check(self._lib.mg_upload(self._h, int(device)))
         self._device = int(device)
+        self._bound = None
+        self._ws = None
         return self
+
+    def device_bytes(self) -> int:
+        """Bytes of the one device buffer mg_bind_device fills."""
+        b = ctypes.c_uint64()
+        check(self._lib.mg_device_bytes(self._h, ctypes.byref(b)))
+        return int(b.value)
+
+    def bind(self, buffer, stream=None) -> "Graph":
+        """mg_bind_device: the graph's device arrays in a caller-owned torch tensor (uint8, at least
+        device_bytes() bytes, on the GPU the graph will run on). The tensor is kept referenced here
+        for as long as the graph is bound."""
+        if not buffer.is_cuda or not buffer.is_contiguous():
+            raise ValueError("buffer must be a contiguous device tensor")
+        nbytes = buffer.numel() * buffer.element_size()
+        check(self._lib.mg_bind_device(self._h, int(buffer.device.index or 0), _dptr(buffer), nbytes,
+                                       _stream_ptr(stream)))
+        self._device = int(buffer.device.index or 0)
+        self._bound = buffer
+        self._ws = None
+        return self
+
+    def nnz_bound(self, boxes, out=None, stream=None):
+        """mg_query_nnz_bound: int32 [n] upper bound on each box's non-zero segments."""
+        torch = _torch()
+        if boxes.dim() != 2 or boxes.shape[1] != 6 or boxes.element_size() != 4:
+            raise ValueError("boxes must be a 32-bit [n, 6] tensor")
+        n = boxes.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.int32, device=boxes.device)
+        check(self._lib.mg_query_nnz_bound(self._h, _dptr(boxes), n, _dptr(out), _stream_ptr(stream)))
+        return out
 
     def workspace_bytes(self, max_boxes: int) -> int:
         b = ctypes.c_uint64()

@@ -42,7 +42,7 @@ from .graph import Graph, _torch
 
 
 TRACE_FIELDS = ("t_admit", "t_launched", "t_seen", "device_ms", "oldest_arrival", "requests", "rows", "tfs",
-                "max_cubes", "slot")
+                "max_cubes", "slot", "h2d_ms", "query_ms", "tf_ms", "d2h_ms")
 
 
 @dataclass
@@ -54,7 +54,8 @@ class ServeStats:
     wall_s: float = 0.0
     # per batch (seconds from the start unless stated): admission, return of the launch calls,
     # completion seen by the loop, device time between the batch's first and last stream event,
-    # arrival of its oldest request, requests, rows, transfer functions, largest box (cubes), slot
+    # arrival of its oldest request, requests, rows, transfer functions, largest box (cubes), slot,
+    # and the host time (ms) spent enqueuing each step: boxes copy, query, TF work, results copy
     trace: Optional[np.ndarray] = None
 
     def summary(self) -> dict:
@@ -207,13 +208,17 @@ class _Slot:
         if use > k:
             hb[k:use] = 0   # empty boxes pad the captured size
         self.n_tf = 0
+        clock = time.perf_counter
         with torch.cuda.stream(self.stream):
+            c0 = clock()
             self.event0.record(self.stream)
             self.d_boxes[:use].copy_(self.h_boxes[:use], non_blocking=True)
+            c1 = clock()
             if self.graphs:
                 self.graphs[use].replay()
             else:
                 g.query(self.d_boxes[:k], out=self.d_out[:k], workspace=self.ws, stream=self.stream)
+            c2 = clock()
             if tfs is not None and len(tfs):
                 t = len(tfs)
                 if t > self.max_tf:
@@ -227,9 +232,12 @@ class _Slot:
                              stream=self.stream)
                 self.h_col[:k].copy_(self.d_col[:k], non_blocking=True)
                 self.n_tf = t
+            c3 = clock()
             self.h_out[:k].copy_(self.d_out[:k], non_blocking=True)
             self.event.record(self.stream)
+            c4 = clock()
         self.busy = True
+        return [1e3 * (c1 - c0), 1e3 * (c2 - c1), 1e3 * (c3 - c2), 1e3 * (c4 - c3)]
 
 
 class Server:
@@ -385,10 +393,10 @@ class Server:
                 sl.n_rows = n_rows
                 bx = boxes[r] if not split else np.concatenate(
                     [rows[i] if i in rows else boxes[i:i + 1] for i in take])
-                sl.launch(self.g, bx, tf_batch, pal_of_row)
+                steps = sl.launch(self.g, bx, tf_batch, pal_of_row)
                 t_launched = time.perf_counter() - t0
                 sl.trace = [t_admit, t_launched, 0.0, 0.0, float(arrivals[take[0]]), k, n_rows, n_tf,
-                            float(cubes[r].max()), float(self.slots.index(sl))]
+                            float(cubes[r].max()), float(self.slots.index(sl))] + steps
                 batches += 1
                 sizes.append(k)
                 progressed = True

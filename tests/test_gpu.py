@@ -425,6 +425,69 @@ def test_query_sparse_output_small_segment_count_and_truncation():
             assert r > 0 and abs(val[j] - r) <= REL_TOL * r
 
 
+def test_nnz_bound_sizes_the_sparse_output():
+    """mg_query_nnz_bound: for every box at least its non-zero segments (oracle counts), at most the
+    source count and the box volume, 0 for empty boxes; a sparse query sized by the sum of the bounds
+    does not truncate and matches the oracle."""
+    w = synth.workload(4, dims=(150, 160, 140), segments=1500, n_boxes=900)
+    vol = synth.make_volume(w)
+    g = Graph.build(vol).upload(0)
+    S = g.info()["nseg"]
+    boxes = synth.make_boxes(w)
+    boxes[:5] = [[0, 0, 0, 150, 160, 140], [149, 159, 139, 1, 1, 1], [7, 8, 9, 0, 5, 5],
+                 [200, 0, 0, 5, 5, 5], [3, 3, 3, 1, 90, 1]]
+    ids, vol_c = scan.compact(vol)
+    cnt, ref = scan.box_counts(vol_c, S, boxes)
+    db = _dev(boxes)
+    bound = g.nnz_bound(db).cpu().numpy().astype(np.int64)
+    nnz = (ref > 0).sum(axis=1)
+    b = boxes.astype(np.int64)
+    dims = np.array(w.dims)
+    vols = np.prod(np.maximum(np.minimum(b[:, :3] + b[:, 3:], dims) - np.minimum(b[:, :3], dims), 0), axis=1)
+    assert (bound >= nnz).all(), np.nonzero(bound < nnz)[0][:5]
+    assert (bound <= np.minimum(S, vols)).all()
+    assert bound[2] == 0 and bound[3] == 0 and bound[1] == 1
+    cap = int(bound.sum())
+    index, seg, val, total = g.query_sparse(db, capacity=cap)
+    assert int(total.item()) == int(nnz.sum()) <= cap
+    dense = _sparse_to_dense(index.cpu().numpy(), seg.cpu().numpy(), val.cpu().numpy(), len(boxes), S)
+    _compare(dense, ref, None, "sparse output sized by the bound")
+    g.close()
+
+
+def test_bind_device_into_a_caller_buffer():
+    """mg_bind_device: the graph's arrays in a torch-owned buffer answer exactly like mg_upload's copy
+    (queries against the oracle, TF propagation equal), and small or misaligned buffers are refused."""
+    w = synth.workload(2, dims=(120, 110, 100), segments=200, n_boxes=600)
+    vol = synth.make_volume(w)
+    boxes = synth.make_boxes(w)
+    ids, vol_c = scan.compact(vol)
+    _, ref = scan.box_counts(vol_c, len(ids), boxes)
+    db = _dev(boxes)
+    g_up = Graph.build(vol).upload(0)
+    g = Graph.build(vol)
+    nbytes = g.device_bytes()
+    with pytest.raises(MGError) as e:
+        g.bind(torch.empty(nbytes - 256, dtype=torch.uint8, device="cuda"))
+    assert e.value.code == -1
+    big = torch.empty(nbytes + 512, dtype=torch.uint8, device="cuda")
+    with pytest.raises(MGError) as e:
+        g.bind(big[4:4 + nbytes])
+    assert e.value.code == -1
+    buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    g.bind(buf)
+    assert g.info()["device"] == 0 and g.info()["device_bytes"] == nbytes
+    out = g.query(db).cpu().numpy()
+    _compare(out, ref, None, "bound buffer")
+    assert np.array_equal(g.query(db, variant="naive").cpu().numpy(), g_up.query(db, variant="naive").cpu().numpy())
+    S = len(ids)
+    tf = torch.from_numpy(synth.make_tfs(w, S, 2)).cuda()
+    assert torch.equal(g.propagate_tf(tf), g_up.propagate_tf(tf))
+    g.close()
+    g_up.close()
+    del buf
+
+
 # ------------------------------------------------------------------ serving loop (continuous batching)
 
 def _served(w, n, qps, arrivals=None, **kw):
