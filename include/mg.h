@@ -191,9 +191,10 @@ int mg_workspace_init(mg_graph *g, void *d_work, uint64_t work_bytes, void *stre
  *            is accumulated in fp32 with compensated (two-sum) updates.
  *   d_work   workspace of mg_workspace_bytes(g, n) bytes, initialised once.
  * Boxes whose nodes overflow the per-box LDS tables are redone with a larger
- * LDS table, then in global-memory tables that hold every node of graphs of
- * up to 50,331,647 nodes; only on larger graphs can a box still overflow,
- * and its row is then all NaN.
+ * LDS table, then in global-memory tables: first many workers' tables of
+ * 65,536 slots, then (for what overflows those) tables that hold every node
+ * of graphs of up to 50,331,647 nodes; only on larger graphs can a box still
+ * overflow, and its row is then all NaN.
  */
 int mg_query_boxes(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *d_out,
                    void *d_work, uint64_t work_bytes, void *stream);
@@ -204,9 +205,12 @@ int mg_query_boxes_plain(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float
                          void *d_work, uint64_t work_bytes, void *stream);
 
 /* mg_query_boxes that also reports the work of each box, for roofline
- * accounting: d_stats device uint32 [n][2] = (cubes in the box's footprint,
- * distinct internal graph nodes the box touched: scattered onto or reached
- * by the push). */
+ * accounting: d_stats device uint32 [n][2]. [q][0] = cubes in box q's
+ * footprint. [q][1] bits 0..29 = entries the box's node table held: the
+ * distinct internal nodes it scattered onto or reached by the push, plus,
+ * for graphs with more sources than the LDS source arrays hold, the distinct
+ * sources it touched (a source in those arrays takes no entry); bit 30 = the
+ * box was answered by the retry launch, bit 31 = by a global-memory launch. */
 int mg_query_boxes_stats(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *d_out,
                          uint32_t *d_stats, void *d_work, uint64_t work_bytes, void *stream);
 
@@ -240,6 +244,19 @@ int mg_query_nnz_bound(mg_graph *g, const uint32_t *d_boxes, uint32_t n, uint32_
  * level-0 voxel of the box is read and counted. Same output as above. */
 int mg_naive_boxes(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *d_out,
                    void *d_work, uint64_t work_bytes, void *stream);
+
+/* Host-side check of the query kernels' load addresses (no GPU needed): for
+ * boxes (host uint32 [n][6]) on a volume of nx x ny x nz voxels, replays every
+ * load the batched query kernels issue (all `unroll` loads of every block, 4, 8
+ * or 16), with the kernels' own slab builder and tile-walk helpers. flags: bit
+ * 0 = level 0 from the 16-bit copy, bit 1 = also the naive scan's loads. Checks
+ * that each load lies inside its slab and inside the map buffer, that each
+ * consumed load reads exactly the element of a footprint cube (or voxel) of the
+ * box, and that every cube of the footprint is read once. counts host uint64
+ * [4]: boxes, slabs, lane loads, cubes. MG_ELIMIT with the first violation in
+ * the message. */
+int mg_check_load_addresses(uint32_t nx, uint32_t ny, uint32_t nz, uint32_t flags, const uint32_t *boxes,
+                            uint32_t n, uint32_t unroll, uint64_t *counts);
 
 /* Footprint of each box as seen by the GPU decomposition: d_level_counts
  * device uint32 [n][n_levels] cubes per level. If d_cubes is not NULL, also
@@ -334,6 +351,8 @@ typedef struct {
                                results                                                        */
     uint32_t chunk_small;   /* boxes a small-tier workgroup takes per dequeue from its work
                                queue: 0 (one) or 1..64                                          */
+    uint32_t tf_planes;     /* transfer functions per thread of the propagation kernel (their
+                               gathers in flight together): 0 (default: 4), 1, 2, 4 or 8     */
 } mg_launch_cfg;
 
 int mg_get_launch(const mg_graph *g, mg_launch_cfg *out);
@@ -374,6 +393,18 @@ int mg_load(const char *path, mg_graph **out);
  * truncated field. unpack(pack(g)) has g's maps, nodes, weights and codebook. */
 int mg_pack(const mg_graph *g, uint8_t *buf, uint64_t capacity, uint64_t *size);
 int mg_unpack(const uint8_t *buf, uint64_t size, uint32_t threads, mg_graph **out);
+
+/* mg_unpack straight onto a GPU: the host reads the header, the node triples,
+ * the codebook and the labels; the voxel data (A), r(l) bits per voxel, is
+ * copied to `device` as it is and decoded there by a HIP kernel (one thread
+ * per voxel) into the node maps, renumbered like mg_unpack's. The new graph is
+ * on `device` as after mg_upload (library-allocated) and gives the same
+ * results; its maps are never expanded in host memory, so mg_export_map copies
+ * them back from the device, and mg_save, mg_pack, mg_quantize, mg_upload and
+ * mg_bind_device return MG_ESTATE for it. A stored node ID out of range is
+ * MG_EFORMAT (checked on the device for every voxel). `buf` is host memory,
+ * read during the call only. */
+int mg_unpack_device(const uint8_t *buf, uint64_t size, uint32_t threads, int device, mg_graph **out);
 
 /* Kernel timing: when enabled, the dominant kernel of each query /
  * propagation call is bracketed by HIP events on the call's stream;

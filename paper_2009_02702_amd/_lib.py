@@ -43,7 +43,8 @@ class LaunchCfg(ctypes.Structure):
     _fields_ = [("unroll_big", ctypes.c_uint32), ("unroll_small", ctypes.c_uint32),
                 ("unroll_naive", ctypes.c_uint32), ("tf_block", ctypes.c_uint32), ("table_big", ctypes.c_uint32),
                 ("table_small", ctypes.c_uint32), ("table_retry", ctypes.c_uint32), ("block_small", ctypes.c_uint32),
-                ("block_big", ctypes.c_uint32), ("chunk_small", ctypes.c_uint32)]
+                ("block_big", ctypes.c_uint32), ("chunk_small", ctypes.c_uint32),
+                ("tf_planes", ctypes.c_uint32)]
 
 
 _lib = None
@@ -54,9 +55,9 @@ SYMBOLS = [
     "mg_workspace_bytes", "mg_workspace_init", "mg_query_boxes", "mg_query_boxes_plain", "mg_query_boxes_stats",
     "mg_query_boxes_sparse",
     "mg_naive_boxes",
-    "mg_footprint", "mg_propagate_tf", "mg_palette_fetch", "mg_box_colour", "mg_lut_build", "mg_export_lut", "mg_query_boxes_lut", "mg_query_boxes_err",
+    "mg_check_load_addresses", "mg_footprint", "mg_propagate_tf", "mg_palette_fetch", "mg_box_colour", "mg_lut_build", "mg_export_lut", "mg_query_boxes_lut", "mg_query_boxes_err",
     "mg_get_launch", "mg_set_launch", "mg_autotune",
-    "mg_save", "mg_load", "mg_pack", "mg_unpack", "mg_timing_enable", "mg_timing_read",
+    "mg_save", "mg_load", "mg_pack", "mg_unpack", "mg_unpack_device", "mg_timing_enable", "mg_timing_read",
     "mg_last_error", "mg_free",
 ]
 
@@ -96,6 +97,7 @@ def load() -> ctypes.CDLL:
         "mg_query_boxes_stats": ([G, vp, u32, vp, vp, vp, u64, vp], i32),
         "mg_query_boxes_sparse": ([G, vp, u32, vp, vp, vp, u32, vp, vp, u64, vp], i32),
         "mg_naive_boxes": ([G, vp, u32, vp, vp, u64, vp], i32),
+        "mg_check_load_addresses": ([u32, u32, u32, u32, vp, u32, u32, vp], i32),
         "mg_footprint": ([G, vp, u32, vp, vp, u32, vp, vp], i32),
         "mg_propagate_tf": ([G, vp, u32, vp, vp], i32),
         "mg_palette_fetch": ([G, vp, u32, u32, vp, u32, vp, vp], i32),
@@ -111,6 +113,7 @@ def load() -> ctypes.CDLL:
         "mg_load": ([ctypes.c_char_p, ctypes.POINTER(G)], i32),
         "mg_pack": ([G, vp, u64, ctypes.POINTER(u64)], i32),
         "mg_unpack": ([vp, u64, u32, ctypes.POINTER(G)], i32),
+        "mg_unpack_device": ([vp, u64, u32, i32, ctypes.POINTER(G)], i32),
         "mg_timing_enable": ([G, i32], i32),
         "mg_timing_read": ([G, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u32)], i32),
         "mg_last_error": ([], ctypes.c_char_p),

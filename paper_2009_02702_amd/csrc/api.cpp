@@ -112,6 +112,7 @@ int mg_quantize(const mg_graph *h, uint32_t bits, uint32_t threads, mg_graph **o
 {
     if (!h || !out) return fail(MG_EINVAL, "mg_quantize: null argument");
     if (h->g.quant_bits) return fail(MG_EINVAL, "mg_quantize: the graph is already quantized");
+    if (h->g.maps_on_device) return fail(MG_ESTATE, "mg_quantize: the node maps exist only on the device");
     *out = nullptr;
     mg_graph *q = new (std::nothrow) mg_graph;
     if (!q) return fail(MG_ENOMEM, "mg_quantize: out of host memory");
@@ -186,6 +187,10 @@ int mg_export_map(const mg_graph *h, uint32_t level, uint32_t *out)
     if (!h || !out) return fail(MG_EINVAL, "mg_export_map: null argument");
     const mg::Graph &g = h->g;
     if (level >= g.n_levels) return fail(MG_EINVAL, "mg_export_map: level out of range");
+    if (g.maps_on_device) {  // decoded on the GPU: copied back from there
+        std::string err;
+        return done(mg::dev_export_map(g, level, out, &err), "mg_export_map: " + err);
+    }
     std::memcpy(out, g.maps.data() + g.lev_off[level], (g.lev_off[level + 1] - g.lev_off[level]) * 4);
     return MG_OK;
 }
@@ -288,6 +293,20 @@ int mg_query_boxes_sparse(mg_graph *h, const uint32_t *d_boxes, uint32_t n, uint
                 err);
 }
 
+int mg_check_load_addresses(uint32_t nx, uint32_t ny, uint32_t nz, uint32_t flags, const uint32_t *boxes,
+                            uint32_t n, uint32_t unroll, uint64_t *counts)
+{
+    if (!counts || (n && !boxes)) return fail(MG_EINVAL, "mg_check_load_addresses: null argument");
+    if (!nx || !ny || !nz || uint64_t(nx) * ny * nz >= (1ull << 31))
+        return fail(MG_EINVAL, "mg_check_load_addresses: dimensions must be >= 1 with fewer than 2^31 voxels");
+    if (!(unroll == 4 || unroll == 8 || unroll == 16))
+        return fail(MG_EINVAL, "mg_check_load_addresses: unroll must be 4, 8 or 16");
+    const uint32_t dims[3] = {nx, ny, nz};
+    std::string err;
+    if (flags > 3) return fail(MG_EINVAL, "mg_check_load_addresses: unknown flags");
+    return done(mg::dev_check_load_addresses(dims, flags, boxes, n, unroll, counts, &err), err);
+}
+
 int mg_naive_boxes(mg_graph *h, const uint32_t *d_boxes, uint32_t n, float *d_out, void *d_work,
                    uint64_t work_bytes, void *stream)
 {
@@ -385,6 +404,7 @@ int mg_query_boxes_err(mg_graph *h, const uint32_t *d_boxes, uint32_t n, float *
 int mg_pack(const mg_graph *h, uint8_t *buf, uint64_t capacity, uint64_t *size)
 {
     if (!h || !size) return fail(MG_EINVAL, "mg_pack: null argument");
+    if (h->g.maps_on_device) return fail(MG_ESTATE, "mg_pack: the node maps exist only on the device");
     std::vector<uint8_t> s;
     std::string err;
     if (int rc = mg::pack_graph(h->g, &s, &err)) return fail(rc, "mg_pack: " + err);
@@ -407,6 +427,30 @@ int mg_unpack(const uint8_t *buf, uint64_t size, uint32_t threads, mg_graph **ou
     if (int rc = mg::unpack_graph(buf, size, threads, &h->g, &err)) {
         delete h;
         return fail(rc, "mg_unpack: " + err);
+    }
+    *out = h;
+    return MG_OK;
+}
+
+int mg_unpack_device(const uint8_t *buf, uint64_t size, uint32_t threads, int device, mg_graph **out)
+{
+    if (!buf || !out) return fail(MG_EINVAL, "mg_unpack_device: null argument");
+    if (device < 0) return fail(MG_EINVAL, "mg_unpack_device: negative device");
+    *out = nullptr;
+    mg_graph *h = new (std::nothrow) mg_graph;
+    if (!h) return fail(MG_ENOMEM, "mg_unpack_device: out of host memory");
+    std::string err;
+    mg::StreamMaps sm;
+    int rc;
+    try {
+        rc = mg::unpack_graph(buf, size, threads, &h->g, &err, &sm);
+        if (rc == MG_OK) rc = mg::dev_upload_stream(&h->g, buf, size, sm, device, &err);
+    } catch (const std::bad_alloc &) {
+        rc = MG_ENOMEM, err = "out of host memory";
+    }
+    if (rc != MG_OK) {
+        delete h;
+        return fail(rc, "mg_unpack_device: " + err);
     }
     *out = h;
     return MG_OK;
@@ -454,6 +498,7 @@ int mg_save(const mg_graph *h, const char *path)
 {
     if (!h || !path) return fail(MG_EINVAL, "mg_save: null argument");
     const mg::Graph &g = h->g;
+    if (g.maps_on_device) return fail(MG_ESTATE, "mg_save: the node maps exist only on the device");
     FILE *f = std::fopen(path, "wb");
     if (!f) return fail(MG_EIO, std::string("mg_save: cannot open ") + path);
     uint32_t hdr[9] = {g.dims[0], g.dims[1], g.dims[2], g.nseg, g.n_nodes, g.depth, g.n_levels, g.max_mixture,

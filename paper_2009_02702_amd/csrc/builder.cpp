@@ -326,7 +326,8 @@ void level_dims(const uint32_t dims[3], std::vector<uint32_t> *out)
 // Topological levels (Sec. "Reconstruction"), the deferred step schedule, IDs
 // renumbered by (rank, creation order) with sources fixed, and the mip voxels
 // of levels >= 1 remapped to the new IDs (level 0 holds sources only).
-int finalize_dag(const RawDag &d, bool defer, uint32_t max_depth, unsigned nt, Graph *g, std::string *err)
+int finalize_dag(const RawDag &d, bool defer, uint32_t max_depth, unsigned nt, Graph *g, std::string *err,
+                 std::vector<uint32_t> *perm_out)
 {
     const uint32_t N = uint32_t(d.a.size());
     std::vector<uint32_t> rank(N, 0);
@@ -425,11 +426,14 @@ int finalize_dag(const RawDag &d, bool defer, uint32_t max_depth, unsigned nt, G
     for (uint32_t n = 0; n < d.nseg; ++n) g->sched[n] = n;
     for (uint32_t n = d.nseg; n < N; ++n) g->sched[spos[g->step[n]]++] = n;
     const uint64_t total = g->maps.size();
-    uint32_t *mp = g->maps.data();
-    const uint64_t first_internal = g->lev_off[1];
-    parallel_chunks(total - first_internal, nt, [&](uint64_t b, uint64_t e, unsigned) {
-        for (uint64_t i = b; i < e; ++i) mp[first_internal + i] = perm[mp[first_internal + i]];
-    });
+    if (total == g->lev_off[g->n_levels] && total > g->lev_off[1]) {  // maps on the host: renumber
+        uint32_t *mp = g->maps.data();
+        const uint64_t first_internal = g->lev_off[1];
+        parallel_chunks(total - first_internal, nt, [&](uint64_t b, uint64_t e, unsigned) {
+            for (uint64_t i = b; i < e; ++i) mp[first_internal + i] = perm[mp[first_internal + i]];
+        });
+    }
+    if (perm_out) *perm_out = std::move(perm);
     return MG_OK;
 }
 
@@ -828,10 +832,11 @@ int validate_graph(const Graph &g, std::string *err)
     std::vector<uint32_t> ld;
     level_dims(g.dims, &ld);
     if (ld != g.lev_dims || g.n_levels != ld.size() / 3 || g.lev_off.size() != g.n_levels + 1 ||
-        g.maps.size() != g.lev_off[g.n_levels]) {
+        (!g.maps_on_device && g.maps.size() != g.lev_off[g.n_levels])) {
         *err = "level dimensions do not match the volume";
         return MG_EFORMAT;
     }
+    if (g.maps_on_device) return MG_OK;  // the GPU decoder checks every voxel's node ID
     for (uint64_t i = 0; i < g.lev_off[1]; ++i)
         if (g.maps[i] >= S) {
             *err = "a level-0 voxel does not hold a source";

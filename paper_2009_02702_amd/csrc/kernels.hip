@@ -27,6 +27,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -49,7 +50,9 @@ constexpr uint32_t kHashRetry = 8192;         // boxes that overflowed a tier ta
 constexpr uint32_t kBigLog2 = 14;             // boxes of >= 2^14 cubes go to the big tier
 constexpr uint32_t kHashGlobal = 1u << 16;    // fewest per-worker hash slots in the fallback tables
 constexpr uint32_t kSegLdsMax = 2048;         // sources kept in LDS
-constexpr uint32_t kFallbackWorkers = 128;    // workers of the global-table kernel
+constexpr uint32_t kFallbackWorkers = 128;    // workers of the final global-table launch (budget)
+constexpr uint32_t kTfPlanes = 4;             // transfer functions per thread of a propagation step
+constexpr uint32_t kMidWorkers = 256;         // workers of the mid-size global-table launch
 constexpr uint32_t kQueues = 8;                // work queues per tier
 constexpr uint32_t kQueueStride = 64;          // u32 between queue counters (256 bytes)
 constexpr int kUnroll = 4;                     // node-ID loads in flight per lane (plain, fallback)
@@ -80,27 +83,30 @@ struct LevelTable {
     uint64_t total16;
 };
 
-// A slab of cubes at one level, as read from memory: the fast axis is the
-// contiguous one of the chosen copy (x in maps, y in maps_t); the other two are
-// ordered so that the slow axis is the thinner one. Lanes cover tiles of
-// 2^ltx cubes along the fast axis times 64 / 2^ltx rows along the mid axis.
+// A slab of cubes at one level, as the query kernels read it: e2 slices (slow
+// axis, the thinnest) of e1 rows (mid axis) of e0 cubes (fast axis, the
+// contiguous axis of the chosen copy: x in maps, y in maps_t), read as `units`
+// 4-byte units per row: one 32-bit node ID per cube (kind 0), or, from the
+// 16-bit level-0 copy, aligned pairs of source IDs (kind 1; a row whose first
+// cube is at an odd position starts one element early, `odd`).
 struct Slab {
-    uint64_t base;       // element index of the first cube in the combined map buffer
-    uint32_t e0, e1, e2; // extents along the fast, mid and slow axes
-    uint32_t s1, s2;     // element strides of the mid and slow axes (fast axis: 1)
-    uint32_t bx, by, bz; // first cube, level coordinates
+    uint64_t base;         // byte offset of the first unit in its buffer (maps or maps16)
+    uint32_t e0, e1, e2;   // cubes along the fast, mid and slow axes
+    uint32_t s1b, s2b;     // bytes between rows / slices (0 where the extent is 1)
+    uint32_t units;        // 4-byte units per row
+    uint32_t bx, by, bz;   // first cube, level coordinates
     uint8_t level;
-    uint8_t ltx;         // log2 of the tile width along the fast axis
-    uint8_t axes;        // fast | mid << 2 | slow << 4 (0 = x, 1 = y, 2 = z)
-    uint8_t pad;
+    uint8_t kind;          // 0: 32-bit node IDs, 1: pairs of 16-bit level-0 source IDs
+    uint8_t axes;          // fast | mid << 2 | slow << 4 (0 = x, 1 = y, 2 = z)
+    uint8_t odd;           // kind 1: the row's first unit starts one element before the slab
 };
 static_assert(sizeof(Slab) == 48, "Slab layout");
 
 __host__ __device__ inline uint32_t slab_count(const Slab &sl) { return sl.e0 * sl.e1 * sl.e2; }
 
 // Level coordinates of the cube at (fast, mid, slow) offsets (i0, i1, i2).
-__device__ inline void slab_coords(const Slab &sl, uint32_t i0, uint32_t i1, uint32_t i2, uint32_t *x,
-                                   uint32_t *y, uint32_t *z)
+__host__ __device__ inline void slab_coords(const Slab &sl, uint32_t i0, uint32_t i1, uint32_t i2, uint32_t *x,
+                                            uint32_t *y, uint32_t *z)
 {
     uint32_t c[3] = {sl.bx, sl.by, sl.bz};
     c[sl.axes & 3] += i0;
@@ -110,7 +116,7 @@ __device__ inline void slab_coords(const Slab &sl, uint32_t i0, uint32_t i1, uin
 }
 
 // Clipped box: half-open ranges; returns false for an empty box.
-__device__ inline bool clip_box(const uint32_t *b, const LevelTable &lt, uint32_t lo[3], uint32_t hi[3])
+__host__ __device__ inline bool clip_box(const uint32_t *b, const LevelTable &lt, uint32_t lo[3], uint32_t hi[3])
 {
     bool ok = true;
     for (int a = 0; a < 3; ++a) {
@@ -122,9 +128,13 @@ __device__ inline bool clip_box(const uint32_t *b, const LevelTable &lt, uint32_
     return ok;
 }
 
+// The slab of level `lev` covering cells [x0, x1) x [y0, y1) x [z0, z1): the
+// fast axis is x (rows from maps) unless the block is thinner in x than in y
+// (rows along y from maps_t); of the other two, the thinner is the slow axis.
+// Level 0 uses the 16-bit copy when lt.use16.
 template <bool WRITE>
-__device__ inline void put_slab(Slab *out, int *n, const LevelTable &lt, uint32_t lev, uint32_t x0, uint32_t x1,
-                                uint32_t y0, uint32_t y1, uint32_t z0, uint32_t z1)
+__host__ __device__ inline void put_slab(Slab *out, int *n, const LevelTable &lt, uint32_t lev, uint32_t x0,
+                                         uint32_t x1, uint32_t y0, uint32_t y1, uint32_t z0, uint32_t z1)
 {
     if (x1 <= x0 || y1 <= y0 || z1 <= z0) return;
     if (!WRITE) {
@@ -133,40 +143,45 @@ __device__ inline void put_slab(Slab *out, int *n, const LevelTable &lt, uint32_
     }
     const uint32_t ex = x1 - x0, ey = y1 - y0, ez = z1 - z0;
     const uint32_t X = lt.dims[lev][0], Y = lt.dims[lev][1], Z = lt.dims[lev][2];
+    const bool pairs = lev == 0 && lt.use16;
+    const uint32_t px = pairs ? lt.pitch_x : X, py = pairs ? lt.pitch_y : Y;
     Slab s;
     s.level = uint8_t(lev);
+    s.kind = pairs ? 1 : 0;
     s.bx = x0, s.by = y0, s.bz = z0;
-    s.pad = 0;
-    uint32_t f, m, w, ef, em, ew, sm, sw;
-    if (ex < ey) {
-        // rows along y in the transposed copy: index y + Y (z + Z x)
+    // element strides of the mid and slow axes in the chosen copy, and the first element
+    uint32_t f, m, w, ef, em, ew;
+    uint64_t sm, sw, first;
+    if (ex < ey) {  // y fastest: element y + py (z + Z x)
         f = 1, ef = ey;
-        const uint32_t sz = Y, sx = Y * Z;
+        const uint64_t sz = py, sx = uint64_t(py) * Z;
         if (ez >= ex) m = 2, em = ez, sm = sz, w = 0, ew = ex, sw = sx;
         else m = 0, em = ex, sm = sx, w = 2, ew = ez, sw = sz;
-        s.base = lt.total + lt.off[lev] + y0 + uint64_t(Y) * (z0 + uint64_t(Z) * x0);
-    } else {
+        first = (pairs ? lt.total16 : lt.total + lt.off[lev]) + y0 + uint64_t(py) * (z0 + uint64_t(Z) * x0);
+    } else {        // x fastest: element x + px (y + Y z)
         f = 0, ef = ex;
-        const uint32_t sy = X, sz = X * Y;
+        const uint64_t sy = px, sz = uint64_t(px) * Y;
         if (ey >= ez) m = 1, em = ey, sm = sy, w = 2, ew = ez, sw = sz;
         else m = 2, em = ez, sm = sz, w = 1, ew = ey, sw = sy;
-        s.base = lt.off[lev] + x0 + uint64_t(X) * (y0 + uint64_t(Y) * z0);
+        first = (pairs ? 0 : lt.off[lev]) + x0 + uint64_t(px) * (y0 + uint64_t(Y) * z0);
     }
-    s.e0 = ef, s.e1 = em, s.e2 = ew;
-    s.s1 = sm, s.s2 = sw;
+    const uint32_t odd = pairs ? ((f == 1 ? y0 : x0) & 1u) : 0u;
+    const uint32_t esz = pairs ? 2u : 4u;
     s.axes = uint8_t(f | (m << 2) | (w << 4));
-    uint32_t ltx = 0;
-    while (ltx < 6 && (1u << ltx) < ef) ++ltx;  // tile width: smallest power of two >= e0, at most 64
-    if (sm >= (1u << 24)) ltx = 6;  // one row per tile: lane byte offsets stay below 2^32
-    s.ltx = uint8_t(ltx);
+    s.odd = uint8_t(odd);
+    s.e0 = ef, s.e1 = em, s.e2 = ew;
+    s.base = esz * (first - odd);
+    s.s1b = em > 1 ? uint32_t(esz * sm) : 0u;  // < 2^32 whenever the extent is above 1
+    s.s2b = ew > 1 ? uint32_t(esz * sw) : 0u;
+    s.units = pairs ? (ef + odd + 1) >> 1 : ef;
     out[(*n)++] = s;
 }
 
 // Slabs of level `lev` of the box's footprint (at most 6), written to out[0..]
 // when WRITE. Returns their count.
 template <bool WRITE>
-__device__ inline int level_slabs(const LevelTable &lt, const uint32_t lo[3], const uint32_t hi[3], uint32_t lev,
-                                  Slab *out)
+__host__ __device__ inline int level_slabs(const LevelTable &lt, const uint32_t lo[3], const uint32_t hi[3],
+                                           uint32_t lev, Slab *out)
 {
     uint32_t a[3], b[3], ia[3], ib[3];
     bool outer = true, inner = true;
@@ -434,76 +449,160 @@ __device__ inline bool run_head(uint32_t v, uint64_t above, uint32_t *len)
 
 __device__ inline uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Streams one slab of node IDs: a wave covers a block of UNROLL lane tiles;
-// lane (lx, ly) = (lane mod 2^ltx, lane / 2^ltx) reads element
-// (t0 * 2^ltx + lx, rb * rows + u * 64/2^ltx + ly) of slow slice k2, u < UNROLL,
-// so the UNROLL loads of a lane are independent and all in flight together.
-// Row tiles that start past the slab's last row are not consumed (a wave-
-// uniform bound n_u) and load from the last tile that starts inside it; lanes
-// outside the slab read their tile's first element, inside the slab, and see
-// kEmpty, so every load stays inside the slab. Blocks
-// (k2, rb, t0) are dealt to waves round-robin starting at wave `first`;
-// `use(v)` consumes each of the UNROLL values of a block (every lane calls it).
-// The row base of every u is a wave-uniform pointer (scalar registers) and a
-// lane adds a 32-bit byte offset (< 64 rows of the mid stride), so a load
-// costs no 64-bit vector arithmetic. Returns false if `stop()` became true
+// ---------------------------------------------------------------- tiled slab walk
+//
+// A slab is read as e2 slices of e1 rows of `units` 4-byte units (32-bit node
+// IDs, or aligned pairs of 16-bit level-0 IDs). A wave covers a tile of 2^ltx
+// units x 2^(6 - ltx) rows (lane (lx, ly) = (lane mod 2^ltx, lane / 2^ltx)),
+// and a block is UNROLL tiles stacked along the rows, so a lane's UNROLL loads
+// are independent and all in flight together. Blocks (t0, rb, k2) are dealt
+// to the waves round-robin. The row of tile u is a wave-uniform pointer (scalar
+// registers): the block's first row plus u row steps; a lane adds its 32-bit
+// byte offset. Row tiles that start past the slab's last row are not consumed
+// (the wave-uniform bound n_u) and load from the last tile that starts inside
+// it; lanes outside the slab read their tile's first unit (inside the slab) and
+// see kEmpty, so every load stays inside the slab. The same helpers give the
+// addresses to the kernels and to the host-side replay (mg_check_load_addresses).
+
+struct TileWalk {
+    uint32_t units, e1, e2;   // units per row, rows per slice, slices
+    uint32_t s1b;             // bytes between rows
+    uint64_t s2b;             // bytes between slices
+    uint32_t ltx, lty, ty;    // tile: 2^ltx units x ty = 2^lty rows
+    uint32_t rows;            // rows per block (ty * UNROLL)
+    uint32_t n_t0, n_rb, n_blk;
+    uint64_t row_step;        // bytes between the rows of tiles u and u + 1
+};
+
+__host__ __device__ inline TileWalk tile_walk(uint32_t units, uint32_t e1, uint32_t e2, uint32_t s1b, uint64_t s2b,
+                                              uint32_t unroll)
+{
+    TileWalk w;
+    w.units = units, w.e1 = e1, w.e2 = e2, w.s1b = s1b, w.s2b = s2b;
+    uint32_t ltx = 0;
+    while (ltx < 6 && (1u << ltx) < units) ++ltx;   // smallest power of two >= units, at most 64
+    if (s1b >= (1u << 26)) ltx = 6;                 // one row per tile: lane offsets stay below 2^32
+    w.ltx = ltx;
+    w.lty = 6u - ltx;
+    w.ty = 1u << w.lty;
+    w.rows = w.ty * unroll;
+    w.n_t0 = (units + (1u << ltx) - 1) >> ltx;
+    w.n_rb = (e1 + w.rows - 1) / w.rows;
+    w.n_blk = w.n_t0 * w.n_rb * e2;
+    w.row_step = uint64_t(w.ty) * s1b;
+    return w;
+}
+
+// Byte offset, from the slab's first unit, of block (t0, rb, k2)'s first row.
+__host__ __device__ inline uint64_t tile_block_offset(const TileWalk &w, uint32_t t0, uint32_t rb, uint32_t k2)
+{
+    return uint64_t(rb) * w.rows * w.s1b + uint64_t(k2) * w.s2b + (uint64_t(t0) << w.ltx) * 4u;
+}
+
+// Row tiles of block row rb that start inside the slab (>= 1 for rb < n_rb).
+__host__ __device__ inline uint32_t tile_n_u(const TileWalk &w, uint32_t rb, uint32_t unroll)
+{
+    const uint32_t n = (w.e1 - rb * w.rows + w.ty - 1) >> w.lty;
+    return n < unroll ? n : unroll;
+}
+
+// A lane's byte offset inside its tile (< 2^32: ly < 64 and s1b < 2^26 unless ly == 0).
+__host__ __device__ inline uint32_t tile_lane_bytes(const TileWalk &w, uint32_t lane)
+{
+    return (lane >> w.ltx) * w.s1b + (lane & ((1u << w.ltx) - 1)) * 4u;
+}
+
+// Its unit index along the row in tile column t0.
+__host__ __device__ inline uint32_t tile_unit(const TileWalk &w, uint32_t t0, uint32_t lane)
+{
+    return (t0 << w.ltx) + (lane & ((1u << w.ltx) - 1));
+}
+
+// Row tiles of block (t0, rb) in which the lane's unit lies inside the slab (<= n_u).
+__host__ __device__ inline uint32_t tile_n_ok(const TileWalk &w, uint32_t t0, uint32_t rb, uint32_t lane)
+{
+    const uint32_t row0 = rb * w.rows + (lane >> w.ltx);
+    return (tile_unit(w, t0, lane) < w.units && row0 < w.e1) ? ((w.e1 - row0 + w.ty - 1) >> w.lty) : 0u;
+}
+
+// The byte offset of load u of a lane in block (t0, rb, k2): the tile row stays on
+// tile n_u - 1 past it, and lanes outside the slab read the tile's first unit.
+__host__ __device__ inline uint64_t tile_load_offset(const TileWalk &w, uint64_t blk, uint32_t u, uint32_t n_u,
+                                                     uint32_t n_ok, uint32_t lane_bytes)
+{
+    return blk + uint64_t(u < n_u ? u : n_u - 1) * w.row_step + (u < n_ok ? lane_bytes : 0u);
+}
+
+// Which elements of a 16-bit pair unit lie in the slab (bit 0: low, bit 1: high); the
+// row's first unit starts one element early when `odd`.
+__host__ __device__ inline uint32_t pair_bits(uint32_t unit, uint32_t e0, uint32_t odd)
+{
+    return ((unit > 0 || odd == 0) ? 1u : 0u) | ((2 * unit + 1 < e0 + odd) ? 2u : 0u);
+}
+
+// The naive scan's walk of a clipped box: level 0 as one slab of ez slices of ey rows,
+// from the 16-bit x-fastest copy (pairs; *odd = parity of the first x) or the 32-bit
+// map; *base = byte offset of the first unit.
+__host__ __device__ inline TileWalk naive_walk(const LevelTable &lt, const uint32_t lo[3], const uint32_t hi[3],
+                                               bool use16, uint32_t unroll, uint64_t *base, uint32_t *odd)
+{
+    const uint32_t ex = hi[0] - lo[0], ey = hi[1] - lo[1], ez = hi[2] - lo[2];
+    if (use16) {
+        const uint64_t px = lt.pitch_x, pxy = px * lt.vol[1];
+        *odd = lo[0] & 1u;
+        *base = 2 * (lo[0] - *odd + px * lo[1] + pxy * lo[2]);
+        return tile_walk((ex + *odd + 1) >> 1, ey, ez, ey > 1 ? uint32_t(2 * px) : 0u, ez > 1 ? 2 * pxy : 0u, unroll);
+    }
+    const uint64_t X = lt.vol[0], XY = X * lt.vol[1];
+    *odd = 0;
+    *base = 4 * (lo[0] + X * lo[1] + XY * lo[2]);
+    return tile_walk(ex, ey, ez, ey > 1 ? uint32_t(4 * X) : 0u, ez > 1 ? 4 * XY : 0u, unroll);
+}
+
+// Streams a slab of 32-bit node IDs; `use(v)` consumes each of a block's n_u
+// values (every lane calls it, kEmpty outside the slab). The next block's loads
+// are in flight while a block is consumed. Blocks are dealt round-robin to the
+// waves starting at wave `first`. Returns false if `stop()` became true
 // (checked every 8 blocks).
 template <int UNROLL, int WAVES, class Use, class Stop>
-__device__ inline bool stream_slab(const uint32_t *__restrict__ p, uint32_t e0, uint32_t e1, uint32_t e2, uint32_t s1,
-                                   uint32_t s2, uint32_t ltx, uint32_t first, Use use, Stop stop)
+__device__ inline bool stream_slab(const char *__restrict__ p, const TileWalk &tw, uint32_t first, Use use,
+                                   Stop stop)
 {
     const uint32_t lane = threadIdx.x & 63, wave = uni(threadIdx.x >> 6);  // the wave index is uniform
-    const uint32_t lty = 6u - ltx;
-    const uint32_t ty = 1u << lty;                        // rows per tile
-    const uint32_t n_t0 = (e0 + (1u << ltx) - 1) >> ltx;  // tiles along the fast axis
-    const uint32_t rows = ty * UNROLL;                     // rows per block
-    const uint32_t n_rb = (e1 + rows - 1) / rows;          // blocks along the mid axis
-    const uint32_t n_blk = n_t0 * n_rb * e2;
-    const uint32_t lx = lane & ((1u << ltx) - 1), ly = lane >> ltx;
-    const uint32_t ly_bytes = ly * s1 * 4u;                // < 64 * s1 * 4 < 2^32 (s1 < 2^24)
-    const uint64_t row_step = uint64_t(ty) * s1 * 4u;      // bytes between the rows of u and u + 1
-    const uint32_t lane_bytes = ly_bytes + lx * 4u;
+    const uint32_t lane_bytes = tile_lane_bytes(tw, lane);
     uint32_t fb = (wave + WAVES - first) % WAVES;
-    if (fb >= n_blk) return true;
+    if (fb >= tw.n_blk) return true;
     // block fb < WAVES as (t0, rb, k2), by subtraction (no division)
     uint32_t t0 = fb, rb = 0, k2 = 0;
-    while (t0 >= n_t0) {
-        t0 -= n_t0;
-        if (++rb == n_rb) rb = 0, ++k2;
+    while (t0 >= tw.n_t0) {
+        t0 -= tw.n_t0;
+        if (++rb == tw.n_rb) rb = 0, ++k2;
     }
-    // Loads of block (t0, rb, k2) into v. n_u: row tiles of the block that start inside
-    // the slab (wave-uniform, >= 1); n_ok: tiles in which this lane's element is inside
-    // (<= n_u). Every load is issued; a lane outside the slab reads the first element of
-    // tile min(u, n_u - 1), which is inside the slab; tiles u >= n_u are not consumed.
     auto load = [&](uint32_t (&v)[UNROLL], uint32_t &n_u, uint32_t &n_ok, uint32_t bt0, uint32_t brb,
                     uint32_t bk2) {
-        const uint32_t i0 = (bt0 << ltx) + lx;
-        const uint32_t row0 = brb * rows + ly;
-        n_u = min(uint32_t(UNROLL), (e1 - brb * rows + ty - 1) >> lty);
+        n_u = tile_n_u(tw, brb, UNROLL);
         __builtin_assume(n_u >= 1);  // brb < n_rb: the block's first tile starts inside the slab
-        n_ok = (i0 < e0 && row0 < e1) ? ((e1 - row0 + ty - 1) >> lty) : 0u;
-        const char *blk = reinterpret_cast<const char *>(p) +
-                          (uint64_t(brb) * rows * s1 + uint64_t(bk2) * s2 + (bt0 << ltx)) * 4u;
+        n_ok = tile_n_ok(tw, bt0, brb, lane);
+        const char *blk = p + tile_block_offset(tw, bt0, brb, bk2);
         const char *row = blk;
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            if (u > 0 && uint32_t(u) < n_u) row += row_step;  // stays on tile n_u - 1 after it
+            if (u > 0 && uint32_t(u) < n_u) row += tw.row_step;  // stays on tile n_u - 1 after it
             v[u] = *reinterpret_cast<const uint32_t *>(row + (uint32_t(u) < n_ok ? lane_bytes : 0u));
         }
     };
-    // software pipeline: the next block's loads are in flight while this block is consumed
     uint32_t v[UNROLL], n_u, n_ok;
     load(v, n_u, n_ok, t0, rb, k2);
     uint32_t iter = 0;
-    for (; fb < n_blk; fb += WAVES) {
+    for (; fb < tw.n_blk; fb += WAVES) {
         if ((++iter & 7u) == 0 && stop()) return false;
         // this wave's next block; after its last one, the current block again (loaded, unused)
         uint32_t nt0 = t0 + WAVES, nrb = rb, nk2 = k2;
-        while (nt0 >= n_t0) {
-            nt0 -= n_t0;
-            if (++nrb == n_rb) nrb = 0, ++nk2;
+        while (nt0 >= tw.n_t0) {
+            nt0 -= tw.n_t0;
+            if (++nrb == tw.n_rb) nrb = 0, ++nk2;
         }
-        const bool more = fb + WAVES < n_blk;
+        const bool more = fb + WAVES < tw.n_blk;
         if (!more) nt0 = t0, nrb = rb, nk2 = k2;
         uint32_t w[UNROLL], w_n_u, w_n_ok;
         load(w, w_n_u, w_n_ok, nt0, nrb, nk2);
@@ -518,75 +617,57 @@ __device__ inline bool stream_slab(const uint32_t *__restrict__ p, uint32_t e0, 
     return true;
 }
 
-// Streams one level-0 slab of the 16-bit copy: lane (lx, ly) reads one aligned
-// 32-bit word, the pair of elements (2 pp - odd, 2 pp + 1 - odd) of row
-// rb * rows + u * 64/2^ltx + ly of slow slice k2, pp = t0 * 2^ltx + lx, where
-// `odd` is the parity of the slab's first element along the fast axis (rows are
-// padded to an even length, so every pair lies inside its row). Elements outside
-// the slab are handed to `use(lo, hi)` as kEmpty. Block walk and row-tile
-// bounds as in stream_slab; the software pipeline keeps three blocks in flight
-// (level 0 is most of the cubes, and its 32-bit words leave registers to spare).
+// Streams a slab of the 16-bit level-0 copy, two elements per unit; `use(lo, hi)`
+// gets kEmpty for elements outside the slab (e0 elements per row, the row's first
+// unit one element early when `odd`). Three blocks in flight (level 0 is most of
+// the cubes, and its 32-bit words leave registers to spare): a block past the
+// wave's last one is replaced by the block before it (valid addresses, never consumed).
 template <int UNROLL, int WAVES, class Use>
-__device__ inline void stream_pairs(const uint16_t *__restrict__ p, uint32_t e0, uint32_t e1, uint32_t e2,
-                                    uint32_t s1, uint32_t s2, uint32_t odd, uint32_t ltx, uint32_t first, Use use)
+__device__ inline void stream_pairs(const char *__restrict__ p, const TileWalk &tw, uint32_t e0, uint32_t odd,
+                                    uint32_t first, Use use)
 {
     const uint32_t lane = threadIdx.x & 63, wave = uni(threadIdx.x >> 6);
-    const uint32_t np = (e0 + odd + 1) >> 1;               // pairs along the fast axis
-    const uint32_t lty = 6u - ltx;
-    const uint32_t ty = 1u << lty;
-    const uint32_t n_t0 = (np + (1u << ltx) - 1) >> ltx;
-    const uint32_t rows = ty * UNROLL;
-    const uint32_t n_rb = (e1 + rows - 1) / rows;
-    const uint32_t n_blk = n_t0 * n_rb * e2;
-    const uint32_t lx = lane & ((1u << ltx) - 1), ly = lane >> ltx;
-    const uint32_t lane_bytes = ly * s1 * 2u + lx * 4u;   // s1 < 2^24
-    const uint64_t row_step = uint64_t(ty) * s1 * 2u;
-    const char *p0 = reinterpret_cast<const char *>(p - odd);  // aligned start of the slab's first row
+    const uint32_t lane_bytes = tile_lane_bytes(tw, lane);
     uint32_t fb = (wave + WAVES - first) % WAVES;
-    if (fb >= n_blk) return;
+    if (fb >= tw.n_blk) return;
     uint32_t t0 = fb, rb = 0, k2 = 0;
-    while (t0 >= n_t0) {
-        t0 -= n_t0;
-        if (++rb == n_rb) rb = 0, ++k2;
+    while (t0 >= tw.n_t0) {
+        t0 -= tw.n_t0;
+        if (++rb == tw.n_rb) rb = 0, ++k2;
     }
     // n_lo / n_hi: row tiles in which this lane's low / high element is inside the slab
     auto load = [&](uint32_t (&v)[UNROLL], uint32_t &n_u, uint32_t &n_lo, uint32_t &n_hi, uint32_t bt0,
                     uint32_t brb, uint32_t bk2) {
-        const uint32_t pp = (bt0 << ltx) + lx;
-        const uint32_t row0 = brb * rows + ly;
-        n_u = min(uint32_t(UNROLL), (e1 - brb * rows + ty - 1) >> lty);
+        n_u = tile_n_u(tw, brb, UNROLL);
         __builtin_assume(n_u >= 1);
-        const uint32_t n_ok = (pp < np && row0 < e1) ? ((e1 - row0 + ty - 1) >> lty) : 0u;
-        n_lo = (pp > 0 || odd == 0) ? n_ok : 0u;
-        n_hi = (2 * pp + 1 < e0 + odd) ? n_ok : 0u;
-        const char *blk = p0 + (uint64_t(brb) * rows * s1 + uint64_t(bk2) * s2) * 2u + (bt0 << ltx) * 4u;
+        const uint32_t n_ok = tile_n_ok(tw, bt0, brb, lane);
+        const uint32_t pb = pair_bits(tile_unit(tw, bt0, lane), e0, odd);
+        n_lo = (pb & 1u) ? n_ok : 0u;
+        n_hi = (pb & 2u) ? n_ok : 0u;
+        const char *blk = p + tile_block_offset(tw, bt0, brb, bk2);
         const char *row = blk;
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            if (u > 0 && uint32_t(u) < n_u) row += row_step;
+            if (u > 0 && uint32_t(u) < n_u) row += tw.row_step;
             v[u] = *reinterpret_cast<const uint32_t *>(row + (uint32_t(u) < n_ok ? lane_bytes : 0u));
         }
     };
-    // three blocks in flight: this wave's current block v, its next block w and the one
-    // after, x, which is loaded before v is consumed (so v waits only for its own loads).
-    // A block past the wave's last one is replaced by the block before it (valid
-    // addresses, never consumed).
     auto advance = [&](uint32_t &bt0, uint32_t &brb, uint32_t &bk2) {
         bt0 += WAVES;
-        while (bt0 >= n_t0) {
-            bt0 -= n_t0;
-            if (++brb == n_rb) brb = 0, ++bk2;
+        while (bt0 >= tw.n_t0) {
+            bt0 -= tw.n_t0;
+            if (++brb == tw.n_rb) brb = 0, ++bk2;
         }
     };
     uint32_t v[UNROLL], n_u, n_lo, n_hi;
     load(v, n_u, n_lo, n_hi, t0, rb, k2);
     uint32_t t1 = t0, rb1 = rb, k21 = k2;
-    if (fb + WAVES < n_blk) advance(t1, rb1, k21);
+    if (fb + WAVES < tw.n_blk) advance(t1, rb1, k21);
     uint32_t w[UNROLL], w_n_u, w_n_lo, w_n_hi;
     load(w, w_n_u, w_n_lo, w_n_hi, t1, rb1, k21);
-    for (; fb < n_blk; fb += WAVES) {
+    for (; fb < tw.n_blk; fb += WAVES) {
         uint32_t t2 = t1, rb2 = rb1, k22 = k21;
-        if (fb + 2 * WAVES < n_blk) advance(t2, rb2, k22);
+        if (fb + 2 * WAVES < tw.n_blk) advance(t2, rb2, k22);
         uint32_t x[UNROLL], x_n_u, x_n_lo, x_n_hi;
         load(x, x_n_u, x_n_lo, x_n_hi, t2, rb2, k22);
 #pragma unroll
@@ -616,27 +697,18 @@ __device__ inline void count_pairs(uint32_t *cnt, uint32_t lo, uint32_t hi, uint
         atomicAdd(&cnt[hi], (e_lo ? 0u - (2 * lane + 1) : 0u) + (e_hi ? 2 * lane + 2 : 0u));
 }
 
-// Tile width for a pair-streamed slab: smallest 2^ltx pairs covering the row, at most 64;
-// one row per tile when the mid stride is 2^24 elements or more (lane offsets < 2^32).
-__device__ inline uint32_t pair_ltx(uint32_t e0, uint32_t odd, uint32_t s1)
-{
-    const uint32_t np = (e0 + odd + 1) >> 1;
-    uint32_t ltx = 0;
-    while (ltx < 6 && (1u << ltx) < np) ++ltx;
-    return s1 >= (1u << 24) ? 6u : ltx;
-}
-
 // Scatter: every cube of every slab adds 8^level to its node. Neighbouring
 // lanes usually hold the same node (mixtures are spatially coherent), so a run
 // of equal nodes in a wave adds its total once. Runs on sources add to an
 // integer counter through their two end lanes (start: -a 8^l, end: (b+1) 8^l
 // for lanes a..b), which needs no run length; runs on internal nodes (rare)
 // take a branch that the whole wave skips when no lane needs it, and add
-// run length * 8^level at their start lane.
+// run length * 8^level at their start lane. Level-0 slabs of the 16-bit copy
+// (kind 1) hold two sources per unit (count_pairs).
 template <int BLOCK, int UNROLL, bool SPARSE>
-__device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint32_t *__restrict__ maps,
-                                     const uint16_t *__restrict__ maps16, const LevelTable &lt,
-                                     const QueryState &st, const GraphView &gv, const uint32_t *flags_lds)
+__device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const char *__restrict__ maps,
+                                     const char *__restrict__ maps16, const QueryState &st, const GraphView &gv,
+                                     const uint32_t *flags_lds)
 {
     constexpr uint32_t kWaves = BLOCK / 64;
     const uint32_t nseg = gv.nseg;
@@ -645,21 +717,11 @@ __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint3
     for (int si = 0; si < n_slabs; ++si) {
         const Slab &sp = slabs[si];
         if (uni(*flags_lds) & 1u) return;  // overflowed: the box goes to the retry launch
-        if (!SPARSE && lt.use16 && uni(sp.level) == 0) {
-            // level 0: every node is a source; read the 16-bit copy, two cubes per lane
-            const uint32_t axes = uni(sp.axes), f = axes & 3, m = (axes >> 2) & 3, w = (axes >> 4) & 3;
-            const uint32_t X = lt.dims[0][0], Y = lt.dims[0][1], Z = lt.dims[0][2];
-            const bool tr = f == 1;  // rows along y: the y-fastest copy
-            uint64_t str[3];
-            if (tr) str[0] = uint64_t(lt.pitch_y) * Z, str[1] = 1, str[2] = lt.pitch_y;
-            else str[0] = 1, str[1] = lt.pitch_x, str[2] = uint64_t(lt.pitch_x) * Y;
-            const uint32_t bx = uni(sp.bx), by = uni(sp.by), bz = uni(sp.bz);
-            const uint64_t base16 = (tr ? lt.total16 : 0) + bx * str[0] + by * str[1] + bz * str[2];
-            const uint32_t odd = (tr ? by : bx) & 1u;
-            const uint32_t s1 = uint32_t(str[m]), s2 = uint32_t(str[w]);
-            const uint32_t e0 = uni(sp.e0);
-            stream_pairs<UNROLL, kWaves>(maps16 + base16, e0, uni(sp.e1), uni(sp.e2), s1, s2, odd,
-                                         pair_ltx(e0, odd, s1), uint32_t(si) % kWaves,
+        const uint64_t base = (uint64_t(uni(uint32_t(sp.base >> 32))) << 32) | uni(uint32_t(sp.base));
+        const TileWalk tw = tile_walk(uni(sp.units), uni(sp.e1), uni(sp.e2), uni(sp.s1b), uni(sp.s2b), UNROLL);
+        if (!SPARSE && uni(sp.kind) == 1) {
+            // level 0: every node is a source; two cubes per unit
+            stream_pairs<UNROLL, kWaves>(maps16 + base, tw, uni(sp.e0), uni(sp.odd), uint32_t(si) % kWaves,
                                          [&](uint32_t lo, uint32_t hi) { count_pairs(st.seg_cnt, lo, hi, lane); });
             continue;
         }
@@ -667,10 +729,8 @@ __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const uint3
         // a run of lanes [a, b] on one source adds (b + 1 - a) 8^l as -a 8^l at its start lane
         // and (b + 1) 8^l at its end lane (uint32 wrap-around; the counts stay below 2^32)
         const uint32_t w_start = 0u - (lane << lw8), w_end = (lane + 1) << lw8;
-        const uint64_t base = (uint64_t(uni(uint32_t(sp.base >> 32))) << 32) | uni(uint32_t(sp.base));
         const bool go = stream_slab<UNROLL, kWaves>(
-            maps + base, uni(sp.e0), uni(sp.e1), uni(sp.e2), uni(sp.s1), uni(sp.s2), uni(sp.ltx),
-            uint32_t(si) % kWaves,
+            maps + base, tw, uint32_t(si) % kWaves,
             [&](uint32_t v) {
                 if (SPARSE) {
                     uint32_t len;
@@ -748,14 +808,18 @@ struct QueryArgs {
     uint32_t n;
     const uint32_t *order;        // query order (batched) or nullptr (identity)
     uint32_t *counters;           // [0] next big-tier box, [1] boxes in list 1, [2] next box of the
-                                  // global fallback, [3] next small-tier box, [4] next retry box,
-                                  // [5] boxes in list 2, [8] number of big-tier boxes
+                                  // final global tables, [3] next small-tier box, [4] next retry
+                                  // box, [5] boxes in list 2, [6] boxes in list 3, [7] next box of
+                                  // the mid-size global tables, [8] number of big-tier boxes
     uint32_t table_cap;           // LDS hash slots of this launch
     uint32_t chunk;               // small tier: boxes per dequeue (0: automatic)
     uint32_t g_slots;             // hash slots of each fallback worker's global table
     uint32_t *queues;             // tier work queues: counter of queue j at [j * kQueueStride]
     uint32_t *overflow;           // list 1: boxes whose tier table overflowed
     uint32_t *overflow2;          // list 2: boxes whose retry table overflowed too
+    const uint32_t *g_list;       // global-table launches: the boxes they answer,
+    uint32_t g_count_idx;         // counters[] entry holding how many,
+    uint32_t g_next_idx;          // and the one they dequeue with
     uint32_t *ovf_out;            // where this launch reports overflowed boxes (nullptr: mark NaN)
     uint32_t ovf_out_idx;         // counters[] entry that counts them
     uint32_t stats_tag;           // OR-ed into stats[q][1]: which launch answered the box
@@ -832,6 +896,39 @@ __device__ inline void write_result(const QueryArgs &A, QueryShared &sh, const Q
                                     bool nonempty, double vol)
 {
     const uint32_t nseg = A.gv.nseg;
+    if (!SPARSE && !A.out) {
+        // per-source arrays, sparse output (the global-table launches): count the box's
+        // non-zero sources, reserve their entries with one global atomic, write them
+        if (threadIdx.x == 0) sh.nnz = 0;
+        __syncthreads();
+        // a source got voxels iff any of its three words is non-zero (mass below 256 voxels
+        // can sit in the compensation word alone; an untouched source is exactly zero)
+        uint32_t mine = 0;
+        for (uint32_t s = threadIdx.x; s < nseg; s += BLOCK)
+            mine += (ld(&st.seg_cnt[s]) | __float_as_uint(ld(&st.seg_hi[s])) | __float_as_uint(ld(&st.seg_lo[s]))) !=
+                    0u;
+        if (mine) atomicAdd(&sh.nnz, mine);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            sh.base = sh.nnz ? atomicAdd(A.sp_total, sh.nnz) : 0u;
+            A.sp_index[2 * uint64_t(q)] = sh.base;
+            A.sp_index[2 * uint64_t(q) + 1] = sh.nnz;
+            sh.nnz = 0;
+        }
+        __syncthreads();
+        for (uint32_t s = threadIdx.x; s < nseg; s += BLOCK) {
+            const uint32_t c_int = ld(&st.seg_cnt[s]);
+            const float h = ld(&st.seg_hi[s]), l = ld(&st.seg_lo[s]);
+            if ((c_int | __float_as_uint(h) | __float_as_uint(l)) == 0u) continue;
+            const double c = double(c_int) + double(h) + double(l);
+            const uint32_t pos = sh.base + atomicAdd(&sh.nnz, 1u);
+            if (pos < A.sp_cap) {
+                A.sp_seg[pos] = s;
+                A.sp_val[pos] = float(c / vol);
+            }
+        }
+        return;
+    }
     if (!SPARSE) {
         float *o = A.out + uint64_t(q) * nseg;
         for (uint32_t s = threadIdx.x; s < nseg; s += BLOCK) {
@@ -915,7 +1012,8 @@ __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const Quer
     __syncthreads();
     if (nonempty) build_slabs(A.lt, lo, hi, st.slabs, &sh.n_slabs);
     __syncthreads();
-    scatter_slabs<BLOCK, UNROLL, SPARSE>(st.slabs, sh.n_slabs, A.maps, A.maps16, A.lt, st, A.gv, &sh.flags);
+    scatter_slabs<BLOCK, UNROLL, SPARSE>(st.slabs, sh.n_slabs, reinterpret_cast<const char *>(A.maps),
+                                         reinterpret_cast<const char *>(A.maps16), st, A.gv, &sh.flags);
     __syncthreads();
     if (ERR || A.lut_ptr)
         expand_lut<BLOCK, SPARSE, ERR>(A, st);
@@ -1092,9 +1190,17 @@ __global__ __launch_bounds__(BLOCK) void query_retry_kernel(QueryArgs A)
     }
 }
 
-// Fallback for boxes that overflowed the retry table too (list 2): per-worker
-// tables and source arrays in the workspace (global memory).
-template <bool SPARSE, bool ERR>
+// Boxes that overflowed every LDS table, answered with per-worker tables and
+// source arrays in the workspace (global memory): first by many workers with
+// mid-size tables (list 2; what overflows those goes to list 3), then by a few
+// workers whose tables hold every node of the graph (list 3, or list 2 when
+// the graph is small enough for those tables alone). Sources always have
+// per-worker arrays here (dense state, whatever the output): a cube run on a
+// source is one global atomic add without a returned value, where a table
+// entry would take a probe round trip.
+// Boxes that overflowed every LDS table, in per-worker global-memory tables (node
+// table and per-source arrays): each workgroup takes boxes from list A.g_list.
+template <bool ERR>
 __global__ __launch_bounds__(kBlock) void query_fallback_kernel(QueryArgs A)
 {
     extern __shared__ __align__(16) char dyn[];
@@ -1108,24 +1214,24 @@ __global__ __launch_bounds__(kBlock) void query_fallback_kernel(QueryArgs A)
     st.lo = A.g_lo + w * gs;
     st.used = A.g_used + w * gs;
     st.cap = A.g_slots;
-    st.limit = A.g_slots / 4 * 3;
+    st.slabs = reinterpret_cast<Slab *>(dyn);  // the only dynamic LDS of this kernel
+    st.limit = st.cap / 4 * 3;
     st.n_used = &sh.n_used;
     st.flags = &sh.flags;
     st.max_key = &sh.max_key;
-    st.seg_cnt = SPARSE ? nullptr : A.g_seg_cnt + w * A.gv.nseg;
-    st.seg_hi = SPARSE ? nullptr : A.g_seg_hi + w * A.gv.nseg;
-    st.seg_lo = SPARSE ? nullptr : A.g_seg_lo + w * A.gv.nseg;
-    st.slabs = reinterpret_cast<Slab *>(dyn);  // the only dynamic LDS of this kernel
+    st.seg_cnt = A.g_seg_cnt + w * A.gv.nseg;
+    st.seg_hi = A.g_seg_hi + w * A.gv.nseg;
+    st.seg_lo = A.g_seg_lo + w * A.gv.nseg;
     st.seg_var = ERR ? A.g_seg_var + w * A.gv.nseg : nullptr;
     load_rank_ptr<kBlock>(A, sh);
     __syncthreads();
-    const uint32_t n_over = ld(&A.counters[5]);
+    const uint32_t n_over = ld(&A.counters[A.g_count_idx]);
     for (;;) {
-        if (threadIdx.x == 0) sh.q = atomicAdd(&A.counters[2], 1u);
+        if (threadIdx.x == 0) sh.q = atomicAdd(&A.counters[A.g_next_idx], 1u);
         __syncthreads();
         const uint32_t k = sh.q;
-        if (k >= n_over) break;
-        run_query<kBlock, kUnroll, SPARSE, ERR>(A, sh, st, A.overflow2[k], false);
+        if (k >= n_over) break;  // uniform
+        run_query<kBlock, kUnroll, false, ERR>(A, sh, st, A.g_list[k], A.ovf_out != nullptr);
     }
 }
 
@@ -1226,33 +1332,29 @@ __global__ __launch_bounds__(kBlock) void naive_kernel(NaiveArgs A)
     uint32_t lo[3], hi[3];
     const bool nonempty = clip_box(A.boxes + 6 * uint64_t(q), A.lt, lo, hi);
     __syncthreads();
-    if (nonempty && A.lt.use16) {
-        const uint32_t ex = hi[0] - lo[0], ey = hi[1] - lo[1], ez = hi[2] - lo[2];
-        const uint32_t px = A.lt.pitch_x, pxy = A.lt.pitch_x * A.lt.vol[1];
-        const uint32_t odd = lo[0] & 1u, lane = threadIdx.x & 63;
-        stream_pairs<UNROLL, kBlock / 64>(A.map16 + (lo[0] + uint64_t(px) * lo[1] + uint64_t(pxy) * lo[2]), ex, ey, ez,
-                                          px, pxy, odd, pair_ltx(ex, odd, px), 0u,
-                                          [&](uint32_t a, uint32_t b) { count_pairs(cnt, a, b, lane); });
-    } else if (nonempty) {
-        const uint32_t ex = hi[0] - lo[0], ey = hi[1] - lo[1], ez = hi[2] - lo[2];
-        const uint32_t X = A.lt.vol[0], XY = A.lt.vol[0] * A.lt.vol[1];
-        const uint32_t *__restrict__ p = A.map0 + (lo[0] + uint64_t(X) * lo[1] + uint64_t(XY) * lo[2]);
-        uint32_t ltx = 0;
-        while (ltx < 6 && (1u << ltx) < ex) ++ltx;
-        if (X >= (1u << 24)) ltx = 6;  // one row per tile: lane byte offsets stay below 2^32
-        // runs of equal IDs: -start lane at the start, end lane + 1 at the end (see scatter_slabs)
-        const uint32_t lane = threadIdx.x & 63, w_start = 0u - lane, w_end = lane + 1;
-        stream_slab<UNROLL, kBlock / 64>(
-            p, ex, ey, ez, X, XY, ltx, 0u,
-            [&](uint32_t v) {
-                const uint32_t prev = uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x138, 0xF, 0xF, true));
-                const uint32_t next = uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x130, 0xF, 0xF, true));
-                if (v != kEmpty) {
-                    if (v != prev || lane == 0) atomicAdd(&cnt[v], w_start);
-                    if (v != next || lane == 63) atomicAdd(&cnt[v], w_end);
-                }
-            },
-            []() { return false; });
+    if (nonempty) {
+        uint64_t base;
+        uint32_t odd;
+        const TileWalk tw = naive_walk(A.lt, lo, hi, A.lt.use16 != 0, UNROLL, &base, &odd);
+        const uint32_t lane = threadIdx.x & 63;
+        if (A.lt.use16) {
+            stream_pairs<UNROLL, kBlock / 64>(reinterpret_cast<const char *>(A.map16) + base, tw, hi[0] - lo[0], odd,
+                                              0u, [&](uint32_t a, uint32_t b) { count_pairs(cnt, a, b, lane); });
+        } else {
+            // runs of equal IDs: -start lane at the start, end lane + 1 at the end (see scatter_slabs)
+            const uint32_t w_start = 0u - lane, w_end = lane + 1;
+            stream_slab<UNROLL, kBlock / 64>(
+                reinterpret_cast<const char *>(A.map0) + base, tw, 0u,
+                [&](uint32_t v) {
+                    const uint32_t prev = uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x138, 0xF, 0xF, true));
+                    const uint32_t next = uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x130, 0xF, 0xF, true));
+                    if (v != kEmpty) {
+                        if (v != prev || lane == 0) atomicAdd(&cnt[v], w_start);
+                        if (v != next || lane == 63) atomicAdd(&cnt[v], w_end);
+                    }
+                },
+                []() { return false; });
+        }
     }
     __syncthreads();
     const double vol = nonempty ? double(hi[0] - lo[0]) * double(hi[1] - lo[1]) * double(hi[2] - lo[2]) : 0.0;
@@ -1285,7 +1387,8 @@ __global__ __launch_bounds__(kBlock) void footprint_kernel(LevelTable lt, const 
             const uint32_t i0 = r % sl.e0, i1 = (r / sl.e0) % sl.e1, i2 = r / (sl.e0 * sl.e1);
             uint32_t x, y, z;
             slab_coords(sl, i0, i1, i2, &x, &y, &z);
-            const uint32_t node = maps[sl.base + i0 + uint64_t(i1) * sl.s1 + uint64_t(i2) * sl.s2];
+            // kind-0 slab (the table is built without the 16-bit copy): 4-byte units
+            const uint32_t node = maps[sl.base / 4 + i0 + uint64_t(i1) * (sl.s1b / 4) + uint64_t(i2) * (sl.s2b / 4)];
             const uint32_t k = atomicAdd(count, 1u);
             if (k < cap) {
                 uint32_t *c = cubes + 6 * uint64_t(k);
@@ -1367,25 +1470,38 @@ __global__ void tf_sources_kernel(const uint8_t *tf, uint32_t T, uint32_t nseg, 
     out[uint64_t(t) * n_nodes + s] = make_float4(float(c.x) * k, float(c.y) * k, float(c.z) * k, float(c.w) * k);
 }
 
-// One step of the schedule: thread (x, y) computes node sched[lo_i + x] for transfer
-// function y (grid.y = T), so a step launches T threads per node and the gathers of
-// all T planes are in flight together. Lanes of a wave share the plane and take
-// consecutive schedule entries (coalesced schedule reads and, nodes being numbered
-// by rank, mostly contiguous stores).
+// One step of the schedule: thread (x, y) computes node sched[lo_i + x] for the
+// transfer functions P y .. P y + P - 1 (grid.y = ceil(T / P)): it loads the node's
+// entry and both predecessors' colours in all P planes before it stores any, so
+// 2 P gathers per thread are in flight together. Lanes of a wave take consecutive
+// schedule entries (coalesced schedule reads and, nodes being numbered by rank,
+// mostly contiguous stores).
+template <int P>
 __global__ void tf_step_kernel(const SchedNode *__restrict__ sched, uint32_t lo_i, uint32_t hi_i, uint32_t n_nodes,
-                               float4 *out)
+                               uint32_t T, float4 *out)
 {
     const uint32_t i = lo_i + blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= hi_i) return;
     const SchedNode t = sched[i];
-    float4 *o = out + uint64_t(blockIdx.y) * n_nodes;
-    const float4 va = o[t.a], vb = o[t.b];
-    float4 r;
-    r.x = fmaf(t.w, vb.x - va.x, va.x);
-    r.y = fmaf(t.w, vb.y - va.y, va.y);
-    r.z = fmaf(t.w, vb.z - va.z, va.z);
-    r.w = fmaf(t.w, vb.w - va.w, va.w);
-    o[t.id] = r;
+    const uint32_t p0 = blockIdx.y * P;
+    float4 va[P], vb[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+        if (P == 1 || p0 + p < T) {
+            const float4 *o = out + uint64_t(p0 + p) * n_nodes;
+            va[p] = o[t.a];
+            vb[p] = o[t.b];
+        }
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+        if (P == 1 || p0 + p < T) {
+            float4 r;
+            r.x = fmaf(t.w, vb[p].x - va[p].x, va[p].x);
+            r.y = fmaf(t.w, vb[p].y - va[p].y, va[p].y);
+            r.z = fmaf(t.w, vb[p].z - va[p].z, va[p].z);
+            r.w = fmaf(t.w, vb[p].w - va[p].w, va[p].w);
+            out[uint64_t(p0 + p) * n_nodes + t.id] = r;
+        }
 }
 
 // Mean colour of a box under one propagated palette: every footprint cube adds
@@ -1417,7 +1533,7 @@ __global__ __launch_bounds__(kBlock) void box_colour_kernel(LevelTable lt, const
         const uint32_t c = slab_count(sl);
         for (uint32_t r = threadIdx.x; r < c; r += kBlock) {
             const uint32_t i0 = r % sl.e0, i1 = (r / sl.e0) % sl.e1, i2 = r / (sl.e0 * sl.e1);
-            const uint32_t node = maps[sl.base + i0 + uint64_t(i1) * sl.s1 + uint64_t(i2) * sl.s2];
+            const uint32_t node = maps[sl.base / 4 + i0 + uint64_t(i1) * (sl.s1b / 4) + uint64_t(i2) * (sl.s2b / 4)];
             const float4 v = pal[node];
             acc[0] += w * v.x, acc[1] += w * v.y, acc[2] += w * v.z, acc[3] += w * v.w;
         }
@@ -1451,6 +1567,41 @@ __global__ void palette_fetch_kernel(const float4 *__restrict__ palette, uint32_
     const uint32_t node = in ? map[x + uint64_t(X) * (y + uint64_t(Y) * z)] : 0u;
     for (uint32_t t = 0; t < T; ++t)
         out[uint64_t(t) * n + i] = in ? palette[uint64_t(t) * n_nodes + node] : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// The voxel data (A) of a graph stream (Table "bitstream"): per level, voxel by
+// voxel (x fastest), the node ID minus i_min(l) in r(l) bits, least significant
+// bit first. One thread per voxel: the field is read from the two 32-bit words
+// that hold it; level-0 IDs are sources, the others are renumbered by `perm`.
+// An ID out of range sets *bad and writes node 0.
+struct StreamLevels {
+    uint32_t n_levels;
+    uint32_t nseg, n_nodes;
+    uint64_t off[MG_MAX_LEVELS + 1];     // first voxel of each level
+    uint64_t bit[MG_MAX_LEVELS];         // bit of its first field, from the first word
+    uint32_t r[MG_MAX_LEVELS], lo[MG_MAX_LEVELS];
+};
+
+__global__ void unpack_maps_kernel(StreamLevels sl, const uint32_t *__restrict__ words,
+                                   const uint32_t *__restrict__ perm, uint32_t *__restrict__ maps, uint32_t *bad)
+{
+    const uint64_t total = sl.off[sl.n_levels];
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += stride) {
+        uint32_t l = 0;
+        while (i >= sl.off[l + 1]) ++l;
+        const uint32_t r = sl.r[l];
+        const uint64_t b = sl.bit[l] + (i - sl.off[l]) * r;
+        const uint64_t w = b >> 5;
+        const uint64_t two = (uint64_t(words[w + 1]) << 32) | words[w];
+        const uint64_t field = r ? (two >> (b & 31)) & ((uint64_t(1) << r) - 1) : 0;
+        const uint64_t id = sl.lo[l] + field;
+        const uint64_t limit = l == 0 ? sl.nseg : sl.n_nodes;
+        uint32_t node = 0;
+        if (id < limit) node = l == 0 ? uint32_t(id) : perm[id];
+        else atomicOr(bad, 1u);
+        maps[i] = node;
+    }
 }
 
 // 16-bit copies of level 0: x-fastest with row pitch px, and y-fastest (y + py (z + Z x))
@@ -1490,41 +1641,56 @@ __global__ void fill_u32_kernel(uint32_t *p, uint64_t n, uint32_t v)
     for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
-LevelTable level_table(const Graph &g)
+// Levels, offsets and the 16-bit copy's pitches of a volume (the graph's own
+// level table for its dims; the host-side address check builds one from dims).
+LevelTable level_table_dims(const uint32_t dims[3])
 {
     LevelTable lt;
     std::memset(&lt, 0, sizeof(lt));
-    lt.n_levels = g.n_levels;
-    for (int a = 0; a < 3; ++a) lt.vol[a] = g.dims[a];
-    for (uint32_t l = 0; l < g.n_levels; ++l) {
-        for (int a = 0; a < 3; ++a) lt.dims[l][a] = g.lev_dims[3 * l + a];
-        lt.off[l] = g.lev_off[l];
+    std::vector<uint32_t> ld;
+    level_dims(dims, &ld);
+    lt.n_levels = uint32_t(ld.size() / 3);
+    for (int a = 0; a < 3; ++a) lt.vol[a] = dims[a];
+    uint64_t off = 0;
+    for (uint32_t l = 0; l < lt.n_levels && l < MG_MAX_LEVELS; ++l) {
+        for (int a = 0; a < 3; ++a) lt.dims[l][a] = ld[3 * l + a];
+        lt.off[l] = off;
+        off += uint64_t(ld[3 * l]) * ld[3 * l + 1] * ld[3 * l + 2];
     }
-    lt.total = g.lev_off[g.n_levels];
-    lt.pitch_x = g.dims[0] + (g.dims[0] & 1u);
-    lt.pitch_y = g.dims[1] + (g.dims[1] & 1u);
-    lt.total16 = uint64_t(lt.pitch_x) * g.dims[1] * g.dims[2];
+    lt.total = off;
+    lt.pitch_x = dims[0] + (dims[0] & 1u);
+    lt.pitch_y = dims[1] + (dims[1] & 1u);
+    lt.total16 = uint64_t(lt.pitch_x) * dims[1] * dims[2];
     lt.use16 = 0;  // set per launch where the 16-bit copy is used
     return lt;
 }
 
+LevelTable level_table(const Graph &g) { return level_table_dims(g.dims); }
+
 // ---------------------------------------------------------------- workspace layout
+
+// Per-worker global-memory tables of one global-table launch.
+struct GlobalPool {
+    uint32_t workers, slots;
+    uint32_t *keys, *cnt, *used;
+    float *hi, *lo;
+    uint32_t *seg_cnt;
+    float *seg_hi, *seg_lo, *seg_var;
+};
 
 struct Workspace {
     uint32_t *counters;   // 64 u32
-    uint32_t *queues;     // kQueues * kQueueStride u32: [0] next, [1] overflow count, [2] next fallback
+    uint32_t *queues;     // kQueues * kQueueStride u32: per-queue counters of the two tiers
     uint32_t *buckets;    // 64 u32
     uint32_t *bucket_of;  // [max_boxes]
     uint32_t *order;      // [max_boxes]
-    uint32_t *overflow;   // [max_boxes]
-    uint32_t *overflow2;  // [max_boxes]
-    uint32_t *g_keys, *g_cnt, *g_used;
-    float *g_hi, *g_lo;
-    uint32_t *g_seg_cnt;
-    float *g_seg_hi, *g_seg_lo, *g_seg_var;
+    uint32_t *overflow;   // [max_boxes] list 1: overflowed a tier table
+    uint32_t *overflow2;  // [max_boxes] list 2: overflowed the retry table too
+    uint32_t *overflow3;  // [max_boxes] list 3: overflowed a mid-size global table too
+    GlobalPool fin;       // tables that hold every node of the graph
+    GlobalPool mid;       // many workers with mid-size tables (workers 0: none)
     uint64_t bytes;
     uint32_t max_boxes;
-    uint32_t workers;     // fallback workers the tables are carved for
 };
 
 inline uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
@@ -1544,38 +1710,50 @@ inline uint32_t fallback_workers(const Graph &g)
 {
     return std::max<uint32_t>(16u, uint32_t(uint64_t(kFallbackWorkers) * kHashGlobal / fallback_slots(g)));
 }
+// Mid-size global tables: kMidWorkers workers of kHashGlobal slots each, for
+// boxes that overflow every LDS table but touch fewer than 3/4 x kHashGlobal
+// nodes (the largest boxes of the 15,917-capsule volume touch ~30,000). Only
+// where the final tables are larger than that.
+inline uint32_t mid_workers(const Graph &g) { return fallback_slots(g) > kHashGlobal ? kMidWorkers : 0u; }
 
-// Carves the workspace for `workers` fallback workers (0: fallback_workers(g));
+// Carves the workspace for `fin_workers` workers of the final tables (0:
+// fallback_workers(g)) and `mid_workers` of the mid-size ones (~0u: mid_workers(g));
 // with base == nullptr only computes the size.
-Workspace carve(const Graph &g, char *base, uint32_t max_boxes, uint32_t workers = 0)
+Workspace carve(const Graph &g, char *base, uint32_t max_boxes, uint32_t fin_workers = 0,
+                uint32_t n_mid = ~0u)
 {
     Workspace w;
-    w.workers = workers ? workers : fallback_workers(g);
     uint64_t off = 0;
     auto take = [&](uint64_t bytes) {
         char *p = base ? base + off : nullptr;
         off += align256(bytes);
         return p;
     };
+    auto pool = [&](GlobalPool &p, uint32_t workers, uint32_t slots) {
+        p.workers = workers, p.slots = slots;
+        const uint64_t hs = uint64_t(workers) * slots;
+        p.keys = reinterpret_cast<uint32_t *>(take(hs * 4));
+        p.cnt = reinterpret_cast<uint32_t *>(take(hs * 4));
+        p.used = reinterpret_cast<uint32_t *>(take(hs * 4));
+        p.hi = reinterpret_cast<float *>(take(hs * 4));
+        p.lo = reinterpret_cast<float *>(take(hs * 4));
+        const uint64_t ss = uint64_t(workers) * g.nseg;
+        p.seg_cnt = reinterpret_cast<uint32_t *>(take(ss * 4));
+        p.seg_hi = reinterpret_cast<float *>(take(ss * 4));
+        p.seg_lo = reinterpret_cast<float *>(take(ss * 4));
+        p.seg_var = reinterpret_cast<float *>(take(ss * 4));
+    };
     // fixed-size part first, so that its layout does not depend on max_boxes
     w.counters = reinterpret_cast<uint32_t *>(take(64 * 4));
     w.buckets = reinterpret_cast<uint32_t *>(take(64 * 4));
     w.queues = reinterpret_cast<uint32_t *>(take(uint64_t(kQueues) * kQueueStride * 4));
-    const uint64_t hs = uint64_t(w.workers) * fallback_slots(g);
-    w.g_keys = reinterpret_cast<uint32_t *>(take(hs * 4));
-    w.g_cnt = reinterpret_cast<uint32_t *>(take(hs * 4));
-    w.g_used = reinterpret_cast<uint32_t *>(take(hs * 4));
-    w.g_hi = reinterpret_cast<float *>(take(hs * 4));
-    w.g_lo = reinterpret_cast<float *>(take(hs * 4));
-    const uint64_t ss = uint64_t(w.workers) * g.nseg;
-    w.g_seg_cnt = reinterpret_cast<uint32_t *>(take(ss * 4));
-    w.g_seg_hi = reinterpret_cast<float *>(take(ss * 4));
-    w.g_seg_lo = reinterpret_cast<float *>(take(ss * 4));
-    w.g_seg_var = reinterpret_cast<float *>(take(ss * 4));
+    pool(w.fin, fin_workers ? fin_workers : fallback_workers(g), fallback_slots(g));
+    pool(w.mid, n_mid == ~0u ? mid_workers(g) : n_mid, kHashGlobal);
     w.bucket_of = reinterpret_cast<uint32_t *>(take(uint64_t(max_boxes) * 4));
     w.order = reinterpret_cast<uint32_t *>(take(uint64_t(max_boxes) * 4));
     w.overflow = reinterpret_cast<uint32_t *>(take(uint64_t(max_boxes) * 4));
     w.overflow2 = reinterpret_cast<uint32_t *>(take(uint64_t(max_boxes) * 4));
+    w.overflow3 = reinterpret_cast<uint32_t *>(take(uint64_t(max_boxes) * 4));
     w.bytes = off;
     w.max_boxes = max_boxes;
     return w;
@@ -1682,6 +1860,192 @@ int occupancy(DeviceState &d, const void *k, int block, uint32_t dyn, int *out, 
 
 }  // namespace
 
+// ---------------------------------------------------------------- host-side address check
+
+// Every load the query kernels (and, if naive, the naive scan) issue for these
+// boxes, replayed on the host with the kernels' own slab builder and tile-walk
+// helpers, UNROLL loads per block. counts: [0] boxes, [1] slabs, [2] lane
+// loads checked, [3] cubes read.
+int check_load_addresses(const uint32_t dims[3], bool use16, bool naive, const uint32_t *boxes, uint32_t n,
+                         uint32_t unroll, uint64_t counts[4], std::string *err)
+{
+    LevelTable lt = level_table_dims(dims);
+    if (lt.n_levels > kMaxLevelsDev) {
+        *err = "more than " + std::to_string(kMaxLevelsDev) + " mip levels";
+        return MG_ELIMIT;
+    }
+    lt.use16 = use16 ? 1u : 0u;
+    const uint64_t bytes32 = 2 * lt.total * 4;  // maps then maps_t
+    const uint64_t n16t = uint64_t(lt.pitch_y) * dims[2] * dims[0];
+    const uint64_t bytes16 = (lt.total16 + n16t) * 2;
+    for (int k = 0; k < 4; ++k) counts[k] = 0;
+    std::vector<Slab> slabs(kMaxSlabs);
+    std::string where;
+    // Replays every load of a tile walk (all UNROLL loads of every block, consumed or
+    // not) and hands each consumed in-slab unit to unit(t, row, slice, pair bits).
+    auto replay = [&](const TileWalk &tw, uint64_t base, uint64_t buf, uint32_t e0, uint32_t odd, bool pairs,
+                      auto unit) -> bool {
+        const uint64_t extent = uint64_t(tw.e2 - 1) * tw.s2b + uint64_t(tw.e1 - 1) * tw.s1b + 4ull * tw.units;
+        if (base % 4 != 0) {
+            where = "unaligned slab base";
+            return false;
+        }
+        uint64_t seen = 0;
+        for (uint32_t b = 0; b < tw.n_blk; ++b) {
+            const uint32_t t0 = b % tw.n_t0, rb = (b / tw.n_t0) % tw.n_rb, k2 = b / (tw.n_t0 * tw.n_rb);
+            const uint64_t blk = tile_block_offset(tw, t0, rb, k2);
+            const uint32_t n_u = tile_n_u(tw, rb, unroll);
+            if (n_u < 1) {
+                where = "a block without a row tile";
+                return false;
+            }
+            for (uint32_t lane = 0; lane < 64; ++lane) {
+                const uint32_t lane_bytes = tile_lane_bytes(tw, lane);
+                const uint32_t n_ok = tile_n_ok(tw, t0, rb, lane);
+                if (uint64_t((lane >> tw.ltx)) * tw.s1b + (lane & ((1u << tw.ltx) - 1)) * 4ull >= (1ull << 32)) {
+                    where = "lane offset does not fit 32 bits";
+                    return false;
+                }
+                const uint32_t x = tile_unit(tw, t0, lane);
+                const uint32_t pb = pairs ? pair_bits(x, e0, odd) : 1u;
+                for (uint32_t u = 0; u < unroll; ++u) {
+                    const uint64_t off = tile_load_offset(tw, blk, u, n_u, n_ok, lane_bytes);
+                    ++counts[2];
+                    if (off + 4 > extent) {
+                        where = "load past the slab";
+                        return false;
+                    }
+                    if (base + off + 4 > buf) {
+                        where = "load past the buffer";
+                        return false;
+                    }
+                    if (u < n_u && u < n_ok) {  // consumed, inside the slab
+                        const uint32_t row = rb * tw.rows + u * tw.ty + (lane >> tw.ltx);
+                        if (off != uint64_t(k2) * tw.s2b + uint64_t(row) * tw.s1b + 4ull * x) {
+                            where = "load is not its unit";
+                            return false;
+                        }
+                        ++seen;
+                        if (!unit(x, row, k2, pb)) return false;
+                    }
+                }
+            }
+        }
+        if (seen != uint64_t(tw.units) * tw.e1 * tw.e2) {
+            where = "units read " + std::to_string(seen) + " of " + std::to_string(uint64_t(tw.units) * tw.e1 * tw.e2);
+            return false;
+        }
+        return true;
+    };
+    for (uint32_t q = 0; q < n; ++q) {
+        uint32_t lo[3], hi[3];
+        if (!clip_box(boxes + 6 * uint64_t(q), lt, lo, hi)) continue;
+        ++counts[0];
+        int ns = 0;
+        uint64_t cubes_closed = 0;
+        for (uint32_t l = 0; l < lt.n_levels; ++l) {
+            const int k = level_slabs<false>(lt, lo, hi, l, nullptr);
+            if (k > 6) {  // the LDS slab table holds 6 per level
+                *err = "box " + std::to_string(q) + ": more than 6 slabs at one level";
+                return MG_ELIMIT;
+            }
+            level_slabs<true>(lt, lo, hi, l, slabs.data() + ns);
+            ns += k;
+            uint64_t outer = 1, inner = 1;
+            for (int d = 0; d < 3; ++d) {
+                const uint64_t one = uint64_t(1) << l;
+                const uint64_t a = (uint64_t(lo[d]) + one - 1) >> l, b = hi[d] >> l;
+                const uint64_t pa = (uint64_t(lo[d]) + 2 * one - 1) >> (l + 1), pb = hi[d] >> (l + 1);
+                outer *= b > a ? b - a : 0;
+                inner *= pb > pa ? 2 * (pb - pa) : 0;
+            }
+            cubes_closed += outer - inner;
+        }
+        uint64_t cubes = 0;
+        for (int i = 0; i < ns; ++i) {
+            const Slab &sl = slabs[i];
+            ++counts[1];
+            const uint32_t L = sl.level;
+            const TileWalk tw = tile_walk(sl.units, sl.e1, sl.e2, sl.s1b, sl.s2b, unroll);
+            const bool tr = (sl.axes & 3) == 1;
+            const uint32_t X = lt.dims[L][0], Y = lt.dims[L][1], Z = lt.dims[L][2];
+            auto unit = [&](uint32_t x, uint32_t row, uint32_t k2, uint32_t pb) -> bool {
+                for (uint32_t h = 0; h < (sl.kind ? 2u : 1u); ++h) {
+                    if (!((pb >> h) & 1u)) continue;
+                    const uint32_t i0 = sl.kind ? 2 * x + h - sl.odd : x;
+                    uint32_t cx, cy, cz;
+                    slab_coords(sl, i0, row, k2, &cx, &cy, &cz);
+                    const uint32_t cc[3] = {cx, cy, cz};
+                    for (int d = 0; d < 3; ++d)
+                        if ((uint64_t(cc[d]) + 1) << L > hi[d] || uint64_t(cc[d]) << L < lo[d]) {
+                            where = "cube outside the box";
+                            return false;
+                        }
+                    uint64_t el;
+                    if (sl.kind) el = tr ? lt.total16 + cy + uint64_t(lt.pitch_y) * (cz + uint64_t(Z) * cx)
+                                         : cx + uint64_t(lt.pitch_x) * (cy + uint64_t(Y) * cz);
+                    else el = tr ? lt.total + lt.off[L] + cy + uint64_t(Y) * (cz + uint64_t(Z) * cx)
+                                 : lt.off[L] + cx + uint64_t(X) * (cy + uint64_t(Y) * cz);
+                    const uint64_t byte = sl.base + uint64_t(k2) * sl.s2b + uint64_t(row) * sl.s1b + 4ull * x;
+                    const uint64_t at = sl.kind ? byte / 2 + h : byte / 4;
+                    if (el != at) {
+                        where = "address is not the cube's element";
+                        return false;
+                    }
+                    ++cubes;
+                }
+                return true;
+            };
+            if (!replay(tw, sl.base, sl.kind ? bytes16 : bytes32, sl.e0, sl.odd, sl.kind != 0, unit)) {
+                *err = "box " + std::to_string(q) + " level " + std::to_string(L) + " slab " + std::to_string(sl.e0) +
+                       "x" + std::to_string(sl.e1) + " kind " + std::to_string(sl.kind) + ": " + where;
+                return MG_ELIMIT;
+            }
+        }
+        if (cubes != cubes_closed) {
+            *err = "box " + std::to_string(q) + ": " + std::to_string(cubes) + " cubes read, the footprint has " +
+                   std::to_string(cubes_closed);
+            return MG_ELIMIT;
+        }
+        counts[3] += cubes;
+        if (naive) {  // the naive scan reads level 0 of the box from the x-fastest copy
+            uint64_t base;
+            uint32_t odd;
+            const TileWalk tw = naive_walk(lt, lo, hi, use16, unroll, &base, &odd);
+            uint64_t vox = 0;
+            auto unit = [&](uint32_t x, uint32_t row, uint32_t k2, uint32_t pb) -> bool {
+                for (uint32_t h = 0; h < (use16 ? 2u : 1u); ++h) {
+                    if (!((pb >> h) & 1u)) continue;
+                    const uint32_t cx = lo[0] + (use16 ? 2 * x + h - odd : x), cy = lo[1] + row, cz = lo[2] + k2;
+                    if (cx >= hi[0] || cy >= hi[1] || cz >= hi[2]) {
+                        where = "voxel outside the box";
+                        return false;
+                    }
+                    const uint64_t el = use16 ? cx + uint64_t(lt.pitch_x) * (cy + uint64_t(dims[1]) * cz)
+                                              : cx + uint64_t(dims[0]) * (cy + uint64_t(dims[1]) * cz);
+                    const uint64_t off = base + uint64_t(k2) * tw.s2b + uint64_t(row) * tw.s1b + 4ull * x;
+                    if (el != (use16 ? off / 2 + h : off / 4)) {
+                        where = "address is not the voxel's element";
+                        return false;
+                    }
+                    ++vox;
+                }
+                return true;
+            };
+            const uint64_t vox0 = uint64_t(dims[0]) * dims[1] * dims[2];  // level 0 of the 32-bit maps
+            if (!replay(tw, base, use16 ? lt.total16 * 2 : vox0 * 4, hi[0] - lo[0], odd, use16, unit)) {
+                *err = "box " + std::to_string(q) + " naive scan: " + where;
+                return MG_ELIMIT;
+            }
+            if (vox != uint64_t(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2])) {
+                *err = "box " + std::to_string(q) + " naive scan: voxels read " + std::to_string(vox);
+                return MG_ELIMIT;
+            }
+        }
+    }
+    return MG_OK;
+}
+
 // ---------------------------------------------------------------- entry points
 
 // Byte offsets of the graph's device arrays inside one buffer (each 256-byte
@@ -1721,7 +2085,89 @@ DeviceLayout device_layout(const Graph &g)
 // Fills `base` (device memory of layout.bytes bytes on `device`) with the
 // graph's arrays and derived copies, enqueued on `stream`, then waits for
 // them; the graph then reads only this memory. owned: mg_free releases it.
-int dev_bind(Graph *g, int device, void *base, uint64_t bytes, hipStream_t s, bool owned, std::string *err)
+// Where a graph's maps come from when they are not on the host: its stream.
+struct StreamSrc {
+    const uint8_t *buf;
+    uint64_t size;
+    const StreamMaps *sm;
+};
+
+// Decodes the stream's voxel data into d.maps (x fastest, every level) on `s`;
+// waits for it and checks every node ID.
+int decode_stream_maps(Graph *g, const StreamSrc &src, hipStream_t s, std::string *err)
+{
+    const StreamMaps &sm = *src.sm;
+    DeviceState &d = g->dev;
+    StreamLevels lv;
+    std::memset(&lv, 0, sizeof(lv));
+    lv.n_levels = g->n_levels;
+    lv.nseg = g->nseg;
+    lv.n_nodes = g->n_nodes;
+    // the staged words start at the 32-bit word holding (A)'s first bit
+    const uint64_t first_byte = (sm.a_bit >> 5) * 4;
+    const uint64_t lead = sm.a_bit - first_byte * 8;
+    uint64_t bits = 0;
+    for (uint32_t l = 0; l < g->n_levels; ++l) {
+        lv.off[l] = g->lev_off[l];
+        lv.bit[l] = lead + sm.bit_off[l];
+        lv.r[l] = sm.r[l];
+        lv.lo[l] = sm.lo[l];
+        bits = sm.bit_off[l] + uint64_t(sm.r[l]) * (g->lev_off[l + 1] - g->lev_off[l]);
+    }
+    lv.off[g->n_levels] = g->lev_off[g->n_levels];
+    // every field lies in the staged words; one zero word past the last field
+    const uint64_t words = (lead + bits + 31) / 32 + 1;
+    const uint64_t avail = src.size > first_byte ? std::min<uint64_t>(src.size - first_byte, words * 4) : 0;
+    void *stage = nullptr, *perm = nullptr, *bad = nullptr;
+    const uint64_t perm_bytes = std::max<uint64_t>(sm.perm.size(), 1) * 4;
+    if (hipMalloc(&stage, words * 4) != hipSuccess || hipMalloc(&perm, perm_bytes) != hipSuccess ||
+        hipMalloc(&bad, 4) != hipSuccess) {
+        (void)hipGetLastError();
+        if (stage) (void)hipFree(stage);
+        if (perm) (void)hipFree(perm);
+        *err = "device allocation for decoding the graph stream failed";
+        return MG_ENOMEM;
+    }
+    int rc = MG_OK;
+    uint32_t flag = 0;
+    auto run = [&]() -> int {
+        HIP_TRY(hipMemcpyAsync(stage, src.buf + first_byte, avail, hipMemcpyHostToDevice, s));
+        if (avail < words * 4)  // the stream ends inside the last words: zero the rest
+            hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, s,
+                               static_cast<uint32_t *>(stage) + avail / 4, words - avail / 4, 0u);
+        if (avail % 4) {       // a partial last word: its bytes past the stream read as zero
+            uint32_t tail = 0;
+            std::memcpy(&tail, src.buf + first_byte + (avail / 4) * 4, avail % 4);
+            HIP_TRY(hipMemcpyAsync(static_cast<uint32_t *>(stage) + avail / 4, &tail, 4, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));  // `tail` lives on this stack frame
+        }
+        if (!sm.perm.empty())
+            HIP_TRY(hipMemcpyAsync(perm, sm.perm.data(), sm.perm.size() * 4, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, s, static_cast<uint32_t *>(bad), uint64_t(1), 0u);
+        const uint64_t total = g->lev_off[g->n_levels];
+        const uint32_t blocks = uint32_t(std::min<uint64_t>((total + 255) / 256, 65536));
+        hipLaunchKernelGGL(unpack_maps_kernel, dim3(blocks), dim3(256), 0, s, lv,
+                           static_cast<const uint32_t *>(stage), static_cast<const uint32_t *>(perm), d.maps,
+                           static_cast<uint32_t *>(bad));
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(&flag, bad, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return MG_OK;
+    };
+    rc = run();
+    (void)hipFree(stage);
+    (void)hipFree(perm);
+    (void)hipFree(bad);
+    if (rc) return rc;
+    if (flag) {
+        *err = "graph stream: voxel node ID out of range";
+        return MG_EFORMAT;
+    }
+    return MG_OK;
+}
+
+int dev_bind(Graph *g, int device, void *base, uint64_t bytes, hipStream_t s, bool owned, std::string *err,
+             const StreamSrc *src = nullptr)
 {
     DeviceState &d = g->dev;
     const DeviceLayout L = device_layout(*g);
@@ -1762,7 +2208,11 @@ int dev_bind(Graph *g, int device, void *base, uint64_t bytes, hipStream_t s, bo
     HIP_TRY(hipMemcpyAsync(d.sched, sched.data(), sched.size() * sizeof(SchedNode), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d.rank_ptr, g->rank_ptr.data(), g->rank_ptr.size() * 4, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d.mixlen, mixlen.data(), mixlen.size() * 4, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(d.maps, g->maps.data(), nmap * 4, hipMemcpyHostToDevice, s));
+    if (src) {
+        if (int rc = decode_stream_maps(g, *src, s, err)) return rc;
+    } else {
+        HIP_TRY(hipMemcpyAsync(d.maps, g->maps.data(), nmap * 4, hipMemcpyHostToDevice, s));
+    }
     for (uint32_t l = 0; l < g->n_levels; ++l) {
         const uint32_t X = g->lev_dims[3 * l], Y = g->lev_dims[3 * l + 1], Z = g->lev_dims[3 * l + 2];
         const uint64_t cnt = uint64_t(X) * Y * Z;
@@ -1788,6 +2238,10 @@ uint64_t dev_device_bytes(const Graph &g) { return device_layout(g).bytes; }
 
 int dev_bind_device(Graph *g, int device, void *base, uint64_t bytes, void *stream, std::string *err)
 {
+    if (g->maps_on_device) {
+        *err = "the graph's node maps exist only on its device (decoded from a stream there)";
+        return MG_ESTATE;
+    }
     DeviceGuard guard;
     if (g->dev.device >= 0) dev_free(g);
     int ndev = 0;
@@ -1802,7 +2256,7 @@ int dev_bind_device(Graph *g, int device, void *base, uint64_t bytes, void *stre
     return rc;
 }
 
-int dev_upload(Graph *g, int device, std::string *err)
+int upload_with(Graph *g, int device, const StreamSrc *src, std::string *err)
 {
     DeviceGuard guard;
     if (g->dev.device >= 0) dev_free(g);
@@ -1820,12 +2274,41 @@ int dev_upload(Graph *g, int device, std::string *err)
         *err = "mg_upload: device allocation of " + std::to_string(bytes) + " bytes failed";
         return MG_ENOMEM;
     }
-    const int rc = dev_bind(g, device, base, bytes, nullptr, true, err);
+    const int rc = dev_bind(g, device, base, bytes, nullptr, true, err, src);
     if (rc) {
         if (g->dev.base != base) (void)hipFree(base);  // not recorded yet: release it here
         dev_free(g);
     }
     return rc;
+}
+
+int dev_upload(Graph *g, int device, std::string *err)
+{
+    if (g->maps_on_device) {
+        *err = "the graph's node maps exist only on its device (decoded from a stream there)";
+        return MG_ESTATE;
+    }
+    return upload_with(g, device, nullptr, err);
+}
+
+int dev_upload_stream(Graph *g, const uint8_t *buf, uint64_t size, const StreamMaps &sm, int device,
+                      std::string *err)
+{
+    const StreamSrc src{buf, size, &sm};
+    return upload_with(g, device, &src, err);
+}
+
+int dev_export_map(const Graph &g, uint32_t level, uint32_t *out, std::string *err)
+{
+    if (g.dev.device < 0 || !g.dev.maps) {
+        *err = "the graph is not on a device";
+        return MG_ESTATE;
+    }
+    DeviceGuard guard;
+    HIP_TRY(hipSetDevice(g.dev.device));
+    const uint64_t n = g.lev_off[level + 1] - g.lev_off[level];
+    HIP_TRY(hipMemcpy(out, g.dev.maps + g.lev_off[level], n * 4, hipMemcpyDeviceToHost));
+    return MG_OK;
 }
 
 int dev_upload_lut(Graph *g, std::string *err)
@@ -1925,18 +2408,27 @@ uint64_t dev_workspace_bytes(const Graph &g, uint32_t max_boxes)
 // The global fallback tables of a workspace in their clean state (empty keys,
 // zero counts and mass), by fill kernels on `s` (no memset: callers may
 // capture the stream into a graph).
+void clear_pool(const Graph &g, const GlobalPool &p, hipStream_t s)
+{
+    const uint64_t hs = uint64_t(p.workers) * p.slots;
+    if (hs) {
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, p.keys, hs, kEmpty);
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, p.cnt, hs, 0u);
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, reinterpret_cast<uint32_t *>(p.hi), hs, 0u);
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, reinterpret_cast<uint32_t *>(p.lo), hs, 0u);
+    }
+    const uint64_t ss = uint64_t(p.workers) * g.nseg;
+    if (!ss) return;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, p.seg_cnt, ss, 0u);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, reinterpret_cast<uint32_t *>(p.seg_hi), ss, 0u);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, reinterpret_cast<uint32_t *>(p.seg_lo), ss, 0u);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, reinterpret_cast<uint32_t *>(p.seg_var), ss, 0u);
+}
+
 void clear_fallback_tables(const Graph &g, const Workspace &w, hipStream_t s)
 {
-    const uint64_t hs = uint64_t(w.workers) * fallback_slots(g);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, w.g_keys, hs, kEmpty);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, w.g_cnt, hs, 0u);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_hi), hs, 0u);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(1024), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_lo), hs, 0u);
-    const uint64_t ss = uint64_t(w.workers) * g.nseg;
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, w.g_seg_cnt, ss, 0u);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_seg_hi), ss, 0u);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_seg_lo), ss, 0u);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, s, reinterpret_cast<uint32_t *>(w.g_seg_var), ss, 0u);
+    clear_pool(g, w.fin, s);
+    clear_pool(g, w.mid, s);
 }
 
 int dev_workspace_init(Graph *g, void *work, uint64_t bytes, void *stream, std::string *err)
@@ -2028,12 +2520,31 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
     A.ovf_out_idx = 5;
     hipLaunchKernelGGL(kretry, dim3(uint32_t(d.ncu) * uint32_t(occ_retry)), dim3(kBlockBig), dyn_retry, s, A);
     HIP_TRY(hipGetLastError());
-    A.ovf_out = nullptr;
+    // boxes that overflowed every LDS table: global-memory tables, first many workers with
+    // mid-size tables (overflow: list 3), then the few whose tables hold the whole graph
     A.stats_tag = 0x80000000u;
-    const QueryKernel kfallback = query_fallback_kernel<SPARSE, ERR>;
-    A.g_slots = fallback_slots(*g);
-    hipLaunchKernelGGL(kfallback, dim3(w.workers), dim3(kBlock),
-                       6u * L * uint32_t(sizeof(Slab)), s, A);
+    const QueryKernel kfallback = query_fallback_kernel<ERR>;
+    const uint32_t dyn_fb = 6u * L * uint32_t(sizeof(Slab));
+    auto use_pool = [&](const GlobalPool &p) {
+        A.g_slots = p.slots;
+        A.g_keys = p.keys, A.g_cnt = p.cnt, A.g_used = p.used, A.g_hi = p.hi, A.g_lo = p.lo;
+        A.g_seg_cnt = p.seg_cnt, A.g_seg_hi = p.seg_hi, A.g_seg_lo = p.seg_lo, A.g_seg_var = p.seg_var;
+    };
+    if (w.mid.workers) {
+        use_pool(w.mid);
+        A.g_list = w.overflow2, A.g_count_idx = 5, A.g_next_idx = 7;
+        A.ovf_out = w.overflow3;
+        A.ovf_out_idx = 6;
+        hipLaunchKernelGGL(kfallback, dim3(w.mid.workers), dim3(kBlock), dyn_fb, s, A);
+        HIP_TRY(hipGetLastError());
+        A.g_list = w.overflow3, A.g_count_idx = 6;
+    } else {
+        A.g_list = w.overflow2, A.g_count_idx = 5;
+    }
+    use_pool(w.fin);
+    A.g_next_idx = 2;
+    A.ovf_out = nullptr;
+    hipLaunchKernelGGL(kfallback, dim3(w.fin.workers), dim3(kBlock), dyn_fb, s, A);
     HIP_TRY(hipGetLastError());
     // the timed region: every kernel that answers boxes (tiers or plain, retry, fallback)
     return timing_end(g, s, err);
@@ -2041,7 +2552,7 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
 
 namespace {
 
-// The query path on a carved workspace.
+// The query path on a carved workspace (the caller's or the library's scratch).
 int query_in(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const SparseOut *sp, const Workspace &w,
              hipStream_t s, int variant, uint32_t *stats, std::string *err, float *out_err)
 {
@@ -2114,8 +2625,6 @@ int query_in(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const Spar
     A.ovf_out = w.overflow;
     A.ovf_out_idx = 1;
     A.stats = stats;
-    A.g_keys = w.g_keys, A.g_cnt = w.g_cnt, A.g_used = w.g_used, A.g_hi = w.g_hi, A.g_lo = w.g_lo;
-    A.g_seg_cnt = w.g_seg_cnt, A.g_seg_hi = w.g_seg_hi, A.g_seg_lo = w.g_seg_lo, A.g_seg_var = w.g_seg_var;
     if (variant == kQueryLut || variant == kQueryLutErr) {
         if (!g->dev.lut_ptr) {
             *err = "the mixture lookup table is not on the device (mg_lut_build)";
@@ -2167,7 +2676,6 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const Spa
     return query_in(g, boxes, n, out, sp, w, static_cast<hipStream_t>(stream), variant, stats, err, out_err);
 }
 
-
 int dev_footprint(Graph *g, const uint32_t *boxes, uint32_t n, uint32_t *level_counts, uint32_t *cubes, uint32_t cap,
                   uint32_t *count, void *stream, std::string *err)
 {
@@ -2214,11 +2722,14 @@ int dev_propagate_tf(Graph *g, const uint8_t *tf, uint32_t T, float *out, void *
                        g->n_nodes, o);
     HIP_TRY(hipGetLastError());
     const uint32_t tb = g->dev.cfg.tf_block;
+    const uint32_t P = std::min<uint32_t>(g->dev.cfg.tf_planes ? g->dev.cfg.tf_planes : kTfPlanes, T);
+    const uint32_t P2 = P >= 8 ? 8u : P >= 4 ? 4u : P >= 2 ? 2u : 1u;  // planes per thread
+    auto step = P2 == 8 ? tf_step_kernel<8> : P2 == 4 ? tf_step_kernel<4> : P2 == 2 ? tf_step_kernel<2> : tf_step_kernel<1>;
     for (uint32_t st = 1; st <= g->depth; ++st) {
         const uint32_t lo = g->step_ptr[st], hi = g->step_ptr[st + 1];
         if (hi <= lo) continue;
-        hipLaunchKernelGGL(tf_step_kernel, dim3((hi - lo + tb - 1) / tb, T), dim3(tb), 0, s, g->dev.sched, lo, hi,
-                           g->n_nodes, o);
+        hipLaunchKernelGGL(step, dim3((hi - lo + tb - 1) / tb, (T + P2 - 1) / P2), dim3(tb), 0, s, g->dev.sched, lo,
+                           hi, g->n_nodes, T, o);
         HIP_TRY(hipGetLastError());
     }
     return timing_end(g, s, err);
@@ -2240,6 +2751,11 @@ int dev_set_launch(Graph *g, const mg_launch_cfg *cfg, std::string *err)
             *err = "mg_set_launch: table sizes must be 0 or a power of two in [64, 8192]";
             return MG_EINVAL;
         }
+    if (!(cfg->tf_planes == 0 || cfg->tf_planes == 1 || cfg->tf_planes == 2 || cfg->tf_planes == 4 ||
+          cfg->tf_planes == 8)) {
+        *err = "mg_set_launch: tf_planes must be 0, 1, 2, 4 or 8";
+        return MG_EINVAL;
+    }
     const uint32_t tb = cfg->tf_block;
     if (!valid_unroll(cfg->unroll_big) || !valid_unroll(cfg->unroll_small) || !valid_unroll(cfg->unroll_naive) ||
         !(tb == 64 || tb == 128 || tb == 256 || tb == 512 || tb == 1024)) {
@@ -2360,6 +2876,12 @@ int dev_timing_read(Graph *g, double *ms, uint32_t *launches, std::string *err)
     *launches = d.ev_used;
     d.ev_used = 0;
     return MG_OK;
+}
+
+int dev_check_load_addresses(const uint32_t dims[3], uint32_t flags, const uint32_t *boxes, uint32_t n,
+                              uint32_t unroll, uint64_t counts[4], std::string *err)
+{
+    return check_load_addresses(dims, (flags & 1u) != 0, (flags & 2u) != 0, boxes, n, unroll, counts, err);
 }
 
 }  // namespace mg

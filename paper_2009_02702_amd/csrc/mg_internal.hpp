@@ -52,7 +52,7 @@ struct DeviceState {
         int blocks;     // blocks per CU
     };
     std::vector<Occ> occupancy;  // per kernel variant and LDS size
-    mg_launch_cfg cfg = {16, 8, 16, 256, 0, 0, 0, 0, 0};
+    mg_launch_cfg cfg = {16, 8, 16, 256, 0, 0, 0, 0, 0, 0};
     bool timing = false;
     std::vector<void *> ev_start, ev_stop;  // hipEvent_t pairs recorded around the dominant kernel
     uint32_t ev_used = 0;
@@ -67,7 +67,9 @@ struct Graph {
     uint32_t max_mixture = 1;
     std::vector<uint32_t> lev_dims;   // 3 per level
     std::vector<uint64_t> lev_off;    // n_levels + 1 offsets into maps
-    std::vector<uint32_t> maps;       // node ID per mip voxel, all levels, x fastest
+    std::vector<uint32_t> maps;       // node ID per mip voxel, all levels, x fastest (empty when
+                                      // maps_on_device: decoded on the GPU from a graph stream)
+    bool maps_on_device = false;
     std::vector<uint32_t> seg_ids;    // source -> original volume ID
     std::vector<uint32_t> child_a, child_b, rank, step;  // [n_nodes]
     std::vector<float> alpha;                            // [n_nodes]
@@ -122,7 +124,9 @@ int build_lut(Graph *g, uint32_t threads, std::string *err);
 int quantize_graph(const Graph &src, uint32_t bits, uint32_t threads, Graph *dst, std::string *err);
 // Ranks, step schedule and rank-sorted IDs of a DAG in creation order; the maps
 // already in g (levels >= 1) are renumbered with the nodes.
-int finalize_dag(const RawDag &d, bool defer, uint32_t max_depth, unsigned nt, Graph *g, std::string *err);
+// perm (if given) receives each creation-order ID's new ID.
+int finalize_dag(const RawDag &d, bool defer, uint32_t max_depth, unsigned nt, Graph *g, std::string *err,
+                 std::vector<uint32_t> *perm = nullptr);
 // Greedy factorization (Sec. "Compression") of mixtures given as sorted
 // (source, count) vectors, in scanline order; appends the sources and the
 // interpolation nodes to d and returns each mixture's node in root. Consumes mix.
@@ -132,7 +136,19 @@ int greedy_factorize(uint32_t nseg, std::vector<std::vector<std::pair<uint32_t, 
 unsigned resolve_threads(uint32_t t);
 // Bit-packed graph stream (Table "bitstream"); quantized graphs only.
 int pack_graph(const Graph &g, std::vector<uint8_t> *out, std::string *err);
-int unpack_graph(const uint8_t *buf, uint64_t size, uint32_t threads, Graph *g, std::string *err);
+// Where a stream's voxel data (A) lies, for decoding it on the GPU: bit offset
+// of (A) in the stream, per level the offset of its first voxel from there,
+// r(l) and i_min(l), and the renumbering of the stream's node IDs.
+struct StreamMaps {
+    uint64_t a_bit = 0;
+    std::vector<uint64_t> bit_off;
+    std::vector<uint32_t> r, lo;
+    std::vector<uint32_t> perm;   // stream (creation-order) ID -> graph ID
+};
+// dev == nullptr: the maps are decoded on the host; else (A) is skipped, the
+// graph gets maps_on_device, and *dev describes (A) for dev_upload_stream.
+int unpack_graph(const uint8_t *buf, uint64_t size, uint32_t threads, Graph *g, std::string *err,
+                 StreamMaps *dev = nullptr);
 // Structural validation of a graph's host arrays (used by mg_load).
 int validate_graph(const Graph &g, std::string *err);
 // Level dimensions: halve with rounding up until 1^3.
@@ -140,6 +156,12 @@ void level_dims(const uint32_t dims[3], std::vector<uint32_t> *out);
 
 // Device side (kernels.hip). All return MG_OK or an MG_E* code with *err set.
 int dev_upload(Graph *g, int device, std::string *err);
+// A graph whose maps are still in its stream: device buffer allocated as by
+// dev_upload, the voxel data (A) decoded on the GPU into the node maps.
+int dev_upload_stream(Graph *g, const uint8_t *buf, uint64_t size, const StreamMaps &sm, int device,
+                      std::string *err);
+// Host copy of one level of the device maps.
+int dev_export_map(const Graph &g, uint32_t level, uint32_t *out, std::string *err);
 uint64_t dev_device_bytes(const Graph &g);
 int dev_bind_device(Graph *g, int device, void *base, uint64_t bytes, void *stream, std::string *err);
 int dev_nnz_bound(Graph *g, const uint32_t *boxes, uint32_t n, uint32_t *bound, void *stream, std::string *err);
@@ -157,6 +179,9 @@ struct SparseOut {
 int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const SparseOut *sp, void *work,
               uint64_t bytes, void *stream, int variant, uint32_t *stats, std::string *err,
               float *out_err = nullptr);
+// Replays on the host every load the query kernels issue for these boxes.
+int dev_check_load_addresses(const uint32_t dims[3], uint32_t flags, const uint32_t *boxes, uint32_t n,
+                              uint32_t unroll, uint64_t counts[4], std::string *err);
 int dev_footprint(Graph *g, const uint32_t *boxes, uint32_t n, uint32_t *level_counts, uint32_t *cubes,
                   uint32_t cap, uint32_t *count, void *stream, std::string *err);
 int dev_propagate_tf(Graph *g, const uint8_t *tf, uint32_t T, float *out, void *stream, std::string *err);

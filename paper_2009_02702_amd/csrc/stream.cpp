@@ -74,6 +74,7 @@ class BitReader {
         return true;
     }
     uint64_t pos() const { return pos_; }
+    void skip(uint64_t bits) { pos_ += bits; }
 
   private:
     const uint8_t *p_;
@@ -146,7 +147,7 @@ int pack_graph(const Graph &g, std::vector<uint8_t> *out, std::string *err)
     return MG_OK;
 }
 
-int unpack_graph(const uint8_t *buf, uint64_t size, uint32_t threads, Graph *g, std::string *err)
+int unpack_graph(const uint8_t *buf, uint64_t size, uint32_t threads, Graph *g, std::string *err, StreamMaps *dev)
 {
     BitReader rd(buf, size);
     uint64_t v = 0;
@@ -202,19 +203,34 @@ int unpack_graph(const uint8_t *buf, uint64_t size, uint32_t threads, Graph *g, 
     for (uint32_t l = 0; l < g->n_levels; ++l) need += uint64_t(r[l]) * (g->lev_off[l + 1] - g->lev_off[l]);
     need += n_int * (2 * bpn + b) + (uint64_t(1) << b) * 2 * kCodeBits + 32ull * S;
     if (rd.pos() + need > size * 8) return fail("truncated bulk data");
-    try {
-        g->maps.assign(g->lev_off[g->n_levels], 0);
-    } catch (...) {
-        *err = "host allocation of the node maps failed";
-        return MG_ENOMEM;
-    }
-    for (uint32_t l = 0; l < g->n_levels; ++l) {
-        const uint64_t limit = l == 0 ? S : N;  // level-0 voxels are sources
-        for (uint64_t i = g->lev_off[l]; i < g->lev_off[l + 1]; ++i) {
-            MG_GET(r[l], "truncated voxel data");
-            const uint64_t id = uint64_t(lo[l]) + v;
-            if (id >= limit) return fail("voxel node ID out of range");
-            g->maps[i] = uint32_t(id);
+    if (dev) {  // (A) stays in the stream, to be decoded on the GPU
+        dev->a_bit = rd.pos();
+        dev->r = r;
+        dev->lo = lo;
+        dev->bit_off.assign(g->n_levels, 0);
+        uint64_t off = 0;
+        for (uint32_t l = 0; l < g->n_levels; ++l) {
+            dev->bit_off[l] = off;
+            off += uint64_t(r[l]) * (g->lev_off[l + 1] - g->lev_off[l]);
+        }
+        rd.skip(off);
+        g->maps.clear();
+        g->maps_on_device = true;
+    } else {
+        try {
+            g->maps.assign(g->lev_off[g->n_levels], 0);
+        } catch (...) {
+            *err = "host allocation of the node maps failed";
+            return MG_ENOMEM;
+        }
+        for (uint32_t l = 0; l < g->n_levels; ++l) {
+            const uint64_t limit = l == 0 ? S : N;  // level-0 voxels are sources
+            for (uint64_t i = g->lev_off[l]; i < g->lev_off[l + 1]; ++i) {
+                MG_GET(r[l], "truncated voxel data");
+                const uint64_t id = uint64_t(lo[l]) + v;
+                if (id >= limit) return fail("voxel node ID out of range");
+                g->maps[i] = uint32_t(id);
+            }
         }
     }
     // (B) nodes, then (C) the codebook they index
@@ -261,7 +277,7 @@ int unpack_graph(const uint8_t *buf, uint64_t size, uint32_t threads, Graph *g, 
         d.alpha.push_back(c), d.sigma.push_back(sg[code[j]]), d.code.push_back(code[j]);
     }
     g->nseg = S;
-    if (int rc = finalize_dag(d, true, 0, resolve_threads(threads), g, err)) return rc;
+    if (int rc = finalize_dag(d, true, 0, resolve_threads(threads), g, err, dev ? &dev->perm : nullptr)) return rc;
     g->quant_bits = b;
     g->codebook = std::move(cw);
     g->code_sigma = std::move(sg);

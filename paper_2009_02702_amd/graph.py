@@ -93,6 +93,17 @@ class Graph:
         check(_lib.load().mg_unpack(data, len(data), threads, ctypes.byref(h)))
         return cls(h)
 
+    @classmethod
+    def unpack_device(cls, stream: bytes, device: int = 0, threads: int = 0) -> "Graph":
+        """mg_unpack_device: a graph on `device` from a bit-packed stream, its voxel IDs decoded on
+        the GPU."""
+        h = ctypes.c_void_p()
+        data = bytes(stream)
+        check(_lib.load().mg_unpack_device(data, len(data), threads, int(device), ctypes.byref(h)))
+        g = cls(h)
+        g._device = int(device)
+        return g
+
     def close(self) -> None:
         if self._h:
             self._ws = None
@@ -373,7 +384,7 @@ class Graph:
         return {"unroll_big": c.unroll_big, "unroll_small": c.unroll_small, "unroll_naive": c.unroll_naive,
                 "tf_block": c.tf_block, "table_big": c.table_big, "table_small": c.table_small,
                 "table_retry": c.table_retry, "block_small": c.block_small, "block_big": c.block_big,
-                "chunk_small": c.chunk_small}
+                "chunk_small": c.chunk_small, "tf_planes": c.tf_planes}
 
     def set_launch_config(self, **kw) -> None:
         cur = self.launch_config()

@@ -273,6 +273,25 @@ class Server:
         device = torch.device("cuda:%d" % g._device)
         self.slots = [_Slot(g, max_batch, max_tf, device, use_graphs, classes) for _ in range(slots)]
         self.device_bytes = slots * slot_bytes(max_batch, max_tf)
+        self.warm()
+
+    def warm(self, rounds: int = 3) -> None:
+        """Every slot busy at once with a full batch of empty boxes, every TF slot used and
+        every copy, `rounds` times: the runtime's per-launch resources are sized for the heaviest
+        load before the first request (a host stall of several ms in a copy or graph launch
+        otherwise shows up once a run, as the load first grows)."""
+        torch = _torch()
+        empty = np.zeros((self.max_batch, 6), dtype=np.uint32)
+        S = self.g.info()["nseg"]
+        tfs = np.zeros((self.max_tf, S, 4), dtype=np.uint8) if self.max_tf else None
+        pal = np.zeros(self.max_batch, dtype=np.int32) if self.max_tf else None
+        for _ in range(rounds):
+            for sl in self.slots:
+                sl.launch(self.g, empty, tfs, pal)
+            for sl in self.slots:
+                sl.event.synchronize()
+                sl.busy = False
+        torch.cuda.synchronize()
 
     def serve(self, boxes: np.ndarray, arrivals: np.ndarray, tf_index: Optional[np.ndarray] = None,
               tfs: Optional[np.ndarray] = None, results: Optional[np.ndarray] = None,

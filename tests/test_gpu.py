@@ -204,16 +204,25 @@ def test_tf_matches_oracle_every_mip_voxel():
     g = _graph("tf", vol)
     inf = g.info()
     S = inf["nseg"]
-    tfs = synth.make_tfs(synth.workload(3), S, 3)
-    col = g.propagate_tf(torch.from_numpy(tfs).cuda()).cpu().numpy().astype(np.float64)
+    tfs = synth.make_tfs(synth.workload(3), S, 5)
     ids, vol_c = scan.compact(vol)
     atol = 4 * max(inf["depth"], 1) * 2.0 ** -24
-    for t in range(3):
-        for l in range(inf["n_levels"]):
-            want = otf.level_colours(vol_c, S, tfs[t], l)
-            node = g.export_map(l)
-            got = col[t][node]
-            assert np.abs(got - want).max() <= atol, (t, l, np.abs(got - want).max())
+    want = [[otf.level_colours(vol_c, S, tfs[t], l) for l in range(inf["n_levels"])] for t in range(5)]
+    first = None
+    # transfer functions per thread: a launch knob (5 planes: the last thread row is ragged)
+    for planes in (0, 1, 2, 4, 8):
+        g.set_launch_config(tf_planes=planes)
+        col = g.propagate_tf(torch.from_numpy(tfs).cuda()).cpu().numpy()
+        for t in range(5):
+            for l in range(inf["n_levels"]):
+                got = col[t][g.export_map(l)].astype(np.float64)
+                assert np.abs(got - want[t][l]).max() <= atol, (planes, t, l, np.abs(got - want[t][l]).max())
+        if first is None:
+            first = col
+        assert np.array_equal(col, first), planes   # same arithmetic per node and plane
+    g.set_launch_config(tf_planes=0)
+    with pytest.raises(MGError):
+        g.set_launch_config(tf_planes=3)
 
 
 def test_tf_constant_is_exact_and_one_hot_gives_mixture():
@@ -330,6 +339,45 @@ def test_overflow_retry_and_global_fallback_paths():
         g.set_launch_config(table_big=0, table_small=0, table_retry=64)
         _compare(g.query(db, variant=v).cpu().numpy(), ref, None, "plain with tiny retry table")
     g.set_launch_config(table_big=0, table_small=0, table_retry=0)
+
+
+def test_mid_size_global_tables():
+    """A graph larger than one mid-size global table (65,536 slots) with tiny LDS tables: boxes
+    overflow every LDS table and are answered by the many-worker mid-size global tables (with
+    per-source arrays), the largest ones by the whole-graph tables; dense rows and sparse entries
+    match the oracle."""
+    w = synth.workload(4, dims=(150, 170, 160), segments=5000, n_boxes=700)
+    vol = synth.make_volume(w)
+    g = Graph.build(vol).upload(0)
+    inf = g.info()
+    assert inf["n_nodes"] * 4 // 3 + 2 > 65536, inf["n_nodes"]
+    S = inf["nseg"]
+    boxes = synth.make_boxes(w)
+    boxes[:4] = [[0, 0, 0, 150, 170, 160], [1, 2, 3, 140, 160, 150], [149, 169, 159, 1, 1, 1], [9, 9, 9, 0, 3, 3]]
+    ids, vol_c = scan.compact(vol)
+    _, ref = scan.box_counts(vol_c, S, boxes)
+    db = _dev(boxes)
+    g.set_launch_config(table_big=64, table_small=64, table_retry=64)
+    out, stats = g.query_stats(db)
+    st = stats.cpu().numpy().view(np.uint32)
+    assert int((st[:, 1] >> 31).sum()) > 100
+    _compare(out.cpu().numpy(), ref, None, "mid-size global tables, dense rows")
+    nnz = int((ref > 0).sum())
+    want = (ref > 0).sum(axis=1)
+    for tables in ((0, 0, 0), (64, 64, 64)):
+        g.set_launch_config(table_big=tables[0], table_small=tables[1], table_retry=tables[2])
+        index, seg, val, total = g.query_sparse(db, capacity=nnz)
+        idx = index.cpu().numpy().astype(np.int64)
+        bad = np.nonzero(idx[:, 1] != want)[0]
+        assert len(bad) == 0, "tables %s: %d boxes with wrong entry counts, e.g. %s" % (
+            tables, len(bad), [(int(q), int(idx[q, 1]), int(want[q]), int(st[q, 1] >> 30), int(st[q, 0]))
+                               for q in bad[:6]])
+        assert int(total.item()) == nnz
+        dense = _sparse_to_dense(idx, seg.cpu().numpy(), val.cpu().numpy(), len(boxes), S)
+        _compare(dense, ref, None, "sparse entries, tables %s" % (tables,))
+    g.set_launch_config(table_big=0, table_small=0, table_retry=0)
+    _compare(g.query(db).cpu().numpy(), ref, None, "default tables")
+    g.close()
 
 
 # ------------------------------------------------------------------ many segments: sources in the table

@@ -154,3 +154,44 @@ def test_graph_from_the_bit_packed_stream_answers_like_its_source():
     ob, eb = r.query_err(db)
     _compare(ob.cpu().numpy(), f, l0, "unpacked err/fractions")
     _compare_err(eb.cpu().numpy(), u, "unpacked err")
+
+
+def test_stream_decoded_on_the_gpu():
+    """mg_unpack_device: the stream's voxel data decoded by the GPU gives exactly the maps the host
+    reader gives (every level, bit for bit), and the graph answers like the host-read one; a node ID
+    out of range in the voxel data is MG_EFORMAT; host-only operations are refused."""
+    g, q, boxes, f, u, l0, S = _setup(2, (70, 66, 52), 150, 300, 9)
+    stream = q.pack()
+    h = Graph.unpack(stream).upload(0)
+    d = Graph.unpack_device(stream, 0)
+    L = h.info()["n_levels"]
+    assert d.info()["n_nodes"] == h.info()["n_nodes"] and d.info()["device"] == 0
+    for lev in range(L):
+        assert np.array_equal(d.export_map(lev), h.export_map(lev)), lev
+    db = _dev(boxes)
+    a = h.query(db).cpu().numpy().astype(np.float64)
+    b = d.query(db).cpu().numpy().astype(np.float64)
+    assert np.array_equal(a == 0, b == 0) and np.allclose(a, b, rtol=2e-6, atol=0)
+    _compare(b, f, l0, "decoded on the GPU")
+    for call in (d.pack, lambda: d.upload(0), lambda: d.save("/tmp/mg_never_written.bin")):
+        with pytest.raises(MGError) as e:
+            call()
+        assert e.value.code == -4
+    # a level-0 voxel ID past the sources: all ones in the first voxel's field (S is not a
+    # power of two, so i_min + 2^r - 1 >= S)
+    n = h.info()["n_nodes"]
+    assert S & (S - 1)
+    bpn = max(1, int(np.ceil(np.log2(n))))
+    a_bit = 32 + 1 + 6 + 32 + 3 * 32 + 4 + bpn + L * 2 * bpn
+    r0 = int(np.ceil(np.log2(S)))
+    bad = bytearray(stream)
+    for k in range(a_bit, a_bit + r0):
+        bad[k >> 3] |= 1 << (k & 7)
+    with pytest.raises(MGError) as e:
+        Graph.unpack_device(bytes(bad), 0)
+    assert e.value.code == -7
+    with pytest.raises(MGError) as e:
+        Graph.unpack(bytes(bad))
+    assert e.value.code == -7
+    d.close()
+    h.close()
