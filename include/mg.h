@@ -214,6 +214,27 @@ int mg_query_boxes_plain(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float
 int mg_query_boxes_stats(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *d_out,
                          uint32_t *d_stats, void *d_work, uint64_t work_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * mg_query_boxes with the library's own workspace instead of d_work, so the
+ * call allocates nothing. The workspace is one static device array of
+ * MG_NOALLOC_SCRATCH_BYTES (64 MiB) per GPU, which the library's code object
+ * holds from its first use on that GPU (mg_upload looks up its address) until
+ * the process ends. Same arguments, kernels and results as mg_query_boxes
+ * (boxes, output layout, clipping); the global fallback tables get as many
+ * workers as fit beside the per-box arrays.
+ * Boxes that overflow every LDS table go straight to the tables that hold
+ * the whole graph (no mid-size tables).
+ * Limits (MG_ELIMIT, the message states the limit for this graph): 20 bytes
+ * of scratch per box, and one worker's fallback table (20 bytes per slot,
+ * slots >= 4/3 x n_nodes rounded up to a power of two) must fit, i.e. graphs
+ * of up to about 1.5 M nodes.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents: calls that overlap in time on one GPU (other streams, other
+ * threads, other graphs) race; order them on one stream or synchronise. */
+#define MG_NOALLOC_SCRATCH_BYTES (64u << 20)
+int mg_query_boxes_noalloc(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *d_out, void *stream);
+
 /* Box histograms with sparse output, for many segments: the same path, with
  * each box's non-zero segments appended to one entry buffer.
  *   d_index  device uint32 [n][2]: first entry of the box and its number of

@@ -53,7 +53,7 @@ SYMBOLS = [
     "mg_build", "mg_info", "mg_quantize", "mg_export_codebook", "mg_export_dag", "mg_export_map", "mg_segment_ids", "mg_upload",
     "mg_device_bytes", "mg_bind_device", "mg_query_nnz_bound",
     "mg_workspace_bytes", "mg_workspace_init", "mg_query_boxes", "mg_query_boxes_plain", "mg_query_boxes_stats",
-    "mg_query_boxes_sparse",
+    "mg_query_boxes_sparse", "mg_query_boxes_noalloc",
     "mg_naive_boxes",
     "mg_check_load_addresses", "mg_footprint", "mg_propagate_tf", "mg_palette_fetch", "mg_box_colour", "mg_lut_build", "mg_export_lut", "mg_query_boxes_lut", "mg_query_boxes_err",
     "mg_get_launch", "mg_set_launch", "mg_autotune",
@@ -96,6 +96,7 @@ def load() -> ctypes.CDLL:
         "mg_query_boxes_plain": ([G, vp, u32, vp, vp, u64, vp], i32),
         "mg_query_boxes_stats": ([G, vp, u32, vp, vp, vp, u64, vp], i32),
         "mg_query_boxes_sparse": ([G, vp, u32, vp, vp, vp, u32, vp, vp, u64, vp], i32),
+        "mg_query_boxes_noalloc": ([G, vp, u32, vp, vp], i32),
         "mg_naive_boxes": ([G, vp, u32, vp, vp, u64, vp], i32),
         "mg_check_load_addresses": ([u32, u32, u32, u32, vp, u32, u32, vp], i32),
         "mg_footprint": ([G, vp, u32, vp, vp, u32, vp, vp], i32),

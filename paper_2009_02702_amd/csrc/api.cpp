@@ -293,6 +293,15 @@ int mg_query_boxes_sparse(mg_graph *h, const uint32_t *d_boxes, uint32_t n, uint
                 err);
 }
 
+int mg_query_boxes_noalloc(mg_graph *h, const uint32_t *d_boxes, uint32_t n, float *d_out, void *stream)
+{
+    if (!h) return fail(MG_EINVAL, "mg_query_boxes_noalloc: null graph");
+    if (n == 0) return MG_OK;
+    if (!d_boxes || !d_out) return fail(MG_EINVAL, "mg_query_boxes_noalloc: null buffer");
+    std::string err;
+    return done(mg::dev_query_noalloc(&h->g, d_boxes, n, d_out, stream, &err), err);
+}
+
 int mg_check_load_addresses(uint32_t nx, uint32_t ny, uint32_t nz, uint32_t flags, const uint32_t *boxes,
                             uint32_t n, uint32_t unroll, uint64_t *counts)
 {

@@ -1858,6 +1858,45 @@ int occupancy(DeviceState &d, const void *k, int block, uint32_t dyn, int *out, 
     return MG_OK;
 }
 
+// ---------------------------------------------------------------- no-allocation scratch
+
+// The workspace of mg_query_boxes_noalloc: one array per device, held from the
+// module's load until the process ends. Host code never passes `scratch`
+// itself to a kernel (in host code the name is a stand-in, not a device
+// address); it uses the address hipGetSymbolAddress returns for each device.
+constexpr uint64_t kScratchBytes = uint64_t(MG_NOALLOC_SCRATCH_BYTES);
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+struct ScratchSlot {
+    char *ptr = nullptr;                // device address of `scratch` on this device
+    uint64_t layout[3] = {0, 0, 0};     // (sources, fallback slots, workers) last cleared; 0: never
+};
+std::mutex g_scratch_mu;
+std::vector<ScratchSlot> g_scratch;      // per device ordinal
+
+// The device address of the scratch array on the current device (looked up once per device).
+int scratch_slot(int device, ScratchSlot **out, std::string *err)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0) {
+        *err = "no device";
+        return MG_ESTATE;
+    }
+    if (g_scratch.size() <= size_t(device)) g_scratch.resize(size_t(device) + 1);
+    ScratchSlot &sl = g_scratch[size_t(device)];
+    if (!sl.ptr) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            *err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return MG_EDEVICE;
+        }
+        sl.ptr = static_cast<char *>(p);
+    }
+    *out = &sl;
+    return MG_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- host-side address check
@@ -2230,6 +2269,9 @@ int dev_bind(Graph *g, int device, void *base, uint64_t bytes, hipStream_t s, bo
     }
     // the host staging vectors above die with this call
     HIP_TRY(hipStreamSynchronize(s));
+    // set-up of the no-allocation path on this device (the scratch array's address)
+    ScratchSlot *sl = nullptr;
+    if (int rc = scratch_slot(device, &sl, err)) return rc;
     if (!g->lut_ptr.empty()) return dev_upload_lut(g, err);
     return MG_OK;
 }
@@ -2674,6 +2716,46 @@ int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const Spa
     }
     const Workspace w = carve(*g, static_cast<char *>(work), n);
     return query_in(g, boxes, n, out, sp, w, static_cast<hipStream_t>(stream), variant, stats, err, out_err);
+}
+
+int dev_query_noalloc(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *stream, std::string *err)
+{
+    DeviceGuard guard;
+    int rc = check_device(g, err);
+    if (rc) return rc;
+    ScratchSlot *sl = nullptr;
+    if ((rc = scratch_slot(g->dev.device, &sl, err))) return rc;
+    // as many workers of the final global tables as fit beside the per-box arrays (at least
+    // one), none with mid-size tables (a speed-up only: every box fits the final tables)
+    uint32_t workers = fallback_workers(*g);
+    while (workers > 1 && carve(*g, nullptr, n, workers, 0).bytes > kScratchBytes) --workers;
+    const Workspace probe = carve(*g, nullptr, n, workers, 0);
+    if (probe.bytes > kScratchBytes) {
+        const uint64_t fixed = carve(*g, nullptr, 1, 1, 0).bytes;
+        *err = fixed > kScratchBytes
+                   ? "mg_query_boxes_noalloc: the graph's global fallback table (" + std::to_string(fixed) +
+                         " bytes for " + std::to_string(g->n_nodes) + " nodes) exceeds the " +
+                         std::to_string(kScratchBytes) + "-byte scratch"
+                   : "mg_query_boxes_noalloc: " + std::to_string(n) + " boxes exceed the " +
+                         std::to_string(kScratchBytes) + "-byte scratch (at most " +
+                         std::to_string((kScratchBytes - fixed) / 20) + " boxes on this graph)";
+        return MG_ELIMIT;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Workspace w = carve(*g, sl->ptr, n, workers, 0);
+    // the scratch keeps the last call's contents; every query leaves the fallback
+    // tables clean, so they are cleared only when their layout changes
+    const uint64_t layout[3] = {g->nseg, fallback_slots(*g), workers};
+    if (std::memcmp(layout, sl->layout, sizeof(layout)) != 0) {
+        clear_fallback_tables(*g, w, s);
+        HIP_TRY(hipGetLastError());
+        std::memcpy(sl->layout, layout, sizeof(layout));
+    }
+    const bool timing = g->dev.timing;
+    g->dev.timing = false;  // no events are created on this path
+    rc = query_in(g, boxes, n, out, nullptr, w, s, kQueryBatched, nullptr, err, nullptr);
+    g->dev.timing = timing;
+    return rc;
 }
 
 int dev_footprint(Graph *g, const uint32_t *boxes, uint32_t n, uint32_t *level_counts, uint32_t *cubes, uint32_t cap,

@@ -179,6 +179,8 @@ struct SparseOut {
 int dev_query(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const SparseOut *sp, void *work,
               uint64_t bytes, void *stream, int variant, uint32_t *stats, std::string *err,
               float *out_err = nullptr);
+// mg_query_boxes on the library's static device scratch (allocates nothing).
+int dev_query_noalloc(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *stream, std::string *err);
 // Replays on the host every load the query kernels issue for these boxes.
 int dev_check_load_addresses(const uint32_t dims[3], uint32_t flags, const uint32_t *boxes, uint32_t n,
                               uint32_t unroll, uint64_t counts[4], std::string *err);

@@ -221,6 +221,21 @@ class Graph:
         check(fn(self._h, _dptr(boxes), n, _dptr(out), _dptr(ws), ws.numel(), _stream_ptr(stream)))
         return out
 
+    def query_noalloc(self, boxes, out=None, stream=None):
+        """mg_query_boxes_noalloc: the batched query on the library's static device scratch (no
+        workspace, no allocation inside the call). out: fp32 [n, S], allocated here if None."""
+        torch = _torch()
+        if boxes.dim() != 2 or boxes.shape[1] != 6 or boxes.element_size() != 4:
+            raise ValueError("boxes must be a 32-bit [n, 6] tensor")
+        n = boxes.shape[0]
+        S = self.info()["nseg"]
+        if out is None:
+            out = torch.empty((n, S), dtype=torch.float32, device=boxes.device)
+        if tuple(out.shape) != (n, S) or out.dtype != torch.float32 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous fp32 [n, S] tensor")
+        check(self._lib.mg_query_boxes_noalloc(self._h, _dptr(boxes), n, _dptr(out), _stream_ptr(stream)))
+        return out
+
     def query_err(self, boxes, out=None, err=None, workspace=None, stream=None):
         """Quantized graphs: (fractions fp32 [n, S], uncertainties fp32 [n, S]) from the lookup table."""
         torch = _torch()
