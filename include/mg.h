@@ -93,6 +93,8 @@ typedef struct {
     int32_t device;         /* device ordinal after mg_upload, else -1                */
     uint32_t max_mixture;   /* largest number of segments in one node's mixture      */
     uint32_t quant_bits;    /* 0: exact weights; else the quantizer's bit rate       */
+    uint32_t runs_mask;     /* after mg_upload: bit 2 l + o set where level l keeps
+                               row runs along x (o = 0) or y (o = 1)                  */
 } mg_info_t;
 
 /* Build a graph from a host uint32 ID volume (CPU; Sec. "Normalized Histogram
@@ -270,12 +272,16 @@ int mg_naive_boxes(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *d_ou
  * boxes (host uint32 [n][6]) on a volume of nx x ny x nz voxels, replays every
  * load the batched query kernels issue (all `unroll` loads of every block, 4, 8
  * or 16), with the kernels' own slab builder and tile-walk helpers. flags: bit
- * 0 = level 0 from the 16-bit copy, bit 1 = also the naive scan's loads. Checks
- * that each load lies inside its slab and inside the map buffer, that each
- * consumed load reads exactly the element of a footprint cube (or voxel) of the
- * box, and that every cube of the footprint is read once. counts host uint64
- * [4]: boxes, slabs, lane loads, cubes. MG_ELIMIT with the first violation in
- * the message. */
+ * 0 = level 0 from the 16-bit copy, bit 1 = also the naive scan's loads, bit 2
+ * = slabs with rows of at least 16 cubes summed from row runs (every level and
+ * orientation the run builder accepts). Checks that each load lies inside its
+ * slab and inside the map buffer, that each consumed load reads exactly the
+ * element of a footprint cube (or voxel) of the box, for run slabs that each
+ * row segment lies in the box on its row and indexes its row and skip entry in
+ * range (run loads are clamped to the row's runs by the kernel), and that every
+ * cube of the footprint is read once. counts host uint64 [4]: boxes, slabs,
+ * lane loads (run segments for run slabs), cubes. MG_ELIMIT with the first
+ * violation in the message. */
 int mg_check_load_addresses(uint32_t nx, uint32_t ny, uint32_t nz, uint32_t flags, const uint32_t *boxes,
                             uint32_t n, uint32_t unroll, uint64_t *counts);
 
@@ -374,6 +380,13 @@ typedef struct {
                                queue: 0 (one) or 1..64                                          */
     uint32_t tf_planes;     /* transfer functions per thread of the propagation kernel (their
                                gathers in flight together): 0 (default: 4), 1, 2, 4 or 8     */
+    uint32_t tf_schedule;   /* order of the propagation launches: 0 (default) rank by rank, the
+                               nodes in ID order; 1 the graph's step schedule (deferred when
+                               built with defer = 1). Same colours either way                  */
+    uint32_t run_min_row;   /* footprint slabs whose rows are at least this many cubes long are
+                               summed from the rows' runs of equal node IDs where the graph
+                               has them; shorter rows stream cube by cube. 0: default (16);
+                               0xFFFFFFFF: never (every slab streams)                          */
 } mg_launch_cfg;
 
 int mg_get_launch(const mg_graph *g, mg_launch_cfg *out);

@@ -36,7 +36,7 @@ class Info(ctypes.Structure):
     _fields_ = [("nseg", ctypes.c_uint32), ("n_nodes", ctypes.c_uint32), ("depth", ctypes.c_uint32),
                 ("n_levels", ctypes.c_uint32), ("dims", (ctypes.c_uint32 * 3) * MAX_LEVELS),
                 ("map_voxels", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64), ("device", ctypes.c_int32),
-                ("max_mixture", ctypes.c_uint32), ("quant_bits", ctypes.c_uint32)]
+                ("max_mixture", ctypes.c_uint32), ("quant_bits", ctypes.c_uint32), ("runs_mask", ctypes.c_uint32)]
 
 
 class LaunchCfg(ctypes.Structure):
@@ -44,7 +44,8 @@ class LaunchCfg(ctypes.Structure):
                 ("unroll_naive", ctypes.c_uint32), ("tf_block", ctypes.c_uint32), ("table_big", ctypes.c_uint32),
                 ("table_small", ctypes.c_uint32), ("table_retry", ctypes.c_uint32), ("block_small", ctypes.c_uint32),
                 ("block_big", ctypes.c_uint32), ("chunk_small", ctypes.c_uint32),
-                ("tf_planes", ctypes.c_uint32)]
+                ("tf_planes", ctypes.c_uint32), ("tf_schedule", ctypes.c_uint32),
+                ("run_min_row", ctypes.c_uint32)]
 
 
 _lib = None

@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libmg.so")
 OBJ = os.path.join(HERE, "_build")
 
-HOST_SOURCES = ["builder.cpp", "factorize.cpp", "stream.cpp", "api.cpp"]
+HOST_SOURCES = ["builder.cpp", "factorize.cpp", "stream.cpp", "runs.cpp", "api.cpp"]
 HIP_SOURCES = ["kernels.hip"]
 ARCH = "gfx950"
 

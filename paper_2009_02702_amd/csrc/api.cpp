@@ -159,6 +159,7 @@ int mg_info(const mg_graph *h, mg_info_t *out)
     out->device = g.dev.device;
     out->max_mixture = g.max_mixture;
     out->quant_bits = g.quant_bits;
+    out->runs_mask = g.dev.runs_mask;
     return MG_OK;
 }
 
@@ -312,7 +313,7 @@ int mg_check_load_addresses(uint32_t nx, uint32_t ny, uint32_t nz, uint32_t flag
         return fail(MG_EINVAL, "mg_check_load_addresses: unroll must be 4, 8 or 16");
     const uint32_t dims[3] = {nx, ny, nz};
     std::string err;
-    if (flags > 3) return fail(MG_EINVAL, "mg_check_load_addresses: unknown flags");
+    if (flags > 7) return fail(MG_EINVAL, "mg_check_load_addresses: unknown flags");
     return done(mg::dev_check_load_addresses(dims, flags, boxes, n, unroll, counts, &err), err);
 }
 

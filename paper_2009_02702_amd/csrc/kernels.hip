@@ -51,7 +51,13 @@ constexpr uint32_t kBigLog2 = 14;             // boxes of >= 2^14 cubes go to th
 constexpr uint32_t kHashGlobal = 1u << 16;    // fewest per-worker hash slots in the fallback tables
 constexpr uint32_t kSegLdsMax = 2048;         // sources kept in LDS
 constexpr uint32_t kFallbackWorkers = 128;    // workers of the final global-table launch (budget)
+constexpr uint32_t kRunSeg = 256;             // cells of a row one thread sums from the runs
+constexpr int kRunBatch = 4;                   // runs a thread loads at once
+constexpr uint32_t kRunMinRow = 16;            // rows shorter than this stream cube by cube (default)
 constexpr uint32_t kTfPlanes = 4;             // transfer functions per thread of a propagation step
+constexpr uint32_t kTfTailPairs = 4096;        // steps of at most this many node x TF pairs may share a launch
+constexpr uint32_t kTfTailSteps = 16;          // at most this many of them
+constexpr uint32_t kTfTailBlock = 1024;        // threads of that launch (one workgroup)
 constexpr uint32_t kMidWorkers = 256;         // workers of the mid-size global-table launch
 constexpr uint32_t kQueues = 8;                // work queues per tier
 constexpr uint32_t kQueueStride = 64;          // u32 between queue counters (256 bytes)
@@ -81,6 +87,20 @@ struct LevelTable {
     uint32_t use16;
     uint32_t pitch_x, pitch_y;
     uint64_t total16;
+    // row runs (kind-2 slabs): bit 2 l + o set where level l has runs along x (o = 0)
+    // or y (o = 1) and the launch reads them; slabs whose rows are at least run_min
+    // cubes long are summed from runs
+    uint32_t runs_mask;
+    uint32_t run_min;
+};
+
+// Row runs of one level and orientation as the kernels read them (the device copy
+// of the host's LevelRuns): runs[j] = exclusive end << 32 | node.
+struct RunLevel {
+    const uint32_t *row_ptr;   // [rows + 1]
+    const uint16_t *skip;      // [rows][chunks]
+    const uint64_t *runs;
+    uint32_t rows, chunks;
 };
 
 // A slab of cubes at one level, as the query kernels read it: e2 slices (slow
@@ -88,7 +108,9 @@ struct LevelTable {
 // contiguous axis of the chosen copy: x in maps, y in maps_t), read as `units`
 // 4-byte units per row: one 32-bit node ID per cube (kind 0), or, from the
 // 16-bit level-0 copy, aligned pairs of source IDs (kind 1; a row whose first
-// cube is at an odd position starts one element early, `odd`).
+// cube is at an odd position starts one element early, `odd`); or, kind 2, each
+// row segment summed from the row runs of its level and orientation (base, s1b,
+// s2b, units unused).
 struct Slab {
     uint64_t base;         // byte offset of the first unit in its buffer (maps or maps16)
     uint32_t e0, e1, e2;   // cubes along the fast, mid and slow axes
@@ -96,7 +118,7 @@ struct Slab {
     uint32_t units;        // 4-byte units per row
     uint32_t bx, by, bz;   // first cube, level coordinates
     uint8_t level;
-    uint8_t kind;          // 0: 32-bit node IDs, 1: pairs of 16-bit level-0 source IDs
+    uint8_t kind;          // 0: 32-bit node IDs, 1: pairs of 16-bit level-0 source IDs, 2: row runs
     uint8_t axes;          // fast | mid << 2 | slow << 4 (0 = x, 1 = y, 2 = z)
     uint8_t odd;           // kind 1: the row's first unit starts one element before the slab
 };
@@ -108,11 +130,11 @@ __host__ __device__ inline uint32_t slab_count(const Slab &sl) { return sl.e0 * 
 __host__ __device__ inline void slab_coords(const Slab &sl, uint32_t i0, uint32_t i1, uint32_t i2, uint32_t *x,
                                             uint32_t *y, uint32_t *z)
 {
-    uint32_t c[3] = {sl.bx, sl.by, sl.bz};
-    c[sl.axes & 3] += i0;
-    c[(sl.axes >> 2) & 3] += i1;
-    c[(sl.axes >> 4) & 3] += i2;
-    *x = c[0], *y = c[1], *z = c[2];
+    // selects, not an indexed local array (which the device code would keep in scratch)
+    const uint32_t f = sl.axes & 3, m = (sl.axes >> 2) & 3, w = (sl.axes >> 4) & 3;
+    *x = sl.bx + (f == 0 ? i0 : 0u) + (m == 0 ? i1 : 0u) + (w == 0 ? i2 : 0u);
+    *y = sl.by + (f == 1 ? i0 : 0u) + (m == 1 ? i1 : 0u) + (w == 1 ? i2 : 0u);
+    *z = sl.bz + (f == 2 ? i0 : 0u) + (m == 2 ? i1 : 0u) + (w == 2 ? i2 : 0u);
 }
 
 // Clipped box: half-open ranges; returns false for an empty box.
@@ -165,11 +187,16 @@ __host__ __device__ inline void put_slab(Slab *out, int *n, const LevelTable &lt
         else m = 2, em = ez, sm = sz, w = 1, ew = ey, sw = sy;
         first = (pairs ? 0 : lt.off[lev]) + x0 + uint64_t(px) * (y0 + uint64_t(Y) * z0);
     }
+    s.axes = uint8_t(f | (m << 2) | (w << 4));
+    s.e0 = ef, s.e1 = em, s.e2 = ew;
+    if (ef >= lt.run_min && ((lt.runs_mask >> (2 * lev + f)) & 1u)) {  // rows from the runs
+        s.kind = 2, s.odd = 0, s.base = 0, s.s1b = s.s2b = 0, s.units = ef;
+        out[(*n)++] = s;
+        return;
+    }
     const uint32_t odd = pairs ? ((f == 1 ? y0 : x0) & 1u) : 0u;
     const uint32_t esz = pairs ? 2u : 4u;
-    s.axes = uint8_t(f | (m << 2) | (w << 4));
     s.odd = uint8_t(odd);
-    s.e0 = ef, s.e1 = em, s.e2 = ew;
     s.base = esz * (first - odd);
     s.s1b = em > 1 ? uint32_t(esz * sm) : 0u;  // < 2^32 whenever the extent is above 1
     s.s2b = ew > 1 ? uint32_t(esz * sw) : 0u;
@@ -697,6 +724,78 @@ __device__ inline void count_pairs(uint32_t *cnt, uint32_t lo, uint32_t hi, uint
         atomicAdd(&cnt[hi], (e_lo ? 0u - (2 * lane + 1) : 0u) + (e_hi ? 2 * lane + 2 : 0u));
 }
 
+// Kind-2 slab: every row segment is summed from its row's runs. The block's
+// threads take (row, segment) items, a segment being at most kRunSeg cells of
+// one row; a thread finds the run holding the segment's first cell from the
+// skip entry of its 64-cell chunk (the runs before it end at or before that
+// cell and add nothing), then walks the runs kRunBatch at a time, each run
+// adding (cells of it inside the segment) x 8^level to its node. Run loads are
+// clamped to the row's last run, whose end is the row's end, so every walk
+// stops inside its row.
+// A load through a pointer that was itself read from memory (the run table): the
+// cast tells the compiler it is global memory, so it issues a global load rather
+// than a flat one.
+template <class T>
+__device__ inline T load_global(const T *p)
+{
+    return *(const __attribute__((address_space(1))) T *)(p);
+}
+
+// Segments per row of a kind-2 slab, as log2 of the power of two >= ceil(e0 / kRunSeg).
+__host__ __device__ inline uint32_t run_lseg(uint32_t e0)
+{
+    uint32_t lseg = 0;
+    while ((kRunSeg << lseg) < e0) ++lseg;
+    return lseg;
+}
+
+// Item `it` of a kind-2 slab: its row index r in the level's runs of orientation
+// f and its cells [p0, p1) along the row; false for a padding item past the row.
+__host__ __device__ inline bool run_item(const Slab &sp, const LevelTable &lt, uint32_t f, uint32_t lseg,
+                                         uint32_t it, uint32_t *r, uint32_t *p0, uint32_t *p1)
+{
+    const uint32_t c = it & ((1u << lseg) - 1), row = it >> lseg;
+    const uint32_t i2 = sp.e2 == 1 ? 0u : row / sp.e1, i1 = row - i2 * sp.e1;
+    uint32_t x, y, z;
+    slab_coords(sp, 0, i1, i2, &x, &y, &z);
+    const uint32_t fa = f == 0 ? x : y;
+    *p0 = fa + c * kRunSeg;
+    *p1 = min(*p0 + kRunSeg, fa + sp.e0);
+    *r = f == 0 ? y + lt.dims[sp.level][1] * z : z + lt.dims[sp.level][2] * x;
+    return *p0 < *p1;
+}
+
+template <int BLOCK, bool SPARSE>
+__device__ inline void scatter_runs(const Slab &sp, const RunLevel &rl, const LevelTable &lt, const QueryState &st,
+                                    const GraphView &gv)
+{
+    const uint32_t f = uni(sp.axes) & 3u, lw8 = 3 * uni(sp.level);
+    const uint32_t lseg = run_lseg(uni(sp.e0));
+    const uint32_t items = (uni(sp.e1) * uni(sp.e2)) << lseg;
+    for (uint32_t it = threadIdx.x; it < items; it += BLOCK) {
+        uint32_t r, p0, p1;
+        if (!run_item(sp, lt, f, lseg, it, &r, &p0, &p1)) continue;
+        const uint32_t last = load_global(rl.row_ptr + r + 1) - 1;
+        uint32_t j = load_global(rl.row_ptr + r) + load_global(rl.skip + uint64_t(r) * rl.chunks + p0 / kRunSkipCells);
+        uint32_t pos = p0;
+        while (pos < p1) {
+            uint64_t v[kRunBatch];
+#pragma unroll
+            for (int q = 0; q < kRunBatch; ++q) v[q] = load_global(rl.runs + min(j + q, last));
+#pragma unroll
+            for (int q = 0; q < kRunBatch; ++q) {
+                const uint32_t end = uint32_t(v[q] >> 32);
+                if (pos < p1 && end > pos) {
+                    const uint32_t hi = min(end, p1);
+                    scatter_count<SPARSE>(st, gv, uint32_t(v[q]), (hi - pos) << lw8);
+                    pos = hi;
+                }
+            }
+            j += kRunBatch;
+        }
+    }
+}
+
 // Scatter: every cube of every slab adds 8^level to its node. Neighbouring
 // lanes usually hold the same node (mixtures are spatially coherent), so a run
 // of equal nodes in a wave adds its total once. Runs on sources add to an
@@ -707,8 +806,8 @@ __device__ inline void count_pairs(uint32_t *cnt, uint32_t lo, uint32_t hi, uint
 // (kind 1) hold two sources per unit (count_pairs).
 template <int BLOCK, int UNROLL, bool SPARSE>
 __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const char *__restrict__ maps,
-                                     const char *__restrict__ maps16, const QueryState &st, const GraphView &gv,
-                                     const uint32_t *flags_lds)
+                                     const char *__restrict__ maps16, const RunLevel *runs, const LevelTable &lt,
+                                     const QueryState &st, const GraphView &gv, const uint32_t *flags_lds)
 {
     constexpr uint32_t kWaves = BLOCK / 64;
     const uint32_t nseg = gv.nseg;
@@ -717,6 +816,10 @@ __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const char 
     for (int si = 0; si < n_slabs; ++si) {
         const Slab &sp = slabs[si];
         if (uni(*flags_lds) & 1u) return;  // overflowed: the box goes to the retry launch
+        if (uni(sp.kind) == 2) {
+            scatter_runs<BLOCK, SPARSE>(sp, runs[2 * uni(sp.level) + (uni(sp.axes) & 3u)], lt, st, gv);
+            continue;
+        }
         const uint64_t base = (uint64_t(uni(uint32_t(sp.base >> 32))) << 32) | uni(uint32_t(sp.base));
         const TileWalk tw = tile_walk(uni(sp.units), uni(sp.e1), uni(sp.e2), uni(sp.s1b), uni(sp.s2b), UNROLL);
         if (!SPARSE && uni(sp.kind) == 1) {
@@ -802,6 +905,7 @@ struct QueryArgs {
     uint32_t *sp_total;           // entries produced (may exceed sp_cap: then the rest are dropped)
     const uint32_t *maps;         // maps then maps_t
     const uint16_t *maps16;       // level 0 as 16-bit IDs (both orientations), if lt.use16
+    const RunLevel *runs;         // [2 l + o] row runs of level l along x / y, where lt.runs_mask says
     GraphView gv;
     const uint32_t *rank_ptr;     // [depth + 2]
     uint32_t depth;
@@ -1013,7 +1117,8 @@ __device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const Quer
     if (nonempty) build_slabs(A.lt, lo, hi, st.slabs, &sh.n_slabs);
     __syncthreads();
     scatter_slabs<BLOCK, UNROLL, SPARSE>(st.slabs, sh.n_slabs, reinterpret_cast<const char *>(A.maps),
-                                         reinterpret_cast<const char *>(A.maps16), st, A.gv, &sh.flags);
+                                         reinterpret_cast<const char *>(A.maps16), A.runs, A.lt, st, A.gv,
+                                         &sh.flags);
     __syncthreads();
     if (ERR || A.lut_ptr)
         expand_lut<BLOCK, SPARSE, ERR>(A, st);
@@ -1460,37 +1565,71 @@ __global__ __launch_bounds__(kBlock) void nnz_bound_kernel(LevelTable lt, const 
 
 // ---------------------------------------------------------------- TF propagation
 
-__global__ void tf_sources_kernel(const uint8_t *tf, uint32_t T, uint32_t nseg, uint32_t n_nodes, float4 *out)
+// A source's colour under transfer function t: its RGBA8 entry scaled to [0, 1],
+// each channel one rounded product (never contracted into a later subtraction, so
+// a step that reads it here computes exactly what it computes from the stored value).
+__device__ inline float4 tf_source_colour(const uchar4 *tf, uint32_t nseg, uint32_t t, uint32_t src)
 {
-    const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= uint64_t(T) * nseg) return;
-    const uint32_t t = uint32_t(i / nseg), s = uint32_t(i % nseg);
-    const uchar4 c = reinterpret_cast<const uchar4 *>(tf)[i];
+#pragma clang fp contract(off)
+    const uchar4 c = tf[uint64_t(t) * nseg + src];
     const float k = 1.0f / 255.0f;
-    out[uint64_t(t) * n_nodes + s] = make_float4(float(c.x) * k, float(c.y) * k, float(c.z) * k, float(c.w) * k);
+    return make_float4(float(c.x) * k, float(c.y) * k, float(c.z) * k, float(c.w) * k);
 }
 
-// One step of the schedule: thread (x, y) computes node sched[lo_i + x] for the
-// transfer functions P y .. P y + P - 1 (grid.y = ceil(T / P)): it loads the node's
-// entry and both predecessors' colours in all P planes before it stores any, so
-// 2 P gathers per thread are in flight together. Lanes of a wave take consecutive
-// schedule entries (coalesced schedule reads and, nodes being numbered by rank,
-// mostly contiguous stores).
-template <int P>
-__global__ void tf_step_kernel(const SchedNode *__restrict__ sched, uint32_t lo_i, uint32_t hi_i, uint32_t n_nodes,
-                               uint32_t T, float4 *out)
+// The entry of position i of a propagation order: with RANKS the nodes in ID
+// order (IDs are sorted by rank, so a rank is a contiguous ID range and node i's
+// triple is nodes[i]); else the deferred step schedule's entry sched[i].
+template <bool RANKS>
+__device__ inline SchedNode tf_entry(const NodeTriple *__restrict__ nodes, const SchedNode *__restrict__ sched,
+                                     uint32_t i)
 {
-    const uint32_t i = lo_i + blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= hi_i) return;
-    const SchedNode t = sched[i];
+    if (RANKS) {
+        const NodeTriple t = nodes[i];
+        return SchedNode{t.a, t.b, t.w, i};
+    }
+    return sched[i];
+}
+
+// One step of the order (a rank, or a step of the deferred schedule): thread
+// (x, y) computes the node at position lo_i + x for the transfer functions
+// P y .. P y + P - 1 (grid.y = ceil(T / P)): it loads the node's entry and both
+// predecessors' colours in all P planes before it stores any, so 2 P gathers
+// per thread are in flight together. Lanes of a wave take consecutive entries
+// (coalesced entry reads and, nodes being numbered by rank, contiguous stores).
+// FIRST: the first step, whose nodes' predecessors are all sources (every
+// predecessor is scheduled at an earlier step): it reads their colours from the
+// transfer functions themselves, and threads x >= hi_i - lo_i write the sources'
+// own colours (the same values), so the frame needs no separate source pass.
+template <int P, bool FIRST, bool RANKS>
+__global__ void tf_step_kernel(const NodeTriple *__restrict__ nodes, const SchedNode *__restrict__ sched,
+                               uint32_t lo_i, uint32_t hi_i, uint32_t n_nodes, uint32_t T,
+                               const uchar4 *__restrict__ tf, uint32_t nseg, float4 *out)
+{
+#pragma clang fp contract(off)
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t p0 = blockIdx.y * P;
+    const uint32_t n_step = hi_i - lo_i;
+    if (x >= n_step) {
+        if (!FIRST || x - n_step >= nseg) return;
+        const uint32_t src = x - n_step;
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+            if (P == 1 || p0 + p < T) out[uint64_t(p0 + p) * n_nodes + src] = tf_source_colour(tf, nseg, p0 + p, src);
+        return;
+    }
+    const SchedNode t = tf_entry<RANKS>(nodes, sched, lo_i + x);
     float4 va[P], vb[P];
 #pragma unroll
     for (int p = 0; p < P; ++p)
         if (P == 1 || p0 + p < T) {
-            const float4 *o = out + uint64_t(p0 + p) * n_nodes;
-            va[p] = o[t.a];
-            vb[p] = o[t.b];
+            if (FIRST) {
+                va[p] = tf_source_colour(tf, nseg, p0 + p, t.a);
+                vb[p] = tf_source_colour(tf, nseg, p0 + p, t.b);
+            } else {
+                const float4 *o = out + uint64_t(p0 + p) * n_nodes;
+                va[p] = o[t.a];
+                vb[p] = o[t.b];
+            }
         }
 #pragma unroll
     for (int p = 0; p < P; ++p)
@@ -1502,6 +1641,38 @@ __global__ void tf_step_kernel(const SchedNode *__restrict__ sched, uint32_t lo_
             r.w = fmaf(t.w, vb[p].w - va[p].w, va[p].w);
             out[uint64_t(p0 + p) * n_nodes + t.id] = r;
         }
+}
+
+// The last steps of the schedule when each is small (at most kTfTailPairs node x
+// transfer-function pairs): one workgroup runs them in order, a block barrier
+// between steps (all its waves share one CU and its L1, so the stores of a step
+// are visible to the loads of the next), instead of one launch per step.
+struct TfTail {
+    uint32_t n_steps;
+    uint32_t lo[kTfTailSteps + 1];  // step k: schedule entries lo[k] .. lo[k + 1]
+};
+
+template <bool RANKS>
+__global__ __launch_bounds__(kTfTailBlock) void tf_tail_kernel(const NodeTriple *__restrict__ nodes,
+                                                               const SchedNode *__restrict__ sched, TfTail tail,
+                                                               uint32_t n_nodes, uint32_t T, float4 *out)
+{
+    for (uint32_t k = 0; k < tail.n_steps; ++k) {
+        const uint32_t lo = tail.lo[k], n = tail.lo[k + 1] - lo;
+        for (uint32_t j = threadIdx.x; j < n * T; j += kTfTailBlock) {  // plane-major: lanes take consecutive nodes
+            const uint32_t t = j / n;
+            const SchedNode e = tf_entry<RANKS>(nodes, sched, lo + j % n);
+            float4 *o = out + uint64_t(t) * n_nodes;
+            const float4 va = o[e.a], vb = o[e.b];
+            float4 r;
+            r.x = fmaf(e.w, vb.x - va.x, va.x);
+            r.y = fmaf(e.w, vb.y - va.y, va.y);
+            r.z = fmaf(e.w, vb.z - va.z, va.z);
+            r.w = fmaf(e.w, vb.w - va.w, va.w);
+            o[e.id] = r;
+        }
+        __syncthreads();
+    }
 }
 
 // Mean colour of a box under one propagated palette: every footprint cube adds
@@ -1662,6 +1833,7 @@ LevelTable level_table_dims(const uint32_t dims[3])
     lt.pitch_y = dims[1] + (dims[1] & 1u);
     lt.total16 = uint64_t(lt.pitch_x) * dims[1] * dims[2];
     lt.use16 = 0;  // set per launch where the 16-bit copy is used
+    lt.runs_mask = 0, lt.run_min = 0xFFFFFFFFu;  // and where row runs are read
     return lt;
 }
 
@@ -1905,8 +2077,8 @@ int scratch_slot(int device, ScratchSlot **out, std::string *err)
 // boxes, replayed on the host with the kernels' own slab builder and tile-walk
 // helpers, UNROLL loads per block. counts: [0] boxes, [1] slabs, [2] lane
 // loads checked, [3] cubes read.
-int check_load_addresses(const uint32_t dims[3], bool use16, bool naive, const uint32_t *boxes, uint32_t n,
-                         uint32_t unroll, uint64_t counts[4], std::string *err)
+int check_load_addresses(const uint32_t dims[3], bool use16, bool naive, bool runs, const uint32_t *boxes,
+                         uint32_t n, uint32_t unroll, uint64_t counts[4], std::string *err)
 {
     LevelTable lt = level_table_dims(dims);
     if (lt.n_levels > kMaxLevelsDev) {
@@ -1914,6 +2086,14 @@ int check_load_addresses(const uint32_t dims[3], bool use16, bool naive, const u
         return MG_ELIMIT;
     }
     lt.use16 = use16 ? 1u : 0u;
+    if (runs) {  // row runs at every level and orientation whose rows the run builder accepts
+        lt.run_min = kRunMinRow;
+        for (uint32_t l = 0; l < lt.n_levels && 2 * l + 1 < 32; ++l) {
+            const uint64_t X = lt.dims[l][0], Y = lt.dims[l][1], Z = lt.dims[l][2];
+            if (X <= 0xFFFFu && Y * Z < 0xFFFFFFFFull) lt.runs_mask |= 1u << (2 * l);
+            if (Y <= 0xFFFFu && Z * X < 0xFFFFFFFFull) lt.runs_mask |= 1u << (2 * l + 1);
+        }
+    }
     const uint64_t bytes32 = 2 * lt.total * 4;  // maps then maps_t
     const uint64_t n16t = uint64_t(lt.pitch_y) * dims[2] * dims[0];
     const uint64_t bytes16 = (lt.total16 + n16t) * 2;
@@ -2005,6 +2185,45 @@ int check_load_addresses(const uint32_t dims[3], bool use16, bool naive, const u
             const Slab &sl = slabs[i];
             ++counts[1];
             const uint32_t L = sl.level;
+            if (sl.kind == 2) {  // row runs: every item's row and skip entry, its cells inside the box
+                const uint32_t f = sl.axes & 3u, lseg = run_lseg(sl.e0);
+                const uint64_t len = lt.dims[L][f], rows = f == 0 ? uint64_t(lt.dims[L][1]) * lt.dims[L][2]
+                                                                 : uint64_t(lt.dims[L][2]) * lt.dims[L][0];
+                const uint64_t chunks = (len + kRunSkipCells - 1) / kRunSkipCells;
+                const uint64_t items = (uint64_t(sl.e1) * sl.e2) << lseg;
+                if (f > 1 || items >= (1ull << 32)) where = "run slab orientation or size";
+                for (uint64_t it = 0; where.empty() && it < items; ++it) {
+                    uint32_t r, p0, p1;
+                    if (!run_item(sl, lt, f, lseg, uint32_t(it), &r, &p0, &p1)) continue;
+                    ++counts[2];
+                    if (r >= rows || uint64_t(r) * chunks + p0 / kRunSkipCells >= rows * chunks || p1 > len) {
+                        where = "run row or skip entry out of range";
+                        break;
+                    }
+                    // the segment's first and last cube, and the row they lie on
+                    const uint32_t row = uint32_t(it >> lseg);
+                    const uint32_t i2 = sl.e2 == 1 ? 0u : row / sl.e1, i1 = row - i2 * sl.e1;
+                    const uint32_t fa = f == 0 ? sl.bx : sl.by;
+                    for (const uint32_t i0 : {p0 - fa, p1 - 1 - fa}) {
+                        uint32_t cx, cy, cz;
+                        slab_coords(sl, i0, i1, i2, &cx, &cy, &cz);
+                        const uint32_t cc[3] = {cx, cy, cz};
+                        for (int d = 0; d < 3; ++d)
+                            if ((uint64_t(cc[d]) + 1) << L > hi[d] || uint64_t(cc[d]) << L < lo[d])
+                                where = "run segment outside the box";
+                        if ((f == 0 ? cy + uint64_t(lt.dims[L][1]) * cz : cz + uint64_t(lt.dims[L][2]) * cx) != r)
+                            where = "run segment is not on its row";
+                    }
+                    cubes += p1 - p0;
+                }
+                if (!where.empty()) {
+                    *err = "box " + std::to_string(q) + " level " + std::to_string(L) + " run slab " +
+                           std::to_string(sl.e0) + "x" + std::to_string(sl.e1) + "x" + std::to_string(sl.e2) + ": " +
+                           where;
+                    return MG_ELIMIT;
+                }
+                continue;
+            }
             const TileWalk tw = tile_walk(sl.units, sl.e1, sl.e2, sl.s1b, sl.s2b, unroll);
             const bool tr = (sl.axes & 3) == 1;
             const uint32_t X = lt.dims[L][0], Y = lt.dims[L][1], Z = lt.dims[L][2];
@@ -2092,6 +2311,8 @@ int check_load_addresses(const uint32_t dims[3], bool use16, bool naive, const u
 struct DeviceLayout {
     uint64_t nodes, sched, rank_ptr, mixlen, maps, maps16;
     uint64_t n16, n16t;   // elements of the two 16-bit level-0 copies (0 if none)
+    uint64_t run_table;   // RunLevel [2 n_levels]
+    std::vector<uint64_t> run_rp, run_sk, run_rn;  // per level and orientation: row_ptr, skip, runs
     uint64_t bytes;
 };
 
@@ -2117,6 +2338,14 @@ DeviceLayout device_layout(const Graph &g)
         L.n16t = uint64_t(lt.pitch_y) * g.dims[2] * g.dims[0];
     }
     L.maps16 = take((L.n16 + L.n16t) * sizeof(uint16_t));
+    // row runs of every level and orientation that has them (built from the host maps)
+    ensure_runs(g);
+    L.run_table = take(2 * uint64_t(g.n_levels) * sizeof(RunLevel));
+    for (const LevelRuns &r : g.runs) {
+        L.run_rp.push_back(r.rows ? take(r.row_ptr.size() * 4) : 0);
+        L.run_sk.push_back(r.rows ? take(r.skip.size() * 2) : 0);
+        L.run_rn.push_back(r.rows ? take(r.runs.size() * 8) : 0);
+    }
     L.bytes = off;
     return L;
 }
@@ -2267,6 +2496,26 @@ int dev_bind(Graph *g, int device, void *base, uint64_t bytes, hipStream_t s, bo
                            g->dims[0], g->dims[1], g->dims[2], lt.pitch_x, lt.pitch_y, L.n16, L.n16t);
         HIP_TRY(hipGetLastError());
     }
+    // row runs and their table
+    std::vector<RunLevel> table(2 * size_t(g->n_levels));
+    d.runs_mask = 0;
+    for (size_t k = 0; k < g->runs.size() && k < table.size(); ++k) {
+        const LevelRuns &r = g->runs[k];
+        RunLevel &t = table[k];
+        t = RunLevel{nullptr, nullptr, nullptr, 0, 0};
+        if (!r.rows || k >= 64) continue;
+        t.row_ptr = reinterpret_cast<const uint32_t *>(b + L.run_rp[k]);
+        t.skip = reinterpret_cast<const uint16_t *>(b + L.run_sk[k]);
+        t.runs = reinterpret_cast<const uint64_t *>(b + L.run_rn[k]);
+        t.rows = r.rows, t.chunks = r.chunks;
+        HIP_TRY(hipMemcpyAsync(b + L.run_rp[k], r.row_ptr.data(), r.row_ptr.size() * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(b + L.run_sk[k], r.skip.data(), r.skip.size() * 2, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(b + L.run_rn[k], r.runs.data(), r.runs.size() * 8, hipMemcpyHostToDevice, s));
+        if (k < 32) d.runs_mask |= 1u << k;
+    }
+    d.run_table = b + L.run_table;
+    if (!table.empty())
+        HIP_TRY(hipMemcpyAsync(d.run_table, table.data(), table.size() * sizeof(RunLevel), hipMemcpyHostToDevice, s));
     // the host staging vectors above die with this call
     HIP_TRY(hipStreamSynchronize(s));
     // set-up of the no-allocation path on this device (the scratch array's address)
@@ -2695,6 +2944,11 @@ int query_in(Graph *g, const uint32_t *boxes, uint32_t n, float *out, const Spar
     // sources in LDS arrays while they fit, else as table entries (sparse mode)
     const bool sparse = sp != nullptr || g->nseg > kSegLdsMax;
     A.lt.use16 = (!sparse && g->dev.maps16) ? 1u : 0u;
+    // row runs where the graph has them, for slabs whose rows are long enough
+    const uint32_t run_min = g->dev.cfg.run_min_row ? g->dev.cfg.run_min_row : kRunMinRow;
+    A.lt.runs_mask = run_min == 0xFFFFFFFFu ? 0u : g->dev.runs_mask;
+    A.lt.run_min = run_min;
+    A.runs = static_cast<const RunLevel *>(g->dev.run_table);
     if (A.out_err) return launch_query<false, true>(g, A, w, lt, n, s, variant, err);
     return sparse ? launch_query<true, false>(g, A, w, lt, n, s, variant, err)
                   : launch_query<false, false>(g, A, w, lt, n, s, variant, err);
@@ -2796,22 +3050,50 @@ int dev_propagate_tf(Graph *g, const uint8_t *tf, uint32_t T, float *out, void *
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     float4 *o = reinterpret_cast<float4 *>(out);
-    const uint64_t src = uint64_t(T) * g->nseg;
     // the timed region is the whole frame: sources, then every step
     rc = timing_begin(g, s, err);
     if (rc) return rc;
-    hipLaunchKernelGGL(tf_sources_kernel, dim3(uint32_t((src + 255) / 256)), dim3(256), 0, s, tf, T, g->nseg,
-                       g->n_nodes, o);
-    HIP_TRY(hipGetLastError());
     const uint32_t tb = g->dev.cfg.tf_block;
     const uint32_t P = std::min<uint32_t>(g->dev.cfg.tf_planes ? g->dev.cfg.tf_planes : kTfPlanes, T);
     const uint32_t P2 = P >= 8 ? 8u : P >= 4 ? 4u : P >= 2 ? 2u : 1u;  // planes per thread
-    auto step = P2 == 8 ? tf_step_kernel<8> : P2 == 4 ? tf_step_kernel<4> : P2 == 2 ? tf_step_kernel<2> : tf_step_kernel<1>;
-    for (uint32_t st = 1; st <= g->depth; ++st) {
-        const uint32_t lo = g->step_ptr[st], hi = g->step_ptr[st + 1];
+    using StepKernel = void (*)(const NodeTriple *, const SchedNode *, uint32_t, uint32_t, uint32_t, uint32_t,
+                                const uchar4 *, uint32_t, float4 *);
+    // the order: ranks (default) or the graph's deferred step schedule
+    const bool ranks = g->dev.cfg.tf_schedule == 0;
+    const std::vector<uint32_t> &ptr = ranks ? g->rank_ptr : g->step_ptr;
+    auto pick = [&](bool first) -> StepKernel {
+#define MG_TF_STEP(F, R)                                                                                       \
+    (P2 == 8 ? tf_step_kernel<8, F, R> : P2 == 4 ? tf_step_kernel<4, F, R> : P2 == 2 ? tf_step_kernel<2, F, R> \
+                                                                           : tf_step_kernel<1, F, R>)
+        if (ranks) return first ? MG_TF_STEP(true, true) : MG_TF_STEP(false, true);
+        return first ? MG_TF_STEP(true, false) : MG_TF_STEP(false, false);
+#undef MG_TF_STEP
+    };
+    const uchar4 *tf4 = reinterpret_cast<const uchar4 *>(tf);
+    const uint32_t D = g->depth;
+    auto step_size = [&](uint32_t st) { return ptr[st + 1] - ptr[st]; };
+    // trailing small steps (two or more) go to the one-workgroup kernel
+    uint32_t tail0 = D + 1;
+    while (tail0 > 2 && D + 2 - tail0 <= kTfTailSteps && uint64_t(step_size(tail0 - 1)) * T <= kTfTailPairs) --tail0;
+    if (D + 1 - tail0 < 2) tail0 = D + 1;
+    // step 1 (possibly empty) with the sources' colours, then the other steps
+    const uint32_t n1 = D >= 1 ? step_size(1) : 0u;
+    hipLaunchKernelGGL(pick(true), dim3((n1 + g->nseg + tb - 1) / tb, (T + P2 - 1) / P2), dim3(tb), 0, s,
+                       g->dev.nodes, g->dev.sched, g->nseg, g->nseg + n1, g->n_nodes, T, tf4, g->nseg, o);
+    HIP_TRY(hipGetLastError());
+    for (uint32_t st = 2; st < tail0; ++st) {
+        const uint32_t lo = ptr[st], hi = ptr[st + 1];
         if (hi <= lo) continue;
-        hipLaunchKernelGGL(step, dim3((hi - lo + tb - 1) / tb, (T + P2 - 1) / P2), dim3(tb), 0, s, g->dev.sched, lo,
-                           hi, g->n_nodes, T, o);
+        hipLaunchKernelGGL(pick(false), dim3((hi - lo + tb - 1) / tb, (T + P2 - 1) / P2), dim3(tb), 0, s,
+                           g->dev.nodes, g->dev.sched, lo, hi, g->n_nodes, T, tf4, g->nseg, o);
+        HIP_TRY(hipGetLastError());
+    }
+    if (tail0 <= D) {
+        TfTail tail;
+        tail.n_steps = D + 1 - tail0;
+        for (uint32_t k = 0; k <= tail.n_steps; ++k) tail.lo[k] = ptr[tail0 + k];
+        hipLaunchKernelGGL(ranks ? tf_tail_kernel<true> : tf_tail_kernel<false>, dim3(1), dim3(kTfTailBlock), 0, s,
+                           g->dev.nodes, g->dev.sched, tail, g->n_nodes, T, o);
         HIP_TRY(hipGetLastError());
     }
     return timing_end(g, s, err);
@@ -2834,8 +3116,8 @@ int dev_set_launch(Graph *g, const mg_launch_cfg *cfg, std::string *err)
             return MG_EINVAL;
         }
     if (!(cfg->tf_planes == 0 || cfg->tf_planes == 1 || cfg->tf_planes == 2 || cfg->tf_planes == 4 ||
-          cfg->tf_planes == 8)) {
-        *err = "mg_set_launch: tf_planes must be 0, 1, 2, 4 or 8";
+          cfg->tf_planes == 8) || cfg->tf_schedule > 1) {
+        *err = "mg_set_launch: tf_planes must be 0, 1, 2, 4 or 8 and tf_schedule 0 or 1";
         return MG_EINVAL;
     }
     const uint32_t tb = cfg->tf_block;
@@ -2963,7 +3245,8 @@ int dev_timing_read(Graph *g, double *ms, uint32_t *launches, std::string *err)
 int dev_check_load_addresses(const uint32_t dims[3], uint32_t flags, const uint32_t *boxes, uint32_t n,
                               uint32_t unroll, uint64_t counts[4], std::string *err)
 {
-    return check_load_addresses(dims, (flags & 1u) != 0, (flags & 2u) != 0, boxes, n, unroll, counts, err);
+    return check_load_addresses(dims, (flags & 1u) != 0, (flags & 2u) != 0, (flags & 4u) != 0, boxes, n, unroll, counts,
+                                err);
 }
 
 }  // namespace mg

@@ -38,6 +38,8 @@ struct DeviceState {
     uint32_t *maps = nullptr;      // all levels, x fastest
     uint32_t *maps_t = nullptr;    // all levels, y fastest then z then x
     uint16_t *maps16 = nullptr;    // level 0 as 16-bit IDs, both orientations (rows padded to even)
+    void *run_table = nullptr;     // row runs per level and orientation (RunLevel [2 n_levels])
+    uint32_t runs_mask = 0;        // bit 2 l + o: level l has runs along x (o = 0) / y (o = 1)
     uint64_t *lut_ptr = nullptr;   // [n_nodes + 1] mixture lookup table rows (optional)
     uint32_t *lut_seg = nullptr;   // [lut nnz]
     float *lut_val = nullptr;      // [lut nnz]
@@ -52,10 +54,22 @@ struct DeviceState {
         int blocks;     // blocks per CU
     };
     std::vector<Occ> occupancy;  // per kernel variant and LDS size
-    mg_launch_cfg cfg = {16, 8, 16, 256, 0, 0, 0, 0, 0, 0};
+    mg_launch_cfg cfg = {16, 8, 16, 256, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     bool timing = false;
     std::vector<void *> ev_start, ev_stop;  // hipEvent_t pairs recorded around the dominant kernel
     uint32_t ev_used = 0;
+};
+
+// Runs of equal node IDs along the rows of one level in one orientation
+// (runs.cpp): row_ptr[rows + 1] into runs, runs[j] = (exclusive end along the
+// row) << 32 | node, skip[rows][chunks] = index from row_ptr[r] of the run
+// holding cell 64 c. Empty (rows == 0) where the level keeps no runs.
+constexpr uint32_t kRunSkipCells = 64;  // cells of a row per skip entry
+struct LevelRuns {
+    uint32_t rows = 0, len = 0, chunks = 0;
+    std::vector<uint32_t> row_ptr;
+    std::vector<uint64_t> runs;
+    std::vector<uint16_t> skip;
 };
 
 struct Graph {
@@ -88,8 +102,16 @@ struct Graph {
     std::vector<float> codebook, code_sigma;             // [2^bits] codeword and sigma of each bin
     std::vector<float> node_sigma;                       // [n_nodes] sigma of each node's weight
     std::vector<uint32_t> node_code;                     // [n_nodes] codebook index of each node's weight
+    // row runs of every level, [2 l] along x and [2 l + 1] along y: derived from
+    // the host maps on first use (ensure_runs), a cache of the graph's own data
+    mutable std::vector<LevelRuns> runs;
+    mutable bool runs_ready = false;
     DeviceState dev;
 };
+
+// Fills g.runs from the host maps once (no runs for graphs whose maps are only on
+// the device). Not safe against a concurrent first call on the same graph.
+void ensure_runs(const Graph &g);
 
 // A DAG in creation order (children before parents; sources 0 .. nseg-1 have
 // a = b = n): what finalize_dag turns into a Graph's node arrays.

@@ -125,7 +125,7 @@ class Graph:
             "nseg": i.nseg, "n_nodes": i.n_nodes, "depth": i.depth, "n_levels": i.n_levels,
             "dims": [tuple(i.dims[l]) for l in range(i.n_levels)], "map_voxels": i.map_voxels,
             "device_bytes": i.device_bytes, "device": i.device, "max_mixture": i.max_mixture,
-            "quant_bits": i.quant_bits,
+            "quant_bits": i.quant_bits, "runs_mask": i.runs_mask,
         }
 
     def export_dag(self) -> dict:
@@ -399,7 +399,8 @@ class Graph:
         return {"unroll_big": c.unroll_big, "unroll_small": c.unroll_small, "unroll_naive": c.unroll_naive,
                 "tf_block": c.tf_block, "table_big": c.table_big, "table_small": c.table_small,
                 "table_retry": c.table_retry, "block_small": c.block_small, "block_big": c.block_big,
-                "chunk_small": c.chunk_small, "tf_planes": c.tf_planes}
+                "chunk_small": c.chunk_small, "tf_planes": c.tf_planes, "tf_schedule": c.tf_schedule,
+                "run_min_row": c.run_min_row}
 
     def set_launch_config(self, **kw) -> None:
         cur = self.launch_config()

@@ -132,6 +132,46 @@ def test_query_reduced_recipes(config, dims, segments, n):
     print(errs)
 
 
+@pytest.mark.parametrize("config,dims,segments,n", [
+    (2, (160, 150, 140), 300, 1500), (3, (256, 200, 40), 120, 800), (4, (150, 180, 120), 900, 800),
+    (5, (118, 113, 79), 353, 800), (4, (160, 200, 150), 4000, 600),
+])
+def test_query_from_row_runs_every_row_length(config, dims, segments, n):
+    """Slabs summed from row runs: runs for rows of every length (run_min_row 1), the default
+    (rows of 16 cubes or more) and never (every slab streams cube by cube) all give the oracle's
+    histograms, for the batched, plain and lookup-table queries and the sparse output; tiny tables
+    send boxes through the retry and global-table launches with runs on. The last recipe has more
+    sources than the LDS arrays hold (sources are table entries)."""
+    w = synth.workload(config, dims=dims, segments=segments, n_boxes=n)
+    vol = synth.make_volume(w)
+    boxes = synth.make_boxes(w)
+    X, Y, Z = dims
+    boxes[:4] = [[0, 0, 0, X, Y, Z], [X - 1, Y - 1, Z - 1, 1, 1, 1], [1, 2, 3, X - 1, Y - 2, 1],
+                 [0, 3, 0, X, 1, Z]]
+    g = _graph(("runs", config, dims, segments), vol)
+    _lut(g)
+    assert g.info()["runs_mask"] & 3, "level 0 keeps no row runs"
+    S = g.info()["nseg"]
+    ids, vol_c = scan.compact(vol)
+    _, ref = scan.box_counts(vol_c, len(ids), boxes)
+    db = _dev(boxes)
+    l0 = _level0_only(g, db)
+    nnz = int((ref > 0).sum())
+    try:
+        for rm in (1, 0, 0xFFFFFFFF):
+            g.set_launch_config(run_min_row=rm)
+            for v in ("batched", "plain", "lut"):
+                _compare(g.query(db, variant=v).cpu().numpy(), ref, l0, "run_min %d %s" % (rm, v))
+            index, seg, val, total = g.query_sparse(db, capacity=nnz)
+            assert int(total.item()) == nnz
+            dense = _sparse_to_dense(index.cpu().numpy(), seg.cpu().numpy(), val.cpu().numpy(), len(boxes), S)
+            _compare(dense, ref, l0, "run_min %d sparse" % rm)
+        g.set_launch_config(run_min_row=1, table_big=64, table_small=64, table_retry=64)
+        _compare(g.query(db).cpu().numpy(), ref, l0, "runs, tiny tables")
+    finally:
+        g.set_launch_config(run_min_row=0, table_big=0, table_small=0, table_retry=0)
+
+
 def test_query_edge_cases():
     vol = synth.make_volume(synth.workload(2, dims=(33, 35, 31), segments=25))
     nx, ny, nz = 33, 35, 31
@@ -199,30 +239,45 @@ def test_query_full_config2_sampled():
 
 # ------------------------------------------------------------------ TF propagation (a8)
 
-def test_tf_matches_oracle_every_mip_voxel():
-    vol = synth.make_volume(synth.workload(3, dims=(40, 36, 12), segments=30))
-    g = _graph("tf", vol)
+@pytest.mark.parametrize("dims,segments", [((40, 36, 12), 30), ((72, 64, 40), 400)])
+def test_tf_matches_oracle_every_mip_voxel(dims, segments):
+    """Every node's colour at every mip voxel against the oracle's mean TF colour. With the
+    deferred schedule the first volume's steps after the first are all small (one workgroup runs
+    them); the second has steps of more than 4096 node x TF pairs (one launch each) before its
+    small last steps. Rank by rank, both volumes have large first ranks and small last ones."""
+    vol = synth.make_volume(synth.workload(3, dims=dims, segments=segments))
+    g = _graph("tf%d" % segments, vol)
     inf = g.info()
     S = inf["nseg"]
+    steps = np.diff(g.export_dag()["step_ptr"])[1:]
+    if segments == 400:
+        assert steps.max() * 5 > 4096 and steps[-1] * 5 <= 4096, steps
     tfs = synth.make_tfs(synth.workload(3), S, 5)
     ids, vol_c = scan.compact(vol)
     atol = 4 * max(inf["depth"], 1) * 2.0 ** -24
-    want = [[otf.level_colours(vol_c, S, tfs[t], l) for l in range(inf["n_levels"])] for t in range(5)]
+    want = [[None] * inf["n_levels"] for _ in range(5)]
+    for l in range(inf["n_levels"]):   # the oracle's level colours, mixtures computed once per level
+        h = mipmap.mixtures_level(vol_c, S, l)
+        for t in range(5):
+            want[t][l] = h @ otf.rgba_to_float(tfs[t])
     first = None
-    # transfer functions per thread: a launch knob (5 planes: the last thread row is ragged)
-    for planes in (0, 1, 2, 4, 8):
-        g.set_launch_config(tf_planes=planes)
+    # transfer functions per thread (5 planes: the last thread row is ragged) and the order of the
+    # launches (rank by rank, or the deferred step schedule): launch knobs, never a change of colours
+    for sched, planes in ((0, 0), (0, 1), (0, 2), (0, 4), (0, 8), (1, 0), (1, 1), (1, 8)):
+        g.set_launch_config(tf_planes=planes, tf_schedule=sched)
         col = g.propagate_tf(torch.from_numpy(tfs).cuda()).cpu().numpy()
         for t in range(5):
             for l in range(inf["n_levels"]):
                 got = col[t][g.export_map(l)].astype(np.float64)
-                assert np.abs(got - want[t][l]).max() <= atol, (planes, t, l, np.abs(got - want[t][l]).max())
+                assert np.abs(got - want[t][l]).max() <= atol, (sched, planes, t, l, np.abs(got - want[t][l]).max())
         if first is None:
             first = col
-        assert np.array_equal(col, first), planes   # same arithmetic per node and plane
-    g.set_launch_config(tf_planes=0)
+        assert np.array_equal(col, first), (sched, planes)   # same arithmetic per node and plane
+    g.set_launch_config(tf_planes=0, tf_schedule=0)
     with pytest.raises(MGError):
         g.set_launch_config(tf_planes=3)
+    with pytest.raises(MGError):
+        g.set_launch_config(tf_schedule=2)
 
 
 def test_tf_constant_is_exact_and_one_hot_gives_mixture():
