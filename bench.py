@@ -405,6 +405,11 @@ def main():
         e2, k2 = run(v, args.competitor_steps, 1, True)
         comp[v] = {"value": args.competitor_steps * n / e2, "ms_per_step": 1e3 * e2 / args.competitor_steps,
                    "kernel_ms": k2}
+        # HBM bytes per batch from the committed counter summaries, where they match this kernel source
+        hbm = read_traffic({"naive": "naive_kernel", "lut": "query_lut"}.get(v, ""), w.name, 0.0)
+        if hbm is not None:
+            comp[v]["hbm_bytes_per_batch"] = hbm
+            comp[v]["hbm_gbs"] = hbm / (k2 * 1e-3) / 1e9
         if v == "lut":
             comp[v]["max_abs_diff_vs_push"] = float((out - torch.from_numpy(res_main).to(out.device)).abs().max())
             comp[v]["lut_entries"] = lut_nnz

@@ -273,12 +273,13 @@ int mg_naive_boxes(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *d_ou
  * load the batched query kernels issue (all `unroll` loads of every block, 4, 8
  * or 16), with the kernels' own slab builder and tile-walk helpers. flags: bit
  * 0 = level 0 from the 16-bit copy, bit 1 = also the naive scan's loads, bit 2
- * = slabs with rows of at least 16 cubes summed from row runs (every level and
- * orientation the run builder accepts). Checks that each load lies inside its
+ * = slabs with rows of at least run_min cubes summed from row runs (every level
+ * and orientation the run builder accepts), bits 8..31 = run_min (0: the
+ * default of mg_launch_cfg.run_min_row). Checks that each load lies inside its
  * slab and inside the map buffer, that each consumed load reads exactly the
  * element of a footprint cube (or voxel) of the box, for run slabs that each
  * row segment lies in the box on its row and indexes its row and skip entry in
- * range (run loads are clamped to the row's runs by the kernel), and that every
+ * range (run loads are clamped to the run array by the kernel), and that every
  * cube of the footprint is read once. counts host uint64 [4]: boxes, slabs,
  * lane loads (run segments for run slabs), cubes. MG_ELIMIT with the first
  * violation in the message. */
@@ -385,7 +386,7 @@ typedef struct {
                                built with defer = 1). Same colours either way                  */
     uint32_t run_min_row;   /* footprint slabs whose rows are at least this many cubes long are
                                summed from the rows' runs of equal node IDs where the graph
-                               has them; shorter rows stream cube by cube. 0: default (16);
+                               has them; shorter rows stream cube by cube. 0: default (128);
                                0xFFFFFFFF: never (every slab streams)                          */
 } mg_launch_cfg;
 

@@ -313,7 +313,7 @@ int mg_check_load_addresses(uint32_t nx, uint32_t ny, uint32_t nz, uint32_t flag
         return fail(MG_EINVAL, "mg_check_load_addresses: unroll must be 4, 8 or 16");
     const uint32_t dims[3] = {nx, ny, nz};
     std::string err;
-    if (flags > 7) return fail(MG_EINVAL, "mg_check_load_addresses: unknown flags");
+    if (flags & 0xF8u) return fail(MG_EINVAL, "mg_check_load_addresses: unknown flags");
     return done(mg::dev_check_load_addresses(dims, flags, boxes, n, unroll, counts, &err), err);
 }
 

@@ -52,8 +52,9 @@ constexpr uint32_t kHashGlobal = 1u << 16;    // fewest per-worker hash slots in
 constexpr uint32_t kSegLdsMax = 2048;         // sources kept in LDS
 constexpr uint32_t kFallbackWorkers = 128;    // workers of the final global-table launch (budget)
 constexpr uint32_t kRunSeg = 256;             // cells of a row one thread sums from the runs
-constexpr int kRunBatch = 4;                   // runs a thread loads at once
-constexpr uint32_t kRunMinRow = 16;            // rows shorter than this stream cube by cube (default)
+constexpr int kRunBatch = 4;                   // runs a thread loads at once per segment
+constexpr int kRunItems = 1;                   // segments a thread walks at once
+constexpr uint32_t kRunMinRow = 128;           // rows shorter than this stream cube by cube (default)
 constexpr uint32_t kTfPlanes = 4;             // transfer functions per thread of a propagation step
 constexpr uint32_t kTfTailPairs = 4096;        // steps of at most this many node x TF pairs may share a launch
 constexpr uint32_t kTfTailSteps = 16;          // at most this many of them
@@ -95,12 +96,12 @@ struct LevelTable {
 };
 
 // Row runs of one level and orientation as the kernels read them (the device copy
-// of the host's LevelRuns): runs[j] = exclusive end << 32 | node.
+// of the host's LevelRuns): runs[j] = exclusive end << 32 | node; skip[r][c] =
+// index of the run holding cell 64 c of row r.
 struct RunLevel {
-    const uint32_t *row_ptr;   // [rows + 1]
-    const uint16_t *skip;      // [rows][chunks]
-    const uint64_t *runs;
-    uint32_t rows, chunks;
+    const uint32_t *skip;      // [rows][chunks]
+    const uint64_t *runs;      // [n_runs]
+    uint32_t rows, chunks, n_runs;
 };
 
 // A slab of cubes at one level, as the query kernels read it: e2 slices (slow
@@ -164,28 +165,18 @@ __host__ __device__ inline void put_slab(Slab *out, int *n, const LevelTable &lt
         return;
     }
     const uint32_t ex = x1 - x0, ey = y1 - y0, ez = z1 - z0;
-    const uint32_t X = lt.dims[lev][0], Y = lt.dims[lev][1], Z = lt.dims[lev][2];
-    const bool pairs = lev == 0 && lt.use16;
-    const uint32_t px = pairs ? lt.pitch_x : X, py = pairs ? lt.pitch_y : Y;
     Slab s;
     s.level = uint8_t(lev);
-    s.kind = pairs ? 1 : 0;
     s.bx = x0, s.by = y0, s.bz = z0;
-    // element strides of the mid and slow axes in the chosen copy, and the first element
-    uint32_t f, m, w, ef, em, ew;
-    uint64_t sm, sw, first;
-    if (ex < ey) {  // y fastest: element y + py (z + Z x)
-        f = 1, ef = ey;
-        const uint64_t sz = py, sx = uint64_t(py) * Z;
-        if (ez >= ex) m = 2, em = ez, sm = sz, w = 0, ew = ex, sw = sx;
-        else m = 0, em = ex, sm = sx, w = 2, ew = ez, sw = sz;
-        first = (pairs ? lt.total16 : lt.total + lt.off[lev]) + y0 + uint64_t(py) * (z0 + uint64_t(Z) * x0);
-    } else {        // x fastest: element x + px (y + Y z)
-        f = 0, ef = ex;
-        const uint64_t sy = px, sz = uint64_t(px) * Y;
-        if (ey >= ez) m = 1, em = ey, sm = sy, w = 2, ew = ez, sw = sz;
-        else m = 2, em = ez, sm = sz, w = 1, ew = ey, sw = sy;
-        first = (pairs ? 0 : lt.off[lev]) + x0 + uint64_t(px) * (y0 + uint64_t(Y) * z0);
+    // fast axis f (x unless the block is thinner in x than in y), then mid m and slow w
+    const uint32_t f = ex < ey ? 1u : 0u, ef = f ? ey : ex;
+    uint32_t m, w, em, ew;
+    if (f) {
+        if (ez >= ex) m = 2, em = ez, w = 0, ew = ex;
+        else m = 0, em = ex, w = 2, ew = ez;
+    } else {
+        if (ey >= ez) m = 1, em = ey, w = 2, ew = ez;
+        else m = 2, em = ez, w = 1, ew = ey;
     }
     s.axes = uint8_t(f | (m << 2) | (w << 4));
     s.e0 = ef, s.e1 = em, s.e2 = ew;
@@ -193,6 +184,21 @@ __host__ __device__ inline void put_slab(Slab *out, int *n, const LevelTable &lt
         s.kind = 2, s.odd = 0, s.base = 0, s.s1b = s.s2b = 0, s.units = ef;
         out[(*n)++] = s;
         return;
+    }
+    // element strides of the mid and slow axes in the chosen copy, and the first element
+    const uint32_t X = lt.dims[lev][0], Y = lt.dims[lev][1], Z = lt.dims[lev][2];
+    const bool pairs = lev == 0 && lt.use16;
+    const uint32_t px = pairs ? lt.pitch_x : X, py = pairs ? lt.pitch_y : Y;
+    s.kind = pairs ? 1 : 0;
+    uint64_t sm, sw, first;
+    if (f) {  // y fastest: element y + py (z + Z x)
+        const uint64_t sz = py, sx = uint64_t(py) * Z;
+        sm = m == 2 ? sz : sx, sw = m == 2 ? sx : sz;
+        first = (pairs ? lt.total16 : lt.total + lt.off[lev]) + y0 + uint64_t(py) * (z0 + uint64_t(Z) * x0);
+    } else {  // x fastest: element x + px (y + Y z)
+        const uint64_t sy = px, sz = uint64_t(px) * Y;
+        sm = m == 1 ? sy : sz, sw = m == 1 ? sz : sy;
+        first = (pairs ? 0 : lt.off[lev]) + x0 + uint64_t(px) * (y0 + uint64_t(Y) * z0);
     }
     const uint32_t odd = pairs ? ((f == 1 ? y0 : x0) & 1u) : 0u;
     const uint32_t esz = pairs ? 2u : 4u;
@@ -726,12 +732,14 @@ __device__ inline void count_pairs(uint32_t *cnt, uint32_t lo, uint32_t hi, uint
 
 // Kind-2 slab: every row segment is summed from its row's runs. The block's
 // threads take (row, segment) items, a segment being at most kRunSeg cells of
-// one row; a thread finds the run holding the segment's first cell from the
-// skip entry of its 64-cell chunk (the runs before it end at or before that
-// cell and add nothing), then walks the runs kRunBatch at a time, each run
-// adding (cells of it inside the segment) x 8^level to its node. Run loads are
-// clamped to the row's last run, whose end is the row's end, so every walk
-// stops inside its row.
+// one row, kRunItems at a time: the skip entry of its 64-cell chunk gives the
+// run holding the chunk's first cell (runs before the segment end at or before
+// its first cell and add nothing); runs are loaded kRunBatch at a time, and
+// each adds (cells of it inside the segment) x 8^level to its node. A row's
+// last run ends at the row's end, so a walk never passes it; run loads are also
+// clamped to the array. (Two or four segments per thread in flight, or the
+// wave's first runs merged per node before their atomics, measured slower:
+// the tier kernels then need more registers.)
 // A load through a pointer that was itself read from memory (the run table): the
 // cast tells the compiler it is global memory, so it issues a global load rather
 // than a flat one.
@@ -772,26 +780,47 @@ __device__ inline void scatter_runs(const Slab &sp, const RunLevel &rl, const Le
     const uint32_t f = uni(sp.axes) & 3u, lw8 = 3 * uni(sp.level);
     const uint32_t lseg = run_lseg(uni(sp.e0));
     const uint32_t items = (uni(sp.e1) * uni(sp.e2)) << lseg;
-    for (uint32_t it = threadIdx.x; it < items; it += BLOCK) {
-        uint32_t r, p0, p1;
-        if (!run_item(sp, lt, f, lseg, it, &r, &p0, &p1)) continue;
-        const uint32_t last = load_global(rl.row_ptr + r + 1) - 1;
-        uint32_t j = load_global(rl.row_ptr + r) + load_global(rl.skip + uint64_t(r) * rl.chunks + p0 / kRunSkipCells);
-        uint32_t pos = p0;
-        while (pos < p1) {
-            uint64_t v[kRunBatch];
+    const uint32_t top = rl.n_runs - 1;
+    // runs v[0 .. kRunBatch) from j: each adds its cells in [pos, p1)
+    auto consume = [&](const uint64_t *v, uint32_t &pos, uint32_t p1) {
 #pragma unroll
-            for (int q = 0; q < kRunBatch; ++q) v[q] = load_global(rl.runs + min(j + q, last));
-#pragma unroll
-            for (int q = 0; q < kRunBatch; ++q) {
-                const uint32_t end = uint32_t(v[q] >> 32);
-                if (pos < p1 && end > pos) {
-                    const uint32_t hi = min(end, p1);
-                    scatter_count<SPARSE>(st, gv, uint32_t(v[q]), (hi - pos) << lw8);
-                    pos = hi;
-                }
+        for (int q = 0; q < kRunBatch; ++q) {
+            const uint32_t end = uint32_t(v[q] >> 32);
+            if (pos < p1 && end > pos) {
+                const uint32_t hi = min(end, p1);
+                scatter_count<SPARSE>(st, gv, uint32_t(v[q]), (hi - pos) << lw8);
+                pos = hi;
             }
-            j += kRunBatch;
+        }
+    };
+    for (uint32_t base = threadIdx.x; base < items; base += BLOCK * kRunItems) {
+        uint32_t p0[kRunItems], p1[kRunItems], j[kRunItems];
+#pragma unroll
+        for (int k = 0; k < kRunItems; ++k) {
+            uint32_t r;
+            const uint32_t it = base + uint32_t(k) * BLOCK;
+            if (it < items && run_item(sp, lt, f, lseg, it, &r, &p0[k], &p1[k])) {
+                j[k] = load_global(rl.skip + uint64_t(r) * rl.chunks + p0[k] / kRunSkipCells);
+            } else {
+                p0[k] = p1[k] = 0, j[k] = 0;
+            }
+        }
+        uint64_t v[kRunItems][kRunBatch];
+#pragma unroll
+        for (int k = 0; k < kRunItems; ++k)
+#pragma unroll
+            for (int q = 0; q < kRunBatch; ++q) v[k][q] = load_global(rl.runs + min(j[k] + q, top));
+#pragma unroll
+        for (int k = 0; k < kRunItems; ++k) {
+            uint32_t pos = p0[k];
+            consume(v[k], pos, p1[k]);
+            while (pos < p1[k]) {  // segments that cross more runs
+                j[k] += kRunBatch;
+                uint64_t w[kRunBatch];
+#pragma unroll
+                for (int q = 0; q < kRunBatch; ++q) w[q] = load_global(rl.runs + min(j[k] + q, top));
+                consume(w, pos, p1[k]);
+            }
         }
     }
 }
@@ -1238,7 +1267,10 @@ __global__ __launch_bounds__(kBlock) void query_plain_kernel(QueryArgs A)
 // Batched tiers: persistent blocks take queries from the largest-first order.
 // BIG: positions [0, counters[8]); otherwise [counters[8], n).
 template <int BLOCK, bool BIG, int UNROLL, bool SPARSE, bool ERR>
-__global__ __launch_bounds__(BLOCK) void query_tier_kernel(QueryArgs A)
+// Six waves per SIMD (24 per CU: 1536 threads): the register budget the kernel is
+// tuned for (at most 80 VGPRs), so that the memory latency of the streamed node
+// IDs stays hidden.
+__global__ __launch_bounds__(BLOCK, 1536 / BLOCK) void query_tier_kernel(QueryArgs A)
 {
     extern __shared__ __align__(16) char dyn[];
     __shared__ QueryShared sh;
@@ -2077,8 +2109,8 @@ int scratch_slot(int device, ScratchSlot **out, std::string *err)
 // boxes, replayed on the host with the kernels' own slab builder and tile-walk
 // helpers, UNROLL loads per block. counts: [0] boxes, [1] slabs, [2] lane
 // loads checked, [3] cubes read.
-int check_load_addresses(const uint32_t dims[3], bool use16, bool naive, bool runs, const uint32_t *boxes,
-                         uint32_t n, uint32_t unroll, uint64_t counts[4], std::string *err)
+int check_load_addresses(const uint32_t dims[3], bool use16, bool naive, bool runs, uint32_t run_min,
+                         const uint32_t *boxes, uint32_t n, uint32_t unroll, uint64_t counts[4], std::string *err)
 {
     LevelTable lt = level_table_dims(dims);
     if (lt.n_levels > kMaxLevelsDev) {
@@ -2087,11 +2119,11 @@ int check_load_addresses(const uint32_t dims[3], bool use16, bool naive, bool ru
     }
     lt.use16 = use16 ? 1u : 0u;
     if (runs) {  // row runs at every level and orientation whose rows the run builder accepts
-        lt.run_min = kRunMinRow;
+        lt.run_min = run_min ? run_min : kRunMinRow;
         for (uint32_t l = 0; l < lt.n_levels && 2 * l + 1 < 32; ++l) {
             const uint64_t X = lt.dims[l][0], Y = lt.dims[l][1], Z = lt.dims[l][2];
-            if (X <= 0xFFFFu && Y * Z < 0xFFFFFFFFull) lt.runs_mask |= 1u << (2 * l);
-            if (Y <= 0xFFFFu && Z * X < 0xFFFFFFFFull) lt.runs_mask |= 1u << (2 * l + 1);
+            if (Y * Z < 0xFFFFFFFFull) lt.runs_mask |= 1u << (2 * l);
+            if (Z * X < 0xFFFFFFFFull) lt.runs_mask |= 1u << (2 * l + 1);
         }
     }
     const uint64_t bytes32 = 2 * lt.total * 4;  // maps then maps_t
@@ -2312,7 +2344,7 @@ struct DeviceLayout {
     uint64_t nodes, sched, rank_ptr, mixlen, maps, maps16;
     uint64_t n16, n16t;   // elements of the two 16-bit level-0 copies (0 if none)
     uint64_t run_table;   // RunLevel [2 n_levels]
-    std::vector<uint64_t> run_rp, run_sk, run_rn;  // per level and orientation: row_ptr, skip, runs
+    std::vector<uint64_t> run_sk, run_rn;  // per level and orientation: skip, runs
     uint64_t bytes;
 };
 
@@ -2342,8 +2374,7 @@ DeviceLayout device_layout(const Graph &g)
     ensure_runs(g);
     L.run_table = take(2 * uint64_t(g.n_levels) * sizeof(RunLevel));
     for (const LevelRuns &r : g.runs) {
-        L.run_rp.push_back(r.rows ? take(r.row_ptr.size() * 4) : 0);
-        L.run_sk.push_back(r.rows ? take(r.skip.size() * 2) : 0);
+        L.run_sk.push_back(r.rows ? take(r.skip.size() * 4) : 0);
         L.run_rn.push_back(r.rows ? take(r.runs.size() * 8) : 0);
     }
     L.bytes = off;
@@ -2502,14 +2533,12 @@ int dev_bind(Graph *g, int device, void *base, uint64_t bytes, hipStream_t s, bo
     for (size_t k = 0; k < g->runs.size() && k < table.size(); ++k) {
         const LevelRuns &r = g->runs[k];
         RunLevel &t = table[k];
-        t = RunLevel{nullptr, nullptr, nullptr, 0, 0};
-        if (!r.rows || k >= 64) continue;
-        t.row_ptr = reinterpret_cast<const uint32_t *>(b + L.run_rp[k]);
-        t.skip = reinterpret_cast<const uint16_t *>(b + L.run_sk[k]);
+        t = RunLevel{nullptr, nullptr, 0, 0, 0};
+        if (!r.rows || r.runs.empty()) continue;
+        t.skip = reinterpret_cast<const uint32_t *>(b + L.run_sk[k]);
         t.runs = reinterpret_cast<const uint64_t *>(b + L.run_rn[k]);
-        t.rows = r.rows, t.chunks = r.chunks;
-        HIP_TRY(hipMemcpyAsync(b + L.run_rp[k], r.row_ptr.data(), r.row_ptr.size() * 4, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(b + L.run_sk[k], r.skip.data(), r.skip.size() * 2, hipMemcpyHostToDevice, s));
+        t.rows = r.rows, t.chunks = r.chunks, t.n_runs = uint32_t(r.runs.size());
+        HIP_TRY(hipMemcpyAsync(b + L.run_sk[k], r.skip.data(), r.skip.size() * 4, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(b + L.run_rn[k], r.runs.data(), r.runs.size() * 8, hipMemcpyHostToDevice, s));
         if (k < 32) d.runs_mask |= 1u << k;
     }
@@ -3199,6 +3228,15 @@ int dev_autotune(Graph *g, const uint32_t *boxes, uint32_t n, float *out, void *
         if ((rc = time_variant(kQueryBatched, &ms))) break;
         if (ms < best) best = ms, best_cfg.chunk_small = c;
     }
+    // shortest row summed from runs (where the graph keeps runs)
+    for (uint32_t m : {64u, 256u}) {
+        if (rc || !g->dev.runs_mask) break;
+        g->dev.cfg = best_cfg;
+        g->dev.cfg.run_min_row = m;
+        float ms = 0;
+        if ((rc = time_variant(kQueryBatched, &ms))) break;
+        if (ms < best) best = ms, best_cfg.run_min_row = m;
+    }
     float best_naive = 1e30f;
     for (uint32_t u : us) {
         if (rc) break;
@@ -3245,8 +3283,8 @@ int dev_timing_read(Graph *g, double *ms, uint32_t *launches, std::string *err)
 int dev_check_load_addresses(const uint32_t dims[3], uint32_t flags, const uint32_t *boxes, uint32_t n,
                               uint32_t unroll, uint64_t counts[4], std::string *err)
 {
-    return check_load_addresses(dims, (flags & 1u) != 0, (flags & 2u) != 0, (flags & 4u) != 0, boxes, n, unroll, counts,
-                                err);
+    return check_load_addresses(dims, (flags & 1u) != 0, (flags & 2u) != 0, (flags & 4u) != 0, flags >> 8, boxes, n,
+                                unroll, counts, err);
 }
 
 }  // namespace mg

@@ -62,14 +62,14 @@ struct DeviceState {
 
 // Runs of equal node IDs along the rows of one level in one orientation
 // (runs.cpp): row_ptr[rows + 1] into runs, runs[j] = (exclusive end along the
-// row) << 32 | node, skip[rows][chunks] = index from row_ptr[r] of the run
-// holding cell 64 c. Empty (rows == 0) where the level keeps no runs.
+// row) << 32 | node, skip[rows][chunks] = index of the run holding cell 64 c of
+// row r. Empty (rows == 0) where the level keeps no runs.
 constexpr uint32_t kRunSkipCells = 64;  // cells of a row per skip entry
 struct LevelRuns {
     uint32_t rows = 0, len = 0, chunks = 0;
     std::vector<uint32_t> row_ptr;
     std::vector<uint64_t> runs;
-    std::vector<uint16_t> skip;
+    std::vector<uint32_t> skip;
 };
 
 struct Graph {

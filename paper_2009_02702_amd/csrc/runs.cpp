@@ -11,10 +11,11 @@
 //
 // Per level and orientation: row_ptr[r] = first run of row r (row_ptr[rows] =
 // runs), runs[j] = (end << 32) | node with `end` the exclusive end of run j
-// along the row, and skip[r * chunks + c] = index, from row_ptr[r], of the run
-// that holds cell 64 c of row r (a segment starting at cell f begins its walk
-// at most 63 cells before f). Built only where the runs are at most a quarter
-// of the level's cells (long runs) and a row fits 16-bit run indices.
+// along the row, and skip[r * chunks + c] = index of the run that holds cell
+// 64 c of row r (a segment starting at cell f begins its walk at most 63 cells
+// before f; the row's last run ends at the row's end, so a walk that stops at
+// the segment's end never leaves the row). Built only where the runs are at
+// most a quarter of the level's cells (long runs).
 #include <algorithm>
 #include <thread>
 #include <vector>
@@ -71,11 +72,11 @@ bool build_x(const uint32_t *m, uint32_t X, uint32_t Y, uint32_t Z, unsigned nt,
         for (uint32_t r = r0; r < r1; ++r) {
             const uint32_t *p = m + uint64_t(X) * r;
             uint64_t *o = out->runs.data() + out->row_ptr[r];
-            uint16_t *sk = out->skip.data() + uint64_t(r) * out->chunks;
+            uint32_t *sk = out->skip.data() + uint64_t(r) * out->chunks;
             uint32_t j = 0;
             for (uint32_t i = 0; i < X; ++i) {
                 if (i > 0 && p[i] != p[i - 1]) o[j++] = (uint64_t(i) << 32) | p[i - 1];
-                if (i % kRunSkipCells == 0) sk[i / kRunSkipCells] = uint16_t(j);
+                if (i % kRunSkipCells == 0) sk[i / kRunSkipCells] = out->row_ptr[r] + j;
             }
             o[j] = (uint64_t(X) << 32) | p[X - 1];
         }
@@ -110,7 +111,7 @@ bool build_y(const uint32_t *m, uint32_t X, uint32_t Y, uint32_t Z, unsigned nt,
                     const uint32_t v = s[x + uint64_t(X) * y];
                     if (y > 0 && v != s[x + uint64_t(X) * (y - 1)])
                         out->runs[out->row_ptr[r] + j[x]++] = (uint64_t(y) << 32) | s[x + uint64_t(X) * (y - 1)];
-                    if (y % kRunSkipCells == 0) out->skip[r * out->chunks + y / kRunSkipCells] = uint16_t(j[x]);
+                    if (y % kRunSkipCells == 0) out->skip[r * out->chunks + y / kRunSkipCells] = out->row_ptr[r] + j[x];
                 }
             for (uint32_t x = 0; x < X; ++x) {
                 const uint64_t r = z + uint64_t(Z) * x;
@@ -133,10 +134,9 @@ void ensure_runs(const Graph &g)
     for (uint32_t l = 0; l < g.n_levels; ++l) {
         const uint32_t X = g.lev_dims[3 * l], Y = g.lev_dims[3 * l + 1], Z = g.lev_dims[3 * l + 2];
         const uint32_t *m = g.maps.data() + g.lev_off[l];
-        // rows along x (row y + Y z) and along y (row z + Z x); run indices within a row are 16-bit
-        if (X <= 0xFFFFu && uint64_t(Y) * Z < 0xFFFFFFFFull && !build_x(m, X, Y, Z, nt, &g.runs[2 * l]))
-            g.runs[2 * l] = LevelRuns();
-        if (Y <= 0xFFFFu && uint64_t(Z) * X < 0xFFFFFFFFull && !build_y(m, X, Y, Z, nt, &g.runs[2 * l + 1]))
+        // rows along x (row y + Y z) and along y (row z + Z x)
+        if (uint64_t(Y) * Z < 0xFFFFFFFFull && !build_x(m, X, Y, Z, nt, &g.runs[2 * l])) g.runs[2 * l] = LevelRuns();
+        if (uint64_t(Z) * X < 0xFFFFFFFFull && !build_y(m, X, Y, Z, nt, &g.runs[2 * l + 1]))
             g.runs[2 * l + 1] = LevelRuns();
     }
 }

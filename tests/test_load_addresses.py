@@ -18,15 +18,16 @@ import pytest
 from paper_2009_02702_amd import _lib, synth
 
 
-def _check(dims, boxes, use16, unroll, naive=True, runs=False):
+def _check(dims, boxes, use16, unroll, naive=True, runs=False, run_min=0):
+    """runs: slabs with rows of at least run_min cubes (0: the library default) from row runs."""
     lib = _lib.load()
     b = np.ascontiguousarray(boxes, dtype=np.uint32).reshape(-1, 6)
     counts = (ctypes.c_uint64 * 4)()
-    flags = int(use16) | (2 if naive else 0) | (4 if runs else 0)
+    flags = int(use16) | (2 if naive else 0) | (4 if runs else 0) | (run_min << 8)
     rc = lib.mg_check_load_addresses(int(dims[0]), int(dims[1]), int(dims[2]), flags,
                                      b.ctypes.data_as(ctypes.c_void_p), len(b), int(unroll), counts)
     msg = lib.mg_last_error().decode() if rc else ""
-    assert rc == 0, "%s use16=%d unroll=%d runs=%d: %s" % (dims, use16, unroll, runs, msg)
+    assert rc == 0, "%s use16=%d unroll=%d runs=%d/%d: %s" % (dims, use16, unroll, runs, run_min, msg)
     return list(counts)
 
 
@@ -57,9 +58,10 @@ def test_bench_batch_every_load():
     boxes = synth.make_boxes(w)
     counts = _check(w.dims, boxes, 1, 16, naive=False)
     assert counts[0] == len(boxes) and counts[3] > 2.5e9
-    runs = _check(w.dims, boxes, 1, 8, naive=False, runs=True)
-    assert runs[0] == counts[0] and runs[1] == counts[1] and runs[3] == counts[3]
-    assert runs[2] < counts[2] / 10   # far fewer segment walks than lane loads
+    for run_min, share in ((0, 0.5), (1, 0.1)):
+        runs = _check(w.dims, boxes, 1, 16, naive=False, runs=True, run_min=run_min)
+        assert runs[0] == counts[0] and runs[1] == counts[1] and runs[3] == counts[3]
+        assert runs[2] < counts[2] * share   # fewer loads and segment walks than lane loads
 
 
 @pytest.mark.parametrize("config", [1, 3, 4, 5])
@@ -71,9 +73,10 @@ def test_full_size_volumes_sampled(config):
     boxes = np.concatenate([synth.make_boxes(w, 800), far, _odd_parity_boxes(w.dims, 200, config)])
     small = np.concatenate([far[:7], _odd_parity_boxes(w.dims, 100, config + 10) % np.uint32(64) + 1])
     small[len(far[:7]):, :3] = _odd_parity_boxes(w.dims, 100, config + 10)[:, :3]
-    for use16, unroll, runs in ((1, 8, False), (0, 16, False), (1, 4, False), (1, 8, True), (0, 4, True)):
-        _check(w.dims, boxes, use16, unroll, naive=False, runs=runs)
-        _check(w.dims, small, use16, unroll, naive=True, runs=runs)
+    for use16, unroll, runs, rm in ((1, 8, False, 0), (0, 16, False, 0), (1, 4, False, 0), (1, 8, True, 0),
+                                    (0, 4, True, 1), (1, 16, True, 16)):
+        _check(w.dims, boxes, use16, unroll, naive=False, runs=runs, run_min=rm)
+        _check(w.dims, small, use16, unroll, naive=True, runs=runs, run_min=rm)
 
 
 def test_widest_rows_and_largest_units():
@@ -81,8 +84,9 @@ def test_widest_rows_and_largest_units():
     dims = (32768, 1024, 2)
     boxes = [[0, 0, 0, 32768, 1024, 2], [1, 3, 0, 32767, 5, 2], [32767, 1023, 1, 1, 1, 1],
              [5, 0, 0, 32000, 1, 1], [0, 1, 1, 32768, 1023, 1]]
-    for use16, unroll, runs in ((1, 8, False), (0, 4, False), (1, 16, False), (1, 8, True)):
-        _check(dims, boxes, use16, unroll, runs=runs)
+    for use16, unroll, runs, rm in ((1, 8, False, 0), (0, 4, False, 0), (1, 16, False, 0), (1, 8, True, 0),
+                                    (1, 4, True, 1)):
+        _check(dims, boxes, use16, unroll, runs=runs, run_min=rm)
 
 
 @pytest.mark.parametrize("dims", [(1, 1, 1), (2, 3, 5), (7, 1, 9), (5, 8, 3), (1, 13, 2)])
@@ -92,7 +96,7 @@ def test_tiny_volumes_every_box(dims):
     boxes = [[x0, y0, z0, dx, dy, dz] for x0, dx in rng[0] for y0, dy in rng[1] for z0, dz in rng[2]]
     boxes += [[X, 0, 0, 1, 1, 1], [0, 0, 0, 0, 1, 1], [0, 0, 0, 0xFFFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF]]
     for use16, runs in ((0, False), (1, False), (1, True)):
-        counts = _check(dims, boxes, use16, 4, runs=runs)
+        counts = _check(dims, boxes, use16, 4, runs=runs, run_min=1)
         assert counts[0] == len(boxes) - 2     # the two empty boxes are skipped
 
 
@@ -105,3 +109,4 @@ def test_rejects_bad_arguments():
     assert lib.mg_check_load_addresses(0, 8, 8, 1, p, 1, 8, counts) == -1
     assert lib.mg_check_load_addresses(8, 8, 8, 1, p, 1, 8, None) == -1
     assert lib.mg_check_load_addresses(8, 8, 8, 8, p, 1, 8, counts) == -1
+    assert lib.mg_check_load_addresses(8, 8, 8, 0x80, p, 1, 8, counts) == -1
