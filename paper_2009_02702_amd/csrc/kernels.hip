@@ -180,7 +180,9 @@ __host__ __device__ inline void put_slab(Slab *out, int *n, const LevelTable &lt
     }
     s.axes = uint8_t(f | (m << 2) | (w << 4));
     s.e0 = ef, s.e1 = em, s.e2 = ew;
-    if (ef >= lt.run_min && ((lt.runs_mask >> (2 * lev + f)) & 1u)) {  // rows from the runs
+    // rows from the runs (while the slab's (row, segment) items fit 32 bits)
+    if (ef >= lt.run_min && ((lt.runs_mask >> (2 * lev + f)) & 1u) &&
+        uint64_t(em) * ew * ((ef + kRunSeg - 1) / kRunSeg) < (1ull << 30)) {
         s.kind = 2, s.odd = 0, s.base = 0, s.s1b = s.s2b = 0, s.units = ef;
         out[(*n)++] = s;
         return;
