@@ -90,10 +90,11 @@ def measure_tf(g, w, T, steps, warmup):
     achieved = alg / (kern_ms * 1e-3) / 1e9
     traffic = read_traffic("tf_step_kernel", w.name, alg)
     return {"frames_per_s": steps / el, "ms_per_frame": 1e3 * el / steps, "tfs_per_frame": T,
-            "nodes": N, "depth": D, "steps_launched": D,
+            "nodes": N, "depth": D, "order": "ranks" if g.launch_config()["tf_schedule"] == 0 else "deferred steps",
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                         "kernel": "tf_sources_kernel + tf_step_kernel x steps (one frame, timed together)",
+                         "kernel": "tf_step_kernel per rank (the first also writes the sources' colours) and "
+                                   "tf_tail_kernel for the small last ranks (one frame, timed together)",
                          "kernel_ms": kern_ms, "alg_bytes_per_launch": alg,
                          "alg_bytes_formula": "internal nodes x (12 + 32 T) + sources x 4 T"}}
 

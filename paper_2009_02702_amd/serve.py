@@ -21,7 +21,8 @@ one full slot does not fit, the batch size) is reduced until the slots fit the
 budget, so a small budget makes requests wait longer instead of failing.
 
 Admission is also size-aware: the host counts each box's footprint cubes in
-closed form, and a box of at least `split_cubes` cubes is cut into sub-boxes
+closed form, and a box of at least `split_cubes` cubes is cut into up to
+`max_pieces` sub-boxes of about `piece_cubes` cubes
 along its longest axis at aligned positions (multiples of a power of two, so
 few cubes are cut) that are answered as separate rows of the same batch, in
 parallel on different workgroups. Histograms of disjoint parts add up, so the
@@ -246,13 +247,13 @@ class Server:
     def __init__(self, g: Graph, slots: int = 4, max_batch: int = 4096, max_tf: int = 64,
                  budget_bytes: Optional[int] = None, use_graphs: bool = True,
                  classes=(64, 256, 1024, 4096, 16384), split_cubes: int = 1 << 18,
-                 piece_cubes: int = 1 << 16):
+                 piece_cubes: int = 1 << 15, max_pieces: int = 128):
         torch = _torch()
         self.g = g
         inf = g.info()
         S, N = inf["nseg"], inf["n_nodes"]
         self.dims = inf["dims"][0]
-        self.split_cubes, self.piece_cubes = split_cubes, piece_cubes
+        self.split_cubes, self.piece_cubes, self.max_pieces = split_cubes, piece_cubes, max_pieces
 
         def slot_bytes(b, t):
             return g.workspace_bytes(b) + b * (24 + 4 * S) + t * (4 * S + 16 * N)
@@ -343,7 +344,7 @@ class Server:
         cubes = cube_counts(boxes, self.dims)
         rows = {}
         for i in np.nonzero(cubes >= self.split_cubes)[0]:
-            sub = split_box(boxes[i], self.dims, int(min(64, -(-cubes[i] // self.piece_cubes))))
+            sub = split_box(boxes[i], self.dims, int(min(self.max_pieces, -(-cubes[i] // self.piece_cubes))))
             if len(sub) > 1 and len(sub) <= self.max_batch:
                 rows[int(i)] = sub
         pending = deque()
