@@ -64,6 +64,7 @@ constexpr uint32_t kQueues = 8;                // work queues per tier
 constexpr uint32_t kQueueStride = 64;          // u32 between queue counters (256 bytes)
 constexpr int kUnroll = 4;                     // node-ID loads in flight per lane (plain, fallback)
 constexpr uint32_t kMaxSteps = 64;              // graph depth the step table holds
+constexpr uint32_t kDeferSlots = 128;           // per-wave ring of deferred internal-node runs (dense state)
 
 #define HIP_TRY(expr)                                                                  \
     do {                                                                               \
@@ -844,6 +845,27 @@ __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const char 
     const uint32_t nseg = gv.nseg;
     const uint64_t above = lane_above_mask();
     const uint32_t lane = threadIdx.x & 63;
+    // Runs on internal nodes met while streaming the 32-bit levels (dense state) are
+    // deferred to a per-wave ring in LDS, (node, run length | level << 7), and resolved
+    // 64 at a time, one per lane: resolving one loads the node's (a, b, w) triple (and,
+    // at rank 2, its predecessors'), so the load chains of 64 runs are in flight together
+    // instead of one chain in nearly every wave step. At most 63 entries wait after a
+    // step; the ring holds those plus the 64 a step can add.
+    constexpr uint32_t kRing = SPARSE ? 1u : kDeferSlots;
+    __shared__ uint32_t dq_node[kWaves * kRing];
+    __shared__ uint16_t dq_code[kWaves * kRing];
+    const uint32_t wbase = uni(threadIdx.x >> 6) * kRing;  // this wave's ring
+    uint32_t head = 0, tail = 0;  // entries resolved, entries deferred (wave-uniform)
+    auto resolve = [&](uint32_t n) {  // the n <= 64 oldest entries
+        __builtin_amdgcn_wave_barrier();
+        if (lane < n) {
+            const uint32_t k = wbase + ((head + lane) & (kRing - 1));
+            const uint32_t code = dq_code[k];
+            scatter_count<SPARSE>(st, gv, dq_node[k], (code & 127u) << (3u * (code >> 7)));
+        }
+        head += n;
+        __builtin_amdgcn_wave_barrier();
+    };
     for (int si = 0; si < n_slabs; ++si) {
         const Slab &sp = slabs[si];
         if (uni(*flags_lds) & 1u) return;  // overflowed: the box goes to the retry launch
@@ -859,7 +881,7 @@ __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const char 
                                          [&](uint32_t lo, uint32_t hi) { count_pairs(st.seg_cnt, lo, hi, lane); });
             continue;
         }
-        const uint32_t lw8 = 3 * uni(sp.level);
+        const uint32_t lev = uni(sp.level), lw8 = 3 * lev;
         // a run of lanes [a, b] on one source adds (b + 1 - a) 8^l as -a 8^l at its start lane
         // and (b + 1) 8^l at its end lane (uint32 wrap-around; the counts stay below 2^32)
         const uint32_t w_start = 0u - (lane << lw8), w_end = (lane + 1) << lw8;
@@ -881,16 +903,29 @@ __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const char 
                     if (end) atomicAdd(&st.seg_cnt[v], w_end);
                 }
                 // runs on internal nodes: a branch the wave skips unless a lane needs it
+                // (wave masks straight from the vector compares: every lane is active here)
+                const bool isint = v - nseg < kEmpty - nseg;
                 const uint64_t internal = __builtin_amdgcn_uicmp(v - nseg, kEmpty - nseg, 36 /* ult */);
                 if (__builtin_expect(internal != 0, 0)) {
-                    const uint64_t starts = __builtin_amdgcn_uicmp(v, prev, 33 /* ne */) | 1u;
-                    const uint32_t len = run_len(starts, above, lane);
-                    if (start && v >= nseg && v != kEmpty) scatter_count<SPARSE>(st, gv, v, len << lw8);
+                    const uint64_t put = internal & (__builtin_amdgcn_uicmp(v, prev, 33 /* ne */) | 1u);
+                    const uint64_t ends = __builtin_amdgcn_uicmp(v, next, 33 /* ne */) | (1ull << 63);
+                    if (start && isint) {
+                        // the run ends at the first end lane at or above this one
+                        const uint32_t len = uint32_t(__builtin_ctzll(ends >> lane)) + 1u;
+                        const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                            uint32_t(put >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(put), 0u));
+                        const uint32_t k = wbase + ((tail + below) & (kRing - 1));
+                        dq_node[k] = v;
+                        dq_code[k] = uint16_t(len | (lev << 7));
+                    }
+                    tail += uint32_t(__builtin_popcountll(put));
+                    if (tail - head >= 64u) resolve(64u);
                 }
             },
             [&]() { return (uni(*flags_lds) & 1u) != 0; });
         if (!go) return;
     }
+    if (!SPARSE && tail != head) resolve(tail - head);
 }
 
 // Reverse push through the nodes of rank >= 3 in the table, rank by rank from
@@ -2040,6 +2075,15 @@ bool valid_unroll(uint32_t u) { return u == 4 || u == 8 || u == 16; }
 
 // Blocks per CU of a kernel variant (queried once, cached per device); also
 // raises the kernel's dynamic LDS limit.
+// Static LDS of a kernel (its __shared__ variables), as the code object states it.
+int static_lds(const void *k, uint32_t *out, std::string *err)
+{
+    hipFuncAttributes fa{};
+    HIP_TRY(hipFuncGetAttributes(&fa, k));
+    *out = uint32_t(fa.sharedSizeBytes);
+    return MG_OK;
+}
+
 int occupancy(DeviceState &d, const void *k, int block, uint32_t dyn, int *out, std::string *err)
 {
     for (const auto &e : d.occupancy)
@@ -2047,8 +2091,10 @@ int occupancy(DeviceState &d, const void *k, int block, uint32_t dyn, int *out, 
             *out = e.blocks;
             return MG_OK;
         }
-    if (dyn + sizeof(QueryShared) > uint64_t(d.lds_max)) {
-        *err = "kernel state of " + std::to_string(dyn + sizeof(QueryShared)) + " bytes exceeds the " +
+    uint32_t stat = 0;
+    if (int rc = static_lds(k, &stat, err)) return rc;
+    if (uint64_t(dyn) + stat > uint64_t(d.lds_max)) {
+        *err = "kernel state of " + std::to_string(uint64_t(dyn) + stat) + " bytes exceeds the " +
                std::to_string(d.lds_max) + " bytes of LDS per workgroup";
         return MG_ELIMIT;
     }
@@ -2827,9 +2873,11 @@ int launch_query(Graph *g, QueryArgs &A, const Workspace &w, const LevelTable &l
     const QueryKernel kretry = query_retry_kernel<kBlockBig, 8, SPARSE, ERR>;
     uint32_t cap_retry = d.cfg.table_retry;
     if (!cap_retry) {  // the largest table up to kHashRetry that fits the LDS of a workgroup
+        uint32_t stat = 0;
+        if ((rc = static_lds(reinterpret_cast<const void *>(kretry), &stat, err))) return rc;
         cap_retry = kHashRetry;
         while (cap_retry > kHashBigSparse &&
-               lds_bytes(g->nseg, cap_retry, SPARSE, L, E) + sizeof(QueryShared) > uint64_t(d.lds_max))
+               uint64_t(lds_bytes(g->nseg, cap_retry, SPARSE, L, E)) + stat > uint64_t(d.lds_max))
             cap_retry /= 2;
     }
     const uint32_t dyn_retry = lds_bytes(g->nseg, cap_retry, SPARSE, L, E);
