@@ -53,7 +53,6 @@ constexpr uint32_t kSegLdsMax = 2048;         // sources kept in LDS
 constexpr uint32_t kFallbackWorkers = 128;    // workers of the final global-table launch (budget)
 constexpr uint32_t kRunSeg = 256;             // cells of a row one thread sums from the runs
 constexpr int kRunBatch = 4;                   // runs a thread loads at once per segment
-constexpr int kRunItems = 1;                   // segments a thread walks at once
 constexpr uint32_t kRunMinRow = 128;           // rows shorter than this stream cube by cube (default)
 constexpr uint32_t kTfPlanes = 4;             // transfer functions per thread of a propagation step
 constexpr uint32_t kTfTailPairs = 4096;        // steps of at most this many node x TF pairs may share a launch
@@ -735,7 +734,7 @@ __device__ inline void count_pairs(uint32_t *cnt, uint32_t lo, uint32_t hi, uint
 
 // Kind-2 slab: every row segment is summed from its row's runs. The block's
 // threads take (row, segment) items, a segment being at most kRunSeg cells of
-// one row, kRunItems at a time: the skip entry of its 64-cell chunk gives the
+// one row, one at a time: the skip entry of its 64-cell chunk gives the
 // run holding the chunk's first cell (runs before the segment end at or before
 // its first cell and add nothing); runs are loaded kRunBatch at a time, and
 // each adds (cells of it inside the segment) x 8^level to its node. A row's
@@ -776,54 +775,129 @@ __host__ __device__ inline bool run_item(const Slab &sp, const LevelTable &lt, u
     return *p0 < *p1;
 }
 
+// Runs of cubes on internal nodes (dense state), deferred per wave: entries (node,
+// run length | level << 9) in a ring in LDS, resolved 64 at a time, one per lane.
+// Resolving one loads the node's (a, b, w) triple (and, at rank 2, its
+// predecessors'), so the load chains of 64 runs are in flight together instead
+// of one chain in nearly every step of a slab walk. At most 63 entries wait
+// after an append; the ring holds those plus the 64 one append can add.
+struct DeferRing {
+    uint32_t *node;  // [waves][kDeferSlots]
+    uint16_t *code;  // [waves][kDeferSlots]
+    uint32_t wbase;  // this wave's ring (wave-uniform, as head and tail)
+    uint32_t head;   // entries resolved
+    uint32_t tail;   // entries appended
+};
+
+// A run of `len` cubes of level `lev` on internal node `node` (dense state). A
+// rank-1 node on a cube is the cube's own two-source mixture, so its weight is
+// (voxels of b in the cube) / 8^lev: when w 8^lev is an integer k (levels <= 7,
+// where it is exact in fp32), the run's voxels split exactly into len (8^lev - k)
+// of a and len k of b, which go to the integer counters. Otherwise (a weight
+// that is not such a fraction, as in a quantized graph) the mass is pushed.
+template <bool SPARSE>
+__device__ inline void resolve_count(const QueryState &st, const GraphView &gv, uint32_t node, uint32_t len,
+                                     uint32_t lev)
+{
+    if (!SPARSE && node < gv.r1_end && lev <= 7u) {
+        const NodeTriple t = gv.nodes[node];
+        const uint32_t cube = 1u << (3u * lev);
+        const float kf = t.w * float(cube);  // exact: a power-of-two scale
+        const uint32_t k = uint32_t(kf);
+        if (float(k) == kf && k <= cube) {
+            atomicAdd(&st.seg_cnt[t.a], len * (cube - k));
+            atomicAdd(&st.seg_cnt[t.b], len * k);
+            return;
+        }
+        const uint32_t c = len << (3u * lev);
+        push_pair<SPARSE>(st, t, float(c & 0xFFFFFF00u), float(c & 0xFFu));
+        return;
+    }
+    scatter_count<SPARSE>(st, gv, node, len << (3u * lev));
+}
+
+// Resolves the n <= 64 oldest entries. Every lane of the wave must call.
+template <bool SPARSE>
+__device__ inline void ring_resolve(DeferRing &q, const QueryState &st, const GraphView &gv, uint32_t n)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    __builtin_amdgcn_wave_barrier();
+    if (lane < n) {
+        const uint32_t k = q.wbase + ((q.head + lane) & (kDeferSlots - 1));
+        const uint32_t code = q.code[k];
+        resolve_count<SPARSE>(st, gv, q.node[k], code & 511u, code >> 9);
+    }
+    q.head += n;
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Appends a run of `len` (<= 256) cubes of level `lev` on `node` from each lane
+// with `want`; resolves 64 entries once 64 wait. Every lane of the wave must call.
+template <bool SPARSE>
+__device__ inline void ring_put(DeferRing &q, const QueryState &st, const GraphView &gv, bool want, uint32_t node,
+                                uint32_t len, uint32_t lev)
+{
+    const uint64_t put = __builtin_amdgcn_ballot_w64(want);
+    if (put == 0) return;
+    if (want) {
+        const uint32_t below =
+            __builtin_amdgcn_mbcnt_hi(uint32_t(put >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(put), 0u));
+        const uint32_t k = q.wbase + ((q.tail + below) & (kDeferSlots - 1));
+        q.node[k] = node;
+        q.code[k] = uint16_t(len | (lev << 9));
+    }
+    q.tail += uint32_t(__builtin_popcountll(put));
+    if (q.tail - q.head >= 64u) ring_resolve<SPARSE>(q, st, gv, 64u);
+}
+
+// A kind-2 slab: each lane sums one (row, segment) item from the row runs; the
+// loops are wave-uniform (lanes whose segment is done idle), so that internal-node
+// runs can go to the wave's ring in dense mode.
 template <int BLOCK, bool SPARSE>
 __device__ inline void scatter_runs(const Slab &sp, const RunLevel &rl, const LevelTable &lt, const QueryState &st,
-                                    const GraphView &gv)
+                                    const GraphView &gv, DeferRing &dq)
 {
-    const uint32_t f = uni(sp.axes) & 3u, lw8 = 3 * uni(sp.level);
+    const uint32_t f = uni(sp.axes) & 3u, lev = uni(sp.level), lw8 = 3 * lev;
     const uint32_t lseg = run_lseg(uni(sp.e0));
     const uint32_t items = (uni(sp.e1) * uni(sp.e2)) << lseg;
     const uint32_t top = rl.n_runs - 1;
-    // runs v[0 .. kRunBatch) from j: each adds its cells in [pos, p1)
+    const uint32_t lane = threadIdx.x & 63;
+    // runs v[0 .. kRunBatch): each adds its cells in [pos, p1)
     auto consume = [&](const uint64_t *v, uint32_t &pos, uint32_t p1) {
 #pragma unroll
         for (int q = 0; q < kRunBatch; ++q) {
-            const uint32_t end = uint32_t(v[q] >> 32);
-            if (pos < p1 && end > pos) {
-                const uint32_t hi = min(end, p1);
-                scatter_count<SPARSE>(st, gv, uint32_t(v[q]), (hi - pos) << lw8);
-                pos = hi;
+            const uint32_t end = uint32_t(v[q] >> 32), node = uint32_t(v[q]);
+            const bool act = pos < p1 && end > pos;
+            const uint32_t hi = min(end, p1);
+            if (SPARSE) {
+                if (act) scatter_count<SPARSE>(st, gv, node, (hi - pos) << lw8);
+            } else {
+                if (act && node < gv.nseg) atomicAdd(&st.seg_cnt[node], (hi - pos) << lw8);
+                ring_put<SPARSE>(dq, st, gv, act && node >= gv.nseg, node, hi - pos, lev);
             }
+            if (act) pos = hi;
         }
     };
-    for (uint32_t base = threadIdx.x; base < items; base += BLOCK * kRunItems) {
-        uint32_t p0[kRunItems], p1[kRunItems], j[kRunItems];
+    for (uint32_t b0 = uni(threadIdx.x - lane); b0 < items; b0 += BLOCK) {
+        const uint32_t it = b0 + lane;
+        uint32_t r, p0 = 0, p1 = 0, j = 0;
+        if (!(it < items && run_item(sp, lt, f, lseg, it, &r, &p0, &p1))) p0 = p1 = 0;
+        uint64_t v[kRunBatch] = {};
+        if (p0 < p1) {
+            j = load_global(rl.skip + uint64_t(r) * rl.chunks + p0 / kRunSkipCells);
 #pragma unroll
-        for (int k = 0; k < kRunItems; ++k) {
-            uint32_t r;
-            const uint32_t it = base + uint32_t(k) * BLOCK;
-            if (it < items && run_item(sp, lt, f, lseg, it, &r, &p0[k], &p1[k])) {
-                j[k] = load_global(rl.skip + uint64_t(r) * rl.chunks + p0[k] / kRunSkipCells);
-            } else {
-                p0[k] = p1[k] = 0, j[k] = 0;
-            }
+            for (int q = 0; q < kRunBatch; ++q) v[q] = load_global(rl.runs + min(j + q, top));
         }
-        uint64_t v[kRunItems][kRunBatch];
+        uint32_t pos = p0;
+        consume(v, pos, p1);
+        while (__builtin_amdgcn_ballot_w64(pos < p1) != 0) {  // segments that cross more runs
+            uint64_t w[kRunBatch] = {};
+            if (pos < p1) {
+                j += kRunBatch;
 #pragma unroll
-        for (int k = 0; k < kRunItems; ++k)
-#pragma unroll
-            for (int q = 0; q < kRunBatch; ++q) v[k][q] = load_global(rl.runs + min(j[k] + q, top));
-#pragma unroll
-        for (int k = 0; k < kRunItems; ++k) {
-            uint32_t pos = p0[k];
-            consume(v[k], pos, p1[k]);
-            while (pos < p1[k]) {  // segments that cross more runs
-                j[k] += kRunBatch;
-                uint64_t w[kRunBatch];
-#pragma unroll
-                for (int q = 0; q < kRunBatch; ++q) w[q] = load_global(rl.runs + min(j[k] + q, top));
-                consume(w, pos, p1[k]);
+                for (int q = 0; q < kRunBatch; ++q) w[q] = load_global(rl.runs + min(j + q, top));
             }
+            consume(w, pos, p1);
         }
     }
 }
@@ -851,26 +925,14 @@ __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const char 
     // at rank 2, its predecessors'), so the load chains of 64 runs are in flight together
     // instead of one chain in nearly every wave step. At most 63 entries wait after a
     // step; the ring holds those plus the 64 a step can add.
-    constexpr uint32_t kRing = SPARSE ? 1u : kDeferSlots;
-    __shared__ uint32_t dq_node[kWaves * kRing];
-    __shared__ uint16_t dq_code[kWaves * kRing];
-    const uint32_t wbase = uni(threadIdx.x >> 6) * kRing;  // this wave's ring
-    uint32_t head = 0, tail = 0;  // entries resolved, entries deferred (wave-uniform)
-    auto resolve = [&](uint32_t n) {  // the n <= 64 oldest entries
-        __builtin_amdgcn_wave_barrier();
-        if (lane < n) {
-            const uint32_t k = wbase + ((head + lane) & (kRing - 1));
-            const uint32_t code = dq_code[k];
-            scatter_count<SPARSE>(st, gv, dq_node[k], (code & 127u) << (3u * (code >> 7)));
-        }
-        head += n;
-        __builtin_amdgcn_wave_barrier();
-    };
+    __shared__ uint32_t dq_node[kWaves * (SPARSE ? 1u : kDeferSlots)];
+    __shared__ uint16_t dq_code[kWaves * (SPARSE ? 1u : kDeferSlots)];
+    DeferRing dq{dq_node, dq_code, uni(threadIdx.x >> 6) * kDeferSlots, 0u, 0u};
     for (int si = 0; si < n_slabs; ++si) {
         const Slab &sp = slabs[si];
         if (uni(*flags_lds) & 1u) return;  // overflowed: the box goes to the retry launch
         if (uni(sp.kind) == 2) {
-            scatter_runs<BLOCK, SPARSE>(sp, runs[2 * uni(sp.level) + (uni(sp.axes) & 3u)], lt, st, gv);
+            scatter_runs<BLOCK, SPARSE>(sp, runs[2 * uni(sp.level) + (uni(sp.axes) & 3u)], lt, st, gv, dq);
             continue;
         }
         const uint64_t base = (uint64_t(uni(uint32_t(sp.base >> 32))) << 32) | uni(uint32_t(sp.base));
@@ -914,18 +976,18 @@ __device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const char 
                         const uint32_t len = uint32_t(__builtin_ctzll(ends >> lane)) + 1u;
                         const uint32_t below = __builtin_amdgcn_mbcnt_hi(
                             uint32_t(put >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(put), 0u));
-                        const uint32_t k = wbase + ((tail + below) & (kRing - 1));
+                        const uint32_t k = dq.wbase + ((dq.tail + below) & (kDeferSlots - 1));
                         dq_node[k] = v;
-                        dq_code[k] = uint16_t(len | (lev << 7));
+                        dq_code[k] = uint16_t(len | (lev << 9));
                     }
-                    tail += uint32_t(__builtin_popcountll(put));
-                    if (tail - head >= 64u) resolve(64u);
+                    dq.tail += uint32_t(__builtin_popcountll(put));
+                    if (dq.tail - dq.head >= 64u) ring_resolve<SPARSE>(dq, st, gv, 64u);
                 }
             },
             [&]() { return (uni(*flags_lds) & 1u) != 0; });
         if (!go) return;
     }
-    if (!SPARSE && tail != head) resolve(tail - head);
+    if (!SPARSE && dq.tail != dq.head) ring_resolve<SPARSE>(dq, st, gv, dq.tail - dq.head);
 }
 
 // Reverse push through the nodes of rank >= 3 in the table, rank by rank from
