@@ -93,6 +93,46 @@ def test_builder_lossless_voronoi_and_cylinders():
     _invariants(g, d)
 
 
+@pytest.mark.parametrize("config,dims,segments", [(2, (40, 36, 34), 30), (3, (64, 48, 16), 12),
+                                                  (4, (33, 40, 36), 25)])
+def test_rank1_nodes_on_full_cubes_split_into_whole_voxels(config, dims, segments):
+    """The query kernels split a run of cubes on a rank-1 node into integer source counts when
+    the node's fp32 weight times 8^level is a whole number k. For the exact graph that holds on
+    every full cube (levels <= 7) whose node has rank 1, with k the cube's voxels of child b:
+    the node is the cube's own two-source mixture."""
+    vol = synth.make_volume(synth.workload(config, dims=dims, segments=segments))
+    g = Graph.build(vol)
+    inf = g.info()
+    S = inf["nseg"]
+    d = g.export_dag()
+    r1_end = int(d["rank_ptr"][2])
+    _, vol_c = scan.compact(vol)
+    X, Y, Z = dims
+    seen = 0
+    for l in range(1, min(inf["n_levels"], 8)):
+        m = g.export_map(l)
+        c = mipmap.counts_level(vol_c, S, l)
+        cube = 8 ** l
+        for z in range(Z >> l):
+            for y in range(Y >> l):
+                for x in range(X >> l):
+                    v = int(m[z, y, x])
+                    if not S <= v < r1_end:
+                        continue
+                    k = np.float32(d["alpha"][v]) * np.float32(cube)
+                    assert float(k) == int(k), (l, (x, y, z), v)
+                    a, b = int(d["child_a"][v]), int(d["child_b"][v])
+                    assert int(c[z, y, x][b]) == int(k) and int(c[z, y, x][a]) == cube - int(k)
+                    seen += 1
+    assert seen > 0
+    # a quantized graph's weights are not such fractions in general: the kernels push those
+    q = g.quantize(5)
+    qa = q.export_dag()["alpha"]
+    m1 = g.export_map(1)
+    on1 = [int(v) for v in np.unique(m1) if S <= v < r1_end]
+    assert any(float(np.float32(qa[v]) * 8) != int(np.float32(qa[v]) * 8) for v in on1)
+
+
 def test_builder_sparse_ids_and_uint16():
     vol = np.array([[[4000000000, 7, 7, 123456789], [7, 7, 5, 5]]], dtype=np.uint32)
     g, d = _exact_check(vol)
