@@ -850,9 +850,10 @@ __device__ inline void ring_put(DeferRing &q, const QueryState &st, const GraphV
     if (q.tail - q.head >= 64u) ring_resolve<SPARSE>(q, st, gv, 64u);
 }
 
-// A kind-2 slab: each lane sums one (row, segment) item from the row runs; the
-// loops are wave-uniform (lanes whose segment is done idle), so that internal-node
-// runs can go to the wave's ring in dense mode.
+// A kind-2 slab: each lane sums one (row, segment) item from the row runs. In
+// dense mode the loops are wave-uniform (lanes whose segment is done idle), so
+// that internal-node runs can go to the wave's ring; in sparse mode each lane
+// walks its items on its own.
 template <int BLOCK, bool SPARSE>
 __device__ inline void scatter_runs(const Slab &sp, const RunLevel &rl, const LevelTable &lt, const QueryState &st,
                                     const GraphView &gv, DeferRing &dq)
@@ -878,6 +879,26 @@ __device__ inline void scatter_runs(const Slab &sp, const RunLevel &rl, const Le
             if (act) pos = hi;
         }
     };
+    if constexpr (SPARSE) {  // no ring: each lane walks its own items
+        for (uint32_t it = threadIdx.x; it < items; it += BLOCK) {
+            uint32_t r, p0, p1;
+            if (!run_item(sp, lt, f, lseg, it, &r, &p0, &p1)) continue;
+            uint32_t j = load_global(rl.skip + uint64_t(r) * rl.chunks + p0 / kRunSkipCells);
+            uint64_t v[kRunBatch];
+#pragma unroll
+            for (int q = 0; q < kRunBatch; ++q) v[q] = load_global(rl.runs + min(j + q, top));
+            uint32_t pos = p0;
+            consume(v, pos, p1);
+            while (pos < p1) {  // segments that cross more runs
+                j += kRunBatch;
+                uint64_t w[kRunBatch];
+#pragma unroll
+                for (int q = 0; q < kRunBatch; ++q) w[q] = load_global(rl.runs + min(j + q, top));
+                consume(w, pos, p1);
+            }
+        }
+        return;
+    }
     for (uint32_t b0 = uni(threadIdx.x - lane); b0 < items; b0 += BLOCK) {
         const uint32_t it = b0 + lane;
         uint32_t r, p0 = 0, p1 = 0, j = 0;
@@ -1229,9 +1250,11 @@ __device__ inline void write_failure(const QueryArgs &A, uint32_t q)
 
 // One query, by the whole block. `st` must be clean (keys empty, values 0).
 // ERR: lookup-table expansion that also accumulates uncertainties (dense output).
+// (always inlined: each query kernel is one function, whatever the inliner's size limit)
 template <int BLOCK, int UNROLL, bool SPARSE, bool ERR>
-__device__ inline void run_query(const QueryArgs &A, QueryShared &sh, const QueryState &st, uint32_t q,
-                                 bool report_overflow)
+__device__ __attribute__((always_inline)) inline void run_query(const QueryArgs &A, QueryShared &sh,
+                                                                const QueryState &st, uint32_t q,
+                                                                bool report_overflow)
 {
     uint32_t lo[3], hi[3];
     const bool nonempty = clip_box(A.boxes + 6 * uint64_t(q), A.lt, lo, hi);
