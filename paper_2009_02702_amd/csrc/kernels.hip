@@ -1831,17 +1831,23 @@ __global__ __launch_bounds__(kTfTailBlock) void tf_tail_kernel(const NodeTriple 
 
 // Mean colour of a box under one propagated palette: every footprint cube adds
 // its 8^l voxels times the palette entry of its node, divided by the box
-// volume. One workgroup per box; sums in fp64. Boxes whose palette index is
-// kEmpty get zeros.
-__global__ __launch_bounds__(kBlock) void box_colour_kernel(LevelTable lt, const uint32_t *boxes, uint32_t n,
-                                                            const uint32_t *__restrict__ maps,
-                                                            const float4 *__restrict__ palette, uint32_t T,
-                                                            uint32_t n_nodes, const uint32_t *pal_of_box,
-                                                            float4 *out)
+// volume. One workgroup of kColourBlock threads per box; sums in fp64. Boxes
+// whose palette index is kEmpty get zeros. The level table carries no 16-bit
+// copy and no row runs, so every slab is read as 32-bit node IDs. A thread
+// walks its cubes of a slab kColourBlock apart, its (fast, mid, slow) offsets
+// advanced by carries rather than divided out, kColourUnroll node IDs and then
+// their palette entries in flight at a time.
+constexpr int kColourBlock = 1024;
+constexpr int kColourUnroll = 8;
+__global__ __launch_bounds__(kColourBlock) void box_colour_kernel(LevelTable lt, const uint32_t *boxes, uint32_t n,
+                                                                  const uint32_t *__restrict__ maps,
+                                                                  const float4 *__restrict__ palette, uint32_t T,
+                                                                  uint32_t n_nodes, const uint32_t *pal_of_box,
+                                                                  float4 *out)
 {
     __shared__ Slab slabs[kMaxSlabs];
     __shared__ int n_slabs;
-    __shared__ double part[kBlock / 64][4];
+    __shared__ double part[kColourBlock / 64][4];
     const uint32_t q = blockIdx.x;
     const uint32_t t = pal_of_box[q];
     uint32_t lo[3], hi[3];
@@ -1856,11 +1862,35 @@ __global__ __launch_bounds__(kBlock) void box_colour_kernel(LevelTable lt, const
         const Slab sl = slabs[si];
         const double w = double(uint64_t(1) << (3 * sl.level));
         const uint32_t c = slab_count(sl);
-        for (uint32_t r = threadIdx.x; r < c; r += kBlock) {
-            const uint32_t i0 = r % sl.e0, i1 = (r / sl.e0) % sl.e1, i2 = r / (sl.e0 * sl.e1);
-            const uint32_t node = maps[sl.base / 4 + i0 + uint64_t(i1) * (sl.s1b / 4) + uint64_t(i2) * (sl.s2b / 4)];
-            const float4 v = pal[node];
-            acc[0] += w * v.x, acc[1] += w * v.y, acc[2] += w * v.z, acc[3] += w * v.w;
+        if (threadIdx.x >= c) continue;
+        // this thread's first cube, and the step of kColourBlock cubes, as (fast, mid, slow) offsets
+        const uint32_t e01 = sl.e0 * sl.e1;
+        uint32_t i0 = threadIdx.x % sl.e0, i1 = (threadIdx.x / sl.e0) % sl.e1, i2 = threadIdx.x / e01;
+        const uint32_t d0 = uint32_t(kColourBlock) % sl.e0, d1 = (uint32_t(kColourBlock) / sl.e0) % sl.e1,
+                       d2 = uint32_t(kColourBlock) / e01;
+        const uint32_t *slab = maps + sl.base / 4;
+        const uint64_t s1 = sl.s1b / 4, s2 = sl.s2b / 4;
+        for (uint32_t r = threadIdx.x; r < c; r += kColourBlock * kColourUnroll) {
+            uint32_t node[kColourUnroll];
+#pragma unroll
+            for (int u = 0; u < kColourUnroll; ++u) {
+                // cube r + u kColourBlock, if inside the slab
+                node[u] = r + uint32_t(u) * kColourBlock < c ? slab[i0 + i1 * s1 + i2 * s2] : kEmpty;
+                i0 += d0;
+                const uint32_t c0 = i0 >= sl.e0 ? 1u : 0u;
+                i0 -= c0 ? sl.e0 : 0u;
+                i1 += d1 + c0;
+                const uint32_t c1 = i1 >= sl.e1 ? 1u : 0u;
+                i1 -= c1 ? sl.e1 : 0u;
+                i2 += d2 + c1;
+            }
+            float4 v[kColourUnroll];
+#pragma unroll
+            for (int u = 0; u < kColourUnroll; ++u)
+                v[u] = node[u] != kEmpty ? pal[node[u]] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int u = 0; u < kColourUnroll; ++u)
+                acc[0] += w * v[u].x, acc[1] += w * v[u].y, acc[2] += w * v[u].z, acc[3] += w * v[u].w;
         }
     }
     for (int k = 0; k < 4; ++k)
@@ -1870,7 +1900,7 @@ __global__ __launch_bounds__(kBlock) void box_colour_kernel(LevelTable lt, const
     __syncthreads();
     if (threadIdx.x == 0) {
         double s[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int wv = 0; wv < kBlock / 64; ++wv)
+        for (int wv = 0; wv < kColourBlock / 64; ++wv)
             for (int k = 0; k < 4; ++k) s[k] += part[wv][k];
         const double vol = nonempty ? double(hi[0] - lo[0]) * double(hi[1] - lo[1]) * double(hi[2] - lo[2]) : 1.0;
         out[q] = nonempty ? make_float4(float(s[0] / vol), float(s[1] / vol), float(s[2] / vol), float(s[3] / vol))
@@ -2830,7 +2860,7 @@ int dev_box_colour(Graph *g, const float *palette, uint32_t T, const uint32_t *b
         return MG_ELIMIT;
     }
     const LevelTable lt = level_table(*g);
-    hipLaunchKernelGGL(box_colour_kernel, dim3(n), dim3(kBlock), 0, static_cast<hipStream_t>(stream), lt, boxes, n,
+    hipLaunchKernelGGL(box_colour_kernel, dim3(n), dim3(kColourBlock), 0, static_cast<hipStream_t>(stream), lt, boxes, n,
                        g->dev.maps, reinterpret_cast<const float4 *>(palette), T, g->n_nodes, pal_of_box,
                        reinterpret_cast<float4 *>(out));
     HIP_TRY(hipGetLastError());

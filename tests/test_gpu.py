@@ -366,6 +366,37 @@ def test_adjoint_box_colour():
     assert np.abs(lhs - rhs).max() < 1e-5
 
 
+@pytest.mark.parametrize("dims", [(70, 64, 50), (200, 180, 60)])
+def test_box_colour_kernel_is_the_cube_sum(dims):
+    """mg_box_colour against the mean colour summed over the footprint cubes on the host (slabs
+    of up to 36,000 cubes: several strides of the kernel's 1,024 threads x 8 cubes); rows without
+    a palette get zeros."""
+    w = synth.workload(5, dims=dims, segments=60, n_boxes=400)
+    vol = synth.make_volume(w)
+    g = _graph(("colour", dims), vol)
+    S = g.info()["nseg"]
+    tf = synth.make_tfs(w, S, 2)
+    boxes = synth.make_boxes(w)
+    X, Y, Z = dims
+    boxes[:3] = [[0, 0, 0, X, Y, Z], [1, 1, 1, X - 2, Y - 2, Z - 2], [0, 0, 3, X, Y, 1]]
+    db = _dev(boxes)
+    pal = g.propagate_tf(torch.from_numpy(tf).cuda())
+    pal_np = pal.cpu().numpy().astype(np.float64)
+    which = (np.arange(len(boxes)) % 3).astype(np.int32)
+    which[which == 2] = -1
+    col = g.box_colour(pal, db, torch.from_numpy(which).cuda()).cpu().numpy().astype(np.float64)
+    _, cubes = g.footprint(db, cubes_cap=40_000_000)
+    cubes = cubes.cpu().numpy().astype(np.int64)
+    acc = np.zeros((len(boxes), 4))
+    t = which[cubes[:, 0]]
+    keep = t >= 0
+    np.add.at(acc, cubes[keep, 0], (8.0 ** cubes[keep, 1])[:, None] * pal_np[t[keep], cubes[keep, 5]])
+    vols = np.prod(np.minimum(boxes[:, :3].astype(np.int64) + boxes[:, 3:], dims) - boxes[:, :3], axis=1)
+    want = acc / vols[:, None]
+    assert np.abs(col - want).max() < 1e-6
+    assert (col[which < 0] == 0).all()
+
+
 # ------------------------------------------------------------------ launch configurations (autotuner)
 
 @pytest.mark.parametrize("ub,us,un,bs,bb", [(4, 16, 4, 256, 512), (16, 4, 16, 128, 256), (8, 8, 8, 128, 512),
