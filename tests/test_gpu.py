@@ -172,6 +172,31 @@ def test_query_from_row_runs_every_row_length(config, dims, segments, n):
         g.set_launch_config(run_min_row=0, table_big=0, table_small=0, table_retry=0)
 
 
+@pytest.mark.parametrize("nseg,dims", [(3, (96, 80, 64)), (7, (130, 70, 40))])
+def test_query_on_noise_fills_the_deferred_run_rings(nseg, dims):
+    """Uniform noise over a few segments: nearly every cube above level 0 is an internal node,
+    so each wave step appends up to 64 deferred runs (the ring's fullest case) and rank-1 nodes
+    carry every whole-voxel weight of their level; rank 2 and higher appear too. The batched,
+    plain and lookup-table queries all give the oracle's histograms (noise keeps no row runs:
+    its runs are too short, so every slab streams)."""
+    vol = np.random.default_rng(nseg).integers(0, nseg, size=dims[::-1]).astype(np.uint32)
+    g = _graph(("noise", nseg, dims), vol)
+    _lut(g)
+    X, Y, Z = dims
+    rng = np.random.default_rng(1)
+    lo = rng.integers(0, [X, Y, Z], size=(400, 3))
+    ext = np.maximum(1, (rng.random((400, 3)) * ([X, Y, Z] - lo)).astype(np.int64))
+    boxes = np.concatenate([lo, ext], axis=1).astype(np.uint32)
+    boxes[:3] = [[0, 0, 0, X, Y, Z], [1, 3, 2, X - 1, Y - 3, Z - 2], [2, 0, 0, X - 2, Y, Z]]
+    ids, vol_c = scan.compact(vol)
+    _, ref = scan.box_counts(vol_c, len(ids), boxes)
+    db = _dev(boxes)
+    l0 = _level0_only(g, db)
+    assert g.info()["runs_mask"] == 0
+    for v in ("batched", "plain", "lut"):
+        _compare(g.query(db, variant=v).cpu().numpy(), ref, l0, "noise %s" % v)
+
+
 def test_query_edge_cases():
     vol = synth.make_volume(synth.workload(2, dims=(33, 35, 31), segments=25))
     nx, ny, nz = 33, 35, 31
