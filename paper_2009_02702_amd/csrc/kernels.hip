@@ -404,10 +404,15 @@ __device__ inline void push_rank2(const QueryState &st, const GraphView &gv, con
     float ah, al, bh, bl;
     scale_pair(1.0f - t.w, h, l, &ah, &al);
     scale_pair(t.w, h, l, &bh, &bl);
-    if (t.a < gv.nseg) add_source_mass<SPARSE>(st, t.a, ah, al);
-    else push_pair<SPARSE>(st, gv.nodes[t.a], ah, al);
-    if (t.b < gv.nseg) add_source_mass<SPARSE>(st, t.b, bh, bl);
-    else push_pair<SPARSE>(st, gv.nodes[t.b], bh, bl);
+    // both predecessors' triples in flight before the first addition
+    const bool na = t.a >= gv.nseg, nb = t.b >= gv.nseg;
+    NodeTriple ta = {0u, 0u, 0.0f}, tb = {0u, 0u, 0.0f};
+    if (na) ta = gv.nodes[t.a];
+    if (nb) tb = gv.nodes[t.b];
+    if (na) push_pair<SPARSE>(st, ta, ah, al);
+    else add_source_mass<SPARSE>(st, t.a, ah, al);
+    if (nb) push_pair<SPARSE>(st, tb, bh, bl);
+    else add_source_mass<SPARSE>(st, t.b, bh, bl);
 }
 
 // Mass pushed into `node` during the reverse push. Nodes of rank <= 2 go straight
@@ -799,17 +804,22 @@ template <bool SPARSE>
 __device__ inline void resolve_count(const QueryState &st, const GraphView &gv, uint32_t node, uint32_t len,
                                      uint32_t lev)
 {
-    if (!SPARSE && node < gv.r1_end && lev <= 7u) {
+    if (!SPARSE && node < gv.r2_end) {
+        // ranks 1 and 2: one triple load for the lanes of both
         const NodeTriple t = gv.nodes[node];
+        const uint32_t c = len << (3u * lev);
+        if (node >= gv.r1_end) {
+            push_rank2<SPARSE>(st, gv, t, float(c & 0xFFFFFF00u), float(c & 0xFFu));
+            return;
+        }
         const uint32_t cube = 1u << (3u * lev);
         const float kf = t.w * float(cube);  // exact: a power-of-two scale
         const uint32_t k = uint32_t(kf);
-        if (float(k) == kf && k <= cube) {
+        if (lev <= 7u && float(k) == kf && k <= cube) {
             atomicAdd(&st.seg_cnt[t.a], len * (cube - k));
             atomicAdd(&st.seg_cnt[t.b], len * k);
             return;
         }
-        const uint32_t c = len << (3u * lev);
         push_pair<SPARSE>(st, t, float(c & 0xFFFFFF00u), float(c & 0xFFu));
         return;
     }
