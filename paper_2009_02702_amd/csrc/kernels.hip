@@ -794,27 +794,57 @@ struct DeferRing {
     uint32_t tail;   // entries appended
 };
 
-// A run of `len` cubes of level `lev` on internal node `node` (dense state). A
-// rank-1 node on a cube is the cube's own two-source mixture, so its weight is
-// (voxels of b in the cube) / 8^lev: when w 8^lev is an integer k (levels <= 7,
-// where it is exact in fp32), the run's voxels split exactly into len (8^lev - k)
-// of a and len k of b, which go to the integer counters. Otherwise (a weight
-// that is not such a fraction, as in a quantized graph) the mass is pushed.
+// A run of `len` cubes of level `lev` on internal node `node` (dense state). The
+// node on a cube stands for the cube's own mixture, so the weight of a rank-1 or
+// rank-2 node there is (voxels on the b side) / 8^lev: when w 8^lev is an integer
+// k (levels <= 7, where the product is exact in fp32), the run's voxels split
+// exactly into len (8^lev - k) on the a side and len k on the b side. A side that
+// is a source takes its voxels as an integer count; a side that is a rank-1 node
+// (rank 2 only) splits its n voxels per cube by its own weight w': n w' is a
+// whole number of voxels (w' is a ratio of voxel counts of the mixtures the node
+// serves) up to the fp32 rounding of w', which a distance to the nearest integer
+// of at most n 2^-22 bounds, and that integer is the split. Any other weight (as
+// in a quantized graph) pushes the mass instead. Ranks 1 and 2 share one triple
+// load; a rank-2 node's two predecessor triples are loaded together.
 template <bool SPARSE>
 __device__ inline void resolve_count(const QueryState &st, const GraphView &gv, uint32_t node, uint32_t len,
                                      uint32_t lev)
 {
     if (!SPARSE && node < gv.r2_end) {
-        // ranks 1 and 2: one triple load for the lanes of both
         const NodeTriple t = gv.nodes[node];
         const uint32_t c = len << (3u * lev);
-        if (node >= gv.r1_end) {
-            push_rank2<SPARSE>(st, gv, t, float(c & 0xFFFFFF00u), float(c & 0xFFu));
-            return;
-        }
         const uint32_t cube = 1u << (3u * lev);
         const float kf = t.w * float(cube);  // exact: a power-of-two scale
         const uint32_t k = uint32_t(kf);
+        if (node >= gv.r1_end) {
+            if (!(lev <= 7u && float(k) == kf && k <= cube)) {
+                push_rank2<SPARSE>(st, gv, t, float(c & 0xFFFFFF00u), float(c & 0xFFu));
+                return;
+            }
+            const bool na = t.a >= gv.nseg, nb = t.b >= gv.nseg;
+            NodeTriple ta = {0u, 0u, 0.0f}, tb = {0u, 0u, 0.0f};
+            if (na) ta = gv.nodes[t.a];
+            if (nb) tb = gv.nodes[t.b];
+            // n voxels per cube on one side: to a source, or split by a rank-1 node
+            auto side = [&](uint32_t s, bool isnode, const NodeTriple &u, uint32_t n) {
+                if (n == 0u) return;
+                if (!isnode) {
+                    atomicAdd(&st.seg_cnt[s], len * n);
+                    return;
+                }
+                const float mf = u.w * float(n), m = rintf(mf);
+                if (fabsf(mf - m) <= float(n) * 0x1p-22f && m >= 0.0f && m <= float(n)) {
+                    atomicAdd(&st.seg_cnt[u.a], len * (n - uint32_t(m)));
+                    atomicAdd(&st.seg_cnt[u.b], len * uint32_t(m));
+                    return;
+                }
+                const uint32_t cs = len * n;
+                push_pair<SPARSE>(st, u, float(cs & 0xFFFFFF00u), float(cs & 0xFFu));
+            };
+            side(t.a, na, ta, cube - k);
+            side(t.b, nb, tb, k);
+            return;
+        }
         if (lev <= 7u && float(k) == kf && k <= cube) {
             atomicAdd(&st.seg_cnt[t.a], len * (cube - k));
             atomicAdd(&st.seg_cnt[t.b], len * k);
@@ -942,9 +972,9 @@ __device__ inline void scatter_runs(const Slab &sp, const RunLevel &rl, const Le
 // run length * 8^level at their start lane. Level-0 slabs of the 16-bit copy
 // (kind 1) hold two sources per unit (count_pairs).
 template <int BLOCK, int UNROLL, bool SPARSE>
-__device__ inline void scatter_slabs(const Slab *slabs, int n_slabs, const char *__restrict__ maps,
-                                     const char *__restrict__ maps16, const RunLevel *runs, const LevelTable &lt,
-                                     const QueryState &st, const GraphView &gv, const uint32_t *flags_lds)
+__device__ __attribute__((always_inline)) inline void scatter_slabs(
+    const Slab *slabs, int n_slabs, const char *__restrict__ maps, const char *__restrict__ maps16,
+    const RunLevel *runs, const LevelTable &lt, const QueryState &st, const GraphView &gv, const uint32_t *flags_lds)
 {
     constexpr uint32_t kWaves = BLOCK / 64;
     const uint32_t nseg = gv.nseg;

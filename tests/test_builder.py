@@ -95,20 +95,36 @@ def test_builder_lossless_voronoi_and_cylinders():
 
 @pytest.mark.parametrize("config,dims,segments", [(2, (40, 36, 34), 30), (3, (64, 48, 16), 12),
                                                   (4, (33, 40, 36), 25)])
-def test_rank1_nodes_on_full_cubes_split_into_whole_voxels(config, dims, segments):
-    """The query kernels split a run of cubes on a rank-1 node into integer source counts when
-    the node's fp32 weight times 8^level is a whole number k. For the exact graph that holds on
-    every full cube (levels <= 7) whose node has rank 1, with k the cube's voxels of child b:
-    the node is the cube's own two-source mixture."""
+def test_rank1_and_rank2_nodes_on_full_cubes_split_into_whole_voxels(config, dims, segments):
+    """The query kernels split a run of cubes on a rank-1 or rank-2 node into integer source
+    counts when the node's fp32 weight times 8^level is a whole number k (the voxels on the b
+    side), a rank-1 side of a rank-2 node splitting its n voxels per cube at the integer nearest
+    n w' when that is within n 2^-22. For the exact graph this holds on every full cube (levels
+    <= 7) whose node has rank 1 or 2, and the split is the cube's histogram: the node is the
+    cube's own mixture."""
     vol = synth.make_volume(synth.workload(config, dims=dims, segments=segments))
     g = Graph.build(vol)
     inf = g.info()
     S = inf["nseg"]
     d = g.export_dag()
-    r1_end = int(d["rank_ptr"][2])
+    r1_end, r2_end = int(d["rank_ptr"][2]), int(d["rank_ptr"][3])
+    alpha = d["alpha"].astype(np.float32)
     _, vol_c = scan.compact(vol)
     X, Y, Z = dims
-    seen = 0
+    seen = [0, 0]
+
+    def side(hist, s, n):  # n voxels per cube on a side: a source, or a rank-1 node's split
+        if n == 0:
+            return
+        if s < S:
+            hist[s] += n
+            return
+        mf = np.float32(alpha[s] * np.float32(n))
+        m = int(np.rint(mf))
+        assert abs(float(mf) - m) <= n * 2.0 ** -22 and 0 <= m <= n
+        hist[int(d["child_a"][s])] += n - m
+        hist[int(d["child_b"][s])] += m
+
     for l in range(1, min(inf["n_levels"], 8)):
         m = g.export_map(l)
         c = mipmap.counts_level(vol_c, S, l)
@@ -117,14 +133,16 @@ def test_rank1_nodes_on_full_cubes_split_into_whole_voxels(config, dims, segment
             for y in range(Y >> l):
                 for x in range(X >> l):
                     v = int(m[z, y, x])
-                    if not S <= v < r1_end:
+                    if not S <= v < r2_end:
                         continue
-                    k = np.float32(d["alpha"][v]) * np.float32(cube)
+                    k = np.float32(alpha[v] * np.float32(cube))
                     assert float(k) == int(k), (l, (x, y, z), v)
-                    a, b = int(d["child_a"][v]), int(d["child_b"][v])
-                    assert int(c[z, y, x][b]) == int(k) and int(c[z, y, x][a]) == cube - int(k)
-                    seen += 1
-    assert seen > 0
+                    hist = np.zeros(S, dtype=np.int64)
+                    side(hist, int(d["child_a"][v]), cube - int(k))
+                    side(hist, int(d["child_b"][v]), int(k))
+                    assert np.array_equal(hist, c[z, y, x].astype(np.int64)), (l, (x, y, z), v)
+                    seen[v >= r1_end] += 1
+    assert seen[0] > 0 and seen[1] > 0
     # a quantized graph's weights are not such fractions in general: the kernels push those
     q = g.quantize(5)
     qa = q.export_dag()["alpha"]
