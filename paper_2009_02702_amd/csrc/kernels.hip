@@ -967,10 +967,11 @@ __device__ inline void scatter_runs(const Slab &sp, const RunLevel &rl, const Le
 // lanes usually hold the same node (mixtures are spatially coherent), so a run
 // of equal nodes in a wave adds its total once. Runs on sources add to an
 // integer counter through their two end lanes (start: -a 8^l, end: (b+1) 8^l
-// for lanes a..b), which needs no run length; runs on internal nodes (rare)
-// take a branch that the whole wave skips when no lane needs it, and add
-// run length * 8^level at their start lane. Level-0 slabs of the 16-bit copy
-// (kind 1) hold two sources per unit (count_pairs).
+// for lanes a..b), which needs no run length; runs on internal nodes take a
+// branch that the whole wave skips when no lane needs it, where each start lane
+// hands (node, run length, level) to the wave's deferral ring (dense state) or
+// scatters run length * 8^level at once (sparse state). Level-0 slabs of the
+// 16-bit copy (kind 1) hold two sources per unit (count_pairs).
 template <int BLOCK, int UNROLL, bool SPARSE>
 __device__ __attribute__((always_inline)) inline void scatter_slabs(
     const Slab *slabs, int n_slabs, const char *__restrict__ maps, const char *__restrict__ maps16,
