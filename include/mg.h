@@ -209,10 +209,14 @@ int mg_query_boxes_plain(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float
 /* mg_query_boxes that also reports the work of each box, for roofline
  * accounting: d_stats device uint32 [n][2]. [q][0] = cubes in box q's
  * footprint. [q][1] bits 0..29 = entries the box's node table held: the
- * distinct internal nodes it scattered onto or reached by the push, plus,
- * for graphs with more sources than the LDS source arrays hold, the distinct
- * sources it touched (a source in those arrays takes no entry); bit 30 = the
- * box was answered by the retry launch, bit 31 = by a global-memory launch. */
+ * distinct internal nodes of rank >= 3 it scattered onto or reached by the
+ * push, plus, for graphs with more sources than the LDS source arrays hold,
+ * the distinct sources it touched (a source in those arrays takes no entry).
+ * Nodes of rank 1 and 2 (every predecessor a source, or a source or a rank-1
+ * node) pass their mass straight to the sources and take no entry, so they
+ * are not counted: the figure is a lower bound on the number of internal
+ * nodes in the closure of the box's cubes. Bit 30 = the box was answered by
+ * the retry launch, bit 31 = by a global-memory launch. */
 int mg_query_boxes_stats(mg_graph *g, const uint32_t *d_boxes, uint32_t n, float *d_out,
                          uint32_t *d_stats, void *d_work, uint64_t work_bytes, void *stream);
 
