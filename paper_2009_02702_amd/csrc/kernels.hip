@@ -1771,6 +1771,20 @@ __device__ inline float4 tf_source_colour(const uchar4 *tf, uint32_t nseg, uint3
     return make_float4(float(c.x) * k, float(c.y) * k, float(c.z) * k, float(c.w) * k);
 }
 
+// A node's colour from its predecessors' colours va, vb and its weight w: one
+// fma per channel, v_a + w (v_b - v_a) (every thread that computes a node's
+// colour evaluates exactly this, so a value rebuilt elsewhere is bit-identical).
+__device__ inline float4 tf_lerp(float w, float4 va, float4 vb)
+{
+#pragma clang fp contract(off)
+    float4 r;
+    r.x = fmaf(w, vb.x - va.x, va.x);
+    r.y = fmaf(w, vb.y - va.y, va.y);
+    r.z = fmaf(w, vb.z - va.z, va.z);
+    r.w = fmaf(w, vb.w - va.w, va.w);
+    return r;
+}
+
 // The entry of position i of a propagation order: with RANKS the nodes in ID
 // order (IDs are sorted by rank, so a rank is a contiguous ID range and node i's
 // triple is nodes[i]); else the deferred step schedule's entry sched[i].
@@ -1791,10 +1805,14 @@ __device__ inline SchedNode tf_entry(const NodeTriple *__restrict__ nodes, const
 // predecessors' colours in all P planes before it stores any, so 2 P gathers
 // per thread are in flight together. Lanes of a wave take consecutive entries
 // (coalesced entry reads and, nodes being numbered by rank, contiguous stores).
-// FIRST: the first step, whose nodes' predecessors are all sources (every
-// predecessor is scheduled at an earlier step): it reads their colours from the
-// transfer functions themselves, and threads x >= hi_i - lo_i write the sources'
-// own colours (the same values), so the frame needs no separate source pass.
+// FIRST: the first launch: the nodes of the first step (every predecessor a
+// source) and, in rank order, those of rank 2 too (every predecessor a source or
+// a rank-1 node). It reads source colours from the transfer functions
+// themselves and rebuilds a rank-1 predecessor's colour from that node's own two
+// sources by the same expression the rank-1 node's thread evaluates (so bit for
+// bit the value that thread stores), instead of waiting for it in a launch of
+// its own; threads x >= hi_i - lo_i write the sources' own colours (the same
+// values), so the frame needs no separate source pass.
 template <int P, bool FIRST, bool RANKS>
 __global__ void tf_step_kernel(const NodeTriple *__restrict__ nodes, const SchedNode *__restrict__ sched,
                                uint32_t lo_i, uint32_t hi_i, uint32_t n_nodes, uint32_t T,
@@ -1813,13 +1831,22 @@ __global__ void tf_step_kernel(const NodeTriple *__restrict__ nodes, const Sched
         return;
     }
     const SchedNode t = tf_entry<RANKS>(nodes, sched, lo_i + x);
+    NodeTriple ta{0u, 0u, 0.0f}, tb{0u, 0u, 0.0f};  // a rank-1 predecessor's own triple
+    if (FIRST) {
+        if (t.a >= nseg) ta = nodes[t.a];
+        if (t.b >= nseg) tb = nodes[t.b];
+    }
     float4 va[P], vb[P];
 #pragma unroll
     for (int p = 0; p < P; ++p)
         if (P == 1 || p0 + p < T) {
             if (FIRST) {
-                va[p] = tf_source_colour(tf, nseg, p0 + p, t.a);
-                vb[p] = tf_source_colour(tf, nseg, p0 + p, t.b);
+                va[p] = t.a < nseg ? tf_source_colour(tf, nseg, p0 + p, t.a)
+                                   : tf_lerp(ta.w, tf_source_colour(tf, nseg, p0 + p, ta.a),
+                                             tf_source_colour(tf, nseg, p0 + p, ta.b));
+                vb[p] = t.b < nseg ? tf_source_colour(tf, nseg, p0 + p, t.b)
+                                   : tf_lerp(tb.w, tf_source_colour(tf, nseg, p0 + p, tb.a),
+                                             tf_source_colour(tf, nseg, p0 + p, tb.b));
             } else {
                 const float4 *o = out + uint64_t(p0 + p) * n_nodes;
                 va[p] = o[t.a];
@@ -1828,14 +1855,7 @@ __global__ void tf_step_kernel(const NodeTriple *__restrict__ nodes, const Sched
         }
 #pragma unroll
     for (int p = 0; p < P; ++p)
-        if (P == 1 || p0 + p < T) {
-            float4 r;
-            r.x = fmaf(t.w, vb[p].x - va[p].x, va[p].x);
-            r.y = fmaf(t.w, vb[p].y - va[p].y, va[p].y);
-            r.z = fmaf(t.w, vb[p].z - va[p].z, va[p].z);
-            r.w = fmaf(t.w, vb[p].w - va[p].w, va[p].w);
-            out[uint64_t(p0 + p) * n_nodes + t.id] = r;
-        }
+        if (P == 1 || p0 + p < T) out[uint64_t(p0 + p) * n_nodes + t.id] = tf_lerp(t.w, va[p], vb[p]);
 }
 
 // The last steps of the schedule when each is small (at most kTfTailPairs node x
@@ -1858,13 +1878,7 @@ __global__ __launch_bounds__(kTfTailBlock) void tf_tail_kernel(const NodeTriple 
             const uint32_t t = j / n;
             const SchedNode e = tf_entry<RANKS>(nodes, sched, lo + j % n);
             float4 *o = out + uint64_t(t) * n_nodes;
-            const float4 va = o[e.a], vb = o[e.b];
-            float4 r;
-            r.x = fmaf(e.w, vb.x - va.x, va.x);
-            r.y = fmaf(e.w, vb.y - va.y, va.y);
-            r.z = fmaf(e.w, vb.z - va.z, va.z);
-            r.w = fmaf(e.w, vb.w - va.w, va.w);
-            o[e.id] = r;
+            o[e.id] = tf_lerp(e.w, o[e.a], o[e.b]);
         }
         __syncthreads();
     }
@@ -3307,16 +3321,19 @@ int dev_propagate_tf(Graph *g, const uint8_t *tf, uint32_t T, float *out, void *
     const uchar4 *tf4 = reinterpret_cast<const uchar4 *>(tf);
     const uint32_t D = g->depth;
     auto step_size = [&](uint32_t st) { return ptr[st + 1] - ptr[st]; };
+    // the first launch takes steps 1 .. first_end - 1: in rank order ranks 1 and 2
+    const uint32_t first_end = (ranks && D >= 2) ? 3u : 2u;
     // trailing small steps (two or more) go to the one-workgroup kernel
     uint32_t tail0 = D + 1;
-    while (tail0 > 2 && D + 2 - tail0 <= kTfTailSteps && uint64_t(step_size(tail0 - 1)) * T <= kTfTailPairs) --tail0;
+    while (tail0 > first_end && D + 2 - tail0 <= kTfTailSteps && uint64_t(step_size(tail0 - 1)) * T <= kTfTailPairs)
+        --tail0;
     if (D + 1 - tail0 < 2) tail0 = D + 1;
-    // step 1 (possibly empty) with the sources' colours, then the other steps
-    const uint32_t n1 = D >= 1 ? step_size(1) : 0u;
+    // the first launch (possibly empty) with the sources' colours, then the other steps
+    const uint32_t n1 = D >= 1 ? ptr[first_end] - ptr[1] : 0u;
     hipLaunchKernelGGL(pick(true), dim3((n1 + g->nseg + tb - 1) / tb, (T + P2 - 1) / P2), dim3(tb), 0, s,
                        g->dev.nodes, g->dev.sched, g->nseg, g->nseg + n1, g->n_nodes, T, tf4, g->nseg, o);
     HIP_TRY(hipGetLastError());
-    for (uint32_t st = 2; st < tail0; ++st) {
+    for (uint32_t st = first_end; st < tail0; ++st) {
         const uint32_t lo = ptr[st], hi = ptr[st + 1];
         if (hi <= lo) continue;
         hipLaunchKernelGGL(pick(false), dim3((hi - lo + tb - 1) / tb, (T + P2 - 1) / P2), dim3(tb), 0, s,
