@@ -269,12 +269,21 @@ def test_tf_matches_oracle_every_mip_voxel(dims, segments):
     """Every node's colour at every mip voxel against the oracle's mean TF colour. With the
     deferred schedule the first volume's steps after the first are all small (one workgroup runs
     them); the second has steps of more than 4096 node x TF pairs (one launch each) before its
-    small last steps. Rank by rank, both volumes have large first ranks and small last ones."""
+    small last steps. Rank by rank, both volumes have large first ranks and small last ones.
+    Rank by rank, the first launch also computes rank 2, rebuilding the colours of rank-1
+    predecessors from their sources; the deferred order reads them as stored, so equal colours
+    across the two orders pin that rebuild bit for bit."""
     vol = synth.make_volume(synth.workload(3, dims=dims, segments=segments))
     g = _graph("tf%d" % segments, vol)
     inf = g.info()
     S = inf["nseg"]
-    steps = np.diff(g.export_dag()["step_ptr"])[1:]
+    dag = g.export_dag()
+    rp = np.asarray(dag["rank_ptr"])
+    r2 = np.arange(rp[2], rp[3])
+    for side in ("child_a", "child_b"):   # rank-2 nodes with rank-1 predecessors on either side
+        p = np.asarray(dag[side])[r2]
+        assert ((p >= rp[1]) & (p < rp[2])).any(), side
+    steps = np.diff(dag["step_ptr"])[1:]
     if segments == 400:
         assert steps.max() * 5 > 4096 and steps[-1] * 5 <= 4096, steps
     tfs = synth.make_tfs(synth.workload(3), S, 5)
