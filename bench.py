@@ -93,10 +93,15 @@ def measure_tf(g, w, T, steps, warmup):
             "nodes": N, "depth": D, "order": "ranks" if g.launch_config()["tf_schedule"] == 0 else "deferred steps",
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                         "kernel": "tf_step_kernel per rank (the first also writes the sources' colours) and "
-                                   "tf_tail_kernel for the small last ranks (one frame, timed together)",
+                         "kernel": "tf_step_kernel per rank (the first also writes the sources' colours and, "
+                                   "in rank order, takes rank 2 too) and tf_tail_kernel for the small last ranks "
+                                   "(one frame, timed together)",
                          "kernel_ms": kern_ms, "alg_bytes_per_launch": alg,
-                         "alg_bytes_formula": "internal nodes x (12 + 32 T) + sources x 4 T"}}
+                         "alg_bytes_formula": "internal nodes x (12 + 32 T) + sources x 4 T",
+                         # the first launch rebuilds rank-1 colours for rank-2 nodes instead of reading
+                         # them, so the kernels move fewer bytes than the formula counts
+                         "frac_measured_bytes": (traffic / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                                 if traffic else None)}}
 
 
 def measure_serve(g, w, qps_list, seconds, trace_dir=None):
